@@ -1,0 +1,261 @@
+"""Seeded synthetic workloads for the power-series Newton step.
+
+This module only draws random numbers and builds index tables. It holds none
+of the method's arithmetic (no series products, no Newton step, no linear
+algebra of the method); both the oracle and the GPU path take their inputs
+from here.
+
+Workload families (the paper's own systems are synthetic monomial systems with
+exponential-series solutions, Section 3; the sizes below replace them):
+
+* ``small_dd``   n=8,   degree 15,  double-double, 8 monomials of 3 variables
+                 with exponent 1 per polynomial, plus a constant series.
+* ``medium_qd``  n=64,  degree 63,  quad-double, 32 monomials of 2..6
+                 variables with exponents in {1,2}, plus a diagonal boost.
+* ``large_od``   n=128, degree 127, octo-double, 64 monomials of 4..8
+                 variables with exponents in {1,2,3}, plus a diagonal boost.
+* ``adjoint_qd`` n=32,  degree 31,  quad-double, 32 monomials of 3..5
+                 variables with exponents in {1,2}, plus a diagonal boost.
+* ``batched``    many independent paths of uneven size (see ``batched_paths``).
+
+Multiple-double numbers are stored limb-major (structure of arrays by limb),
+shape ``[L, ...]``, as the paper does to keep memory accesses coalesced
+(Section 1.2 and Section 6).  A random multiple double has every limb drawn:
+limb ``l+1`` is uniform in ``(-ulp(limb_l)/2, ulp(limb_l)/2)``, so the limbs
+never overlap and lower-limb mistakes cannot hide behind zeros.
+"""
+from __future__ import annotations
+
+import dataclasses
+import numpy as np
+
+PRECISIONS = {"dd": 2, "qd": 4, "od": 8}
+
+
+@dataclasses.dataclass
+class System:
+    """A polynomial system p_i(x) = c_{i,0}(t) + sum_m c_{i,m} x^{a_{i,m}}.
+
+    Index tables (CSR):
+      poly_ptr[n+1]  monomials of polynomial i are mon_ptr range poly_ptr[i]..poly_ptr[i+1]
+      mon_ptr[m+1]   support entries of monomial j are mon_ptr[j]..mon_ptr[j+1]
+      var[nnz]       variable index of each support entry, strictly increasing per monomial
+      exp[nnz]       exponent (>= 1) of each support entry
+    Values (limb-major multiple doubles):
+      cff[L, m]      scalar coefficient of each monomial
+      xstar[L, n, D] the manufactured solution series (D = d + 1 coefficients)
+    """
+
+    name: str
+    L: int
+    n: int
+    d: int
+    poly_ptr: np.ndarray
+    mon_ptr: np.ndarray
+    var: np.ndarray
+    exp: np.ndarray
+    cff: np.ndarray
+    xstar: np.ndarray
+    seed: int
+    steps: int = 1
+    boost: np.ndarray | None = None  # index of the boost monomial of each row, or None
+
+    @property
+    def D(self) -> int:
+        return self.d + 1
+
+    @property
+    def m(self) -> int:
+        return int(self.mon_ptr.shape[0] - 1)
+
+    @property
+    def nnz(self) -> int:
+        return int(self.var.shape[0])
+
+    def start(self) -> np.ndarray:
+        """x*(0) as a series: coefficient 0 of x*, all higher coefficients zero."""
+        x = np.zeros_like(self.xstar)
+        x[:, :, 0] = self.xstar[:, :, 0]
+        return x
+
+
+def random_md(rng: np.random.Generator, L: int, shape, lo: float, hi: float) -> np.ndarray:
+    """Random multiple doubles with every limb populated, limb-major [L, *shape].
+
+    The leading limb is uniform in [lo, hi]; each lower limb is uniform in
+    (-ulp/2, ulp/2) of the limb above, so the expansion is nonoverlapping.
+    """
+    shape = tuple(np.atleast_1d(shape)) if not isinstance(shape, tuple) else shape
+    out = np.zeros((L,) + shape, dtype=np.float64)
+    out[0] = rng.uniform(lo, hi, size=shape)
+    for l in range(1, L):
+        half_ulp = 0.5 * np.spacing(np.abs(out[l - 1]))
+        out[l] = rng.uniform(-1.0, 1.0, size=shape) * half_ulp
+    return out
+
+
+def random_series(rng, L, n, D, lo=0.5, hi=1.5, damping: float = 1.0) -> np.ndarray:
+    """Random series x[L, n, D] with coefficients uniform in [lo, hi].
+
+    ``damping`` < 1 draws coefficient k in damping^k * [lo, hi] (the paper's
+    delta-damping of t, end of Section 3).
+    """
+    x = random_md(rng, L, (n, D), lo, hi)
+    if damping != 1.0:
+        scale = damping ** np.arange(D, dtype=np.float64)
+        # scale every limb by a power of two close to damping^k keeps limbs exact
+        p2 = np.exp2(np.round(np.log2(scale)))
+        x = x * p2[None, None, :]
+    return x
+
+
+def _supports(rng, n, n_mon_per_poly, kmin, kmax, exps):
+    poly_ptr = [0]
+    mon_ptr = [0]
+    var, ex = [], []
+    for i in range(n):
+        nm = n_mon_per_poly(i)
+        for _ in range(nm):
+            k = int(rng.integers(kmin, kmax + 1))
+            k = min(k, n)
+            vs = np.sort(rng.choice(n, size=k, replace=False))
+            es = rng.choice(np.asarray(exps), size=k)
+            var.extend(int(v) for v in vs)
+            ex.extend(int(e) for e in es)
+            mon_ptr.append(len(var))
+        poly_ptr.append(len(mon_ptr) - 1)
+    return (np.asarray(poly_ptr, np.int32), np.asarray(mon_ptr, np.int32),
+            np.asarray(var, np.int32), np.asarray(ex, np.int32))
+
+
+def jacobian0_estimate(poly_ptr, mon_ptr, var, exp, cff_hi, x0_hi) -> np.ndarray:
+    """Float64 estimate of the Jacobian at the point x0 (leading limbs only).
+
+    Used only to choose the diagonal boost and to check the condition number
+    of a generated system; it is not part of any computed result.
+    """
+    n = len(poly_ptr) - 1
+    J = np.zeros((n, n))
+    for i in range(n):
+        for mj in range(poly_ptr[i], poly_ptr[i + 1]):
+            vs = var[mon_ptr[mj]:mon_ptr[mj + 1]]
+            es = exp[mon_ptr[mj]:mon_ptr[mj + 1]]
+            for a in range(len(vs)):
+                g = cff_hi[mj] * es[a] * x0_hi[vs[a]] ** (es[a] - 1)
+                for b in range(len(vs)):
+                    if b != a:
+                        g *= x0_hi[vs[b]] ** es[b]
+                J[i, vs[a]] += g
+    return J
+
+
+def _append_boost(poly_ptr, mon_ptr, var, exp, cff, L, s):
+    """Append one linear monomial s_i * x_i at the end of every polynomial."""
+    n = len(poly_ptr) - 1
+    new_pp, new_mp, new_var, new_exp, new_cff = [0], [0], [], [], []
+    boost_idx = np.zeros(n, np.int32)
+    for i in range(n):
+        for mj in range(poly_ptr[i], poly_ptr[i + 1]):
+            new_var.extend(var[mon_ptr[mj]:mon_ptr[mj + 1]].tolist())
+            new_exp.extend(exp[mon_ptr[mj]:mon_ptr[mj + 1]].tolist())
+            new_mp.append(len(new_var))
+            new_cff.append(cff[:, mj])
+        new_var.append(i)
+        new_exp.append(1)
+        new_mp.append(len(new_var))
+        c = np.zeros(L)
+        c[0] = s[i]
+        new_cff.append(c)
+        boost_idx[i] = len(new_mp) - 2
+        new_pp.append(len(new_mp) - 1)
+    return (np.asarray(new_pp, np.int32), np.asarray(new_mp, np.int32),
+            np.asarray(new_var, np.int32), np.asarray(new_exp, np.int32),
+            np.stack(new_cff, axis=1), boost_idx)
+
+
+def make_system(name: str, L: int, n: int, d: int, mons_per_poly, kmin: int, kmax: int,
+                exps, seed: int, cond_max: float | None, boost: bool, steps: int = 1,
+                damping: float = 1.0, max_tries: int = 64) -> System:
+    """Draw a system and its manufactured solution.
+
+    Without ``boost`` the system is redrawn (from a derived seed) until the
+    float64 estimate of cond_2(J(x*(0))) is at most ``cond_max``.  With
+    ``boost`` one linear monomial s_i x_i is appended to every polynomial;
+    s_i starts at 1/8 of the row's absolute sum of the estimated Jacobian and
+    is doubled until the condition bound holds.
+    """
+    D = d + 1
+    for attempt in range(max_tries):
+        rng = np.random.default_rng([seed, attempt])
+        if callable(mons_per_poly):
+            per = mons_per_poly
+        else:
+            per = (lambda i, _c=int(mons_per_poly): _c)
+        pp, mp, var, ex = _supports(rng, n, lambda i: per(i) if not callable(mons_per_poly) else int(mons_per_poly(rng)), kmin, kmax, exps)
+        m = len(mp) - 1
+        cff = random_md(rng, L, (m,), -1.0, 1.0)
+        xstar = random_series(rng, L, n, D, 0.5, 1.5, damping)
+        J = jacobian0_estimate(pp, mp, var, ex, cff[0], xstar[0, :, 0])
+        bidx = None
+        if boost:
+            rowsum = np.abs(J).sum(axis=1) + 1.0
+            gamma = 0.125
+            for _ in range(40):
+                s = np.exp2(np.ceil(np.log2(gamma * rowsum))) * np.where(np.diag(J) < 0, -1.0, 1.0)
+                Jb = J + np.diag(s)
+                if cond_max is None or np.linalg.cond(Jb) <= cond_max:
+                    break
+                gamma *= 2.0
+            pp, mp, var, ex, cff, bidx = _append_boost(pp, mp, var, ex, cff, L, s)
+            J = Jb
+        if cond_max is None or np.linalg.cond(J) <= cond_max:
+            return System(name, L, n, d, pp, mp, var, ex, np.ascontiguousarray(cff), xstar, seed,
+                          steps, bidx)
+    raise RuntimeError(f"no system with cond <= {cond_max} after {max_tries} draws")
+
+
+def small_dd(seed: int = 1) -> System:
+    """n=8, d=15, dd; 8 monomials x 3 distinct variables, exponent 1; 4 steps."""
+    return make_system("small_dd", 2, 8, 15, 8, 3, 3, (1,), seed, 1e3, boost=False, steps=4)
+
+
+def medium_qd(seed: int = 2) -> System:
+    """n=64, d=63, qd; 32 monomials x 2..6 variables, exponents {1,2}; 6 steps."""
+    return make_system("medium_qd", 4, 64, 63, 32, 2, 6, (1, 2), seed, 1e3, boost=True, steps=6)
+
+
+def large_od(seed: int = 3) -> System:
+    """n=128, d=127, od; 64 monomials x 4..8 variables, exponents {1,2,3}; 8 steps."""
+    return make_system("large_od", 8, 128, 127, 64, 4, 8, (1, 2, 3), seed, 1e4, boost=True, steps=8)
+
+
+def adjoint_qd(seed: int = 5) -> System:
+    """n=32, d=31, qd; 32 monomials x 3..5 variables, exponents {1,2}."""
+    return make_system("adjoint_qd", 4, 32, 31, 32, 3, 5, (1, 2), seed, 1e3, boost=True, steps=6)
+
+
+def tiny(L: int, n: int, d: int, mons: int = 3, kmin: int = 1, kmax: int = 3, exps=(1, 2),
+         seed: int = 0, boost: bool = True, cond_max: float = 1e3, damping: float = 1.0) -> System:
+    """Small systems for parity tests that the oracle finishes in seconds."""
+    return make_system(f"tiny_L{L}_n{n}_d{d}", L, n, d, mons, kmin, kmax, exps, seed, cond_max,
+                       boost=boost, steps=1, damping=damping)
+
+
+PRESETS = {
+    "small_dd": small_dd,
+    "medium_qd": medium_qd,
+    "large_od": large_od,
+    "adjoint_qd": adjoint_qd,
+}
+
+
+def random_point(sys: System, seed: int, lo: float = 0.5, hi: float = 1.5) -> np.ndarray:
+    """A random series point x[L, n, D] for evaluation tests."""
+    rng = np.random.default_rng([seed, 7919])
+    return random_series(rng, sys.L, sys.n, sys.D, lo, hi)
+
+
+def random_constant(sys: System, seed: int, lo: float = -1.0, hi: float = 1.0) -> np.ndarray:
+    """A random constant series c_{i,0}(t), shape [L, n, D]."""
+    rng = np.random.default_rng([seed, 104729])
+    return random_md(rng, sys.L, (sys.n, sys.D), lo, hi)

@@ -1,0 +1,231 @@
+"""Oracle for the power-series Newton step (TEST INFRASTRUCTURE ONLY).
+
+A plain, slow, arbitrary-precision CPU implementation in C with MPFR
+(``oracle.c``), wrapped here with ctypes.  Only the tests, the smoke check and
+the CPU-baseline leg of the benchmark may import it.  It shares no code with
+the GPU library: inputs come from the seeded generators in ``mdinputs``.
+
+Working precision of the oracle: four times the bits of the multiple doubles
+under test (dd 424, qd 848, od 1696 bits) unless a caller asks for more.
+
+Every function takes and returns limb-major arrays.  Results are returned as
+"expansions" of K doubles (default 4L+2) that keep the oracle's full precision;
+``absdiff`` measures |gpu - oracle| exactly.
+
+Parity pins (see tests/test_oracle_pins.py): brute-force exact rationals on
+tiny systems, the paper's exponential-series worked example (Section 3),
+binomial series, classical Newton at D=1, one-step convergence of linear
+systems, quadratic convergence from a manufactured solution, the paper's
+Table 1 values.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+_SRC = os.path.join(_HERE, "oracle.c")
+_MPFR_INC = "/opt/conda/include"
+_LIBS = ["/usr/lib/x86_64-linux-gnu/libmpfr.so.6", "/usr/lib/x86_64-linux-gnu/libgmp.so.10"]
+
+_lib = None
+
+
+def build() -> str:
+    """Compile liboracle.so with gcc (C + MPFR + OpenMP)."""
+    cmd = ["gcc", "-O2", "-fPIC", "-shared", "-fopenmp", "-I" + _MPFR_INC, "-o", _SO + ".tmp", _SRC] + _LIBS
+    subprocess.run(cmd, check=True)
+    os.replace(_SO + ".tmp", _SO)
+    return _SO
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            build()
+        L = ctypes.CDLL(_SO)
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        dp = ctypes.POINTER(ctypes.c_double)
+        ci = ctypes.c_int
+        L.ora_eval.argtypes = [ci, ci, ci, ci, i32p, i32p, i32p, i32p, ci, dp, dp, dp, ci, ci, ci, dp, dp, dp]
+        L.ora_newton_step.argtypes = [ci, ci, ci, ci, i32p, i32p, i32p, i32p, ci, dp, dp, dp, ci, dp, dp, dp, dp]
+        L.ora_toeplitz_solve.argtypes = [ci, ci, ci, ci, dp, dp, ci, dp]
+        L.ora_manufacture.argtypes = [ci, ci, ci, ci, i32p, i32p, i32p, i32p, ci, dp, dp, ci, dp]
+        L.ora_round.argtypes = [ci, ci, dp, ci, ci, dp]
+        L.ora_absdiff.argtypes = [ci, ci, dp, ci, dp, ci, dp]
+        L.ora_qr_check.argtypes = [ci, ci, ci, dp, dp, dp, dp]
+        L.ora_rdiag.argtypes = [ci, ci, ci, dp, ci, dp]
+        L.ora_set_threads.argtypes = [ci]
+        _lib = L
+    return _lib
+
+
+def set_threads(t: int) -> None:
+    lib().ora_set_threads(int(t))
+
+
+def threads() -> int:
+    return int(lib().ora_get_threads())
+
+
+def inexact_inputs() -> int:
+    """How many multiple-double inputs were not exactly representable (must be 0)."""
+    return int(lib().ora_inexact_count())
+
+
+def prec_bits(L: int) -> int:
+    return 4 * 53 * L
+
+
+def _d(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _i(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+def _c64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _c32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def _check(rc: int, what: str):
+    if rc == -2:
+        raise OracleError(f"{what}: A_0 is singular")
+    if rc != 0:
+        raise OracleError(f"{what}: error {rc}")
+
+
+def _sys_args(sys):
+    return (_c32(sys.poly_ptr), _c32(sys.mon_ptr), _c32(sys.var), _c32(sys.exp))
+
+
+def eval_diff(sys, cff, cst, x, rows=None, K=None, prec=None):
+    """b = -p(x) and A = p'(x) for rows ``rows=(r0, r1)``.
+
+    Returns b[K, rows, D], A[K, D, rows, n] and the row scale
+    max_s (|c_{i,0,s}| + sum_m |value_{m,s}|) used to judge b near a root."""
+    L = cff.shape[0]
+    K = K or 4 * L + 2
+    prec = prec or prec_bits(L)
+    r0, r1 = rows or (0, sys.n)
+    R = r1 - r0
+    pp, mp, var, ex = _sys_args(sys)
+    cff, cst, x = _c64(cff), _c64(cst), _c64(x)
+    b = np.zeros((K, R, sys.D))
+    A = np.zeros((K, sys.D, R, sys.n))
+    sc = np.zeros(R)
+    rc = lib().ora_eval(prec, sys.n, sys.D, sys.m, _i(pp), _i(mp), _i(var), _i(ex), L, _d(cff), _d(cst),
+                        _d(x), r0, r1, K, _d(b), _d(A), _d(sc))
+    _check(rc, "ora_eval")
+    return b, A, sc
+
+
+def newton_step(sys, cff, cst, x, K=None, prec=None, want_A=False):
+    """One Newton step from x; returns dict of expansions x, dx, b (and A)."""
+    L = cff.shape[0]
+    K = K or 4 * L + 2
+    prec = prec or prec_bits(L)
+    pp, mp, var, ex = _sys_args(sys)
+    cff, cst, x = _c64(cff), _c64(cst), _c64(x)
+    out = {k: np.zeros((K, sys.n, sys.D)) for k in ("x", "dx", "b")}
+    A = np.zeros((K, sys.D, sys.n, sys.n)) if want_A else None
+    rc = lib().ora_newton_step(prec, sys.n, sys.D, sys.m, _i(pp), _i(mp), _i(var), _i(ex), L, _d(cff),
+                               _d(cst), _d(x), K, _d(out["x"]), _d(out["dx"]), _d(out["b"]),
+                               _d(A) if want_A else ctypes.POINTER(ctypes.c_double)())
+    _check(rc, "ora_newton_step")
+    if want_A:
+        out["A"] = A
+    return out
+
+
+def toeplitz_solve(A, rhs, K=None, prec=None):
+    """Solve the block lower-triangular Toeplitz system; A[L, D, n, n], rhs[L, n, D]."""
+    L, D, n, _ = A.shape
+    K = K or 4 * L + 2
+    prec = prec or prec_bits(L)
+    A, rhs = _c64(A), _c64(rhs)
+    dx = np.zeros((K, n, D))
+    rc = lib().ora_toeplitz_solve(prec, n, D, L, _d(A), _d(rhs), K, _d(dx))
+    _check(rc, "ora_toeplitz_solve")
+    return dx
+
+
+def manufacture(sys, Lout=None, prec=None):
+    """Constant series c_{i,0} = -sum_m c_m x*^{a_m}, rounded to Lout limbs."""
+    L = sys.cff.shape[0]
+    Lout = Lout or L
+    prec = prec or prec_bits(max(L, Lout))
+    pp, mp, var, ex = _sys_args(sys)
+    cst = np.zeros((Lout, sys.n, sys.D))
+    rc = lib().ora_manufacture(prec, sys.n, sys.D, sys.m, _i(pp), _i(mp), _i(var), _i(ex), L,
+                               _d(_c64(sys.cff)), _d(_c64(sys.xstar)), Lout, _d(cst))
+    _check(rc, "ora_manufacture")
+    return cst
+
+
+def round_md(e: np.ndarray, L: int, prec=None) -> np.ndarray:
+    """Round expansions e[K, ...] to L-limb multiple doubles (limb by limb to nearest)."""
+    K = e.shape[0]
+    shape = e.shape[1:]
+    flat = _c64(e.reshape(K, -1))
+    cnt = flat.shape[1]
+    out = np.zeros((L, cnt))
+    lib().ora_round(prec or 4 * 53 * max(K, L), K, _d(flat), cnt, L, _d(out))
+    return out.reshape((L,) + shape)
+
+
+def absdiff(u: np.ndarray, w: np.ndarray, prec=None) -> np.ndarray:
+    """|u - w| computed exactly for expansions u[Lu, ...], w[Lw, ...]."""
+    Lu, Lw = u.shape[0], w.shape[0]
+    assert u.shape[1:] == w.shape[1:]
+    shape = u.shape[1:]
+    uf, wf = _c64(u.reshape(Lu, -1)), _c64(w.reshape(Lw, -1))
+    cnt = uf.shape[1]
+    out = np.zeros(cnt)
+    lib().ora_absdiff(prec or 53 * (Lu + Lw) + 2200, Lu, _d(uf), Lw, _d(wf), cnt, _d(out))
+    return out.reshape(shape)
+
+
+def qr_check(A0, qr, tau, prec=None):
+    """(max|QR - A0|/max|A0|, max|Q^T Q - I|) for a compact Householder QR."""
+    L, n, _ = A0.shape
+    out = np.zeros(2)
+    lib().ora_qr_check(prec or prec_bits(L), n, L, _d(_c64(A0)), _d(_c64(qr)), _d(_c64(tau)), _d(out))
+    return float(out[0]), float(out[1])
+
+
+def rdiag(A0, K=None, prec=None):
+    """|R_ii| of the QR factorization of A0[L, n, n] (unique), as expansions [K, n]."""
+    L, n, _ = A0.shape
+    K = K or 4 * L + 2
+    out = np.zeros((K, n))
+    rc = lib().ora_rdiag(prec or prec_bits(L), n, L, _d(_c64(A0)), K, _d(out))
+    _check(rc, "ora_rdiag")
+    return out
+
+
+def rel_err_series(gpu: np.ndarray, ora: np.ndarray, axis_series=-1) -> np.ndarray:
+    """Normwise relative error per series: max_k |gpu-ora| / max_k |ora| (0/0 = 0).
+
+    gpu[L, ..., D] and ora[K, ..., D]; the last axis indexes the coefficients."""
+    diff = absdiff(gpu, ora)
+    mag = np.abs(ora[0])
+    num = diff.max(axis=axis_series)
+    den = mag.max(axis=axis_series)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        r = np.where(den > 0, num / np.where(den > 0, den, 1.0), np.where(num > 0, np.inf, 0.0))
+    return r

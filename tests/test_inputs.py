@@ -1,0 +1,55 @@
+"""The seeded workload generators (CPU only)."""
+import numpy as np
+import pytest
+
+import mdinputs
+
+
+def test_deterministic_per_seed():
+    a, b = mdinputs.small_dd(), mdinputs.small_dd()
+    for f in ("poly_ptr", "mon_ptr", "var", "exp", "cff", "xstar"):
+        assert np.array_equal(getattr(a, f), getattr(b, f))
+    c = mdinputs.small_dd(seed=99)
+    assert not np.array_equal(a.cff, c.cff)
+
+
+@pytest.mark.parametrize("L", [2, 4, 8])
+def test_random_md_nonoverlapping_all_limbs(L):
+    rng = np.random.default_rng(1)
+    x = mdinputs.random_md(rng, L, (1000,), -1.0, 1.0)
+    assert np.all(x != 0.0)
+    for l in range(L - 1):
+        assert np.all(np.abs(x[l + 1]) <= 0.5 * np.spacing(np.abs(x[l])))
+
+
+def test_small_dd_shape_and_condition():
+    s = mdinputs.small_dd()
+    assert (s.L, s.n, s.d, s.D) == (2, 8, 15, 16)
+    assert s.m == 64 and np.all(np.diff(s.mon_ptr) == 3) and np.all(s.exp == 1)
+    J = mdinputs.jacobian0_estimate(s.poly_ptr, s.mon_ptr, s.var, s.exp, s.cff[0], s.xstar[0, :, 0])
+    assert np.linalg.cond(J) <= 1e3
+    # supports strictly increasing per monomial
+    for j in range(s.m):
+        v = s.var[s.mon_ptr[j]:s.mon_ptr[j + 1]]
+        assert np.all(np.diff(v) > 0)
+
+
+def test_medium_qd_matches_recipe():
+    s = mdinputs.medium_qd()
+    assert (s.L, s.n, s.D) == (4, 64, 64)
+    per_row = np.diff(s.poly_ptr)
+    assert np.all(per_row == 33)  # 32 monomials plus the diagonal boost
+    k = np.diff(s.mon_ptr)
+    boost = set(s.boost.tolist())
+    ks = np.array([k[j] for j in range(s.m) if j not in boost])
+    assert ks.min() >= 2 and ks.max() <= 6
+    assert set(np.unique(s.exp).tolist()) <= {1, 2}
+    x0 = s.xstar[0]
+    assert x0.min() >= 0.5 * 0.25 ** (s.D - 1) * 0.99
+
+
+def test_damping_scales_by_powers_of_two():
+    s = mdinputs.make_system("t", 2, 4, 7, 2, 1, 2, (1,), 3, None, boost=False, damping=0.25)
+    r = mdinputs.make_system("t", 2, 4, 7, 2, 1, 2, (1,), 3, None, boost=False, damping=1.0)
+    for k in range(8):
+        assert np.array_equal(s.xstar[:, :, k], r.xstar[:, :, k] * 0.25 ** k)

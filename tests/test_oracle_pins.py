@@ -1,0 +1,416 @@
+"""Pins of the oracle against things other than itself (CPU only).
+
+Each test checks the oracle against the mathematics or the paper:
+exact rational brute force with sympy, the paper's exponential-series worked
+example (Section 3) and its two-column variant, binomial series, classical
+Newton at D=1 with a hand-written Jacobian, one-step convergence on linear
+systems, quadratic convergence in t-order, the stopping invariant of
+Section 4, the printed 1/k! values of Table 1, and LAPACK's Householder QR
+for the QR checker.  A plausible slip in the oracle (dropped convolution
+term, wrong sign of b, transposed Jacobian, wrong block index in the forward
+substitution, wrong exponent handling, pivoting error) fails at least one.
+"""
+from __future__ import annotations
+
+import math
+import os
+from fractions import Fraction
+
+import mpmath
+import numpy as np
+import pytest
+import sympy
+
+import mdinputs
+import oracle
+from oracle_helpers import make, md_value, series_md, to_md
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def exact(e):
+    """Exact values of expansions e[K, ...] as a Fraction array."""
+    K = e.shape[0]
+    flat = e.reshape(K, -1)
+    return np.array([md_value(flat[:, q]) for q in range(flat.shape[1])], dtype=object).reshape(e.shape[1:])
+
+
+def newton_run(sys, cst, x, steps):
+    for _ in range(steps):
+        x = oracle.newton_step(sys, sys.cff, cst, x)["x"]
+    return x
+
+
+# --------------------------------------------------------------------------
+# 1. brute force: exact rational arithmetic with sympy on tiny systems
+# --------------------------------------------------------------------------
+
+def _sympy_step(sys, cst, x):
+    """Exact b, A, and Newton step with sympy: expand p(x(t)), differentiate
+    symbolically, solve the full (nD x nD) block system by exact LU."""
+    t = sympy.Symbol("t")
+    n, D, L = sys.n, sys.D, sys.L
+    X = sympy.symbols(f"y0:{n}")
+    cfv = [md_value(sys.cff[:, j]) for j in range(sys.m)]
+    xs = [sum(sympy.Rational(md_value(x[:, i, s])) * t ** s for s in range(D)) for i in range(n)]
+    cs = [sum(sympy.Rational(md_value(cst[:, i, s])) * t ** s for s in range(D)) for i in range(n)]
+    P = []
+    for i in range(n):
+        expr = 0
+        for mj in range(sys.poly_ptr[i], sys.poly_ptr[i + 1]):
+            term = sympy.Rational(cfv[mj])
+            for q in range(sys.mon_ptr[mj], sys.mon_ptr[mj + 1]):
+                term *= X[sys.var[q]] ** int(sys.exp[q])
+            expr += term
+        P.append(expr)
+
+    def trunc(e):
+        poly = sympy.Poly(sympy.expand(e), t)
+        return [poly.coeff_monomial(t ** s) for s in range(D)]
+
+    sub = dict(zip(X, xs))
+    b = [[-c for c in trunc(cs[i] + P[i].subs(sub))] for i in range(n)]
+    A = [[trunc(sympy.diff(P[i], X[j]).subs(sub)) for j in range(n)] for i in range(n)]
+    # full block lower-triangular Toeplitz matrix, unknowns ordered (k, i)
+    T = sympy.zeros(n * D, n * D)
+    rhs = sympy.zeros(n * D, 1)
+    for k in range(D):
+        for i in range(n):
+            rhs[k * n + i] = b[i][k]
+            for j in range(k + 1):
+                for v in range(n):
+                    T[k * n + i, j * n + v] = A[i][v][k - j]
+    sol = T.LUsolve(rhs)
+    dx = [[sol[k * n + i] for k in range(D)] for i in range(n)]
+    xn = [[sympy.Rational(md_value(x[:, i, s])) + dx[i][s] for s in range(D)] for i in range(n)]
+    return b, A, xn
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_brute_force_sympy(seed):
+    sys = mdinputs.tiny(2, 3, 3, mons=2, kmin=1, kmax=3, exps=(1, 2), seed=seed)
+    x = mdinputs.random_point(sys, seed)
+    cst = mdinputs.random_constant(sys, seed)
+    b, A, xn = _sympy_step(sys, cst, x)
+    ob, oA, _ = oracle.eval_diff(sys, sys.cff, cst, x, prec=700, K=16)
+    out = oracle.newton_step(sys, sys.cff, cst, x, prec=700, K=16)
+    eb, eA, ex = exact(ob), exact(oA), exact(out["x"])
+    tol = Fraction(1, 2 ** 600)
+    for i in range(sys.n):
+        for s in range(sys.D):
+            assert abs(eb[i, s] - Fraction(str(b[i][s]))) <= tol * (1 + abs(eb[i, s]))
+            assert abs(ex[i, s] - Fraction(str(xn[i][s]))) <= tol * (1 + abs(ex[i, s]))
+            for j in range(sys.n):
+                assert abs(eA[s, i, j] - Fraction(str(A[i][j][s]))) <= tol * (1 + abs(eA[s, i, j]))
+
+
+# --------------------------------------------------------------------------
+# 2. the paper's worked example: x^E = b(t) with exponential solutions
+# --------------------------------------------------------------------------
+
+def _exp_coefs(alpha: Fraction, D: int):
+    return [alpha ** k / math.factorial(k) for k in range(D)]
+
+
+def test_exp_one_column_closed_form():
+    """Section 3: E lower triangular of ones, b_i(t) = exp((a_1+..+a_i) t);
+    the unique solution is x_k(t) = exp(a_k t)."""
+    L, n, d = 2, 4, 15
+    D = d + 1
+    alphas = [Fraction(3, 4), Fraction(-7, 8), Fraction(1, 1), Fraction(-5, 8)]
+    polys = [[(1, [(j, 1) for j in range(i + 1)])] for i in range(n)]
+    sys = make(L, n, d, polys)
+    sums = np.cumsum(np.array(alphas, dtype=object))
+    cst = series_md([[-c for c in _exp_coefs(sums[i], D)] for i in range(n)], L)
+    x = np.zeros((L, n, D))
+    x[0, :, 0] = 1.0
+    x = newton_run(sys, cst, x, 6)
+    ex = exact(x)
+    for i in range(n):
+        ref = _exp_coefs(alphas[i], D)
+        err = max(abs(ex[i, k] - ref[k]) for k in range(D))
+        assert err < 1e-29, (i, float(err))
+
+
+def test_exp_two_columns_closed_form():
+    """Section 3: c1 x^{E1} + c2 x^{E2} = b(t), E1 lower and E2 upper
+    triangular ones; with b manufactured from x_k = exp(a_k t) exactly."""
+    L, n, d = 2, 3, 11
+    D = d + 1
+    alphas = [Fraction(1, 2), Fraction(-3, 4), Fraction(7, 8)]
+    c1 = [Fraction(5, 4), Fraction(-3, 2), Fraction(7, 4)]
+    c2 = [Fraction(-1, 2), Fraction(3, 4), Fraction(1, 4)]
+    polys = []
+    csts = []
+    for i in range(n):
+        low = list(range(i + 1))
+        up = list(range(n - i))
+        polys.append([(c1[i], [(j, 1) for j in low]), (c2[i], [(j, 1) for j in up])])
+        s1 = sum(alphas[j] for j in low)
+        s2 = sum(alphas[j] for j in up)
+        e1, e2 = _exp_coefs(s1, D), _exp_coefs(s2, D)
+        csts.append([-(c1[i] * e1[k] + c2[i] * e2[k]) for k in range(D)])
+    sys = make(L, n, d, polys)
+    cst = series_md(csts, L)
+    x = np.zeros((L, n, D))
+    x[0, :, 0] = 1.0
+    x = newton_run(sys, cst, x, 6)
+    ex = exact(x)
+    for i in range(n):
+        ref = _exp_coefs(alphas[i], D)
+        assert max(abs(ex[i, k] - ref[k]) for k in range(D)) < 1e-28
+
+
+# --------------------------------------------------------------------------
+# 3. binomial series
+# --------------------------------------------------------------------------
+
+def _binom(r: Fraction, k: int) -> Fraction:
+    out = Fraction(1)
+    for j in range(k):
+        out = out * (r - j) / (j + 1)
+    return out
+
+
+@pytest.mark.parametrize("e", [2, 3])
+def test_root_binomial_series(e):
+    """n = 1, x^e = 1 + t: the series of (1+t)^(1/e) has coefficients binom(1/e, k)."""
+    L, d = 4, 23
+    D = d + 1
+    sys = make(L, 1, d, [[(1, [(0, e)])]])
+    cst = series_md([[-1, -1] + [0] * (D - 2)], L)
+    x = np.zeros((L, 1, D))
+    x[0, 0, 0] = 1.0
+    x = newton_run(sys, cst, x, 6)
+    ex = exact(x)
+    for k in range(D):
+        assert abs(ex[0, k] - _binom(Fraction(1, e), k)) < 1e-60
+
+
+def test_eval_at_one_plus_t_binomials():
+    """All x_j = 1 + t: c x^a = c (1+t)^deg and d/dx_j = c a_j (1+t)^(deg-1)."""
+    L, n, d = 2, 3, 9
+    D = d + 1
+    polys = [[(Fraction(3, 2), [(0, 2), (1, 1), (2, 3)])], [(Fraction(-1, 4), [(1, 1), (2, 1)])],
+             [(Fraction(1), [(0, 1)])]]
+    sys = make(L, n, d, polys)
+    x = np.zeros((L, n, D))
+    x[0, :, 0] = 1.0
+    x[0, :, 1] = 1.0
+    cst = np.zeros((L, n, D))
+    b, A, _ = oracle.eval_diff(sys, sys.cff, cst, x)
+    eb, eA = exact(b), exact(A)
+    degs = [6, 2, 1]
+    coefs = [Fraction(3, 2), Fraction(-1, 4), Fraction(1)]
+    for i in range(n):
+        for k in range(D):
+            assert eb[i, k] == -coefs[i] * math.comb(degs[i], k)
+    # d p_0 / d x_2 = 3/2 * 3 * (1+t)^5
+    for k in range(D):
+        assert eA[k, 0, 2] == Fraction(9, 2) * math.comb(5, k)
+        assert eA[k, 0, 0] == 3 * math.comb(5, k)
+        assert eA[k, 1, 0] == 0
+        assert eA[k, 2, 0] == (1 if k == 0 else 0)
+
+
+# --------------------------------------------------------------------------
+# 4. D = 1 is classical Newton (hand-written Jacobian, library solve)
+# --------------------------------------------------------------------------
+
+def test_classical_newton_d0():
+    """p1 = x0^2 x1 - 3/4 x1 + 2, p2 = 5/2 x0 x1^2 - x0 - 1/8; one Newton step at
+    a point equals x - J^{-1} p with J written out by hand (non-symmetric)."""
+    L = 4
+    polys = [[(1, [(0, 2), (1, 1)]), (Fraction(-3, 4), [(1, 1)])],
+             [(Fraction(5, 2), [(0, 1), (1, 2)]), (-1, [(0, 1)])]]
+    sys = make(L, 2, 0, polys)
+    cst = series_md([[2], [Fraction(-1, 8)]], L)
+    x0, x1 = Fraction(5, 4), Fraction(-3, 8)
+    x = series_md([[x0], [x1]], L)
+    out = oracle.newton_step(sys, sys.cff, cst, x)
+    mpmath.mp.prec = 600
+    X0, X1 = mpmath.mpf(x0.numerator) / x0.denominator, mpmath.mpf(x1.numerator) / x1.denominator
+    p = mpmath.matrix([X0 ** 2 * X1 - mpmath.mpf(3) / 4 * X1 + 2,
+                       mpmath.mpf(5) / 2 * X0 * X1 ** 2 - X0 - mpmath.mpf(1) / 8])
+    J = mpmath.matrix([[2 * X0 * X1, X0 ** 2 - mpmath.mpf(3) / 4],
+                       [mpmath.mpf(5) / 2 * X1 ** 2 - 1, 5 * X0 * X1]])
+    step = mpmath.lu_solve(J, -p)
+    ex = exact(out["x"])
+    for i, xi in enumerate((X0, X1)):
+        ref = xi + step[i]
+        assert abs(mpmath.mpf(ex[i, 0].numerator) / ex[i, 0].denominator - ref) < mpmath.mpf(2) ** -400
+
+
+def test_linear_system_one_step():
+    """p(x) = M x + c(t): Newton converges in one step from any start to
+    x_k = -M^{-1} c_k for every coefficient k (textbook LU via mpmath)."""
+    rng = np.random.default_rng(11)
+    L, n, d = 4, 5, 4
+    D = d + 1
+    M = [[Fraction(int(v), 8) for v in row] for row in rng.integers(-16, 17, size=(n, n))]
+    for i in range(n):
+        M[i][i] += 20
+    polys = [[(M[i][j], [(j, 1)]) for j in range(n) if M[i][j] != 0] for i in range(n)]
+    sys = make(L, n, d, polys)
+    c = [[Fraction(int(v), 16) for v in row] for row in rng.integers(-32, 33, size=(n, D))]
+    cst = series_md(c, L)
+    x = mdinputs.random_point(sys, 3)
+    out = oracle.newton_step(sys, sys.cff, cst, x)
+    ex = exact(out["x"])
+    mpmath.mp.prec = 900
+    Mm = mpmath.matrix([[mpmath.mpf(v.numerator) / v.denominator for v in row] for row in M])
+    for k in range(D):
+        ck = mpmath.matrix([-mpmath.mpf(c[i][k].numerator) / c[i][k].denominator for i in range(n)])
+        sol = mpmath.lu_solve(Mm, ck)
+        for i in range(n):
+            got = mpmath.mpf(ex[i, k].numerator) / ex[i, k].denominator
+            assert abs(got - sol[i]) < mpmath.mpf(2) ** -800
+
+
+# --------------------------------------------------------------------------
+# 5. quadratic convergence in t-order and the stopping invariant (Section 4)
+# --------------------------------------------------------------------------
+
+def _exact_data_system(L, n, d, seed, mons=4, kmax=3):
+    """Random supports with short dyadic data: x*_k = m/16 * 4^-k, c = j/8, and
+    a diagonal boost.  Every series product is then exact in L limbs, so the
+    manufactured c_{i,0} is exact and x* solves the rounded system exactly."""
+    rng = np.random.default_rng(seed)
+    D = d + 1
+    polys = []
+    for i in range(n):
+        row = [(Fraction(int(rng.integers(-8, 9)) or 1, 8),
+                [(int(v), int(rng.integers(1, 3))) for v in rng.choice(n, size=int(rng.integers(1, kmax + 1)), replace=False)])
+               for _ in range(mons)]
+        row.append((Fraction(16), [(i, 1)]))
+        polys.append(row)
+    sys = make(L, n, d, polys)
+    xs = [[Fraction(int(rng.integers(8, 25)), 16) / 4 ** k for k in range(D)] for _ in range(n)]
+    sys.xstar = series_md(xs, L)
+    return sys
+
+
+def test_quadratic_convergence_order_doubles():
+    """From x*(0), after s Newton steps exactly the coefficients 0..2^s-1 are
+    correct and coefficient 2^s is not: Newton on series doubles the number of
+    correct coefficients (Section 4 grows the order by d := d + 1 + d/2 at
+    best).  The data are exact, so "correct" means equal to the oracle's own
+    rounding at 424 bits."""
+    L, n, d = 2, 4, 15
+    sys = _exact_data_system(L, n, d, seed=7)
+    cst = oracle.manufacture(sys, Lout=L)
+    b, _, _ = oracle.eval_diff(sys, sys.cff, cst, sys.xstar)
+    assert np.abs(b).max() == 0.0  # x* is an exact root of the stored system
+    x = sys.start()
+    for s in range(1, 5):
+        x = oracle.newton_step(sys, sys.cff, cst, x)["x"]
+        err = oracle.absdiff(x, sys.xstar).max(axis=0)  # per coefficient
+        good = 2 ** s
+        assert err[:min(good, sys.D)].max() < 1e-110
+        if good < sys.D:
+            assert err[good] > 1e-20 * 4.0 ** -good
+
+
+def test_zero_residual_gives_zero_update():
+    """Section 4: once b_k = 0 the update dx_k = 0.  With exactly representable
+    data the residual of the first k coefficients is exactly zero."""
+    L, n, d = 2, 3, 7
+    D = d + 1
+    polys = [[(1, [(0, 1), (1, 1)]), (2, [(2, 1)])], [(1, [(1, 2)]), (-1, [(0, 1)])],
+             [(1, [(2, 1)]), (1, [(0, 1), (2, 1)])]]
+    sys = make(L, n, d, polys)
+    xs = [[Fraction(1 + i, 2) if s == 0 else Fraction((-1) ** s * (s + i), 8) for s in range(D)]
+          for i in range(n)]
+    sys.xstar = series_md(xs, L)
+    cst = oracle.manufacture(sys, Lout=L)
+    k = 3
+    x = sys.xstar.copy()
+    x[:, :, k:] = 0.0
+    out = oracle.newton_step(sys, sys.cff, cst, x)
+    eb, edx = exact(out["b"]), exact(out["dx"])
+    for i in range(n):
+        for s in range(k):
+            assert eb[i, s] == 0 and edx[i, s] == 0
+    assert any(edx[i, k] != 0 for i in range(n))
+
+
+# --------------------------------------------------------------------------
+# 6. Table 1: printed values of 1/k!
+# --------------------------------------------------------------------------
+
+def test_table1_inverse_factorials():
+    """Table 1 prints 1/k! for k up to 127.  The oracle's Newton on
+    x0 = e^t, x0 x1 = e^{2t} (Section 3, alpha = 1) at D = 128 gives x1_k = 1/k!;
+    compare with the printed two-digit values: each must be within half a unit
+    of its last printed digit, widened to 0.06 units because the paper prints
+    7.7e-13 for 1/15! = 7.647e-13."""
+    rows = []
+    with open(os.path.join(HERE, "golden", "table1_inverse_factorials.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                k, v = line.split()[:2]
+                rows.append((int(k), float(v)))
+    L, n, d = 8, 2, 127
+    D = d + 1
+    sys = make(L, n, d, [[(1, [(0, 1)])], [(1, [(0, 1), (1, 1)])]])
+    cst = series_md([[-c for c in _exp_coefs(Fraction(1), D)], [-c for c in _exp_coefs(Fraction(2), D)]], L)
+    x = np.zeros((L, n, D))
+    x[0, :, 0] = 1.0
+    x = newton_run(sys, cst, x, 8)
+    ex = exact(x)
+    for k, printed in rows:
+        got = float(ex[1, k])
+        unit = 10.0 ** (math.floor(math.log10(printed)) - 1)
+        assert abs(got - printed) <= 0.6 * unit, (k, got, printed)
+        assert abs(ex[1, k] - Fraction(1, math.factorial(k))) < Fraction(1, 10 ** 125)
+
+
+# --------------------------------------------------------------------------
+# 7. the QR checker and |R_ii| against LAPACK's Householder QR
+# --------------------------------------------------------------------------
+
+def test_qr_check_and_rdiag_against_lapack():
+    rng = np.random.default_rng(5)
+    n = 7
+    A = rng.uniform(-1, 1, size=(n, n)) + 3 * np.eye(n)
+    h, tau = np.linalg.qr(A, mode="raw")   # LAPACK geqrf, column-major
+    F = h.T.copy()                           # row-major: R above, v below the diagonal
+    res, orth = oracle.qr_check(A[None], F[None], tau[None])
+    assert res < 1e-14 and orth < 1e-14
+    rd = oracle.rdiag(A[None])
+    assert np.allclose(rd[0], np.abs(np.diag(F)), rtol=1e-13)
+    # a planted error in one reflector is seen
+    F2 = F.copy()
+    F2[3, 1] += 1e-6
+    res2, orth2 = oracle.qr_check(A[None], F2[None], tau[None])
+    assert res2 > 1e-8
+
+
+# --------------------------------------------------------------------------
+# 8. conversions
+# --------------------------------------------------------------------------
+
+def test_round_and_absdiff_exact():
+    rng = np.random.default_rng(3)
+    vals = [Fraction(int(rng.integers(1, 2 ** 62))) / 2 ** 61 + Fraction(int(rng.integers(1, 2 ** 62)), 2 ** 170)
+            for _ in range(20)]
+    e = to_md(vals, 6)
+    for L in (2, 4):
+        r = oracle.round_md(e, L)
+        for q in range(len(vals)):
+            v = md_value(r[:, q])
+            assert abs(v - vals[q]) <= abs(vals[q]) * Fraction(1, 2 ** (53 * L - 1))
+            for l in range(L - 1):  # nonoverlapping limbs
+                assert r[l + 1, q] == 0 or abs(r[l + 1, q]) <= 0.5 * np.spacing(abs(r[l, q]))
+    d = oracle.absdiff(e, to_md(vals[::-1], 6))
+    for q in range(len(vals)):
+        assert d[q] == float(abs(vals[q] - vals[::-1][q]))
+
+
+def test_manufactured_solution_is_a_root():
+    sys = mdinputs.tiny(4, 4, 7, mons=3, seed=3)
+    cst = oracle.manufacture(sys)
+    b, _, scale = oracle.eval_diff(sys, sys.cff, cst, sys.xstar)
+    # only the rounding of c_{i,0} to four limbs remains
+    assert np.max(np.abs(b[0]).max(axis=1) / scale) < 2.0 ** -205
+    assert oracle.inexact_inputs() == 0
