@@ -1,0 +1,159 @@
+/*
+ * mdnewton -- one Newton step on truncated power series for a polynomial
+ * system in multiple-double arithmetic (double double, quad double, octo
+ * double), on an AMD Instinct MI355X (gfx950).
+ *
+ * The method is that of Verschelde, "GPU Accelerated Newton for Taylor Series
+ * Solutions of Polynomial Homotopies in Multiple Double Precision"
+ * (arXiv:2301.12659): evaluate and differentiate every monomial at the series
+ * x(t) by convolutions (Section 5.1), assemble the series Jacobian
+ * A(t) = A_0 + A_1 t + ... and the residual b(t) = -p(x(t)), and solve the lower
+ * triangular block Toeplitz system of Section 2 with a Householder QR of A_0
+ * (Sections 1.1 and 5.3) and staged back substitutions with right-hand side
+ * updates (Sections 4 and 5.4).
+ *
+ * System.  p_i(x) = c_{i,0}(t) + sum_{m in P_i} c_m x^{a_m}, i = 0..n-1, with a
+ * constant series c_{i,0}(t) per polynomial, a scalar multiple-double
+ * coefficient c_m per monomial and exponent vectors a_m >= 0.  Series are
+ * truncated at degree d: D = d + 1 coefficients (the paper's "order D").
+ *
+ * Numbers.  A multiple double with L limbs (L = 2, 4 or 8) is an unevaluated
+ * sum of L doubles (Section 1.2).  Every numeric array is stored limb-major
+ * ("structure of arrays", Sections 1.2 and 6): limb l of element q of an array
+ * of N elements is at ptr[l * N + q].  Element orders:
+ *   series vectors  x, b, c_{i,0}, dx : [L][n][D]      (variable i, coefficient k)
+ *   Jacobian series A                 : [L][n][n][D]   (row i, column j, coefficient k:
+ *                                                      coefficient of t^k in dp_i/dx_j)
+ *   dense matrices (A_0, QR)          : [L][n][n]      row-major
+ *   monomial coefficients cff         : [L][m]
+ *
+ * Pointers.  Numeric pointers are DEVICE pointers; index arrays passed to
+ * md_plan_create are HOST pointers, validated and copied to the device.  The
+ * caller owns every numeric buffer and the workspace; the plan owns only its
+ * device copies of the index tables.  Calls are asynchronous on the given
+ * stream.
+ *
+ * Errors.  Functions return MD_OK or a negative code for errors the host can
+ * detect (bad sizes, indices out of range, workspace too small, HIP failures);
+ * md_last_error() then describes it.  Conditions found on the device (a
+ * singular A_0, a non-finite result) are written to *dev_status (a device
+ * int32) and can be read after the stream is synchronized.  No exception or
+ * abort crosses this interface.
+ */
+#ifndef MDNEWTON_H
+#define MDNEWTON_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MD_OK 0
+#define MD_EINVAL (-1)     /* invalid argument */
+#define MD_ESINGULAR (-2)  /* A_0 is singular: a Householder column or R_ii is zero */
+#define MD_ENONFINITE (-3) /* a NaN or infinity appeared in the result */
+#define MD_EHIP (-4)       /* a HIP runtime call failed */
+#define MD_ENOSPACE (-5)   /* workspace too small */
+
+/* Precision = number of limbs L. */
+#define MD_DD 2
+#define MD_QD 4
+#define MD_OD 8
+
+/* Largest supported number of series coefficients D = d + 1, dimension n and
+ * exponent.  (The paper's experiments use order 64; Table 1 goes to 127.) */
+#define MD_MAX_COEFFS 128
+#define MD_MAX_DIM 1024
+#define MD_MAX_EXPONENT 8
+
+typedef struct md_plan md_plan;
+
+/* Build a plan for a system of n polynomials in n variables with m monomials,
+ * truncated at degree d (D = d + 1 <= MD_MAX_COEFFS), in precision prec
+ * (MD_DD, MD_QD or MD_OD).  Index tables (host pointers, CSR):
+ *   poly_ptr[n+1] : monomials of polynomial i are poly_ptr[i] .. poly_ptr[i+1]-1
+ *   mon_ptr[m+1]  : support entries of monomial j are mon_ptr[j] .. mon_ptr[j+1]-1
+ *   var[nnz]      : variable of each entry, strictly increasing within a monomial
+ *   exp[nnz]      : exponent of each entry, 1 <= exp <= MD_MAX_EXPONENT
+ * Monomials with an empty support are allowed (constants).  The plan copies
+ * the tables to the device.  Returns MD_EINVAL on any inconsistency. */
+int md_plan_create(int prec, int n, int d, int m, const int32_t *poly_ptr, const int32_t *mon_ptr,
+                   const int32_t *var, const int32_t *exp, md_plan **out);
+int md_plan_destroy(md_plan *plan);
+
+/* Workspace bytes needed by md_eval_diff and md_newton_step for this plan. */
+int md_workspace_size(const md_plan *plan, size_t *bytes);
+
+/* Evaluation and differentiation at a series (Sections 5.1 and 6):
+ *   b(t) = -p(x(t)) mod t^D              -> b   [L][n][D]
+ *   A(t) = dp/dx (x(t)) mod t^D           -> A   [L][n][n][D]
+ * from cff [L][m], cst (the constant series c_{i,0}) [L][n][D] and x [L][n][D].
+ * Each monomial is evaluated and differentiated by the reverse mode of
+ * Section 5.1 (forward, backward and cross products, 3k-5 convolutions for k
+ * variables with exponent one); exponents above one use a common factor. */
+int md_eval_diff(const md_plan *plan, const double *cff, const double *cst, const double *x, double *b,
+                 double *A, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Householder QR of an n x n multiple-double matrix (Sections 1.1 and 5.3),
+ * in place: on return a0 [L][n][n] (row-major) holds R on and above the
+ * diagonal and the Householder vectors below it (unit leading entry
+ * implicit), tau [L][n] the reflector factors: A_0 = Q R with
+ * Q = H_0 H_1 ... H_{n-1}, H_c = I - tau_c v_c v_c^T, v_c = e_c + (entries below).
+ * A zero column sets *dev_status = MD_ESINGULAR. */
+int md_qr_workspace_size(int prec, int n, size_t *bytes);
+int md_qr(int prec, int n, double *a0, double *tau, void *ws, size_t ws_bytes, hipStream_t stream,
+          int32_t *dev_status);
+
+/* Solve the lower triangular block Toeplitz system of Section 2,
+ *   A_0 dx_k = b_k - sum_{j=1..k} A_j dx_{k-j},  k = 0..d,
+ * given the QR factors of A_0 from md_qr (qr [L][n][n], tau [L][n]) and the
+ * Jacobian series A [L][n][n][D] (coefficient 0 is not read).  rhs_dx [L][n][D]
+ * holds b on entry and dx on return.  Q^T and the inverse of R are applied to
+ * every stage (Q^H b and back substitution kernels, Section 5.3; the stage
+ * updates of Section 5.4).  *dev_status gets MD_ESINGULAR for a zero R_ii. */
+int md_solve_workspace_size(int prec, int n, int d, size_t *bytes);
+int md_series_solve(int prec, int n, int d, const double *qr, const double *tau, const double *A,
+                    double *rhs_dx, void *ws, size_t ws_bytes, hipStream_t stream, int32_t *dev_status);
+
+/* One Newton step (Section 2): b = -p(x), A = p'(x), dx from the block
+ * Toeplitz system, x := x + dx in place (x [L][n][D]).  On the device:
+ * *dev_status = MD_OK, MD_ESINGULAR or MD_ENONFINITE; dev_norms [2][D]:
+ * dev_norms[k] = max_i |b_{i,k}| and dev_norms[D + k] = max_i |dx_{i,k}|
+ * (leading limbs), the quantities the paper's Newton loop monitors. */
+int md_newton_step(const md_plan *plan, const double *cff, const double *cst, double *x, int32_t *dev_status,
+                   double *dev_norms, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Elementwise multiple-double arithmetic on device arrays of count elements
+ * (limb-major [L][count]): op 0 add, 1 sub, 2 mul, 3 div, 4 sqrt (of a),
+ * 5 fused c := c + a*b.  b is not read for sqrt.  (Section 1.2 and Section 6:
+ * the inlined arithmetic, exposed for testing and for callers.) */
+int md_arith(int prec, int op, int64_t count, const double *a, const double *b, double *c, hipStream_t stream);
+
+/* Per-kernel-class timing (the paper measures the time of each kernel type,
+ * Section 7, Table 4).  While enabled, the library brackets each class of
+ * launches of md_eval_diff, md_series_solve and md_newton_step with HIP events
+ * on the caller's stream.  md_timing_read synchronizes those events, returns
+ * the accumulated milliseconds and bracket counts per class in
+ * ms[MD_NCLASSES] and launches[MD_NCLASSES], and resets them.  Not thread
+ * safe: one timing client at a time. */
+#define MD_CLASS_CONVOLUTIONS 0 /* power table and monomial eval/diff (convolutions) */
+#define MD_CLASS_ASSEMBLY 1     /* sums into b(t) and A(t) */
+#define MD_CLASS_QR 2           /* Householder QR of A_0 */
+#define MD_CLASS_QHB_BS 3       /* Q^T and back substitution applied to unit vectors: M */
+#define MD_CLASS_GEMM 4         /* N = M A_1 */
+#define MD_CLASS_UPDATES 5      /* staged right-hand-side updates and stage solves */
+#define MD_CLASS_X_UPDATE 6     /* x := x + dx and the norms */
+#define MD_NCLASSES 7
+int md_timing_enable(int on);
+int md_timing_read(double *ms, int64_t *launches);
+
+/* Message for the last host-side error of this thread. */
+const char *md_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

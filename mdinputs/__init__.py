@@ -175,7 +175,7 @@ def _append_boost(poly_ptr, mon_ptr, var, exp, cff, L, s):
 
 def make_system(name: str, L: int, n: int, d: int, mons_per_poly, kmin: int, kmax: int,
                 exps, seed: int, cond_max: float | None, boost: bool, steps: int = 1,
-                damping: float = 1.0, max_tries: int = 64) -> System:
+                damping: float = 1.0, max_tries: int = 64, boost_gamma: float = 0.125) -> System:
     """Draw a system and its manufactured solution.
 
     Without ``boost`` the system is redrawn (from a derived seed) until the
@@ -199,7 +199,7 @@ def make_system(name: str, L: int, n: int, d: int, mons_per_poly, kmin: int, kma
         bidx = None
         if boost:
             rowsum = np.abs(J).sum(axis=1) + 1.0
-            gamma = 0.125
+            gamma = boost_gamma
             for _ in range(40):
                 s = np.exp2(np.ceil(np.log2(gamma * rowsum))) * np.where(np.diag(J) < 0, -1.0, 1.0)
                 Jb = J + np.diag(s)
@@ -214,31 +214,52 @@ def make_system(name: str, L: int, n: int, d: int, mons_per_poly, kmin: int, kma
     raise RuntimeError(f"no system with cond <= {cond_max} after {max_tries} draws")
 
 
+# Damping and boost readings.  The paper recommends decaying coefficients so
+# that the series problem is well conditioned (Section 1.3, the ratio theorem
+# of Fabry) and damps t by a factor delta (end of Section 3).  Coefficients
+# drawn uniform in [0.5, 1.5] for every order make the block Toeplitz solve
+# amplify rounding errors by a factor 4 to 65 per coefficient on these
+# systems, so every preset draws coefficient k in delta^k * [0.5, 1.5] with
+# delta = 1/4 (a power of two: the scaling is exact), and boosted presets
+# start the diagonal boost at twice the row's absolute sum (cond(A_0) ~ 4).
+# The small system has no boost (it is only redrawn until cond(A_0) <= 1e3)
+# and the large one has monomials of degree up to 24: with delta = 1/4 the
+# unconverged coefficients of their Newton iterates grow to 1e4 and 1e22 and
+# the last step cancels them, so those two use delta = 1/8.
+DAMPING = 0.25
+DAMPING_STRONG = 0.125
+BOOST_GAMMA = 2.0
+
+
 def small_dd(seed: int = 1) -> System:
     """n=8, d=15, dd; 8 monomials x 3 distinct variables, exponent 1; 4 steps."""
-    return make_system("small_dd", 2, 8, 15, 8, 3, 3, (1,), seed, 1e3, boost=False, steps=4)
+    return make_system("small_dd", 2, 8, 15, 8, 3, 3, (1,), seed, 1e3, boost=False, steps=4,
+                       damping=DAMPING_STRONG)
 
 
 def medium_qd(seed: int = 2) -> System:
     """n=64, d=63, qd; 32 monomials x 2..6 variables, exponents {1,2}; 6 steps."""
-    return make_system("medium_qd", 4, 64, 63, 32, 2, 6, (1, 2), seed, 1e3, boost=True, steps=6)
+    return make_system("medium_qd", 4, 64, 63, 32, 2, 6, (1, 2), seed, 1e3, boost=True, steps=6,
+                       damping=DAMPING, boost_gamma=BOOST_GAMMA)
 
 
 def large_od(seed: int = 3) -> System:
     """n=128, d=127, od; 64 monomials x 4..8 variables, exponents {1,2,3}; 8 steps."""
-    return make_system("large_od", 8, 128, 127, 64, 4, 8, (1, 2, 3), seed, 1e4, boost=True, steps=8)
+    return make_system("large_od", 8, 128, 127, 64, 4, 8, (1, 2, 3), seed, 1e4, boost=True, steps=8,
+                       damping=DAMPING_STRONG, boost_gamma=BOOST_GAMMA)
 
 
 def adjoint_qd(seed: int = 5) -> System:
     """n=32, d=31, qd; 32 monomials x 3..5 variables, exponents {1,2}."""
-    return make_system("adjoint_qd", 4, 32, 31, 32, 3, 5, (1, 2), seed, 1e3, boost=True, steps=6)
+    return make_system("adjoint_qd", 4, 32, 31, 32, 3, 5, (1, 2), seed, 1e3, boost=True, steps=6,
+                       damping=DAMPING, boost_gamma=BOOST_GAMMA)
 
 
 def tiny(L: int, n: int, d: int, mons: int = 3, kmin: int = 1, kmax: int = 3, exps=(1, 2),
-         seed: int = 0, boost: bool = True, cond_max: float = 1e3, damping: float = 1.0) -> System:
+         seed: int = 0, boost: bool = True, cond_max: float = 1e3, damping: float = DAMPING) -> System:
     """Small systems for parity tests that the oracle finishes in seconds."""
     return make_system(f"tiny_L{L}_n{n}_d{d}", L, n, d, mons, kmin, kmax, exps, seed, cond_max,
-                       boost=boost, steps=1, damping=damping)
+                       boost=boost, steps=1, damping=damping, boost_gamma=BOOST_GAMMA)
 
 
 PRESETS = {

@@ -61,6 +61,7 @@ def lib():
         L.ora_qr_check.argtypes = [ci, ci, ci, dp, dp, dp, dp]
         L.ora_rdiag.argtypes = [ci, ci, ci, dp, ci, dp]
         L.ora_set_threads.argtypes = [ci]
+        L.ora_arith.argtypes = [ci, ci, ci, dp, dp, dp, ci, ci, dp]
         _lib = L
     return _lib
 
@@ -229,3 +230,19 @@ def rel_err_series(gpu: np.ndarray, ora: np.ndarray, axis_series=-1) -> np.ndarr
     with np.errstate(divide="ignore", invalid="ignore"):
         r = np.where(den > 0, num / np.where(den > 0, den, 1.0), np.where(num > 0, np.inf, 0.0))
     return r
+
+
+ARITH_OPS = {"add": 0, "sub": 1, "mul": 2, "div": 3, "sqrt": 4, "fma": 5}
+
+
+def arith(op, a, b=None, c=None, K=None, prec=None):
+    """Reference a+b, a-b, a*b, a/b, sqrt(a) or c+a*b for md arrays [L, count]."""
+    L, count = a.shape
+    K = K or 4 * L + 2
+    opc = ARITH_OPS[op]
+    z = np.zeros((L, count))
+    out = np.zeros((K, count))
+    rc = lib().ora_arith(prec or prec_bits(L), opc, L, _d(_c64(a)), _d(_c64(b if b is not None else z)),
+                         _d(_c64(c if c is not None else z)), count, K, _d(out))
+    _check(rc, "ora_arith")
+    return out

@@ -624,3 +624,40 @@ int ora_rdiag(int prec_bits, int n, int L, const double *A0, int K, double *out)
   vfree(G, nn);
   return rc;
 }
+
+/* Elementwise reference arithmetic on multiple doubles: op 0 a+b, 1 a-b,
+ * 2 a*b, 3 a/b, 4 sqrt(a), 5 c + a*b; inputs [L][count], out[K][count]. */
+int ora_arith(int prec_bits, int op, int L, const double *a, const double *b, const double *c, int count, int K,
+              double *out) {
+  if (op < 0 || op > 5 || L < 1 || K < 1) return ORA_EINVAL;
+#pragma omp parallel num_threads(ora_get_threads())
+  {
+    mpfr_t x, y, z, t;
+    mpfr_init2(x, prec_bits);
+    mpfr_init2(y, prec_bits);
+    mpfr_init2(z, prec_bits);
+    mpfr_init2(t, prec_bits);
+#pragma omp for schedule(static)
+    for (int q = 0; q < count; ++q) {
+      md_get(x, a + q, count, L);
+      if (op != 4) md_get(y, b + q, count, L);
+      switch (op) {
+        case 0: mpfr_add(z, x, y, MPFR_RNDN); break;
+        case 1: mpfr_sub(z, x, y, MPFR_RNDN); break;
+        case 2: mpfr_mul(z, x, y, MPFR_RNDN); break;
+        case 3: mpfr_div(z, x, y, MPFR_RNDN); break;
+        case 4: mpfr_sqrt(z, x, MPFR_RNDN); break;
+        default:
+          md_get(z, c + q, count, L);
+          mpfr_fma(z, x, y, z, MPFR_RNDN);
+          break;
+      }
+      exp_put(out + q, count, K, z, t);
+    }
+    mpfr_clear(x);
+    mpfr_clear(y);
+    mpfr_clear(z);
+    mpfr_clear(t);
+  }
+  return ORA_OK;
+}

@@ -1,0 +1,237 @@
+"""Python binding of libmdnewton (argument marshalling only).
+
+Every function mirrors a C entry point of include/mdnewton.h and takes
+torch.float64 tensors that live on the GPU, limb-major with a leading limb
+axis of size L (2, 4 or 8).  Shapes are checked here before any launch; all
+arithmetic runs in the HIP kernels of the shared library.  There is no CPU
+fallback: if the library is missing, importing this package raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmdnewton.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "mdnewton.h")
+
+MD_OK, MD_EINVAL, MD_ESINGULAR, MD_ENONFINITE, MD_EHIP, MD_ENOSPACE = 0, -1, -2, -3, -4, -5
+MD_DD, MD_QD, MD_OD = 2, 4, 8
+OPS = {"add": 0, "sub": 1, "mul": 2, "div": 3, "sqrt": 4, "fma": 5}
+STATUS_NAMES = {0: "ok", -2: "singular", -3: "nonfinite"}
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run paper_2301_12659_amd.build.build() (or __graft_entry__.build())")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_szp = ctypes.POINTER(ctypes.c_size_t)
+
+_lib.md_plan_create.argtypes = [_i32, _i32, _i32, _i32, _i32p, _i32p, _i32p, _i32p, ctypes.POINTER(_vp)]
+_lib.md_plan_destroy.argtypes = [_vp]
+_lib.md_workspace_size.argtypes = [_vp, _szp]
+_lib.md_eval_diff.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
+_lib.md_qr_workspace_size.argtypes = [_i32, _i32, _szp]
+_lib.md_qr.argtypes = [_i32, _i32, _vp, _vp, _vp, ctypes.c_size_t, _vp, _vp]
+_lib.md_solve_workspace_size.argtypes = [_i32, _i32, _i32, _szp]
+_lib.md_series_solve.argtypes = [_i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp, _vp]
+_lib.md_newton_step.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
+_lib.md_arith.argtypes = [_i32, _i32, ctypes.c_int64, _vp, _vp, _vp, _vp]
+_lib.md_last_error.restype = ctypes.c_char_p
+_lib.md_timing_enable.argtypes = [_i32]
+_lib.md_timing_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+
+# Kernel classes of md_timing_read (the paper's kernel types, Table 4).
+TIMING_CLASSES = ["convolutions", "assembly", "qr", "qhb_bs", "gemm", "updates", "x_update"]
+
+
+def exported_functions():
+    """Names of the functions declared in include/mdnewton.h."""
+    with open(HEADER) as f:
+        text = f.read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char \*)\s*(md_\w+)\s*\(", text, re.M)))
+
+
+class MdError(RuntimeError):
+    def __init__(self, code, what):
+        msg = _lib.md_last_error().decode()
+        super().__init__(f"{what} failed with {code}: {msg}")
+        self.code = code
+
+
+def _check(rc, what):
+    if rc != MD_OK:
+        raise MdError(rc, what)
+
+
+def _stream(stream):
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return _vp(s.cuda_stream)
+
+
+def _ptr(t, shape, name):
+    """Device pointer of a contiguous float64/int32 CUDA tensor of the given shape."""
+    import torch
+
+    if t is None:
+        return _vp(0)
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if t.dtype not in (torch.float64, torch.int32):
+        raise ValueError(f"{name} must be float64 or int32")
+    return _vp(t.data_ptr())
+
+
+def _i32arr(a):
+    a = np.ascontiguousarray(a, dtype=np.int32)
+    return a, a.ctypes.data_as(_i32p)
+
+
+class Plan:
+    """md_plan: a validated system structure resident on the device."""
+
+    def __init__(self, prec, n, d, poly_ptr, mon_ptr, var, exp):
+        self.prec, self.n, self.d = int(prec), int(n), int(d)
+        self.D = self.d + 1
+        self._keep = [_i32arr(poly_ptr), _i32arr(mon_ptr), _i32arr(var), _i32arr(exp)]
+        self.m = int(len(self._keep[1][0]) - 1)
+        self.nnz = int(len(self._keep[2][0]))
+        h = _vp()
+        rc = _lib.md_plan_create(self.prec, self.n, self.d, self.m, self._keep[0][1], self._keep[1][1],
+                                 self._keep[2][1], self._keep[3][1], ctypes.byref(h))
+        _check(rc, "md_plan_create")
+        self._h = h
+
+    @classmethod
+    def from_system(cls, sys):
+        return cls(sys.L, sys.n, sys.d, sys.poly_ptr, sys.mon_ptr, sys.var, sys.exp)
+
+    def workspace_bytes(self):
+        v = ctypes.c_size_t()
+        _check(_lib.md_workspace_size(self._h, ctypes.byref(v)), "md_workspace_size")
+        return int(v.value)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.md_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def workspace(nbytes, device="cuda"):
+    import torch
+
+    return torch.empty(max(int(nbytes), 8) // 8 + 1, dtype=torch.float64, device=device)
+
+
+def eval_diff(plan: Plan, cff, cst, x, b, A, ws, stream=None):
+    L, n, D, m = plan.prec, plan.n, plan.D, plan.m
+    rc = _lib.md_eval_diff(plan._h, _ptr(cff, (L, m), "cff"), _ptr(cst, (L, n, D), "cst"), _ptr(x, (L, n, D), "x"),
+                           _ptr(b, (L, n, D), "b"), _ptr(A, (L, n, n, D), "A"), _ptr(ws, None, "ws"),
+                           ws.numel() * 8, _stream(stream))
+    _check(rc, "md_eval_diff")
+
+
+def qr_workspace_bytes(prec, n):
+    v = ctypes.c_size_t()
+    _check(_lib.md_qr_workspace_size(int(prec), int(n), ctypes.byref(v)), "md_qr_workspace_size")
+    return int(v.value)
+
+
+def qr(prec, n, a0, tau, status, ws=None, stream=None):
+    L = int(prec)
+    rc = _lib.md_qr(L, int(n), _ptr(a0, (L, n, n), "a0"), _ptr(tau, (L, n), "tau"), _ptr(ws, None, "ws"),
+                    0 if ws is None else ws.numel() * 8, _stream(stream), _ptr(status, (1,), "status"))
+    _check(rc, "md_qr")
+
+
+def solve_workspace_bytes(prec, n, d):
+    v = ctypes.c_size_t()
+    _check(_lib.md_solve_workspace_size(int(prec), int(n), int(d), ctypes.byref(v)), "md_solve_workspace_size")
+    return int(v.value)
+
+
+def series_solve(prec, n, d, qr_, tau, A, rhs_dx, ws, status, stream=None):
+    L, D = int(prec), int(d) + 1
+    rc = _lib.md_series_solve(L, int(n), int(d), _ptr(qr_, (L, n, n), "qr"), _ptr(tau, (L, n), "tau"),
+                              _ptr(A, (L, n, n, D), "A"), _ptr(rhs_dx, (L, n, D), "rhs_dx"), _ptr(ws, None, "ws"),
+                              ws.numel() * 8, _stream(stream), _ptr(status, (1,), "status"))
+    _check(rc, "md_series_solve")
+
+
+def newton_step(plan: Plan, cff, cst, x, status, norms, ws, stream=None):
+    L, n, D, m = plan.prec, plan.n, plan.D, plan.m
+    rc = _lib.md_newton_step(plan._h, _ptr(cff, (L, m), "cff"), _ptr(cst, (L, n, D), "cst"),
+                             _ptr(x, (L, n, D), "x"), _ptr(status, (1,), "status"),
+                             _ptr(norms, (2, D), "norms"), _ptr(ws, None, "ws"), ws.numel() * 8, _stream(stream))
+    _check(rc, "md_newton_step")
+
+
+def arith(prec, op, a, b, c, stream=None):
+    L = int(prec)
+    opc = OPS[op] if isinstance(op, str) else int(op)
+    count = a.shape[1]
+    shp = (L, count)
+    rc = _lib.md_arith(L, opc, count, _ptr(a, shp, "a"), _ptr(b, shp if opc != 4 else None, "b"),
+                       _ptr(c, shp, "c"), _stream(stream))
+    _check(rc, "md_arith")
+
+
+def timing_enable(on=True):
+    _check(_lib.md_timing_enable(1 if on else 0), "md_timing_enable")
+
+
+def timing_read():
+    """{class: (milliseconds, brackets)} accumulated since the last read."""
+    k = len(TIMING_CLASSES)
+    ms = (ctypes.c_double * k)()
+    cnt = (ctypes.c_int64 * k)()
+    _check(_lib.md_timing_read(ms, cnt), "md_timing_read")
+    return {TIMING_CLASSES[c]: (float(ms[c]), int(cnt[c])) for c in range(k)}
+
+
+def raw_call(name, *args):
+    """Call an entry point with raw ctypes arguments (tests of the host-side checks)."""
+    return getattr(_lib, name)(*args)
+
+
+class Newton:
+    """Convenience driver: device copies of a system and its workspace.
+
+    Holds cff, cst and x on the device and runs md_newton_step in place."""
+
+    def __init__(self, sys, cst, x0=None, device="cuda"):
+        import torch
+
+        self.sys = sys
+        self.plan = Plan.from_system(sys)
+        t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=device)
+        self.cff = t(sys.cff)
+        self.cst = t(cst)
+        self.x = t(sys.start() if x0 is None else x0)
+        self.ws = workspace(self.plan.workspace_bytes(), device)
+        self.status = torch.zeros(1, dtype=torch.int32, device=device)
+        self.norms = torch.zeros((2, sys.D), dtype=torch.float64, device=device)
+
+    def step(self, stream=None):
+        newton_step(self.plan, self.cff, self.cst, self.x, self.status, self.norms, self.ws, stream)
+
+    def status_code(self):
+        return int(self.status.item())

@@ -1,0 +1,379 @@
+// The C interface of libmdnewton (declared in include/mdnewton.h): plan
+// construction and validation, workspace layout, and the sequence of kernel
+// launches for one Newton step (Section 2).
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+#include <mutex>
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+
+
+struct md_plan {
+  int L, n, d, D, m, nnz, maxexp;
+  int32_t *d_poly_ptr = nullptr, *d_mon_ptr = nullptr, *d_var = nullptr, *d_exp = nullptr;
+  int32_t *d_order = nullptr, *d_asm_ptr = nullptr, *d_asm_ent = nullptr;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+// Per-kernel-class timing with HIP events (the paper accumulates the time of
+// each kernel type, Section 7, Table 4).
+bool g_timing = false;
+struct EventPair {
+  int cls;
+  hipEvent_t a, b;
+};
+std::vector<EventPair> g_pending;
+double g_ms[MD_NCLASSES] = {0};
+int64_t g_count[MD_NCLASSES] = {0};
+
+struct Timed {
+  int cls;
+  hipStream_t st;
+  hipEvent_t a = nullptr, b = nullptr;
+  Timed(int c, hipStream_t s) : cls(c), st(s) {
+    if (!g_timing) return;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+      a = b = nullptr;
+      return;
+    }
+    (void)hipEventRecord(a, st);
+  }
+  ~Timed() {
+    if (!a) return;
+    (void)hipEventRecord(b, st);
+    g_pending.push_back({cls, a, b});
+  }
+};
+
+int fail(int code, const std::string &msg) {
+  g_err = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+  return fail(MD_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+bool valid_prec(int p) { return p == MD_DD || p == MD_QD || p == MD_OD; }
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Workspace regions, in doubles, each aligned to 256 bytes.
+struct Layout {
+  size_t val, der, pw, b, A, qr, tau, invd, M, N, r, dx, total;
+};
+
+Layout newton_layout(const md_plan *p) {
+  const size_t L = p->L, n = p->n, D = p->D;
+  Layout w{};
+  size_t off = 0;
+  auto take = [&](size_t doubles) {
+    size_t o = off;
+    off += align_up(doubles * sizeof(double));
+    return o;
+  };
+  w.val = take(L * p->m * D);
+  w.der = take(L * p->nnz * D);
+  w.pw = take(p->maxexp >= 3 ? L * n * D * (p->maxexp - 2) : 1);
+  w.b = take(L * n * D);
+  w.A = take(L * n * n * D);
+  w.qr = take(L * n * n);
+  w.tau = take(L * n);
+  w.invd = take(L * n);
+  w.M = take(L * n * n);
+  w.N = take(L * n * n);
+  w.r = take(L * n * D);
+  w.dx = take(L * n * D);
+  w.total = off;
+  return w;
+}
+
+size_t solve_bytes(int L, int n, int D) {
+  return align_up((size_t)L * n * sizeof(double)) + 2 * align_up((size_t)L * n * n * sizeof(double)) +
+         align_up((size_t)L * n * D * sizeof(double));
+}
+
+double *at(void *ws, size_t byte_off) { return reinterpret_cast<double *>(static_cast<char *>(ws) + byte_off); }
+
+int series_solve_impl(int L, int n, int D, const double *qr, const double *tau, const double *A, double *rhs_dx,
+                      void *ws, hipStream_t st, int32_t *status) {
+  size_t off = 0;
+  double *invd = at(ws, off);
+  off += align_up((size_t)L * n * sizeof(double));
+  double *M = at(ws, off);
+  off += align_up((size_t)L * n * n * sizeof(double));
+  double *N = at(ws, off);
+  off += align_up((size_t)L * n * n * sizeof(double));
+  double *r = at(ws, off);
+  hipError_t e;
+  {
+    Timed t(MD_CLASS_QHB_BS, st);
+    if ((e = mdk::launch_form_m(L, n, qr, tau, invd, M, status, st)) != hipSuccess) return hip_fail(e, "form M");
+  }
+  if (D > 1) {
+    Timed t(MD_CLASS_GEMM, st);
+    if ((e = mdk::launch_gemm_series(L, n, D, 1, M, A, N, st)) != hipSuccess) return hip_fail(e, "gemm");
+  }
+  {
+    Timed t(MD_CLASS_UPDATES, st);
+    if ((e = mdk::launch_copy(rhs_dx, r, (size_t)L * n * D, st)) != hipSuccess) return hip_fail(e, "copy");
+    if ((e = mdk::launch_stages(L, n, D, M, N, A, r, rhs_dx, st)) != hipSuccess) return hip_fail(e, "stages");
+  }
+  return MD_OK;
+}
+
+}  // namespace
+
+namespace mdk {
+__global__ void copy_kernel(const double *src, double *dst, size_t count) {
+  const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < count) dst[q] = src[q];
+}
+hipError_t launch_copy(const double *src, double *dst, size_t count, hipStream_t st) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(copy_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, src, dst, count);
+  return hipGetLastError();
+}
+}  // namespace mdk
+
+extern "C" {
+
+const char *md_last_error(void) { return g_err.c_str(); }
+
+int md_plan_create(int prec, int n, int d, int m, const int32_t *poly_ptr, const int32_t *mon_ptr,
+                   const int32_t *var, const int32_t *exp, md_plan **out) {
+  if (!out) return fail(MD_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!valid_prec(prec)) return fail(MD_EINVAL, "precision must be 2, 4 or 8 limbs");
+  if (n < 1 || n > MD_MAX_DIM) return fail(MD_EINVAL, "n out of range");
+  if (d < 0 || d + 1 > MD_MAX_COEFFS) return fail(MD_EINVAL, "degree out of range");
+  if (m < 0) return fail(MD_EINVAL, "m < 0");
+  if (!poly_ptr || !mon_ptr || (m > 0 && (!var || !exp) && mon_ptr[m] > 0))
+    return fail(MD_EINVAL, "NULL index table");
+  if (poly_ptr[0] != 0 || poly_ptr[n] != m) return fail(MD_EINVAL, "poly_ptr must run from 0 to m");
+  for (int i = 0; i < n; ++i)
+    if (poly_ptr[i + 1] < poly_ptr[i]) return fail(MD_EINVAL, "poly_ptr not monotone");
+  if (mon_ptr[0] != 0) return fail(MD_EINVAL, "mon_ptr[0] must be 0");
+  for (int j = 0; j < m; ++j)
+    if (mon_ptr[j + 1] < mon_ptr[j]) return fail(MD_EINVAL, "mon_ptr not monotone");
+  const int nnz = mon_ptr[m];
+  int maxexp = 1;
+  for (int j = 0; j < m; ++j)
+    for (int q = mon_ptr[j]; q < mon_ptr[j + 1]; ++q) {
+      if (var[q] < 0 || var[q] >= n) return fail(MD_EINVAL, "variable index out of range");
+      if (q > mon_ptr[j] && var[q] <= var[q - 1])
+        return fail(MD_EINVAL, "variables must be strictly increasing within a monomial");
+      if (exp[q] < 1 || exp[q] > MD_MAX_EXPONENT) return fail(MD_EINVAL, "exponent out of range");
+      maxexp = std::max(maxexp, (int)exp[q]);
+    }
+  md_plan *p = new md_plan();
+  p->L = prec;
+  p->n = n;
+  p->d = d;
+  p->D = d + 1;
+  p->m = m;
+  p->nnz = nnz;
+  p->maxexp = maxexp;
+  // work order: most expensive monomials first, so that workers of one
+  // wavefront get similar work
+  std::vector<int32_t> order(m);
+  std::iota(order.begin(), order.end(), 0);
+  std::vector<int> cost(m);
+  for (int j = 0; j < m; ++j) {
+    int k = mon_ptr[j + 1] - mon_ptr[j], extra = 0;
+    for (int q = mon_ptr[j]; q < mon_ptr[j + 1]; ++q) extra += exp[q] - 1;
+    cost[j] = 3 * k + extra;
+  }
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+  // assembly lists: entries contributing to (row i, column v), in monomial order
+  std::vector<int32_t> row_of(m);
+  for (int i = 0; i < n; ++i)
+    for (int j = poly_ptr[i]; j < poly_ptr[i + 1]; ++j) row_of[j] = i;
+  const size_t nn = (size_t)n * n;
+  std::vector<int32_t> asm_ptr(nn + 1, 0), asm_ent(nnz);
+  for (int j = 0; j < m; ++j)
+    for (int q = mon_ptr[j]; q < mon_ptr[j + 1]; ++q) asm_ptr[(size_t)row_of[j] * n + var[q] + 1]++;
+  for (size_t t = 0; t < nn; ++t) asm_ptr[t + 1] += asm_ptr[t];
+  {
+    std::vector<int32_t> fill(asm_ptr.begin(), asm_ptr.end() - 1);
+    for (int j = 0; j < m; ++j)
+      for (int q = mon_ptr[j]; q < mon_ptr[j + 1]; ++q) asm_ent[fill[(size_t)row_of[j] * n + var[q]]++] = q;
+  }
+  auto up = [&](int32_t **dst, const int32_t *src, size_t cnt) -> hipError_t {
+    hipError_t e = hipMalloc((void **)dst, std::max<size_t>(cnt, 1) * sizeof(int32_t));
+    if (e != hipSuccess) return e;
+    if (cnt) e = hipMemcpy(*dst, src, cnt * sizeof(int32_t), hipMemcpyHostToDevice);
+    return e;
+  };
+  hipError_t e;
+  if ((e = up(&p->d_poly_ptr, poly_ptr, n + 1)) != hipSuccess || (e = up(&p->d_mon_ptr, mon_ptr, m + 1)) != hipSuccess ||
+      (e = up(&p->d_var, var, nnz)) != hipSuccess || (e = up(&p->d_exp, exp, nnz)) != hipSuccess ||
+      (e = up(&p->d_order, order.data(), m)) != hipSuccess ||
+      (e = up(&p->d_asm_ptr, asm_ptr.data(), nn + 1)) != hipSuccess ||
+      (e = up(&p->d_asm_ent, asm_ent.data(), nnz)) != hipSuccess) {
+    md_plan_destroy(p);
+    return hip_fail(e, "plan upload");
+  }
+  *out = p;
+  return MD_OK;
+}
+
+int md_plan_destroy(md_plan *p) {
+  if (!p) return MD_OK;
+  for (int32_t *q : {p->d_poly_ptr, p->d_mon_ptr, p->d_var, p->d_exp, p->d_order, p->d_asm_ptr, p->d_asm_ent})
+    if (q) (void)hipFree(q);
+  delete p;
+  return MD_OK;
+}
+
+int md_workspace_size(const md_plan *p, size_t *bytes) {
+  if (!p || !bytes) return fail(MD_EINVAL, "NULL argument");
+  *bytes = newton_layout(p).total;
+  return MD_OK;
+}
+
+static int eval_diff_impl(const md_plan *p, const double *cff, const double *cst, const double *x, double *b,
+                          double *A, void *ws, hipStream_t st) {
+  Layout w = newton_layout(p);
+  mdk::EvalArgs a;
+  a.n = p->n;
+  a.D = p->D;
+  a.m = p->m;
+  a.nnz = p->nnz;
+  a.mon_ptr = p->d_mon_ptr;
+  a.var = p->d_var;
+  a.exp = p->d_exp;
+  a.order = p->d_order;
+  a.cff = cff;
+  a.x = x;
+  a.pw = at(ws, w.pw);
+  a.val = at(ws, w.val);
+  a.der = at(ws, w.der);
+  hipError_t e;
+  {
+    Timed t(MD_CLASS_CONVOLUTIONS, st);
+    e = mdk::launch_evaldiff(p->L, a, p->maxexp, at(ws, w.pw), st);
+  }
+  if (e != hipSuccess) return hip_fail(e, "eval/diff launch");
+  {
+    Timed t(MD_CLASS_ASSEMBLY, st);
+    e = mdk::launch_assemble(p->L, p->n, p->D, p->m, p->nnz, p->d_poly_ptr, p->d_asm_ptr, p->d_asm_ent, cst, a.val,
+                             a.der, b, A, st);
+  }
+  if (e != hipSuccess) return hip_fail(e, "assembly launch");
+  return MD_OK;
+}
+
+int md_eval_diff(const md_plan *p, const double *cff, const double *cst, const double *x, double *b, double *A,
+                 void *ws, size_t ws_bytes, hipStream_t st) {
+  if (!p || !cst || !x || !b || !A || (p->m > 0 && !cff)) return fail(MD_EINVAL, "NULL argument");
+  if (!ws || ws_bytes < newton_layout(p).total) return fail(MD_ENOSPACE, "workspace too small");
+  return eval_diff_impl(p, cff, cst, x, b, A, ws, st);
+}
+
+int md_qr_workspace_size(int prec, int n, size_t *bytes) {
+  if (!bytes || !valid_prec(prec) || n < 1 || n > MD_MAX_DIM) return fail(MD_EINVAL, "bad argument");
+  *bytes = 0;
+  return MD_OK;
+}
+
+int md_qr(int prec, int n, double *a0, double *tau, void *ws, size_t ws_bytes, hipStream_t st, int32_t *dev_status) {
+  (void)ws;
+  (void)ws_bytes;
+  if (!valid_prec(prec) || n < 1 || n > MD_MAX_DIM) return fail(MD_EINVAL, "bad precision or dimension");
+  if (!a0 || !tau) return fail(MD_EINVAL, "NULL argument");
+  hipError_t e = mdk::launch_qr(prec, n, a0, tau, dev_status, st);
+  return e == hipSuccess ? MD_OK : hip_fail(e, "qr launch");
+}
+
+int md_solve_workspace_size(int prec, int n, int d, size_t *bytes) {
+  if (!bytes || !valid_prec(prec) || n < 1 || n > MD_MAX_DIM || d < 0 || d + 1 > MD_MAX_COEFFS)
+    return fail(MD_EINVAL, "bad argument");
+  *bytes = solve_bytes(prec, n, d + 1);
+  return MD_OK;
+}
+
+int md_series_solve(int prec, int n, int d, const double *qr, const double *tau, const double *A, double *rhs_dx,
+                    void *ws, size_t ws_bytes, hipStream_t st, int32_t *dev_status) {
+  if (!valid_prec(prec) || n < 1 || n > MD_MAX_DIM || d < 0 || d + 1 > MD_MAX_COEFFS)
+    return fail(MD_EINVAL, "bad precision, dimension or degree");
+  if (!qr || !tau || !rhs_dx || (d > 0 && !A)) return fail(MD_EINVAL, "NULL argument");
+  if (!ws || ws_bytes < solve_bytes(prec, n, d + 1)) return fail(MD_ENOSPACE, "workspace too small");
+  return series_solve_impl(prec, n, d + 1, qr, tau, A, rhs_dx, ws, st, dev_status);
+}
+
+int md_newton_step(const md_plan *p, const double *cff, const double *cst, double *x, int32_t *dev_status,
+                   double *dev_norms, void *ws, size_t ws_bytes, hipStream_t st) {
+  if (!p || !cst || !x || (p->m > 0 && !cff)) return fail(MD_EINVAL, "NULL argument");
+  Layout w = newton_layout(p);
+  if (!ws || ws_bytes < w.total) return fail(MD_ENOSPACE, "workspace too small");
+  const int L = p->L, n = p->n, D = p->D;
+  hipError_t e;
+  if ((e = mdk::launch_status_init(dev_status, st)) != hipSuccess) return hip_fail(e, "status");
+  double *b = at(ws, w.b), *A = at(ws, w.A), *qr = at(ws, w.qr), *tau = at(ws, w.tau), *dx = at(ws, w.dx);
+  int rc = eval_diff_impl(p, cff, cst, x, b, A, ws, st);
+  if (rc != MD_OK) return rc;
+  {
+    Timed t(MD_CLASS_QR, st);
+    if ((e = mdk::launch_extract(L, n, D, 0, A, qr, st)) != hipSuccess) return hip_fail(e, "extract A0");
+    if ((e = mdk::launch_qr(L, n, qr, tau, dev_status, st)) != hipSuccess) return hip_fail(e, "qr");
+  }
+  if ((e = mdk::launch_copy(b, dx, (size_t)L * n * D, st)) != hipSuccess) return hip_fail(e, "copy");
+  // the solve's workspace: invd, M, N, r live contiguously from w.invd
+  rc = series_solve_impl(L, n, D, qr, tau, A, dx, at(ws, w.invd), st, dev_status);
+  if (rc != MD_OK) return rc;
+  {
+    Timed t(MD_CLASS_X_UPDATE, st);
+    if ((e = mdk::launch_update(L, n, D, b, dx, x, dev_norms, dev_status, st)) != hipSuccess)
+      return hip_fail(e, "update");
+  }
+  return MD_OK;
+}
+
+int md_timing_enable(int on) {
+  g_timing = on != 0;
+  return MD_OK;
+}
+
+int md_timing_read(double *ms, int64_t *launches) {
+  if (!ms || !launches) return fail(MD_EINVAL, "NULL argument");
+  for (const EventPair &p : g_pending) {
+    float t = 0.0f;
+    hipError_t e = hipEventSynchronize(p.b);
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, p.a, p.b);
+    if (e == hipSuccess) {
+      g_ms[p.cls] += t;
+      g_count[p.cls] += 1;
+    }
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  g_pending.clear();
+  for (int c = 0; c < MD_NCLASSES; ++c) {
+    ms[c] = g_ms[c];
+    launches[c] = g_count[c];
+    g_ms[c] = 0.0;
+    g_count[c] = 0;
+  }
+  return MD_OK;
+}
+
+int md_arith(int prec, int op, int64_t count, const double *a, const double *b, double *c, hipStream_t st) {
+  if (!valid_prec(prec) || op < 0 || op > 5 || count < 0) return fail(MD_EINVAL, "bad precision, op or count");
+  if (count == 0) return MD_OK;
+  if (!a || !c || (op != 4 && !b)) return fail(MD_EINVAL, "NULL argument");
+  if (count > ((int64_t)1 << 31) * 256) return fail(MD_EINVAL, "count too large");
+  hipError_t e = mdk::launch_arith(prec, op, count, a, b, c, st);
+  return e == hipSuccess ? MD_OK : hip_fail(e, "arith launch");
+}
+
+}  // extern "C"

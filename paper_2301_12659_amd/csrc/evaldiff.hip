@@ -1,0 +1,362 @@
+// Evaluation and differentiation of a polynomial system at a power series
+// (Section 5.1: reverse mode of algorithmic differentiation with power-series
+// products; Section 6: operands staged through shared memory into registers),
+// and the assembly of b(t) = -p(x(t)) and of the Jacobian series A(t).
+//
+// Work decomposition.  A "worker" is a group of G lanes of one wavefront
+// (G = the smallest power of two >= ceil(D/2)); it evaluates and
+// differentiates one whole monomial, product after product, with three series
+// buffers in LDS.  A truncated product c_s = sum_{i<=s} a_i b_{s-i} gives lane l
+// the outputs l and D-1-l, so every lane does exactly D+1 multiply-adds: the
+// triangular work is balanced without the zero padding of the paper's
+// kernels (which pad to D^2 multiplications, Section 5.1).
+//
+// Per monomial c * prod_j x_{v_j}^{a_j} with support v_1 < ... < v_k:
+//   common factor   CF = prod_{a_j >= 2} x_{v_j}^{a_j - 1}   (the paper's systems
+//                   have exponent one only; this reading keeps every derivative a
+//                   single cross product), f_0 = c * CF (or the scalar c);
+//   backward        b_1 = x_{v_k}, b_q = b_{q-1} * x_{v_{k-q+1}}, q = 2..k-1;
+//   forward         f_j = f_{j-1} * x_{v_j}, j = 1..k, value = f_k;
+//   cross           d/dx_{v_j} = a_j f_{j-1} * b_{k-j} (j < k), d/dx_{v_k} = a_k f_{k-1}.
+// With exponents one and a scalar f_0 this is the paper's 3k-5 convolutions.
+// The backward products are parked in the derivative slots of the entries
+// that consume them, so no extra memory is needed.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace mdk {
+
+static __host__ __device__ inline int worker_lanes(int D) {
+  int h = (D + 1) / 2, g = 1;
+  while (g < h) g <<= 1;
+  return g;
+}
+
+// Truncated product W = U * V (all in LDS, layout [L][D]) scaled by an integer.
+template <int L>
+__device__ void conv(const double *U, const double *V, double *W, int D, int lane, int scale) {
+  const int o1 = lane, o2 = D - 1 - lane;
+  const bool act = lane < (D + 1) / 2;
+  double acc[L];
+  md::zero<L>(acc);
+  for (int t = 0; t <= D; ++t) {
+    const bool ph1 = t <= o1;
+    int i = ph1 ? t : t - o1 - 1;
+    int j = (ph1 ? o1 : o2) - i;
+    if (!act) {
+      i = 0;
+      j = 0;
+    }
+    double u[L], v[L];
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+      u[l] = U[l * D + i];
+      v[l] = V[l * D + j];
+    }
+    MD<L>::fma(acc, u, v);
+    if (t == o1) {
+      if (act) {
+        md::mul_int<L>(acc, scale);
+#pragma unroll
+        for (int l = 0; l < L; ++l) W[l * D + o1] = acc[l];
+      }
+      md::zero<L>(acc);
+    }
+  }
+  if (act && o2 > o1) {
+    md::mul_int<L>(acc, scale);
+#pragma unroll
+    for (int l = 0; l < L; ++l) W[l * D + o2] = acc[l];
+  }
+}
+
+// W = scale * c * V for a scalar c (registers) and a series V.
+template <int L>
+__device__ void scal(const double (&c)[L], const double *V, double *W, int D, int lane, int G, int scale) {
+  for (int s = lane; s < D; s += G) {
+    double v[L], r[L];
+#pragma unroll
+    for (int l = 0; l < L; ++l) v[l] = V[l * D + s];
+    MD<L>::mul(c, v, r);
+    md::mul_int<L>(r, scale);
+#pragma unroll
+    for (int l = 0; l < L; ++l) W[l * D + s] = r[l];
+  }
+}
+
+// LDS <- global series (limb stride gstride, element offset off).
+__device__ __forceinline__ void load_series(double *S, const double *g, size_t gstride, size_t off, int L, int D,
+                                            int lane, int G) {
+  for (int q = lane; q < L * D; q += G) {
+    const int l = q / D, s = q - l * D;
+    S[q] = g[(size_t)l * gstride + off + s];
+  }
+}
+
+__device__ __forceinline__ void store_series(double *g, size_t gstride, size_t off, const double *S, int L, int D,
+                                             int lane, int G) {
+  for (int q = lane; q < L * D; q += G) {
+    const int l = q / D, s = q - l * D;
+    g[(size_t)l * gstride + off + s] = S[q];
+  }
+}
+
+
+
+template <int L>
+__global__ void __launch_bounds__(256) evaldiff_kernel(EvalArgs a) {
+  extern __shared__ double lds[];
+  const int D = a.D;
+  const int G = worker_lanes(D);
+  const int wpb = blockDim.x / G;  // workers per block
+  const int wid = threadIdx.x / G, lane = threadIdx.x - wid * G;
+  const int widx = blockIdx.x * wpb + wid;
+  if (widx >= a.m) return;  // whole worker exits together
+  double *buf[3] = {lds + (size_t)wid * 3 * L * D, lds + (size_t)wid * 3 * L * D + L * D,
+                    lds + (size_t)wid * 3 * L * D + 2 * L * D};
+  const int mono = a.order[widx];
+  const int e0 = a.mon_ptr[mono], k = a.mon_ptr[mono + 1] - e0;
+  const size_t nD = (size_t)a.n * D, mD = (size_t)a.m * D, zD = (size_t)a.nnz * D;
+  double c[L];
+  ld<L>(a.cff, a.m, mono, c);
+
+  if (k == 0) {  // constant monomial
+    for (int s = lane; s < D; s += G) {
+#pragma unroll
+      for (int l = 0; l < L; ++l) a.val[(size_t)l * mD + (size_t)mono * D + s] = (s == 0) ? c[l] : 0.0;
+    }
+    return;
+  }
+  auto xoff = [&](int v) { return (size_t)v * D; };
+  auto der_off = [&](int j) { return (size_t)(e0 + j) * D; };  // j: 0-based entry
+
+  // ---- backward chain: b_q for q = 2..k-1 parked in the slot of entry k-q (0-based k-q-1+... )
+  if (k >= 3) {
+    double *B = buf[0], *X = buf[1], *Wb = buf[2];
+    load_series(B, a.x, nD, xoff(a.var[e0 + k - 1]), L, D, lane, G);  // b_1 = x_{v_k}
+    for (int q = 2; q <= k - 1; ++q) {
+      load_series(X, a.x, nD, xoff(a.var[e0 + k - q]), L, D, lane, G);  // x_{v_{k-q+1}}
+      wave_sync();
+      conv<L>(B, X, Wb, D, lane, 1);
+      wave_sync();
+      // b_q is consumed by the cross product of forward step j = k - q (1-based),
+      // i.e. entry k - q - 1 (0-based)
+      store_series(a.der, zD, der_off(k - q - 1), Wb, L, D, lane, G);
+      double *t = B;
+      B = Wb;
+      Wb = t;
+      wave_sync();
+    }
+  }
+
+  // ---- common factor and f_0
+  double *U = buf[0], *V = buf[1], *W = buf[2];
+  bool f0_scalar = true;
+  for (int j = 0; j < k; ++j) {
+    const int p = a.exp[e0 + j] - 1;
+    if (p < 1) continue;
+    const int v = a.var[e0 + j];
+    const double *src = (p == 1) ? a.x : a.pw + (size_t)(p - 2) * L * nD;
+    if (f0_scalar) {
+      load_series(U, src, nD, xoff(v), L, D, lane, G);
+      f0_scalar = false;
+      wave_sync();
+    } else {
+      load_series(V, src, nD, xoff(v), L, D, lane, G);
+      wave_sync();
+      conv<L>(U, V, W, D, lane, 1);
+      wave_sync();
+      double *t = U;
+      U = W;
+      W = t;
+    }
+  }
+  if (!f0_scalar) {  // f_0 = c * CF in place
+    scal<L>(c, U, U, D, lane, G, 1);
+    wave_sync();
+  }
+
+  // ---- forward chain with the cross products
+  for (int j = 1; j <= k; ++j) {
+    const int ej = j - 1;  // 0-based entry of v_j
+    const int aj = a.exp[e0 + ej];
+    if (j < k) {
+      if (k - j == 1)
+        load_series(V, a.x, nD, xoff(a.var[e0 + k - 1]), L, D, lane, G);  // b_1 = x_{v_k}
+      else
+        load_series(V, a.der, zD, der_off(ej), L, D, lane, G);  // b_{k-j}
+      wave_sync();
+      if (f0_scalar && j == 1)
+        scal<L>(c, V, W, D, lane, G, aj);
+      else
+        conv<L>(U, V, W, D, lane, aj);
+      wave_sync();
+      store_series(a.der, zD, der_off(ej), W, L, D, lane, G);
+    } else {  // d/dx_{v_k} = a_k f_{k-1}
+      if (f0_scalar && j == 1) {
+        for (int s = lane; s < D; s += G) {
+          double r[L];
+#pragma unroll
+          for (int l = 0; l < L; ++l) r[l] = (s == 0) ? c[l] : 0.0;
+          md::mul_int<L>(r, aj);
+#pragma unroll
+          for (int l = 0; l < L; ++l) a.der[(size_t)l * zD + der_off(ej) + s] = r[l];
+        }
+      } else {
+        for (int s = lane; s < D; s += G) {
+          double r[L];
+#pragma unroll
+          for (int l = 0; l < L; ++l) r[l] = U[l * D + s];
+          md::mul_int<L>(r, aj);
+#pragma unroll
+          for (int l = 0; l < L; ++l) a.der[(size_t)l * zD + der_off(ej) + s] = r[l];
+        }
+      }
+    }
+    wave_sync();
+    // f_j = f_{j-1} * x_{v_j}
+    load_series(V, a.x, nD, xoff(a.var[e0 + ej]), L, D, lane, G);
+    wave_sync();
+    if (f0_scalar && j == 1)
+      scal<L>(c, V, W, D, lane, G, 1);
+    else
+      conv<L>(U, V, W, D, lane, 1);
+    wave_sync();
+    double *t = U;
+    U = W;
+    W = t;
+  }
+  store_series(a.val, mD, (size_t)mono * D, U, L, D, lane, G);
+}
+
+// Powers x_v^p, p = 2..maxexp-1, for the common factors of exponents >= 3.
+template <int L>
+__global__ void __launch_bounds__(256) power_kernel(int n, int D, int maxp, const double *x, double *pw) {
+  extern __shared__ double lds[];
+  const int G = worker_lanes(D);
+  const int wpb = blockDim.x / G;
+  const int wid = threadIdx.x / G, lane = threadIdx.x - wid * G;
+  const int v = blockIdx.x * wpb + wid;
+  if (v >= n) return;
+  double *U = lds + (size_t)wid * 3 * L * D, *X = U + L * D, *W = X + L * D;
+  const size_t nD = (size_t)n * D;
+  load_series(X, x, nD, (size_t)v * D, L, D, lane, G);
+  load_series(U, x, nD, (size_t)v * D, L, D, lane, G);
+  wave_sync();
+  for (int p = 2; p <= maxp; ++p) {
+    conv<L>(U, X, W, D, lane, 1);
+    wave_sync();
+    store_series(pw + (size_t)(p - 2) * L * nD, nD, (size_t)v * D, W, L, D, lane, G);
+    double *t = U;
+    U = W;
+    W = t;
+    wave_sync();
+  }
+}
+
+// b_i(t) = -(c_{i,0}(t) + sum_{m in P_i} value_m(t)), one thread per (i, s).
+template <int L>
+__global__ void assemble_b_kernel(int n, int D, int m, const int32_t *poly_ptr, const double *cst,
+                                  const double *val, double *b) {
+  const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t nD = (size_t)n * D, mD = (size_t)m * D;
+  if (q >= nD) return;
+  const int i = (int)(q / D), s = (int)(q - (size_t)i * D);
+  double acc[L];
+  ld<L>(cst, nD, q, acc);
+  for (int mj = poly_ptr[i]; mj < poly_ptr[i + 1]; ++mj) {
+    double v[L], r[L];
+    ld<L>(val, mD, (size_t)mj * D + s, v);
+    MD<L>::add(acc, v, r);
+    md::copy<L>(r, acc);
+  }
+  md::neg<L>(acc, acc);
+  st<L>(b, nD, q, acc);
+}
+
+// A[i][j][s] = sum of the derivative series of row i's monomials with respect
+// to x_j, in monomial order; one thread per (i, j, s).
+template <int L>
+__global__ void assemble_A_kernel(int n, int D, int nnz, const int32_t *asm_ptr, const int32_t *asm_ent,
+                                  const double *der, double *A) {
+  const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t nnD = (size_t)n * n * D, zD = (size_t)nnz * D;
+  if (q >= nnD) return;
+  const size_t ij = q / D;
+  const int s = (int)(q - ij * D);
+  const int lo = asm_ptr[ij], hi = asm_ptr[ij + 1];
+  double acc[L];
+  md::zero<L>(acc);
+  if (lo < hi) {
+    ld<L>(der, zD, (size_t)asm_ent[lo] * D + s, acc);
+    for (int t = lo + 1; t < hi; ++t) {
+      double v[L], r[L];
+      ld<L>(der, zD, (size_t)asm_ent[t] * D + s, v);
+      MD<L>::add(acc, v, r);
+      md::copy<L>(r, acc);
+    }
+  }
+  st<L>(A, nnD, q, acc);
+}
+
+// ------------------------------------------------------------------ launchers
+
+template <int L>
+hipError_t launch_evaldiff_T(const EvalArgs &a, int maxexp, double *pw_mut, hipStream_t st) {
+  const int G = worker_lanes(a.D);
+  const int wpb = 256 / G;
+  const size_t lds = (size_t)wpb * 3 * L * a.D * sizeof(double);
+  static bool attr_set = false;
+  if (!attr_set) {  // dynamic LDS above 64 KB needs the attribute
+    hipFuncSetAttribute((const void *)power_kernel<L>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    hipFuncSetAttribute((const void *)evaldiff_kernel<L>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    attr_set = true;
+  }
+  if (maxexp >= 3) {
+    const int blocks = (a.n + wpb - 1) / wpb;
+    hipLaunchKernelGGL(power_kernel<L>, dim3(blocks), dim3(256), lds, st, a.n, a.D, maxexp - 1, a.x, pw_mut);
+  }
+  if (a.m > 0) {
+    const int blocks = (a.m + wpb - 1) / wpb;
+    hipLaunchKernelGGL(evaldiff_kernel<L>, dim3(blocks), dim3(256), lds, st, a);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_evaldiff(int L, const EvalArgs &a, int maxexp, double *pw, hipStream_t st) {
+  switch (L) {
+    case 2: return launch_evaldiff_T<2>(a, maxexp, pw, st);
+    case 4: return launch_evaldiff_T<4>(a, maxexp, pw, st);
+    case 8: return launch_evaldiff_T<8>(a, maxexp, pw, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+size_t evaldiff_lds_bytes(int L, int D) {
+  const int G = worker_lanes(D);
+  return (size_t)(256 / G) * 3 * L * D * sizeof(double);
+}
+
+template <int L>
+hipError_t launch_assemble_T(int n, int D, int m, int nnz, const int32_t *poly_ptr, const int32_t *asm_ptr,
+                             const int32_t *asm_ent, const double *cst, const double *val, const double *der,
+                             double *b, double *A, hipStream_t st) {
+  const size_t nD = (size_t)n * D, nnD = (size_t)n * n * D;
+  hipLaunchKernelGGL(assemble_b_kernel<L>, dim3((nD + 255) / 256), dim3(256), 0, st, n, D, m, poly_ptr, cst, val, b);
+  hipLaunchKernelGGL(assemble_A_kernel<L>, dim3((nnD + 255) / 256), dim3(256), 0, st, n, D, nnz, asm_ptr, asm_ent,
+                     der, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_assemble(int L, int n, int D, int m, int nnz, const int32_t *poly_ptr, const int32_t *asm_ptr,
+                           const int32_t *asm_ent, const double *cst, const double *val, const double *der,
+                           double *b, double *A, hipStream_t st) {
+  switch (L) {
+    case 2: return launch_assemble_T<2>(n, D, m, nnz, poly_ptr, asm_ptr, asm_ent, cst, val, der, b, A, st);
+    case 4: return launch_assemble_T<4>(n, D, m, nnz, poly_ptr, asm_ptr, asm_ent, cst, val, der, b, A, st);
+    case 8: return launch_assemble_T<8>(n, D, m, nnz, poly_ptr, asm_ptr, asm_ent, cst, val, der, b, A, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace mdk

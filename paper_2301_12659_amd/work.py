@@ -1,0 +1,92 @@
+"""Algorithmic work of one Newton step, per kernel class.
+
+Counts are the multiple-double operations the method must perform (unpadded
+truncated convolutions: D(D+1)/2 multiply-adds per series product, the
+paper pads to D^2, Section 5.1), expressed as double flops with the
+instruction and flop counts of this library's own generated routines
+(csrc/md_counts.json; a fused multiply-add counts as two flops).
+"""
+from __future__ import annotations
+
+import json
+import os
+
+import numpy as np
+
+_COUNTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", "md_counts.json")
+
+
+def md_costs(L: int) -> dict:
+    with open(_COUNTS) as f:
+        return json.load(f)[str(L)]
+
+
+def monomial_products(k: int, exps) -> tuple[int, int]:
+    """(series-by-series convolutions, scalar-by-series products) of one
+    monomial in the reverse-mode scheme with a common factor."""
+    if k == 0:
+        return 0, 0
+    big = [e for e in exps if e >= 2]
+    conv = max(len(big) - 1, 0)          # common factor chain
+    scal = 1 if big else 0               # f_0 = c * CF
+    f0_scalar = not big
+    conv += max(k - 2, 0)                # backward products
+    for j in range(1, k + 1):
+        if j < k:                        # cross product
+            if f0_scalar and j == 1:
+                scal += 1
+            else:
+                conv += 1
+        if f0_scalar and j == 1:         # forward product
+            scal += 1
+        else:
+            conv += 1
+    return conv, scal
+
+
+def step_work(sys) -> dict:
+    """Multiply-add counts per kernel class for one Newton step of a system
+    (an mdinputs.System or anything with L, n, D, mon_ptr, exp, poly_ptr)."""
+    L, n, D = sys.L, sys.n, sys.D
+    conv = scal = 0
+    for j in range(len(sys.mon_ptr) - 1):
+        e = sys.exp[sys.mon_ptr[j]:sys.mon_ptr[j + 1]]
+        c, s = monomial_products(len(e), e)
+        conv += c
+        scal += s
+    maxexp = int(sys.exp.max()) if len(sys.exp) else 1
+    if maxexp >= 3:
+        conv += n * (maxexp - 2)         # power table
+    tri = D * (D + 1) // 2
+    w = {}
+    w["convolutions"] = {"fma": conv * tri, "mul": scal * D, "products": conv, "scalar_products": scal}
+    # assembly: additions into b and A
+    m = len(sys.mon_ptr) - 1
+    nnz = len(sys.var)
+    w["assembly"] = {"add": (m + 0) * D + max(nnz - 0, 0) * D}
+    qr = sum((n - c) + 2 * (n - c) * (n - c - 1) for c in range(n))
+    w["qr"] = {"fma": qr}
+    w["qhb_bs"] = {"fma": n * (sum(2 * (n - r) for r in range(n)) + n * (n - 1) // 2)}
+    w["gemm"] = {"fma": n * n * n if D > 1 else 0}
+    upd = n * n + sum(2 * n * n + (D - k - 1) * n * n for k in range(1, D))
+    w["updates"] = {"fma": upd}
+    w["x_update"] = {"add": n * D}
+    cost = md_costs(L)
+    for cls, d in w.items():
+        fl = d.get("fma", 0) * cost["fma"]["flops"] + d.get("mul", 0) * cost["mul"]["flops"] + \
+            d.get("add", 0) * cost["add"]["flops"]
+        ins = d.get("fma", 0) * cost["fma"]["instr"] + d.get("mul", 0) * cost["mul"]["instr"] + \
+            d.get("add", 0) * cost["add"]["instr"]
+        d["flops"] = int(fl)
+        d["instr"] = int(ins)
+    return w
+
+
+# The paper's convention (Table 2): md multiplications in zero-padded
+# convolutions (D^2 per product) times 23 / 336 / 1742 double flops.
+PAPER_MUL_COST = {2: 23, 4: 336, 8: 1742}
+
+
+def paper_convention_flops(sys) -> int:
+    w = step_work(sys)["convolutions"]
+    return int(w["products"] * sys.D * sys.D * PAPER_MUL_COST[sys.L])

@@ -1,0 +1,81 @@
+"""The C-ABI library loads and exports every declared entry point; host-side
+argument checks reject bad input before any GPU work (CPU only)."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import mdinputs
+
+
+@pytest.fixture(scope="module")
+def mdn():
+    import paper_2301_12659_amd as mdn
+
+    return mdn
+
+
+def test_exports_every_declared_symbol(mdn):
+    names = mdn.exported_functions()
+    assert {"md_newton_step", "md_eval_diff", "md_qr", "md_series_solve"} <= set(names)
+    for name in names:
+        assert hasattr(mdn._lib, name), name
+
+
+def _plan(mdn, prec, n, d, pp, mp, var, ex):
+    h = ctypes.c_void_p()
+    arrs = [np.ascontiguousarray(a, dtype=np.int32) for a in (pp, mp, var, ex)]
+    ptrs = [a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) for a in arrs]
+    m = len(arrs[1]) - 1
+    rc = mdn.raw_call("md_plan_create", prec, n, d, m, *ptrs, ctypes.byref(h))
+    return rc
+
+
+@pytest.mark.parametrize("bad", [
+    dict(prec=3), dict(n=0), dict(d=-1), dict(d=128), dict(var=[0, 2]), dict(mp=[0, 2, 2], var=[1, 0]),
+    dict(mp=[0, 2, 2], var=[1, 1]), dict(ex=[0, 1]), dict(ex=[1, 9]), dict(pp=[0, 1, 1]), dict(mp=[0, 3, 2]),
+])
+def test_plan_rejects_bad_input(mdn, bad):
+    args = dict(prec=2, n=2, d=3, pp=[0, 1, 2], mp=[0, 1, 2], var=[0, 1], ex=[1, 1])
+    args.update(bad)
+    rc = _plan(mdn, args["prec"], args["n"], args["d"], args["pp"], args["mp"], args["var"], args["ex"])
+    assert rc == mdn.MD_EINVAL
+    assert mdn._lib.md_last_error()
+
+
+def test_other_entry_points_reject_bad_arguments(mdn):
+    assert mdn.raw_call("md_arith", 3, 0, ctypes.c_int64(4), None, None, None, None) == mdn.MD_EINVAL
+    assert mdn.raw_call("md_arith", 4, 9, ctypes.c_int64(4), None, None, None, None) == mdn.MD_EINVAL
+    assert mdn.raw_call("md_arith", 4, 0, ctypes.c_int64(4), None, None, None, None) == mdn.MD_EINVAL
+    assert mdn.raw_call("md_arith", 4, 0, ctypes.c_int64(0), None, None, None, None) == mdn.MD_OK
+    sz = ctypes.c_size_t()
+    assert mdn.raw_call("md_qr_workspace_size", 5, 4, ctypes.byref(sz)) == mdn.MD_EINVAL
+    assert mdn.raw_call("md_solve_workspace_size", 4, 4, 200, ctypes.byref(sz)) == mdn.MD_EINVAL
+    assert mdn.raw_call("md_solve_workspace_size", 4, 10, 15, ctypes.byref(sz)) == mdn.MD_OK and sz.value > 0
+    assert mdn.raw_call("md_qr", 4, 0, None, None, None, 0, None, None) == mdn.MD_EINVAL
+    assert mdn.raw_call("md_series_solve", 4, 4, 3, None, None, None, None, None, 0, None, None) == mdn.MD_EINVAL
+    assert mdn.raw_call("md_newton_step", None, None, None, None, None, None, None, 0, None) == mdn.MD_EINVAL
+    assert mdn.raw_call("md_eval_diff", None, None, None, None, None, None, None, 0, None) == mdn.MD_EINVAL
+
+
+def test_binding_checks_shapes_before_launch(mdn):
+    import torch
+
+    with pytest.raises(ValueError):
+        mdn._ptr(torch.zeros(3, dtype=torch.float64), (3,), "x")  # not a CUDA tensor
+
+
+def test_convolution_count_is_3k_minus_5():
+    """Section 5.1: 3k-5 products for a product of k series (exponent one,
+    scalar coefficient); the common factor adds one product per extra
+    exponent-two variable."""
+    from paper_2301_12659_amd import work
+
+    for k in range(2, 12):
+        assert work.monomial_products(k, [1] * k) == (3 * k - 5, 2)
+    assert work.monomial_products(1, [1]) == (0, 1)
+    # one variable squared: f_0 = c x_v is a series, every product is a convolution
+    assert work.monomial_products(3, [1, 2, 1]) == (3 * 3 - 5 + 2, 1)
+    s = mdinputs.small_dd()
+    w = work.step_work(s)
+    assert w["convolutions"]["products"] == 64 * 4  # 8 x 8 monomials of 3 variables

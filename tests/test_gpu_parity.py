@@ -1,0 +1,255 @@
+"""Parity of the HIP path with the oracle (GPU).
+
+Each test feeds the same seeded inputs to the C-ABI library (through the
+Python binding) and to the oracle, and compares element by element within the
+tolerance of the precision: 1e-28 (dd), 1e-60 (qd), 1e-120 (od), measured
+normwise per series.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import mdinputs
+import oracle
+from gpu_helpers import TOL, dev, host, matrix_series_err, scaled_err, series_err, step_err
+
+pytestmark = pytest.mark.gpu
+
+PRECS = [2, 4, 8]
+
+
+@pytest.fixture(scope="module")
+def mdn():
+    import torch
+
+    assert torch.cuda.is_available()
+    import paper_2301_12659_amd as mdn
+
+    return mdn
+
+
+def _eps(L):
+    return 2.0 ** (-53 * L)
+
+
+# ---------------------------------------------------------------- arithmetic
+
+@pytest.mark.parametrize("L", PRECS)
+@pytest.mark.parametrize("op", ["add", "sub", "mul", "div", "sqrt", "fma"])
+def test_arith(mdn, L, op):
+    import torch
+
+    rng = np.random.default_rng(100 + L)
+    cnt = 3001
+    a = mdinputs.random_md(rng, L, (cnt,), -1.0, 1.0)
+    b = mdinputs.random_md(rng, L, (cnt,), -1.0, 1.0)
+    c = mdinputs.random_md(rng, L, (cnt,), -1.0, 1.0)
+    b[:, : cnt // 4] *= 2.0 ** rng.integers(-40, 40, size=cnt // 4)  # exponent gaps
+    b[:, cnt // 4: cnt // 2] = -a[:, cnt // 4: cnt // 2]               # exact cancellation
+    b[L - 1, cnt // 4: cnt // 2] *= 0.5
+    if op == "sqrt":
+        a = a * np.sign(a[0])[None, :]  # |a| of a multiple double
+    ta, tb, tc = dev(a), dev(b), dev(c)
+    out = tc.clone() if op == "fma" else torch.empty_like(ta)
+    mdn.arith(L, op, ta, tb, out)
+    torch.cuda.synchronize()
+    ref = oracle.arith(op, a, b, c)
+    err = oracle.absdiff(host(out), ref)
+    if op in ("add", "sub"):
+        scale = np.abs(a[0]) + np.abs(b[0])
+    elif op == "fma":
+        scale = np.abs(c[0]) + np.abs(a[0] * b[0])
+    else:
+        scale = np.abs(ref[0])
+    rel = np.max(err / scale)
+    assert rel <= 16 * _eps(L), (op, L, rel / _eps(L))
+
+
+# ---------------------------------------------------------------- eval / diff
+
+EVAL_CASES = [
+    # L, n, d, monomials/poly, kmin, kmax, exps
+    (2, 5, 0, 3, 1, 3, (1, 2)),
+    (2, 6, 1, 3, 1, 3, (1, 2, 3)),
+    (2, 7, 12, 4, 1, 4, (1, 2, 3)),
+    (4, 9, 16, 4, 2, 5, (1, 2)),
+    (4, 12, 32, 3, 1, 6, (1, 2, 3)),
+    (8, 6, 20, 3, 1, 4, (1, 2, 3)),
+    (8, 5, 40, 2, 2, 5, (1, 2)),
+]
+
+
+@pytest.mark.parametrize("case", EVAL_CASES, ids=lambda c: f"L{c[0]}n{c[1]}d{c[2]}")
+def test_eval_diff(mdn, case):
+    import torch
+
+    L, n, d, mons, kmin, kmax, exps = case
+    sys = mdinputs.tiny(L, n, d, mons=mons, kmin=kmin, kmax=kmax, exps=exps, seed=n + d)
+    x = mdinputs.random_point(sys, 1)
+    cst = mdinputs.random_constant(sys, 2)
+    plan = mdn.Plan.from_system(sys)
+    b = torch.empty((L, n, sys.D), dtype=torch.float64, device="cuda")
+    A = torch.empty((L, n, n, sys.D), dtype=torch.float64, device="cuda")
+    ws = mdn.workspace(plan.workspace_bytes())
+    mdn.eval_diff(plan, dev(sys.cff), dev(cst), dev(x), b, A, ws)
+    torch.cuda.synchronize()
+    ob, oA, scale = oracle.eval_diff(sys, sys.cff, cst, x)
+    eb = scaled_err(host(b), ob, scale)
+    eA = matrix_series_err(host(A), oA)
+    assert eb <= TOL[L] and eA <= TOL[L], (eb, eA)
+
+
+def test_eval_diff_constant_and_single_monomials(mdn):
+    """Constant monomials (empty support) and one-variable monomials."""
+    import torch
+    from oracle_helpers import make
+    from fractions import Fraction
+
+    L, n, d = 4, 3, 9
+    polys = [[(Fraction(3, 2), []), (Fraction(1, 4), [(0, 3)])],
+             [(Fraction(-1), [(1, 1)]), (Fraction(5, 8), [(0, 1), (2, 2)])],
+             [(Fraction(7, 8), [(2, 1)])]]
+    sys = make(L, n, d, polys)
+    x = mdinputs.random_point(sys, 4)
+    cst = mdinputs.random_constant(sys, 5)
+    plan = mdn.Plan.from_system(sys)
+    b = torch.empty((L, n, sys.D), dtype=torch.float64, device="cuda")
+    A = torch.empty((L, n, n, sys.D), dtype=torch.float64, device="cuda")
+    ws = mdn.workspace(plan.workspace_bytes())
+    mdn.eval_diff(plan, dev(sys.cff), dev(cst), dev(x), b, A, ws)
+    torch.cuda.synchronize()
+    ob, oA, scale = oracle.eval_diff(sys, sys.cff, cst, x)
+    assert scaled_err(host(b), ob, scale) <= TOL[L]
+    assert matrix_series_err(host(A), oA) <= TOL[L]
+
+
+# ---------------------------------------------------------------- QR
+
+@pytest.mark.parametrize("L,n", [(2, 1), (2, 8), (4, 33), (4, 64), (8, 19)])
+def test_qr(mdn, L, n):
+    import torch
+
+    rng = np.random.default_rng(n + L)
+    A0 = mdinputs.random_md(rng, L, (n, n), -1.0, 1.0)
+    A0[0] += np.diag(np.full(n, 2.0))
+    a = dev(A0)
+    tau = torch.zeros((L, n), dtype=torch.float64, device="cuda")
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    mdn.qr(L, n, a, tau, status)
+    torch.cuda.synchronize()
+    assert int(status.item()) == 0
+    res, orth = oracle.qr_check(A0, host(a), host(tau))
+    assert res <= TOL[L] and orth <= TOL[L], (res, orth)
+    rd = oracle.rdiag(A0)
+    R = host(a)
+    diag = np.stack([R[:, i, i] * np.sign(R[0, i, i]) for i in range(n)], axis=1)  # |R_ii|
+    assert series_err(diag[:, None, :], rd[:, None, :]) <= TOL[L]
+
+
+def test_qr_singular_column(mdn):
+    import torch
+
+    L, n = 4, 6
+    rng = np.random.default_rng(0)
+    A0 = mdinputs.random_md(rng, L, (n, n), -1.0, 1.0)
+    A0[:, :, 3] = 0.0
+    a = dev(A0)
+    tau = torch.zeros((L, n), dtype=torch.float64, device="cuda")
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    mdn.qr(L, n, a, tau, status)
+    torch.cuda.synchronize()
+    assert int(status.item()) == mdn.MD_ESINGULAR
+
+
+# ---------------------------------------------------------------- series solve
+
+def _random_series_matrix(rng, L, n, D):
+    A = mdinputs.random_md(rng, L, (n, n, D), -1.0, 1.0) * (0.25 ** np.arange(D))[None, None, None, :]
+    A[0, :, :, 0] += np.diag(np.full(n, float(n)))
+    return A
+
+
+@pytest.mark.parametrize("L,n,d", [(2, 4, 0), (2, 7, 9), (4, 10, 20), (4, 17, 33), (8, 6, 15)])
+def test_series_solve(mdn, L, n, d):
+    import torch
+
+    D = d + 1
+    rng = np.random.default_rng(7 * n + d)
+    A = _random_series_matrix(rng, L, n, D)
+    rhs = mdinputs.random_md(rng, L, (n, D), -1.0, 1.0)
+    tA = dev(A)
+    qr = tA[..., 0].contiguous()
+    tau = torch.zeros((L, n), dtype=torch.float64, device="cuda")
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    mdn.qr(L, n, qr, tau, status)
+    x = dev(rhs)
+    ws = mdn.workspace(mdn.solve_workspace_bytes(L, n, d))
+    mdn.series_solve(L, n, d, qr, tau, tA, x, ws, status)
+    torch.cuda.synchronize()
+    assert int(status.item()) == 0
+    # oracle layout for A is [L][D][n][n]
+    ref = oracle.toeplitz_solve(np.ascontiguousarray(np.moveaxis(A, -1, 1)), rhs)
+    assert series_err(host(x), ref) <= TOL[L]
+
+
+# ---------------------------------------------------------------- Newton step
+
+@pytest.mark.parametrize("L,n,d", [(2, 6, 7), (4, 8, 15), (4, 11, 26), (8, 5, 11)])
+def test_newton_step_teacher_forced(mdn, L, n, d):
+    sys = mdinputs.tiny(L, n, d, mons=3, kmin=1, kmax=4, exps=(1, 2, 3), seed=3 * n + d)
+    cst = oracle.manufacture(sys)
+    x = sys.start()
+    drv = mdn.Newton(sys, cst, x)
+    for step in range(3):
+        drv.step()
+        got = host(drv.x)
+        ref = oracle.newton_step(sys, sys.cff, cst, x)["x"]
+        assert drv.status_code() == 0
+        assert step_err(got, ref, x) <= TOL[L], (step, step_err(got, ref, x))
+        x = got  # teacher forcing: the next oracle step starts from the GPU's x
+
+
+def test_small_dd_config_converges(mdn):
+    """n=8, d=15, dd, 4 steps from x*(0): each step matches the oracle step from
+    the same input, and the result is the oracle's fixed point."""
+    sys = mdinputs.small_dd()
+    cst = oracle.manufacture(sys)
+    drv = mdn.Newton(sys, cst)
+    x = sys.start()
+    for step in range(sys.steps):
+        drv.step()
+        got = host(drv.x)
+        ref = oracle.newton_step(sys, sys.cff, cst, x)["x"]
+        assert step_err(got, ref, x) <= TOL[2], (step, step_err(got, ref, x))
+        x = got
+    xfix = sys.start()
+    for _ in range(6):
+        xfix = oracle.newton_step(sys, sys.cff, cst, xfix)["x"]
+    assert series_err(host(drv.x), xfix) <= TOL[2]
+    drv.step()  # one more step: its update is at rounding level
+    assert host(drv.norms)[1].max() < TOL[2]
+
+
+def test_singular_jacobian_status(mdn):
+    """Two identical polynomials make A_0 singular: the step reports it."""
+    sys = mdinputs.tiny(4, 4, 3, mons=2, seed=1, boost=False, cond_max=None)
+    # copy polynomial 0 over polynomial 1
+    pp, mp, var, ex, cff = sys.poly_ptr, sys.mon_ptr, sys.var, sys.exp, sys.cff
+    rows = [[(cff[:, j], var[mp[j]:mp[j + 1]], ex[mp[j]:mp[j + 1]]) for j in range(pp[i], pp[i + 1])]
+            for i in range(sys.n)]
+    rows[1] = rows[0]
+    npp, nmp, nv, ne, nc = [0], [0], [], [], []
+    for row in rows:
+        for c, v, e in row:
+            nv += list(v)
+            ne += list(e)
+            nmp.append(len(nv))
+            nc.append(c)
+        npp.append(len(nmp) - 1)
+    sys.poly_ptr, sys.mon_ptr = np.array(npp, np.int32), np.array(nmp, np.int32)
+    sys.var, sys.exp, sys.cff = np.array(nv, np.int32), np.array(ne, np.int32), np.stack(nc, axis=1)
+    cst = mdinputs.random_constant(sys, 0)
+    drv = mdn.Newton(sys, cst, mdinputs.random_point(sys, 0))
+    drv.step()
+    assert drv.status_code() in (mdn.MD_ESINGULAR, mdn.MD_ENONFINITE)
