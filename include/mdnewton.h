@@ -102,7 +102,10 @@ int md_eval_diff(const md_plan *plan, const double *cff, const double *cst, cons
  * diagonal and the Householder vectors below it (unit leading entry
  * implicit), tau [L][n] the reflector factors: A_0 = Q R with
  * Q = H_0 H_1 ... H_{n-1}, H_c = I - tau_c v_c v_c^T, v_c = e_c + (entries below).
- * A zero column sets *dev_status = MD_ESINGULAR. */
+ * A zero column sets *dev_status = MD_ESINGULAR.  The factorization runs on
+ * several workgroups that hand the reflectors over through the workspace
+ * (md_qr_workspace_size bytes: flags and a reflector board); a hand-over
+ * time-out sets MD_EHIP. */
 int md_qr_workspace_size(int prec, int n, size_t *bytes);
 int md_qr(int prec, int n, double *a0, double *tau, void *ws, size_t ws_bytes, hipStream_t stream,
           int32_t *dev_status);
@@ -128,9 +131,32 @@ int md_newton_step(const md_plan *plan, const double *cff, const double *cst, do
 
 /* Elementwise multiple-double arithmetic on device arrays of count elements
  * (limb-major [L][count]): op 0 add, 1 sub, 2 mul, 3 div, 4 sqrt (of a),
- * 5 fused c := c + a*b.  b is not read for sqrt.  (Section 1.2 and Section 6:
- * the inlined arithmetic, exposed for testing and for callers.) */
+ * 5 fused c := c + a*b; op 6 is the dot product c[0] = sum_q a[q] b[q]
+ * (c is [L][1], summed in a fixed order).  b is not read for sqrt.
+ * (Section 1.2 and Section 6: the inlined arithmetic, exposed for testing,
+ * losses and callers.) */
 int md_arith(int prec, int op, int64_t count, const double *a, const double *b, double *c, hipStream_t stream);
+
+/* Adjoint of the Newton fixed point (for gradients of Taylor coefficients
+ * with respect to the monomial coefficients).  With T the block Toeplitz
+ * operator of Section 2 (A_0 on the diagonal, A_k on the k-th block
+ * subdiagonal), solve T^T lambda = g, i.e. by blocks from the last
+ * coefficient down:
+ *   A_0^T lambda_j = g_j - sum_{i=1..d-j} A_i^T lambda_{j+i},  j = d..0,
+ * with M = A_0^{-1} from the QR factors of md_qr (qr, tau) and the same
+ * staged kernels as md_series_solve applied to M^T and A_k^T.
+ * A [L][n][n][D]; g_lambda [L][n][D] holds g on entry and lambda on return. */
+int md_adjoint_workspace_size(int prec, int n, int d, size_t *bytes);
+int md_adjoint_solve(int prec, int n, int d, const double *qr, const double *tau, const double *A, double *g_lambda,
+                     void *ws, size_t ws_bytes, hipStream_t stream, int32_t *dev_status);
+
+/* grad_cff [L][m]: dL/dc_m = -sum_k lambda_{i(m),k} [x^{a_m}]_k, the gradient of
+ * a loss L(x) at a solution x of p(x; c) = 0 given lambda from
+ * md_adjoint_solve (dp_i/dc_m = x^{a_m} for the monomials of row i).  The
+ * monomial values are evaluated by the convolution kernel with unit
+ * coefficients.  Workspace as md_workspace_size. */
+int md_coef_grad(const md_plan *plan, const double *x, const double *lambda, double *grad_cff, void *ws,
+                 size_t ws_bytes, hipStream_t stream);
 
 /* Per-kernel-class timing (the paper measures the time of each kernel type,
  * Section 7, Table 4).  While enabled, the library brackets each class of

@@ -232,8 +232,13 @@ BOOST_GAMMA = 2.0
 
 
 def small_dd(seed: int = 1) -> System:
-    """n=8, d=15, dd; 8 monomials x 3 distinct variables, exponent 1; 4 steps."""
-    return make_system("small_dd", 2, 8, 15, 8, 3, 3, (1,), seed, 1e3, boost=False, steps=4,
+    """n=8, d=15, dd; 8 monomials x 3 distinct variables, exponent 1; 4 steps.
+
+    Redrawn until cond(A_0) <= 1e2 (inside the bound 1e3 of the recipe): the
+    double-double tolerance 1e-28 is only about 8000 units in the last place,
+    and one step amplifies rounding by cond(A_0) times the growth through the
+    stages (about 40 here)."""
+    return make_system("small_dd", 2, 8, 15, 8, 3, 3, (1,), seed, 1e2, boost=False, steps=4,
                        damping=DAMPING_STRONG)
 
 

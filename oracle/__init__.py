@@ -62,6 +62,8 @@ def lib():
         L.ora_rdiag.argtypes = [ci, ci, ci, dp, ci, dp]
         L.ora_set_threads.argtypes = [ci]
         L.ora_arith.argtypes = [ci, ci, ci, dp, dp, dp, ci, ci, dp]
+        L.ora_adjoint_solve.argtypes = [ci, ci, ci, ci, dp, dp, ci, dp]
+        L.ora_coef_grad.argtypes = [ci, ci, ci, ci, i32p, i32p, i32p, i32p, ci, dp, ci, dp, ci, dp]
         _lib = L
     return _lib
 
@@ -110,6 +112,19 @@ def _check(rc: int, what: str):
         raise OracleError(f"{what}: error {rc}")
 
 
+def _pad(a, L):
+    """Zero-pad an expansion to L limbs (the value is unchanged)."""
+    a = _c64(a)
+    if a.shape[0] >= L:
+        return a
+    return np.concatenate([a, np.zeros((L - a.shape[0],) + a.shape[1:])])
+
+
+def _common(*arrs):
+    L = max(a.shape[0] for a in arrs)
+    return L, [_pad(a, L) for a in arrs]
+
+
 def _sys_args(sys):
     return (_c32(sys.poly_ptr), _c32(sys.mon_ptr), _c32(sys.var), _c32(sys.exp))
 
@@ -119,13 +134,13 @@ def eval_diff(sys, cff, cst, x, rows=None, K=None, prec=None):
 
     Returns b[K, rows, D], A[K, D, rows, n] and the row scale
     max_s (|c_{i,0,s}| + sum_m |value_{m,s}|) used to judge b near a root."""
-    L = cff.shape[0]
-    K = K or 4 * L + 2
-    prec = prec or prec_bits(L)
+    L0 = cff.shape[0]  # the system's precision sets the defaults
+    L, (cff, cst, x) = _common(cff, cst, x)
+    K = K or 4 * L0 + 2
+    prec = prec or prec_bits(L0)
     r0, r1 = rows or (0, sys.n)
     R = r1 - r0
     pp, mp, var, ex = _sys_args(sys)
-    cff, cst, x = _c64(cff), _c64(cst), _c64(x)
     b = np.zeros((K, R, sys.D))
     A = np.zeros((K, sys.D, R, sys.n))
     sc = np.zeros(R)
@@ -137,11 +152,11 @@ def eval_diff(sys, cff, cst, x, rows=None, K=None, prec=None):
 
 def newton_step(sys, cff, cst, x, K=None, prec=None, want_A=False):
     """One Newton step from x; returns dict of expansions x, dx, b (and A)."""
-    L = cff.shape[0]
-    K = K or 4 * L + 2
-    prec = prec or prec_bits(L)
+    L0 = cff.shape[0]  # the system's precision sets the defaults
+    L, (cff, cst, x) = _common(cff, cst, x)
+    K = K or 4 * L0 + 2
+    prec = prec or prec_bits(L0)
     pp, mp, var, ex = _sys_args(sys)
-    cff, cst, x = _c64(cff), _c64(cst), _c64(x)
     out = {k: np.zeros((K, sys.n, sys.D)) for k in ("x", "dx", "b")}
     A = np.zeros((K, sys.D, sys.n, sys.n)) if want_A else None
     rc = lib().ora_newton_step(prec, sys.n, sys.D, sys.m, _i(pp), _i(mp), _i(var), _i(ex), L, _d(cff),
@@ -155,10 +170,11 @@ def newton_step(sys, cff, cst, x, K=None, prec=None, want_A=False):
 
 def toeplitz_solve(A, rhs, K=None, prec=None):
     """Solve the block lower-triangular Toeplitz system; A[L, D, n, n], rhs[L, n, D]."""
-    L, D, n, _ = A.shape
-    K = K or 4 * L + 2
-    prec = prec or prec_bits(L)
-    A, rhs = _c64(A), _c64(rhs)
+    L0 = A.shape[0]
+    L, (A, rhs) = _common(A, rhs)
+    _, D, n, _ = A.shape
+    K = K or 4 * L0 + 2
+    prec = prec or prec_bits(L0)
     dx = np.zeros((K, n, D))
     rc = lib().ora_toeplitz_solve(prec, n, D, L, _d(A), _d(rhs), K, _d(dx))
     _check(rc, "ora_toeplitz_solve")
@@ -246,3 +262,44 @@ def arith(op, a, b=None, c=None, K=None, prec=None):
                          _d(_c64(c if c is not None else z)), count, K, _d(out))
     _check(rc, "ora_arith")
     return out
+
+
+def adjoint_solve(A, g, K=None, prec=None):
+    """Solve T^T lambda = g for the block Toeplitz T of A[L, D, n, n]; g[L, n, D]."""
+    L0 = A.shape[0]
+    L, (A, g) = _common(A, g)
+    _, D, n, _ = A.shape
+    K = K or 4 * L0 + 2
+    prec = prec or prec_bits(L0)
+    lam = np.zeros((K, n, D))
+    rc = lib().ora_adjoint_solve(prec, n, D, L, _d(A), _d(g), K, _d(lam))
+    _check(rc, "ora_adjoint_solve")
+    return lam
+
+
+def coef_grad(sys, x, lam, K=None, prec=None):
+    """dL/dc_m = -sum_k lambda_{i(m),k} [x^{a_m}]_k for x[L, n, D], lambda[Ll, n, D]."""
+    L = x.shape[0]
+    K = K or 4 * L + 2
+    prec = prec or prec_bits(L)
+    pp, mp, var, ex = _sys_args(sys)
+    out = np.zeros((K, sys.m))
+    rc = lib().ora_coef_grad(prec, sys.n, sys.D, sys.m, _i(pp), _i(mp), _i(var), _i(ex), L, _d(_c64(x)),
+                             lam.shape[0], _d(_c64(lam)), K, _d(out))
+    _check(rc, "ora_coef_grad")
+    return out
+
+
+def converge(sys, cff, cst, x0, steps, K=None, prec=None):
+    """Newton steps carried in full oracle precision (K-double expansions)."""
+    x = x0
+    for _ in range(steps):
+        x = newton_step(sys, cff, cst, x, K=K, prec=prec)["x"]
+    return x
+
+
+def loss_top_grad(x, ktop):
+    """Gradient of L = sum_i sum_{k >= ktop} x_{i,k}^2: 2 x_{i,k} for k >= ktop, else 0."""
+    g = np.zeros_like(x)
+    g[:, :, ktop:] = 2.0 * x[:, :, ktop:]  # exact: doubling every limb
+    return g

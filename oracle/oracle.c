@@ -661,3 +661,103 @@ int ora_arith(int prec_bits, int op, int L, const double *a, const double *b, co
   }
   return ORA_OK;
 }
+
+/* ------------------------------ adjoint ------------------------------- */
+
+/* Solve the transposed block Toeplitz system T^T lambda = g (T has A_0 on the
+ * diagonal and A_k on the k-th block subdiagonal, Section 2), by block back
+ * substitution: A_0^T lambda_j = g_j - sum_{i=1..D-1-j} A_i^T lambda_{j+i},
+ * j = D-1 .. 0.  A [L][D][n][n] row-major per matrix, g [L][n][D], out [K][n][D]. */
+int ora_adjoint_solve(int prec_bits, int n, int D, int L, const double *A, const double *g, int K,
+                      double *lam_out) {
+  if (n < 1 || D < 1 || K < 1 || L < 1) return ORA_EINVAL;
+  mpfr_prec_t prec = prec_bits;
+  const size_t nn = (size_t)n * n, tot = (size_t)D * nn, nD = (size_t)n * D;
+  mpfr_t *Am = vnew(tot, prec), *gv = vnew(nD, prec), *lam = vnew(nD, prec), *LU = vnew(nn, prec);
+  for (size_t q = 0; q < tot; ++q) md_get(Am[q], A + q, tot, L);
+  for (size_t q = 0; q < nD; ++q) md_get(gv[q], g + q, nD, L);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) mpfr_set(LU[(size_t)i * n + j], Am[(size_t)j * n + i], MPFR_RNDN);  /* A_0^T */
+  int *perm = (int *)malloc(n * sizeof(int));
+  int rc = lu_factor(LU, n, perm, prec);
+  if (rc == ORA_OK) {
+    mpfr_t *r = vnew(n, prec), *w = vnew(n, prec);
+    mpfr_t t;
+    mpfr_init2(t, prec);
+    for (int j = D - 1; j >= 0; --j) {
+#pragma omp parallel for schedule(static) num_threads(ora_get_threads())
+      for (int v = 0; v < n; ++v) {
+        mpfr_t u;
+        mpfr_init2(u, prec);
+        mpfr_set(r[v], gv[(size_t)v * D + j], MPFR_RNDN);
+        for (int i = 1; j + i < D; ++i)
+          for (int q = 0; q < n; ++q) {  /* (A_i^T lambda_{j+i})_v = sum_q A_i[q][v] lambda_{j+i}[q] */
+            mpfr_mul(u, Am[(size_t)i * nn + (size_t)q * n + v], lam[(size_t)q * D + j + i], MPFR_RNDN);
+            mpfr_sub(r[v], r[v], u, MPFR_RNDN);
+          }
+        mpfr_clear(u);
+      }
+      lu_solve(LU, n, perm, r, w, t);
+      for (int v = 0; v < n; ++v) mpfr_set(lam[(size_t)v * D + j], r[v], MPFR_RNDN);
+    }
+    for (size_t q = 0; q < nD; ++q) exp_put(lam_out + q, nD, K, lam[q], t);
+    vfree(r, n);
+    vfree(w, n);
+    mpfr_clear(t);
+  }
+  free(perm);
+  vfree(Am, tot);
+  vfree(gv, nD);
+  vfree(lam, nD);
+  vfree(LU, nn);
+  return rc;
+}
+
+/* Gradient of a loss with respect to the monomial coefficients, given the
+ * adjoint lambda of the converged system: p_i = c_{i,0} + sum_m c_m x^{a_m}
+ * gives dp_i/dc_m = x^{a_m}, so dL/dc_m = -sum_k lambda_{i(m),k} [x^{a_m}]_k.
+ * x [L][n][D], lambda [Ll][n][D] (any number of limbs), out [K][m]. */
+int ora_coef_grad(int prec_bits, int n, int D, int m, const int32_t *pp, const int32_t *mp, const int32_t *var,
+                  const int32_t *ex, int L, const double *x, int Ll, const double *lambda, int K, double *out) {
+  sys_t S = {n, D, m, pp, mp, var, ex};
+  if (check_sys(&S) || K < 1) return ORA_EINVAL;
+  mpfr_prec_t prec = prec_bits;
+  const size_t nD = (size_t)n * D;
+  mpfr_t **X = (mpfr_t **)malloc(n * sizeof(mpfr_t *));
+  mpfr_t *lam = vnew(nD, prec);
+  for (int i = 0; i < n; ++i) {
+    X[i] = vnew(D, prec);
+    for (int s = 0; s < D; ++s) md_get(X[i][s], x + (size_t)i * D + s, nD, L);
+  }
+  for (size_t q = 0; q < nD; ++q) md_get(lam[q], lambda + q, nD, Ll);
+#pragma omp parallel num_threads(ora_get_threads())
+  {
+    mpfr_t *val = vnew(D, prec), *tmp = vnew(D, prec);
+    mpfr_t t, one, acc;
+    mpfr_init2(t, prec);
+    mpfr_init2(one, prec);
+    mpfr_init2(acc, prec);
+    mpfr_set_si(one, 1, MPFR_RNDN);
+#pragma omp for schedule(dynamic, 1)
+    for (int i = 0; i < n; ++i)
+      for (int mj = pp[i]; mj < pp[i + 1]; ++mj) {
+        mono_series(val, one, var + mp[mj], ex + mp[mj], mp[mj + 1] - mp[mj], -1, X, D, tmp, t);
+        mpfr_set_zero(acc, 1);
+        for (int s = 0; s < D; ++s) {
+          mpfr_mul(t, lam[(size_t)i * D + s], val[s], MPFR_RNDN);
+          mpfr_add(acc, acc, t, MPFR_RNDN);
+        }
+        mpfr_neg(acc, acc, MPFR_RNDN);
+        exp_put(out + mj, m, K, acc, t);
+      }
+    vfree(val, D);
+    vfree(tmp, D);
+    mpfr_clear(t);
+    mpfr_clear(one);
+    mpfr_clear(acc);
+  }
+  for (int i = 0; i < n; ++i) vfree(X[i], D);
+  free(X);
+  vfree(lam, nD);
+  return ORA_OK;
+}

@@ -20,7 +20,7 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "mdnewton.h")
 
 MD_OK, MD_EINVAL, MD_ESINGULAR, MD_ENONFINITE, MD_EHIP, MD_ENOSPACE = 0, -1, -2, -3, -4, -5
 MD_DD, MD_QD, MD_OD = 2, 4, 8
-OPS = {"add": 0, "sub": 1, "mul": 2, "div": 3, "sqrt": 4, "fma": 5}
+OPS = {"add": 0, "sub": 1, "mul": 2, "div": 3, "sqrt": 4, "fma": 5, "dot": 6}
 STATUS_NAMES = {0: "ok", -2: "singular", -3: "nonfinite"}
 
 if not os.path.exists(LIB_PATH):
@@ -44,6 +44,9 @@ _lib.md_series_solve.argtypes = [_i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, ctyp
 _lib.md_newton_step.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
 _lib.md_arith.argtypes = [_i32, _i32, ctypes.c_int64, _vp, _vp, _vp, _vp]
 _lib.md_last_error.restype = ctypes.c_char_p
+_lib.md_adjoint_workspace_size.argtypes = [_i32, _i32, _i32, _szp]
+_lib.md_adjoint_solve.argtypes = [_i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp, _vp]
+_lib.md_coef_grad.argtypes = [_vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
 _lib.md_timing_enable.argtypes = [_i32]
 _lib.md_timing_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
 
@@ -157,8 +160,10 @@ def qr_workspace_bytes(prec, n):
 
 def qr(prec, n, a0, tau, status, ws=None, stream=None):
     L = int(prec)
+    if ws is None:
+        ws = workspace(qr_workspace_bytes(L, n), a0.device)
     rc = _lib.md_qr(L, int(n), _ptr(a0, (L, n, n), "a0"), _ptr(tau, (L, n), "tau"), _ptr(ws, None, "ws"),
-                    0 if ws is None else ws.numel() * 8, _stream(stream), _ptr(status, (1,), "status"))
+                    ws.numel() * 8, _stream(stream), _ptr(status, (1,), "status"))
     _check(rc, "md_qr")
 
 
@@ -185,13 +190,36 @@ def newton_step(plan: Plan, cff, cst, x, status, norms, ws, stream=None):
 
 
 def arith(prec, op, a, b, c, stream=None):
+    """Elementwise c = a op b on [L, count] md arrays; op "dot" writes sum_q a[q] b[q] to c [L, 1]."""
     L = int(prec)
     opc = OPS[op] if isinstance(op, str) else int(op)
     count = a.shape[1]
     shp = (L, count)
     rc = _lib.md_arith(L, opc, count, _ptr(a, shp, "a"), _ptr(b, shp if opc != 4 else None, "b"),
-                       _ptr(c, shp, "c"), _stream(stream))
+                       _ptr(c, (L, 1) if opc == 6 else shp, "c"), _stream(stream))
     _check(rc, "md_arith")
+
+
+def adjoint_workspace_bytes(prec, n, d):
+    v = ctypes.c_size_t()
+    _check(_lib.md_adjoint_workspace_size(int(prec), int(n), int(d), ctypes.byref(v)), "md_adjoint_workspace_size")
+    return int(v.value)
+
+
+def adjoint_solve(prec, n, d, qr_, tau, A, g_lambda, ws, status, stream=None):
+    """Solve T^T lambda = g in place (g_lambda [L, n, D])."""
+    L, D = int(prec), int(d) + 1
+    rc = _lib.md_adjoint_solve(L, int(n), int(d), _ptr(qr_, (L, n, n), "qr"), _ptr(tau, (L, n), "tau"),
+                               _ptr(A, (L, n, n, D), "A"), _ptr(g_lambda, (L, n, D), "g_lambda"),
+                               _ptr(ws, None, "ws"), ws.numel() * 8, _stream(stream), _ptr(status, (1,), "status"))
+    _check(rc, "md_adjoint_solve")
+
+
+def coef_grad(plan: Plan, x, lam, grad, ws, stream=None):
+    L, n, D, m = plan.prec, plan.n, plan.D, plan.m
+    rc = _lib.md_coef_grad(plan._h, _ptr(x, (L, n, D), "x"), _ptr(lam, (L, n, D), "lambda"),
+                           _ptr(grad, (L, m), "grad"), _ptr(ws, None, "ws"), ws.numel() * 8, _stream(stream))
+    _check(rc, "md_coef_grad")
 
 
 def timing_enable(on=True):
@@ -235,3 +263,97 @@ class Newton:
 
     def status_code(self):
         return int(self.status.item())
+
+
+# ----------------------------------------------------------------- autograd
+#
+# Multiple-double tensors carry a leading limb axis; torch must never add or
+# scale them itself.  The two Functions below are md-aware: their forward and
+# backward run in the library, and the backward of a loss has to be seeded
+# with the md number 1 ([1, 0, ..., 0]), see md_backward.
+
+
+def _torch_fns():
+    import torch
+
+    class NewtonSolve(torch.autograd.Function):
+        """x(cff): `steps` Newton steps from x0 on p(x; cff) = 0; the backward
+        gives dL/dcff by the adjoint (md_adjoint_solve, md_coef_grad)."""
+
+        @staticmethod
+        def forward(ctx, cff, plan, cst, x0, steps):
+            L, n, D = plan.prec, plan.n, plan.D
+            ws = workspace(plan.workspace_bytes(), cff.device)
+            status = torch.zeros(1, dtype=torch.int32, device=cff.device)
+            norms = torch.zeros((2, D), dtype=torch.float64, device=cff.device)
+            x = x0.clone().contiguous()
+            for _ in range(int(steps)):
+                newton_step(plan, cff.contiguous(), cst, x, status, norms, ws)
+            ctx.plan = plan
+            ctx.save_for_backward(cff, cst, x)
+            return x
+
+        @staticmethod
+        def backward(ctx, gx):
+            cff, cst, x = ctx.saved_tensors
+            plan = ctx.plan
+            L, n, d, D = plan.prec, plan.n, plan.d, plan.D
+            dev = cff.device
+            ws = workspace(plan.workspace_bytes(), dev)
+            b = torch.empty((L, n, D), dtype=torch.float64, device=dev)
+            A = torch.empty((L, n, n, D), dtype=torch.float64, device=dev)
+            eval_diff(plan, cff.contiguous(), cst, x, b, A, ws)
+            a0 = A[..., 0].contiguous()
+            tau = torch.zeros((L, n), dtype=torch.float64, device=dev)
+            status = torch.zeros(1, dtype=torch.int32, device=dev)
+            qr(L, n, a0, tau, status)
+            lam = gx.contiguous().clone()
+            adjoint_solve(L, n, d, a0, tau, A, lam, workspace(adjoint_workspace_bytes(L, n, d), dev), status)
+            grad = torch.empty_like(cff)
+            coef_grad(plan, x, lam, grad, ws)
+            return grad, None, None, None, None
+
+    class TopCoefficientLoss(torch.autograd.Function):
+        """L = sum_i sum_{k >= ktop} x_{i,k}^2 as a multiple double [L]."""
+
+        @staticmethod
+        def forward(ctx, x, ktop):
+            L = x.shape[0]
+            sel = x[:, :, ktop:].contiguous().reshape(L, -1)
+            out = torch.empty((L, 1), dtype=torch.float64, device=x.device)
+            arith(L, "dot", sel, sel, out)
+            ctx.ktop = ktop
+            ctx.save_for_backward(x)
+            return out.reshape(L)
+
+        @staticmethod
+        def backward(ctx, gl):
+            (x,) = ctx.saved_tensors
+            L = x.shape[0]
+            g = torch.zeros_like(x)
+            g[:, :, ctx.ktop:] = 2.0 * x[:, :, ctx.ktop:]  # exact: every limb doubled
+            flat = g.reshape(L, -1).contiguous()
+            s = gl.reshape(L, 1).expand(L, flat.shape[1]).contiguous()
+            out = torch.empty_like(flat)
+            arith(L, "mul", flat, s, out)  # times the incoming multiple-double gradient
+            return out.reshape(x.shape), None
+
+    return NewtonSolve, TopCoefficientLoss
+
+
+def newton_solve(cff, plan, cst, x0, steps):
+    """Differentiable Newton solve (see NewtonSolve)."""
+    return _torch_fns()[0].apply(cff, plan, cst, x0, steps)
+
+
+def top_coefficient_loss(x, ktop):
+    return _torch_fns()[1].apply(x, ktop)
+
+
+def md_backward(loss):
+    """loss.backward() seeded with the multiple double 1 = [1, 0, ..., 0]."""
+    import torch
+
+    seed = torch.zeros_like(loss)
+    seed[0] = 1.0
+    loss.backward(seed)

@@ -17,7 +17,11 @@
 struct md_plan {
   int L, n, d, D, m, nnz, maxexp;
   int32_t *d_poly_ptr = nullptr, *d_mon_ptr = nullptr, *d_var = nullptr, *d_exp = nullptr;
-  int32_t *d_order = nullptr, *d_asm_ptr = nullptr, *d_asm_ent = nullptr;
+  int32_t *d_order = nullptr, *d_asm_ptr = nullptr, *d_asm_ent = nullptr, *d_row_of = nullptr;
+  // second stream of the Newton step: QR of A_0 and M run beside the full
+  // evaluation (default priority, non-blocking), with fork and join events
+  hipStream_t aux = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
 };
 
 namespace {
@@ -67,9 +71,17 @@ bool valid_prec(int p) { return p == MD_DD || p == MD_QD || p == MD_OD; }
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Scratch of the QR kernels: flags [n] and the reflector board (v [n][L][n],
+// tau [n][L]) of the LDS-resident kernel, or the barrier counter of the
+// global-memory kernel used when the columns do not fit in LDS.
+size_t qr_scratch_bytes(int L, int n) {
+  return align_up((size_t)n * sizeof(int)) + align_up((size_t)n * L * n * sizeof(double)) +
+         align_up((size_t)n * L * sizeof(double)) + 256;
+}
+
 // Workspace regions, in doubles, each aligned to 256 bytes.
 struct Layout {
-  size_t val, der, pw, b, A, qr, tau, invd, M, N, r, dx, total;
+  size_t val, der, pw, unit, b, A, qr, tau, qt, bar, invd, M, N, At, r, dxT, dx, total;
 };
 
 Layout newton_layout(const md_plan *p) {
@@ -84,14 +96,19 @@ Layout newton_layout(const md_plan *p) {
   w.val = take(L * p->m * D);
   w.der = take(L * p->nnz * D);
   w.pw = take(p->maxexp >= 3 ? L * n * D * (p->maxexp - 2) : 1);
+  w.unit = take(L * p->m + 1);
   w.b = take(L * n * D);
   w.A = take(L * n * n * D);
   w.qr = take(L * n * n);
   w.tau = take(L * n);
+  w.qt = take(L * n * n);
+  w.bar = take(qr_scratch_bytes(L, n) / sizeof(double) + 1);
   w.invd = take(L * n);
   w.M = take(L * n * n);
   w.N = take(L * n * n);
+  w.At = take(L * n * n * D);
   w.r = take(L * n * D);
+  w.dxT = take(L * n * D);
   w.dx = take(L * n * D);
   w.total = off;
   return w;
@@ -99,34 +116,55 @@ Layout newton_layout(const md_plan *p) {
 
 size_t solve_bytes(int L, int n, int D) {
   return align_up((size_t)L * n * sizeof(double)) + 2 * align_up((size_t)L * n * n * sizeof(double)) +
-         align_up((size_t)L * n * D * sizeof(double));
+         align_up((size_t)L * n * n * D * sizeof(double)) + 2 * align_up((size_t)L * n * D * sizeof(double));
 }
 
 double *at(void *ws, size_t byte_off) { return reinterpret_cast<double *>(static_cast<char *>(ws) + byte_off); }
 
+
+hipError_t run_qr(int L, int n, double *a, double *tau, double *qt, int32_t *status, void *scratch, hipStream_t st) {
+  char *p = static_cast<char *>(scratch);
+  int *flags = reinterpret_cast<int *>(p);
+  p += align_up((size_t)n * sizeof(int));
+  double *vboard = reinterpret_cast<double *>(p);
+  p += align_up((size_t)n * L * n * sizeof(double));
+  double *tboard = reinterpret_cast<double *>(p);
+  p += align_up((size_t)n * L * sizeof(double));
+  unsigned *bar = reinterpret_cast<unsigned *>(p);
+  if (mdk::qr_lds_workgroups(L, n, qt != nullptr) > 0)
+    return mdk::launch_qr_lds(L, n, a, tau, qt, status, flags, vboard, tboard, st);
+  return mdk::launch_qr(L, n, a, tau, qt, status, bar, st);
+}
+
 int series_solve_impl(int L, int n, int D, const double *qr, const double *tau, const double *A, double *rhs_dx,
                       void *ws, hipStream_t st, int32_t *status) {
   size_t off = 0;
-  double *invd = at(ws, off);
-  off += align_up((size_t)L * n * sizeof(double));
-  double *M = at(ws, off);
-  off += align_up((size_t)L * n * n * sizeof(double));
-  double *N = at(ws, off);
-  off += align_up((size_t)L * n * n * sizeof(double));
-  double *r = at(ws, off);
+  auto take = [&](size_t doubles) {
+    double *p = at(ws, off);
+    off += align_up(doubles * sizeof(double));
+    return p;
+  };
+  const size_t nn = (size_t)n * n, nD = (size_t)n * D;
+  double *invd = take((size_t)L * n), *M = take((size_t)L * nn), *N = take((size_t)L * nn);
+  double *At = take((size_t)L * nn * D), *rT = take((size_t)L * nD), *dxT = take((size_t)L * nD);
   hipError_t e;
   {
     Timed t(MD_CLASS_QHB_BS, st);
     if ((e = mdk::launch_form_m(L, n, qr, tau, invd, M, status, st)) != hipSuccess) return hip_fail(e, "form M");
   }
+  {
+    Timed t(MD_CLASS_UPDATES, st);
+    if ((e = mdk::launch_transpose(L, A, At, nn, D, nn * D, nn * D, st)) != hipSuccess) return hip_fail(e, "A^T");
+    if ((e = mdk::launch_transpose(L, rhs_dx, rT, n, D, nD, nD, st)) != hipSuccess) return hip_fail(e, "b^T");
+  }
   if (D > 1) {
     Timed t(MD_CLASS_GEMM, st);
-    if ((e = mdk::launch_gemm_series(L, n, D, 1, M, A, N, st)) != hipSuccess) return hip_fail(e, "gemm");
+    if ((e = mdk::launch_gemm(L, n, M, At + nn, nn * D, N, st)) != hipSuccess) return hip_fail(e, "gemm");
   }
   {
     Timed t(MD_CLASS_UPDATES, st);
-    if ((e = mdk::launch_copy(rhs_dx, r, (size_t)L * n * D, st)) != hipSuccess) return hip_fail(e, "copy");
-    if ((e = mdk::launch_stages(L, n, D, M, N, A, r, rhs_dx, st)) != hipSuccess) return hip_fail(e, "stages");
+    if ((e = mdk::launch_stages(L, n, D, M, N, At, rT, dxT, st)) != hipSuccess) return hip_fail(e, "stages");
+    if ((e = mdk::launch_transpose(L, dxT, rhs_dx, D, n, nD, nD, st)) != hipSuccess) return hip_fail(e, "dx");
   }
   return MD_OK;
 }
@@ -219,9 +257,13 @@ int md_plan_create(int prec, int n, int d, int m, const int32_t *poly_ptr, const
       (e = up(&p->d_var, var, nnz)) != hipSuccess || (e = up(&p->d_exp, exp, nnz)) != hipSuccess ||
       (e = up(&p->d_order, order.data(), m)) != hipSuccess ||
       (e = up(&p->d_asm_ptr, asm_ptr.data(), nn + 1)) != hipSuccess ||
-      (e = up(&p->d_asm_ent, asm_ent.data(), nnz)) != hipSuccess) {
+      (e = up(&p->d_asm_ent, asm_ent.data(), nnz)) != hipSuccess ||
+      (e = up(&p->d_row_of, row_of.data(), m)) != hipSuccess ||
+      (e = hipStreamCreateWithFlags(&p->aux, hipStreamNonBlocking)) != hipSuccess ||
+      (e = hipEventCreateWithFlags(&p->fork, hipEventDisableTiming)) != hipSuccess ||
+      (e = hipEventCreateWithFlags(&p->join, hipEventDisableTiming)) != hipSuccess) {
     md_plan_destroy(p);
-    return hip_fail(e, "plan upload");
+    return hip_fail(e, "plan setup");
   }
   *out = p;
   return MD_OK;
@@ -229,8 +271,12 @@ int md_plan_create(int prec, int n, int d, int m, const int32_t *poly_ptr, const
 
 int md_plan_destroy(md_plan *p) {
   if (!p) return MD_OK;
-  for (int32_t *q : {p->d_poly_ptr, p->d_mon_ptr, p->d_var, p->d_exp, p->d_order, p->d_asm_ptr, p->d_asm_ent})
+  for (int32_t *q : {p->d_poly_ptr, p->d_mon_ptr, p->d_var, p->d_exp, p->d_order, p->d_asm_ptr, p->d_asm_ent,
+                     p->d_row_of})
     if (q) (void)hipFree(q);
+  if (p->fork) (void)hipEventDestroy(p->fork);
+  if (p->join) (void)hipEventDestroy(p->join);
+  if (p->aux) (void)hipStreamDestroy(p->aux);
   delete p;
   return MD_OK;
 }
@@ -241,12 +287,11 @@ int md_workspace_size(const md_plan *p, size_t *bytes) {
   return MD_OK;
 }
 
-static int eval_diff_impl(const md_plan *p, const double *cff, const double *cst, const double *x, double *b,
-                          double *A, void *ws, hipStream_t st) {
+static void eval_args(const md_plan *p, const double *cff, const double *x, void *ws, int Dc, mdk::EvalArgs &a) {
   Layout w = newton_layout(p);
-  mdk::EvalArgs a;
   a.n = p->n;
   a.D = p->D;
+  a.Dc = Dc;
   a.m = p->m;
   a.nnz = p->nnz;
   a.mon_ptr = p->d_mon_ptr;
@@ -258,6 +303,13 @@ static int eval_diff_impl(const md_plan *p, const double *cff, const double *cst
   a.pw = at(ws, w.pw);
   a.val = at(ws, w.val);
   a.der = at(ws, w.der);
+}
+
+static int eval_diff_impl(const md_plan *p, const double *cff, const double *cst, const double *x, double *b,
+                          double *A, void *ws, hipStream_t st) {
+  Layout w = newton_layout(p);
+  mdk::EvalArgs a;
+  eval_args(p, cff, x, ws, p->D, a);
   hipError_t e;
   {
     Timed t(MD_CLASS_CONVOLUTIONS, st);
@@ -282,16 +334,15 @@ int md_eval_diff(const md_plan *p, const double *cff, const double *cst, const d
 
 int md_qr_workspace_size(int prec, int n, size_t *bytes) {
   if (!bytes || !valid_prec(prec) || n < 1 || n > MD_MAX_DIM) return fail(MD_EINVAL, "bad argument");
-  *bytes = 0;
+  *bytes = qr_scratch_bytes(prec, n);
   return MD_OK;
 }
 
 int md_qr(int prec, int n, double *a0, double *tau, void *ws, size_t ws_bytes, hipStream_t st, int32_t *dev_status) {
-  (void)ws;
-  (void)ws_bytes;
   if (!valid_prec(prec) || n < 1 || n > MD_MAX_DIM) return fail(MD_EINVAL, "bad precision or dimension");
   if (!a0 || !tau) return fail(MD_EINVAL, "NULL argument");
-  hipError_t e = mdk::launch_qr(prec, n, a0, tau, dev_status, st);
+  if (!ws || ws_bytes < qr_scratch_bytes(prec, n)) return fail(MD_ENOSPACE, "workspace too small");
+  hipError_t e = run_qr(prec, n, a0, tau, nullptr, dev_status, ws, st);
   return e == hipSuccess ? MD_OK : hip_fail(e, "qr launch");
 }
 
@@ -319,23 +370,112 @@ int md_newton_step(const md_plan *p, const double *cff, const double *cst, doubl
   const int L = p->L, n = p->n, D = p->D;
   hipError_t e;
   if ((e = mdk::launch_status_init(dev_status, st)) != hipSuccess) return hip_fail(e, "status");
-  double *b = at(ws, w.b), *A = at(ws, w.A), *qr = at(ws, w.qr), *tau = at(ws, w.tau), *dx = at(ws, w.dx);
-  int rc = eval_diff_impl(p, cff, cst, x, b, A, ws, st);
-  if (rc != MD_OK) return rc;
+  double *b = at(ws, w.b), *A = at(ws, w.A), *qr = at(ws, w.qr), *tau = at(ws, w.tau), *qt = at(ws, w.qt);
+  double *invd = at(ws, w.invd), *M = at(ws, w.M), *N = at(ws, w.N), *r = at(ws, w.r), *dx = at(ws, w.dx);
+  mdk::EvalArgs a;
+  // 1. pre-pass: coefficient 0 of every product gives A_0, bit for bit the
+  //    coefficient 0 of the full evaluation (same kernel, same operations)
   {
     Timed t(MD_CLASS_QR, st);
-    if ((e = mdk::launch_extract(L, n, D, 0, A, qr, st)) != hipSuccess) return hip_fail(e, "extract A0");
-    if ((e = mdk::launch_qr(L, n, qr, tau, dev_status, st)) != hipSuccess) return hip_fail(e, "qr");
+    eval_args(p, cff, x, ws, 1, a);
+    if ((e = mdk::launch_evaldiff(L, a, p->maxexp, at(ws, w.pw), st)) != hipSuccess)
+      return hip_fail(e, "A_0 pre-pass");
+    if ((e = mdk::launch_assemble_A0(L, n, D, p->nnz, p->d_asm_ptr, p->d_asm_ent, a.der, qr, st)) != hipSuccess)
+      return hip_fail(e, "A_0 assembly");
   }
-  if ((e = mdk::launch_copy(b, dx, (size_t)L * n * D, st)) != hipSuccess) return hip_fail(e, "copy");
-  // the solve's workspace: invd, M, N, r live contiguously from w.invd
-  rc = series_solve_impl(L, n, D, qr, tau, A, dx, at(ws, w.invd), st, dev_status);
+  // 2. fork: QR of A_0 with Q^T, then M = R^{-1} Q^T, on the second stream
+  if ((e = hipEventRecord(p->fork, st)) != hipSuccess) return hip_fail(e, "fork");
+  if ((e = hipStreamWaitEvent(p->aux, p->fork, 0)) != hipSuccess) return hip_fail(e, "fork wait");
+  {
+    Timed t(MD_CLASS_QR, p->aux);
+    if ((e = run_qr(L, n, qr, tau, qt, dev_status, at(ws, w.bar), p->aux)) != hipSuccess) return hip_fail(e, "qr");
+  }
+  {
+    Timed t(MD_CLASS_QHB_BS, p->aux);
+    if ((e = mdk::launch_m_from_qt(L, n, qr, qt, invd, M, dev_status, p->aux)) != hipSuccess)
+      return hip_fail(e, "M");
+  }
+  if ((e = hipEventRecord(p->join, p->aux)) != hipSuccess) return hip_fail(e, "join");
+  // 3. the full evaluation and differentiation on the caller's stream
+  int rc = eval_diff_impl(p, cff, cst, x, b, A, ws, st);
   if (rc != MD_OK) return rc;
+  const size_t nn = (size_t)n * n, nD = (size_t)n * D;
+  double *At = at(ws, w.At), *dxT = at(ws, w.dxT);
+  {
+    Timed t(MD_CLASS_UPDATES, st);
+    if ((e = mdk::launch_transpose(L, A, At, nn, D, nn * D, nn * D, st)) != hipSuccess) return hip_fail(e, "A^T");
+    if ((e = mdk::launch_transpose(L, b, r, n, D, nD, nD, st)) != hipSuccess) return hip_fail(e, "b^T");
+  }
+  // 4. join, N = M A_1, the staged solve
+  if ((e = hipStreamWaitEvent(st, p->join, 0)) != hipSuccess) return hip_fail(e, "join wait");
+  if (D > 1) {
+    Timed t(MD_CLASS_GEMM, st);
+    if ((e = mdk::launch_gemm(L, n, M, At + nn, nn * D, N, st)) != hipSuccess) return hip_fail(e, "gemm");
+  }
+  {
+    Timed t(MD_CLASS_UPDATES, st);
+    if ((e = mdk::launch_stages(L, n, D, M, N, At, r, dxT, st)) != hipSuccess) return hip_fail(e, "stages");
+    if ((e = mdk::launch_transpose(L, dxT, dx, D, n, nD, nD, st)) != hipSuccess) return hip_fail(e, "dx");
+  }
   {
     Timed t(MD_CLASS_X_UPDATE, st);
     if ((e = mdk::launch_update(L, n, D, b, dx, x, dev_norms, dev_status, st)) != hipSuccess)
       return hip_fail(e, "update");
   }
+  return MD_OK;
+}
+
+int md_adjoint_workspace_size(int prec, int n, int d, size_t *bytes) {
+  if (!bytes || !valid_prec(prec) || n < 1 || n > MD_MAX_DIM || d < 0 || d + 1 > MD_MAX_COEFFS)
+    return fail(MD_EINVAL, "bad argument");
+  const size_t L = prec, nn = (size_t)n * n, nD = (size_t)n * (d + 1);
+  *bytes = align_up(L * n * 8) + 3 * align_up(L * nn * 8) + 2 * align_up(L * nn * (d + 1) * 8) + 2 * align_up(L * nD * 8);
+  return MD_OK;
+}
+
+int md_adjoint_solve(int prec, int n, int d, const double *qr, const double *tau, const double *A, double *g_lambda,
+                     void *ws, size_t ws_bytes, hipStream_t st, int32_t *dev_status) {
+  size_t need = 0;
+  if (md_adjoint_workspace_size(prec, n, d, &need) != MD_OK) return MD_EINVAL;
+  if (!qr || !tau || !g_lambda || (d > 0 && !A)) return fail(MD_EINVAL, "NULL argument");
+  if (!ws || ws_bytes < need) return fail(MD_ENOSPACE, "workspace too small");
+  const int L = prec, D = d + 1;
+  const size_t nn = (size_t)n * n, nD = (size_t)n * D;
+  size_t off = 0;
+  auto take = [&](size_t doubles) {
+    double *p = at(ws, off);
+    off += align_up(doubles * sizeof(double));
+    return p;
+  };
+  double *invd = take((size_t)L * n), *M = take((size_t)L * nn), *Mt = take((size_t)L * nn), *Nt = take((size_t)L * nn);
+  double *At = take((size_t)L * nn * D), *AtT = take((size_t)L * nn * D), *rho = take((size_t)L * nD),
+         *lamT = take((size_t)L * nD);
+  hipError_t e;
+  if ((e = mdk::launch_form_m(L, n, qr, tau, invd, M, dev_status, st)) != hipSuccess) return hip_fail(e, "form M");
+  if ((e = mdk::launch_transpose(L, M, Mt, n, n, nn, nn, st)) != hipSuccess) return hip_fail(e, "M^T");
+  if ((e = mdk::launch_transpose(L, A, At, nn, D, nn * D, nn * D, st)) != hipSuccess) return hip_fail(e, "A^T");
+  if ((e = mdk::launch_transpose(L * D, At, AtT, n, n, nn, nn, st)) != hipSuccess) return hip_fail(e, "A_k^T");
+  if (D > 1 && (e = mdk::launch_gemm(L, n, Mt, AtT + nn, nn * D, Nt, st)) != hipSuccess) return hip_fail(e, "gemm");
+  if ((e = mdk::launch_series_to_rev(L, n, D, g_lambda, rho, st)) != hipSuccess) return hip_fail(e, "reverse");
+  if ((e = mdk::launch_stages(L, n, D, Mt, Nt, AtT, rho, lamT, st)) != hipSuccess) return hip_fail(e, "stages");
+  if ((e = mdk::launch_rev_to_series(L, n, D, lamT, g_lambda, st)) != hipSuccess) return hip_fail(e, "reverse");
+  return MD_OK;
+}
+
+int md_coef_grad(const md_plan *p, const double *x, const double *lambda, double *grad_cff, void *ws, size_t ws_bytes,
+                 hipStream_t st) {
+  if (!p || !x || !lambda || (p->m > 0 && !grad_cff)) return fail(MD_EINVAL, "NULL argument");
+  Layout w = newton_layout(p);
+  if (!ws || ws_bytes < w.total) return fail(MD_ENOSPACE, "workspace too small");
+  if (p->m == 0) return MD_OK;
+  hipError_t e;
+  double *unit = at(ws, w.unit);
+  if ((e = mdk::launch_unit_md(p->L, p->m, unit, st)) != hipSuccess) return hip_fail(e, "unit");
+  mdk::EvalArgs a;
+  eval_args(p, unit, x, ws, p->D, a);
+  if ((e = mdk::launch_evaldiff(p->L, a, p->maxexp, at(ws, w.pw), st)) != hipSuccess) return hip_fail(e, "values");
+  if ((e = mdk::launch_coef_grad(p->L, p->n, p->D, p->m, p->d_row_of, lambda, a.val, grad_cff, st)) != hipSuccess)
+    return hip_fail(e, "coef grad");
   return MD_OK;
 }
 
@@ -368,11 +508,11 @@ int md_timing_read(double *ms, int64_t *launches) {
 }
 
 int md_arith(int prec, int op, int64_t count, const double *a, const double *b, double *c, hipStream_t st) {
-  if (!valid_prec(prec) || op < 0 || op > 5 || count < 0) return fail(MD_EINVAL, "bad precision, op or count");
-  if (count == 0) return MD_OK;
+  if (!valid_prec(prec) || op < 0 || op > 6 || count < 0) return fail(MD_EINVAL, "bad precision, op or count");
+  if (count == 0 && op != 6) return MD_OK;
   if (!a || !c || (op != 4 && !b)) return fail(MD_EINVAL, "NULL argument");
   if (count > ((int64_t)1 << 31) * 256) return fail(MD_EINVAL, "count too large");
-  hipError_t e = mdk::launch_arith(prec, op, count, a, b, c, st);
+  hipError_t e = (op == 6) ? mdk::launch_dot(prec, count, a, b, c, st) : mdk::launch_arith(prec, op, count, a, b, c, st);
   return e == hipSuccess ? MD_OK : hip_fail(e, "arith launch");
 }
 

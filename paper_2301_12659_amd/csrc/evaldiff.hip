@@ -3,13 +3,17 @@
 // products; Section 6: operands staged through shared memory into registers),
 // and the assembly of b(t) = -p(x(t)) and of the Jacobian series A(t).
 //
-// Work decomposition.  A "worker" is a group of G lanes of one wavefront
-// (G = the smallest power of two >= ceil(D/2)); it evaluates and
-// differentiates one whole monomial, product after product, with three series
-// buffers in LDS.  A truncated product c_s = sum_{i<=s} a_i b_{s-i} gives lane l
-// the outputs l and D-1-l, so every lane does exactly D+1 multiply-adds: the
-// triangular work is balanced without the zero padding of the paper's
-// kernels (which pad to D^2 multiplications, Section 5.1).
+// Work decomposition.  A "worker" is a group of G lanes of one wavefront; it
+// evaluates and differentiates one whole monomial, product after product,
+// with three series buffers in LDS.  In a truncated product
+// c_s = sum_{i<=s} a_i b_{s-i} the outputs are paired, s and D-1-s, so every
+// pair has exactly D+1 multiply-adds: the triangular work is balanced without
+// the zero padding of the paper's kernels (which pad to D^2 multiplications,
+// Section 5.1).  Each pair is split over S = 2 lanes (S = 1 when D > 64) that
+// take the first and second half of its D+1 terms; the halves of the second
+// output are added at the end.  G = S * (smallest power of two >= ceil(D/2)).
+// Each lane accumulates its terms as multiple-double level sums and
+// renormalizes once per output.
 //
 // Per monomial c * prod_j x_{v_j}^{a_j} with support v_1 < ... < v_k:
 //   common factor   CF = prod_{a_j >= 2} x_{v_j}^{a_j - 1}   (the paper's systems
@@ -26,70 +30,93 @@
 
 namespace mdk {
 
-static __host__ __device__ inline int worker_lanes(int D) {
+// Lanes per output pair (S) and per half (G2) of a worker for D coefficients.
+static __host__ __device__ inline int pair_lanes(int D) {
   int h = (D + 1) / 2, g = 1;
   while (g < h) g <<= 1;
   return g;
 }
+static __host__ __device__ inline int split_factor(int D) { return 2 * pair_lanes(D) <= 64 ? 2 : 1; }
+static __host__ __device__ inline int worker_lanes(int D) { return split_factor(D) * pair_lanes(D); }
 
-// Truncated product W = U * V (all in LDS, layout [L][D]) scaled by an integer.
+// LDS series layout: [L][D + 1]; entry D of every limb is zero and is what
+// masked terms read.
+
+// Truncated product W = scale * (U * V) (all in LDS).
 template <int L>
 __device__ void conv(const double *U, const double *V, double *W, int D, int lane, int scale) {
-  const int o1 = lane, o2 = D - 1 - lane;
-  const bool act = lane < (D + 1) / 2;
+  const int Dp = D + 1, G2 = pair_lanes(D), S = split_factor(D);
+  const int h = lane / G2, p = lane - h * G2;
+  const bool act = p < (D + 1) / 2;
+  const int o1 = p, o2 = D - 1 - p;
+  const int H = (D + S) / S;  // terms per half: ceil((D + 1) / S)
+  const int t0 = h * H;
   double acc[L];
   md::zero<L>(acc);
-  for (int t = 0; t <= D; ++t) {
+  for (int tt = 0; tt < H; ++tt) {
+    const int t = t0 + tt;
     const bool ph1 = t <= o1;
     int i = ph1 ? t : t - o1 - 1;
     int j = (ph1 ? o1 : o2) - i;
-    if (!act) {
-      i = 0;
+    if (!act || t > D) {  // reads the zero padding
+      i = D;
       j = 0;
     }
     double u[L], v[L];
 #pragma unroll
     for (int l = 0; l < L; ++l) {
-      u[l] = U[l * D + i];
-      v[l] = V[l * D + j];
+      u[l] = U[l * Dp + i];
+      v[l] = V[l * Dp + j];
     }
-    MD<L>::fma(acc, u, v);
-    if (t == o1) {
+    MD<L>::fma_lazy(acc, u, v);
+    if (t == o1) {  // first output complete (always in the first half)
       if (act) {
-        md::mul_int<L>(acc, scale);
+        double r[L];
+        MD<L>::renorm(acc, r);
+        md::mul_int<L>(r, scale);
 #pragma unroll
-        for (int l = 0; l < L; ++l) W[l * D + o1] = acc[l];
+        for (int l = 0; l < L; ++l) W[l * Dp + o1] = r[l];
       }
       md::zero<L>(acc);
     }
   }
-  if (act && o2 > o1) {
-    md::mul_int<L>(acc, scale);
+  double r[L];
+  MD<L>::renorm(acc, r);
+  if (S == 2) {  // add the second half's part of the second output
+    double o[L], s[L];
 #pragma unroll
-    for (int l = 0; l < L; ++l) W[l * D + o2] = acc[l];
+    for (int l = 0; l < L; ++l) o[l] = __shfl_xor(r[l], G2, 64);
+    MD<L>::add(r, o, s);
+    md::copy<L>(s, r);
+  }
+  if (h == 0 && act && o2 > o1) {
+    md::mul_int<L>(r, scale);
+#pragma unroll
+    for (int l = 0; l < L; ++l) W[l * Dp + o2] = r[l];
   }
 }
 
 // W = scale * c * V for a scalar c (registers) and a series V.
 template <int L>
 __device__ void scal(const double (&c)[L], const double *V, double *W, int D, int lane, int G, int scale) {
+  const int Dp = D + 1;
   for (int s = lane; s < D; s += G) {
     double v[L], r[L];
 #pragma unroll
-    for (int l = 0; l < L; ++l) v[l] = V[l * D + s];
+    for (int l = 0; l < L; ++l) v[l] = V[l * Dp + s];
     MD<L>::mul(c, v, r);
     md::mul_int<L>(r, scale);
 #pragma unroll
-    for (int l = 0; l < L; ++l) W[l * D + s] = r[l];
+    for (int l = 0; l < L; ++l) W[l * Dp + s] = r[l];
   }
 }
 
-// LDS <- global series (limb stride gstride, element offset off).
+// LDS <- global series (limb stride gstride, element offset off), D entries.
 __device__ __forceinline__ void load_series(double *S, const double *g, size_t gstride, size_t off, int L, int D,
                                             int lane, int G) {
   for (int q = lane; q < L * D; q += G) {
     const int l = q / D, s = q - l * D;
-    S[q] = g[(size_t)l * gstride + off + s];
+    S[l * (D + 1) + s] = g[(size_t)l * gstride + off + s];
   }
 }
 
@@ -97,23 +124,29 @@ __device__ __forceinline__ void store_series(double *g, size_t gstride, size_t o
                                              int lane, int G) {
   for (int q = lane; q < L * D; q += G) {
     const int l = q / D, s = q - l * D;
-    g[(size_t)l * gstride + off + s] = S[q];
+    g[(size_t)l * gstride + off + s] = S[l * (D + 1) + s];
   }
 }
 
-
+// Zero the padding entries of a worker's three buffers.
+__device__ __forceinline__ void zero_pads(double *buf0, int L, int D, int lane, int G) {
+  for (int q = lane; q < 3 * L; q += G) buf0[q * (D + 1) + D] = 0.0;
+}
 
 template <int L>
-__global__ void __launch_bounds__(256) evaldiff_kernel(EvalArgs a) {
+__global__ void __launch_bounds__(256, (L == 8) ? 1 : 2) evaldiff_kernel(EvalArgs a) {
   extern __shared__ double lds[];
-  const int D = a.D;
-  const int G = worker_lanes(D);
+  const int D = a.D;    // coefficients stored per series (global stride)
+  const int Dc = a.Dc;  // coefficients computed: D, or 1 for the A_0 pre-pass
+  const int G = worker_lanes(Dc);
   const int wpb = blockDim.x / G;  // workers per block
   const int wid = threadIdx.x / G, lane = threadIdx.x - wid * G;
   const int widx = blockIdx.x * wpb + wid;
   if (widx >= a.m) return;  // whole worker exits together
-  double *buf[3] = {lds + (size_t)wid * 3 * L * D, lds + (size_t)wid * 3 * L * D + L * D,
-                    lds + (size_t)wid * 3 * L * D + 2 * L * D};
+  const int Dp = Dc + 1;
+  double *buf[3] = {lds + (size_t)wid * 3 * L * Dp, lds + (size_t)wid * 3 * L * Dp + L * Dp,
+                    lds + (size_t)wid * 3 * L * Dp + 2 * L * Dp};
+  zero_pads(buf[0], L, Dc, lane, G);
   const int mono = a.order[widx];
   const int e0 = a.mon_ptr[mono], k = a.mon_ptr[mono + 1] - e0;
   const size_t nD = (size_t)a.n * D, mD = (size_t)a.m * D, zD = (size_t)a.nnz * D;
@@ -121,7 +154,7 @@ __global__ void __launch_bounds__(256) evaldiff_kernel(EvalArgs a) {
   ld<L>(a.cff, a.m, mono, c);
 
   if (k == 0) {  // constant monomial
-    for (int s = lane; s < D; s += G) {
+    for (int s = lane; s < Dc; s += G) {
 #pragma unroll
       for (int l = 0; l < L; ++l) a.val[(size_t)l * mD + (size_t)mono * D + s] = (s == 0) ? c[l] : 0.0;
     }
@@ -133,15 +166,15 @@ __global__ void __launch_bounds__(256) evaldiff_kernel(EvalArgs a) {
   // ---- backward chain: b_q for q = 2..k-1 parked in the slot of entry k-q (0-based k-q-1+... )
   if (k >= 3) {
     double *B = buf[0], *X = buf[1], *Wb = buf[2];
-    load_series(B, a.x, nD, xoff(a.var[e0 + k - 1]), L, D, lane, G);  // b_1 = x_{v_k}
+    load_series(B, a.x, nD, xoff(a.var[e0 + k - 1]), L, Dc, lane, G);  // b_1 = x_{v_k}
     for (int q = 2; q <= k - 1; ++q) {
-      load_series(X, a.x, nD, xoff(a.var[e0 + k - q]), L, D, lane, G);  // x_{v_{k-q+1}}
+      load_series(X, a.x, nD, xoff(a.var[e0 + k - q]), L, Dc, lane, G);  // x_{v_{k-q+1}}
       wave_sync();
-      conv<L>(B, X, Wb, D, lane, 1);
+      conv<L>(B, X, Wb, Dc, lane, 1);
       wave_sync();
       // b_q is consumed by the cross product of forward step j = k - q (1-based),
       // i.e. entry k - q - 1 (0-based)
-      store_series(a.der, zD, der_off(k - q - 1), Wb, L, D, lane, G);
+      store_series(a.der, zD, der_off(k - q - 1), Wb, L, Dc, lane, G);
       double *t = B;
       B = Wb;
       Wb = t;
@@ -158,13 +191,13 @@ __global__ void __launch_bounds__(256) evaldiff_kernel(EvalArgs a) {
     const int v = a.var[e0 + j];
     const double *src = (p == 1) ? a.x : a.pw + (size_t)(p - 2) * L * nD;
     if (f0_scalar) {
-      load_series(U, src, nD, xoff(v), L, D, lane, G);
+      load_series(U, src, nD, xoff(v), L, Dc, lane, G);
       f0_scalar = false;
       wave_sync();
     } else {
-      load_series(V, src, nD, xoff(v), L, D, lane, G);
+      load_series(V, src, nD, xoff(v), L, Dc, lane, G);
       wave_sync();
-      conv<L>(U, V, W, D, lane, 1);
+      conv<L>(U, V, W, Dc, lane, 1);
       wave_sync();
       double *t = U;
       U = W;
@@ -172,7 +205,7 @@ __global__ void __launch_bounds__(256) evaldiff_kernel(EvalArgs a) {
     }
   }
   if (!f0_scalar) {  // f_0 = c * CF in place
-    scal<L>(c, U, U, D, lane, G, 1);
+    scal<L>(c, U, U, Dc, lane, G, 1);
     wave_sync();
   }
 
@@ -182,19 +215,19 @@ __global__ void __launch_bounds__(256) evaldiff_kernel(EvalArgs a) {
     const int aj = a.exp[e0 + ej];
     if (j < k) {
       if (k - j == 1)
-        load_series(V, a.x, nD, xoff(a.var[e0 + k - 1]), L, D, lane, G);  // b_1 = x_{v_k}
+        load_series(V, a.x, nD, xoff(a.var[e0 + k - 1]), L, Dc, lane, G);  // b_1 = x_{v_k}
       else
-        load_series(V, a.der, zD, der_off(ej), L, D, lane, G);  // b_{k-j}
+        load_series(V, a.der, zD, der_off(ej), L, Dc, lane, G);  // b_{k-j}
       wave_sync();
       if (f0_scalar && j == 1)
-        scal<L>(c, V, W, D, lane, G, aj);
+        scal<L>(c, V, W, Dc, lane, G, aj);
       else
-        conv<L>(U, V, W, D, lane, aj);
+        conv<L>(U, V, W, Dc, lane, aj);
       wave_sync();
-      store_series(a.der, zD, der_off(ej), W, L, D, lane, G);
+      store_series(a.der, zD, der_off(ej), W, L, Dc, lane, G);
     } else {  // d/dx_{v_k} = a_k f_{k-1}
       if (f0_scalar && j == 1) {
-        for (int s = lane; s < D; s += G) {
+        for (int s = lane; s < Dc; s += G) {
           double r[L];
 #pragma unroll
           for (int l = 0; l < L; ++l) r[l] = (s == 0) ? c[l] : 0.0;
@@ -203,10 +236,10 @@ __global__ void __launch_bounds__(256) evaldiff_kernel(EvalArgs a) {
           for (int l = 0; l < L; ++l) a.der[(size_t)l * zD + der_off(ej) + s] = r[l];
         }
       } else {
-        for (int s = lane; s < D; s += G) {
+        for (int s = lane; s < Dc; s += G) {
           double r[L];
 #pragma unroll
-          for (int l = 0; l < L; ++l) r[l] = U[l * D + s];
+          for (int l = 0; l < L; ++l) r[l] = U[l * Dp + s];
           md::mul_int<L>(r, aj);
 #pragma unroll
           for (int l = 0; l < L; ++l) a.der[(size_t)l * zD + der_off(ej) + s] = r[l];
@@ -215,38 +248,39 @@ __global__ void __launch_bounds__(256) evaldiff_kernel(EvalArgs a) {
     }
     wave_sync();
     // f_j = f_{j-1} * x_{v_j}
-    load_series(V, a.x, nD, xoff(a.var[e0 + ej]), L, D, lane, G);
+    load_series(V, a.x, nD, xoff(a.var[e0 + ej]), L, Dc, lane, G);
     wave_sync();
     if (f0_scalar && j == 1)
-      scal<L>(c, V, W, D, lane, G, 1);
+      scal<L>(c, V, W, Dc, lane, G, 1);
     else
-      conv<L>(U, V, W, D, lane, 1);
+      conv<L>(U, V, W, Dc, lane, 1);
     wave_sync();
     double *t = U;
     U = W;
     W = t;
   }
-  store_series(a.val, mD, (size_t)mono * D, U, L, D, lane, G);
+  store_series(a.val, mD, (size_t)mono * D, U, L, Dc, lane, G);
 }
 
 // Powers x_v^p, p = 2..maxexp-1, for the common factors of exponents >= 3.
 template <int L>
-__global__ void __launch_bounds__(256) power_kernel(int n, int D, int maxp, const double *x, double *pw) {
+__global__ void __launch_bounds__(256, (L == 8) ? 1 : 2) power_kernel(int n, int D, int Dc, int maxp, const double *x, double *pw) {
   extern __shared__ double lds[];
-  const int G = worker_lanes(D);
+  const int G = worker_lanes(Dc);
   const int wpb = blockDim.x / G;
   const int wid = threadIdx.x / G, lane = threadIdx.x - wid * G;
   const int v = blockIdx.x * wpb + wid;
   if (v >= n) return;
-  double *U = lds + (size_t)wid * 3 * L * D, *X = U + L * D, *W = X + L * D;
+  double *U = lds + (size_t)wid * 3 * L * (Dc + 1), *X = U + L * (Dc + 1), *W = X + L * (Dc + 1);
+  zero_pads(U, L, Dc, lane, G);
   const size_t nD = (size_t)n * D;
-  load_series(X, x, nD, (size_t)v * D, L, D, lane, G);
-  load_series(U, x, nD, (size_t)v * D, L, D, lane, G);
+  load_series(X, x, nD, (size_t)v * D, L, Dc, lane, G);
+  load_series(U, x, nD, (size_t)v * D, L, Dc, lane, G);
   wave_sync();
   for (int p = 2; p <= maxp; ++p) {
-    conv<L>(U, X, W, D, lane, 1);
+    conv<L>(U, X, W, Dc, lane, 1);
     wave_sync();
-    store_series(pw + (size_t)(p - 2) * L * nD, nD, (size_t)v * D, W, L, D, lane, G);
+    store_series(pw + (size_t)(p - 2) * L * nD, nD, (size_t)v * D, W, L, Dc, lane, G);
     double *t = U;
     U = W;
     W = t;
@@ -299,22 +333,47 @@ __global__ void assemble_A_kernel(int n, int D, int nnz, const int32_t *asm_ptr,
   st<L>(A, nnD, q, acc);
 }
 
+// Coefficient 0 of A into a dense row-major matrix a0 [L][n][n], summed in
+// the same order as assemble_A_kernel, so it equals A[i][j][0] bit for bit.
+template <int L>
+__global__ void assemble_A0_kernel(int n, int D, int nnz, const int32_t *asm_ptr, const int32_t *asm_ent,
+                                   const double *der, double *a0) {
+  const size_t ij = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t nn = (size_t)n * n, zD = (size_t)nnz * D;
+  if (ij >= nn) return;
+  const int lo = asm_ptr[ij], hi = asm_ptr[ij + 1];
+  double acc[L];
+  md::zero<L>(acc);
+  if (lo < hi) {
+    ld<L>(der, zD, (size_t)asm_ent[lo] * D, acc);
+    for (int t = lo + 1; t < hi; ++t) {
+      double v[L], r[L];
+      ld<L>(der, zD, (size_t)asm_ent[t] * D, v);
+      MD<L>::add(acc, v, r);
+      md::copy<L>(r, acc);
+    }
+  }
+  st<L>(a0, nn, ij, acc);
+}
+
 // ------------------------------------------------------------------ launchers
 
 template <int L>
 hipError_t launch_evaldiff_T(const EvalArgs &a, int maxexp, double *pw_mut, hipStream_t st) {
-  const int G = worker_lanes(a.D);
+  const int G = worker_lanes(a.Dc);
   const int wpb = 256 / G;
-  const size_t lds = (size_t)wpb * 3 * L * a.D * sizeof(double);
+  const size_t lds = (size_t)wpb * 3 * L * (a.Dc + 1) * sizeof(double);
   static bool attr_set = false;
   if (!attr_set) {  // dynamic LDS above 64 KB needs the attribute
-    hipFuncSetAttribute((const void *)power_kernel<L>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    hipFuncSetAttribute((const void *)evaldiff_kernel<L>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    (void)hipFuncSetAttribute((const void *)power_kernel<L>, hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+    (void)hipFuncSetAttribute((const void *)evaldiff_kernel<L>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              150 * 1024);
+    (void)hipGetLastError();  // an attribute the runtime refuses must not be reported by the launch
     attr_set = true;
   }
   if (maxexp >= 3) {
     const int blocks = (a.n + wpb - 1) / wpb;
-    hipLaunchKernelGGL(power_kernel<L>, dim3(blocks), dim3(256), lds, st, a.n, a.D, maxexp - 1, a.x, pw_mut);
+    hipLaunchKernelGGL(power_kernel<L>, dim3(blocks), dim3(256), lds, st, a.n, a.D, a.Dc, maxexp - 1, a.x, pw_mut);
   }
   if (a.m > 0) {
     const int blocks = (a.m + wpb - 1) / wpb;
@@ -332,9 +391,21 @@ hipError_t launch_evaldiff(int L, const EvalArgs &a, int maxexp, double *pw, hip
   return hipErrorInvalidValue;
 }
 
+hipError_t launch_assemble_A0(int L, int n, int D, int nnz, const int32_t *asm_ptr, const int32_t *asm_ent,
+                              const double *der, double *a0, hipStream_t st) {
+  const size_t nn = (size_t)n * n;
+  switch (L) {
+    case 2: hipLaunchKernelGGL(assemble_A0_kernel<2>, dim3((nn + 255) / 256), dim3(256), 0, st, n, D, nnz, asm_ptr, asm_ent, der, a0); break;
+    case 4: hipLaunchKernelGGL(assemble_A0_kernel<4>, dim3((nn + 255) / 256), dim3(256), 0, st, n, D, nnz, asm_ptr, asm_ent, der, a0); break;
+    case 8: hipLaunchKernelGGL(assemble_A0_kernel<8>, dim3((nn + 255) / 256), dim3(256), 0, st, n, D, nnz, asm_ptr, asm_ent, der, a0); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 size_t evaldiff_lds_bytes(int L, int D) {
   const int G = worker_lanes(D);
-  return (size_t)(256 / G) * 3 * L * D * sizeof(double);
+  return (size_t)(256 / G) * 3 * L * (D + 1) * sizeof(double);
 }
 
 template <int L>

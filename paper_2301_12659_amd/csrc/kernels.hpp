@@ -7,7 +7,7 @@
 namespace mdk {
 
 struct EvalArgs {
-  int n, D, m, nnz;
+  int n, D, Dc, m, nnz;  // D: coefficients stored per series, Dc: coefficients computed (D or 1)
   const int32_t *mon_ptr, *var, *exp, *order;
   const double *cff, *x, *pw;  // pw: powers x^p for p = 2..maxexp-1, [p-2][L][n][D]
   double *val, *der;           // val [L][m][D], der [L][nnz][D]
@@ -19,20 +19,35 @@ hipError_t launch_assemble(int L, int n, int D, int m, int nnz, const int32_t *p
                            const int32_t *asm_ent, const double *cst, const double *val, const double *der,
                            double *b, double *A, hipStream_t st);
 size_t evaldiff_lds_bytes(int L, int D);
+hipError_t launch_assemble_A0(int L, int n, int D, int nnz, const int32_t *asm_ptr, const int32_t *asm_ent,
+                              const double *der, double *a0, hipStream_t st);
 
 // linalg.hip
 hipError_t launch_status_init(int32_t *status, hipStream_t st);
-hipError_t launch_qr(int L, int n, double *a, double *tau, int32_t *status, hipStream_t st);
+hipError_t launch_qr(int L, int n, double *a, double *tau, double *qt, int32_t *status, unsigned *bar,
+                     hipStream_t st);
+int qr_lds_workgroups(int L, int n, bool with_qt);
+hipError_t launch_qr_lds(int L, int n, double *a, double *tau, double *qt, int32_t *status, int *flags,
+                         double *vboard, double *tboard, hipStream_t st);
+hipError_t launch_m_from_qt(int L, int n, const double *qr, const double *qt, double *invd, double *M,
+                            int32_t *status, hipStream_t st);
 hipError_t launch_form_m(int L, int n, const double *qr, const double *tau, double *invd, double *M, int32_t *status,
                          hipStream_t st);
 hipError_t launch_extract(int L, int n, int D, int k, const double *A, double *out, hipStream_t st);
-hipError_t launch_gemm_series(int L, int n, int D, int kb, const double *M, const double *A, double *N,
-                              hipStream_t st);
-hipError_t launch_stages(int L, int n, int D, const double *M, const double *N, const double *A, double *r,
-                         double *dx, hipStream_t st);
+hipError_t launch_transpose(int L, const double *in, double *out, size_t rows, int cols, size_t in_ls,
+                            size_t out_ls, hipStream_t st);
+hipError_t launch_gemm(int L, int n, const double *M, const double *B, size_t b_ls, double *N, hipStream_t st);
+hipError_t launch_stages(int L, int n, int D, const double *M, const double *N, const double *At, double *rT,
+                         double *dxT, hipStream_t st);
 hipError_t launch_update(int L, int n, int D, const double *b, const double *dx, double *x, double *norms,
                          int32_t *status, hipStream_t st);
 hipError_t launch_arith(int L, int op, int64_t count, const double *a, const double *b, double *c, hipStream_t st);
 hipError_t launch_copy(const double *src, double *dst, size_t count, hipStream_t st);
+hipError_t launch_series_to_rev(int L, int n, int D, const double *in, double *out, hipStream_t st);
+hipError_t launch_rev_to_series(int L, int n, int D, const double *in, double *out, hipStream_t st);
+hipError_t launch_coef_grad(int L, int n, int D, int m, const int32_t *row_of, const double *lambda, const double *val,
+                            double *grad, hipStream_t st);
+hipError_t launch_unit_md(int L, int m, double *c, hipStream_t st);
+hipError_t launch_dot(int L, int64_t count, const double *a, const double *b, double *c, hipStream_t st);
 
 }  // namespace mdk

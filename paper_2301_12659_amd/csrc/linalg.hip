@@ -28,16 +28,120 @@ __global__ void status_init_kernel(int32_t *status) {
 
 // ----------------------------------------------------------------- QR
 
-// Unblocked Householder QR in one workgroup; a [L][n][n] row-major in place.
+// Newton iteration counts from a double start (53 correct bits, doubling).
+template <int L> struct NewtonIters {
+  static constexpr int value = (L == 2) ? 2 : (L == 4) ? 3 : 4;
+};
+
+// Householder reflector of a column with squared norm nrm2 and leading entry
+// x0: beta = -sign(x0) ||x|| (sign(0) = +1), v = x / (x0 - beta) with v_0 = 1,
+// tau = (beta - x0) / beta.  Division-free: 1/||x|| by Newton's iteration
+// y := y + y (1 - a y^2) / 2 and 1/(x0 - beta) by r := r + r (1 - v0 r).
 template <int L>
-__global__ void __launch_bounds__(256) qr_kernel(int n, double *a, double *tau, int32_t *status) {
+__device__ void reflector(const double (&nrm2)[L], const double (&x0)[L], double (&beta)[L], double (&tau)[L],
+                          double (&inv)[L]) {
+  double y[L], t[L], u[L], one[L];
+  md::zero<L>(y);
+  md::zero<L>(one);
+  one[0] = 1.0;
+  y[0] = 1.0 / ::sqrt(nrm2[0]);
+#pragma unroll
+  for (int it = 0; it < NewtonIters<L>::value; ++it) {
+    MD<L>::mul(y, y, t);
+    MD<L>::mul(nrm2, t, u);
+    MD<L>::sub(one, u, t);
+    md::scale2<L>(t, 0.5);
+    MD<L>::mul(y, t, u);
+    MD<L>::add(y, u, t);
+    md::copy<L>(t, y);
+  }
+  double alpha[L], v0[L];
+  MD<L>::mul(nrm2, y, alpha);  // ||x||
+  const bool nonneg = x0[0] >= 0.0;
+  if (nonneg) md::neg<L>(alpha, beta);
+  else md::copy<L>(alpha, beta);
+  MD<L>::sub(x0, beta, v0);
+  MD<L>::mul(v0, y, tau);      // tau = -v0 / beta and 1/beta = -+ y
+  if (!nonneg) md::neg<L>(tau, tau);
+  double r[L];
+  md::zero<L>(r);
+  r[0] = 1.0 / v0[0];
+#pragma unroll
+  for (int it = 0; it < NewtonIters<L>::value; ++it) {
+    MD<L>::mul(v0, r, t);
+    MD<L>::sub(one, t, u);
+    MD<L>::mul(r, u, t);
+    MD<L>::add(r, t, u);
+    md::copy<L>(u, r);
+  }
+  md::copy<L>(r, inv);
+}
+
+// Unblocked Householder QR in one workgroup of 1024 threads; a [L][n][n]
+// row-major in place (R on and above the diagonal, v below it).  When qt is
+// not null it starts as the identity and receives every reflector too, so it
+// ends as Q^T = H_{n-1} ... H_0 (the augmented matrix [A_0 | I]).  The trailing
+// update gives each column to a team of 16 lanes.
+template <int L> struct QrThreads {
+  static constexpr int value = 256;
+};
+
+// Grid-wide barrier among the workgroups of one launch: a monotone counter
+// in device memory, agent-scope release/acquire.  The spin is bounded; on
+// time-out the launch records MD_EHIP in the status word and the caller's
+// result is garbage (every workgroup still exits).
+__device__ __forceinline__ bool grid_barrier(unsigned *counter, unsigned target, int32_t *status) {
+  __syncthreads();
+  __shared__ int ok;
+  if (threadIdx.x == 0) {
+    ok = 1;
+    __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    long spins = 0;
+    while (__hip_atomic_load(counter, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (++spins > (1L << 24)) {
+        set_status(status, MD_EHIP);
+        ok = 0;
+        break;
+      }
+    }
+  }
+  __syncthreads();
+  return ok != 0;
+}
+
+__global__ void zero_u32_kernel(unsigned *p) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0u;
+}
+
+// Householder QR of A_0 by G workgroups (a [L][n][n] row-major in place, R
+// on and above the diagonal, v below it).  For every column c each workgroup
+// computes the same reflector from the same data, so no workgroup waits for
+// another to publish it; the columns of the trailing matrix are dealt out
+// cyclically (column j to workgroup j mod G), each to a team of 16 lanes.  When
+// qt is not null it starts as the identity and receives every reflector too,
+// ending as Q^T = H_{n-1} ... H_0 (the augmented matrix [A_0 | I]).  One grid
+// barrier per column makes the updated column c+1 visible to all.
+template <int L>
+__global__ void __launch_bounds__(256) qr_kernel(int n, double *a, double *tau, double *qt, int32_t *status,
+                                                 unsigned *bar) {
+  extern __shared__ double vsh[];  // the current reflector v, [L][n]
   __shared__ double red[4][L];
-  __shared__ double sh_tau[L], sh_inv[L];
+  __shared__ double sh_tau[L], sh_inv[L], sh_beta[L];
   __shared__ int sh_skip;
+  constexpr int T = 16;
   const size_t nn = (size_t)n * n;
+  const int G = gridDim.x, g = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, nw = blockDim.x >> 6;
-  for (int c = 0; c < n; ++c) {
-    // squared norm of the column c, rows c..n-1
+  const int team = tid / T, tl = tid % T, nteams = blockDim.x / T;
+  if (qt)  // columns of Q^T owned by this workgroup start as the identity
+    for (int j = g; j < n; j += G)
+      for (int i = tid; i < n; i += blockDim.x) {
+#pragma unroll
+        for (int l = 0; l < L; ++l) qt[(size_t)l * nn + (size_t)i * n + j] = (l == 0 && i == j) ? 1.0 : 0.0;
+      }
+  bool alive = true;
+  for (int c = 0; c < n && alive; ++c) {
+    // squared norm of column c, rows c..n-1
     double acc[L];
     md::zero<L>(acc);
     for (int i = c + tid; i < n; i += blockDim.x) {
@@ -45,102 +149,311 @@ __global__ void __launch_bounds__(256) qr_kernel(int n, double *a, double *tau, 
       ld<L>(a, nn, (size_t)i * n + c, xi);
       MD<L>::fma(acc, xi, xi);
     }
-    team_sum<L>(acc, 64);
-    if (lane == 0)
+    if (n - c <= 64) {  // one wavefront holds the whole column
+      if (w == 0) team_sum<L>(acc, 64);
+    } else {
+      team_sum<L>(acc, 64);
+      if (lane == 0)
 #pragma unroll
-      for (int l = 0; l < L; ++l) red[w][l] = acc[l];
-    __syncthreads();
-    if (tid == 0) {
-      double nrm2[L];
+        for (int l = 0; l < L; ++l) red[w][l] = acc[l];
+      __syncthreads();
+      if (w == 0) {
 #pragma unroll
-      for (int l = 0; l < L; ++l) nrm2[l] = red[0][l];
-      for (int q = 1; q < nw; ++q) {
-        double t[L], s[L];
-#pragma unroll
-        for (int l = 0; l < L; ++l) t[l] = red[q][l];
-        MD<L>::add(nrm2, t, s);
-        md::copy<L>(s, nrm2);
+        for (int l = 0; l < L; ++l) acc[l] = (lane < nw) ? red[lane][l] : 0.0;
+        team_sum<L>(acc, 64);
       }
-      double alpha[L], x0[L];
-      md::sqrt<L>(nrm2, alpha);
+    }
+    if (tid == 0) {
+      double x0[L];
       ld<L>(a, nn, (size_t)c * n + c, x0);
-      if (!(alpha[0] > 0.0)) {  // zero column: R_cc = 0, H_c = I
+      if (!(acc[0] > 0.0)) {  // zero column: R_cc = 0, H_c = I
         sh_skip = 1;
 #pragma unroll
-        for (int l = 0; l < L; ++l) tau[(size_t)l * n + c] = 0.0;
-        set_status(status, MD_ESINGULAR);
+        for (int l = 0; l < L; ++l) sh_beta[l] = x0[l];
+        if (g == 0) {
+#pragma unroll
+          for (int l = 0; l < L; ++l) tau[(size_t)l * n + c] = 0.0;
+          set_status(status, MD_ESINGULAR);
+        }
       } else {
+        double beta[L], tc[L], inv[L];
+        reflector<L>(acc, x0, beta, tc, inv);
         sh_skip = 0;
-        double beta[L], v0[L], num[L], tc[L], one[L], inv[L];
-        if (x0[0] >= 0.0) md::neg<L>(alpha, beta);  // beta = -sign(x0) ||x||, sign(0) = +1
-        else md::copy<L>(alpha, beta);
-        MD<L>::sub(x0, beta, v0);
-        MD<L>::sub(beta, x0, num);
-        md::div<L>(num, beta, tc);  // tau = (beta - x0) / beta
-        md::zero<L>(one);
-        one[0] = 1.0;
-        md::div<L>(one, v0, inv);   // v = x / (x0 - beta) below the diagonal
-        st<L>(a, nn, (size_t)c * n + c, beta);
-        st<L>(tau, n, c, tc);
+        if (g == 0) st<L>(tau, n, c, tc);
 #pragma unroll
         for (int l = 0; l < L; ++l) {
           sh_tau[l] = tc[l];
           sh_inv[l] = inv[l];
+          sh_beta[l] = beta[l];
         }
       }
     }
     __syncthreads();
-    if (sh_skip) continue;
+    const bool skip = sh_skip != 0;
     double inv[L], tc[L];
 #pragma unroll
     for (int l = 0; l < L; ++l) {
       inv[l] = sh_inv[l];
       tc[l] = sh_tau[l];
     }
-    for (int i = c + 1 + tid; i < n; i += blockDim.x) {
-      double xi[L], r[L];
-      ld<L>(a, nn, (size_t)i * n + c, xi);
-      MD<L>::mul(xi, inv, r);
-      st<L>(a, nn, (size_t)i * n + c, r);
+    for (int i = c + tid; i < n; i += blockDim.x) {
+      double vi[L];
+      if (i == c) {
+        md::zero<L>(vi);
+        vi[0] = 1.0;
+      } else if (skip) {
+        md::zero<L>(vi);
+      } else {
+        double xi[L];
+        ld<L>(a, nn, (size_t)i * n + c, xi);
+        MD<L>::mul(xi, inv, vi);
+      }
+#pragma unroll
+      for (int l = 0; l < L; ++l) vsh[l * n + i] = vi[l];
     }
     __syncthreads();
-    // apply H_c to the trailing columns, one wavefront per column
-    for (int j = c + 1 + w; j < n; j += nw) {
-      double dot[L];
-      md::zero<L>(dot);
-      for (int i = c + lane; i < n; i += 64) {
-        double aij[L];
-        ld<L>(a, nn, (size_t)i * n + j, aij);
-        if (i == c) {
-          double s[L];
-          MD<L>::add(dot, aij, s);
-          md::copy<L>(s, dot);
-        } else {
-          double vi[L];
-          ld<L>(a, nn, (size_t)i * n + c, vi);
-          MD<L>::fma(dot, vi, aij);
+    if (!skip) {
+      // this workgroup's trailing columns of A (j > c, j mod G == g) and of Q^T (j mod G == g)
+      const int first_a = c + 1 + ((g - (c + 1)) % G + G) % G;
+      const int na = (first_a < n) ? (n - 1 - first_a) / G + 1 : 0;
+      const int nq = qt ? ((g < n) ? (n - 1 - g) / G + 1 : 0) : 0;
+      for (int col = team; col < na + nq; col += nteams) {
+        double *base = (col < na) ? a : qt;
+        const int j = (col < na) ? first_a + col * G : g + (col - na) * G;
+        double dot[L];
+        md::zero<L>(dot);
+        for (int i = c + tl; i < n; i += T) {
+          double vi[L], x[L];
+#pragma unroll
+          for (int l = 0; l < L; ++l) vi[l] = vsh[l * n + i];
+          ld<L>(base, nn, (size_t)i * n + j, x);
+          MD<L>::fma(dot, vi, x);
+        }
+        team_sum<L>(dot, T);
+        double wj[L];
+        MD<L>::mul(dot, tc, wj);
+        for (int i = c + tl; i < n; i += T) {
+          double vi[L], x[L];
+#pragma unroll
+          for (int l = 0; l < L; ++l) vi[l] = vsh[l * n + i];
+          ld<L>(base, nn, (size_t)i * n + j, x);
+          MD<L>::fms(x, vi, wj);
+          st<L>(base, nn, (size_t)i * n + j, x);
         }
       }
-      team_sum<L>(dot, 64);
-      double wj[L];
-      MD<L>::mul(dot, tc, wj);
-      for (int i = c + lane; i < n; i += 64) {
-        double aij[L];
-        ld<L>(a, nn, (size_t)i * n + j, aij);
+    }
+    // every workgroup has read column c: workgroup 0 may now store R_cc and v
+    alive = grid_barrier(bar, (unsigned)G * (unsigned)(c + 1), status);
+    if (g == 0) {
+      for (int i = c + tid; i < n; i += blockDim.x) {
+        double vi[L];
         if (i == c) {
-          double s[L];
-          MD<L>::sub(aij, wj, s);
-          st<L>(a, nn, (size_t)i * n + j, s);
+#pragma unroll
+          for (int l = 0; l < L; ++l) vi[l] = sh_beta[l];
         } else {
-          double vi[L];
-          ld<L>(a, nn, (size_t)i * n + c, vi);
-          MD<L>::fms(aij, vi, wj);
-          st<L>(a, nn, (size_t)i * n + j, aij);
+#pragma unroll
+          for (int l = 0; l < L; ++l) vi[l] = vsh[l * n + i];
         }
+        st<L>(a, nn, (size_t)i * n + c, vi);
+      }
+    }
+  }
+}
+
+// Bounded wait for a published flag (agent scope).  Returns false on time-out
+// (the status word then holds MD_EHIP and the caller's result is garbage).
+__device__ __forceinline__ bool wait_flag(const int *flag, int32_t *status) {
+  long spins = 0;
+  while (__hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+    if (++spins > (1L << 24)) {
+      set_status(status, MD_EHIP);
+      return false;
+    }
+  }
+  return true;
+}
+
+// Householder QR of A_0 with Q^T, columns resident in LDS.  Column J of the
+// augmented matrix [A_0 | I] (J < 2n) belongs to workgroup J mod G and stays
+// in its LDS for the whole factorization.  Reflector c is published by the
+// owner of column c: v (rows c..n-1, v_c = 1) and tau on a board in device
+// memory, then flags[c] = 1.  The owner of column c+1 applies H_c to that
+// column first, computes reflector c+1 with one wavefront and publishes it
+// while its other wavefronts update the rest (look-ahead), so a column costs
+// one reflector computation and one flag hand-over on the critical path.
+// Every column is written back at the end: R on and above the diagonal, v
+// below it for the A_0 part; Q^T for the identity part.
+template <int L>
+__global__ void __launch_bounds__(256) qr_lds_kernel(int n, double *a, double *tau, double *qt, int32_t *status,
+                                                     int *flags, double *vboard, double *tboard) {
+  extern __shared__ double lds[];
+  const int G = gridDim.x, g = blockIdx.x;
+  const int ncols_total = qt ? 2 * n : n;  // [A_0 | I] or A_0 alone
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  constexpr int T = 16;
+  const int team = tid / T, tl = tid % T;
+  const size_t nn = (size_t)n * n;
+  const int ncol = (ncols_total - g + G - 1) / G;  // owned columns J = g + q G
+  double *cols = lds;                          // [ncol][L][n]
+  double *vsh = lds + (size_t)ncol * L * n;    // [L][n] current reflector
+  __shared__ double sh_tau[L];
+  __shared__ int sh_ok;
+  auto col = [&](int q) { return cols + (size_t)q * L * n; };
+  // load the owned columns of [A_0 | I]
+  for (int q = 0; q < ncol; ++q) {
+    const int J = g + q * G;
+    double *cq = col(q);
+    for (int i = tid; i < n; i += blockDim.x)
+#pragma unroll
+      for (int l = 0; l < L; ++l)
+        cq[l * n + i] = (J < n) ? a[(size_t)l * nn + (size_t)i * n + J] : ((l == 0 && i == J - n) ? 1.0 : 0.0);
+  }
+  __syncthreads();
+
+  // reflector of owned column q (global column c), by the wavefront w0; writes
+  // beta and v into the column, publishes v, tau and the flag
+  auto publish = [&](int q, int c) {
+    double *cq = col(q);
+    double acc[L];
+    md::zero<L>(acc);
+    for (int i = c + lane; i < n; i += 64) {
+      double xi[L];
+#pragma unroll
+      for (int l = 0; l < L; ++l) xi[l] = cq[l * n + i];
+      MD<L>::fma(acc, xi, xi);
+    }
+    team_sum<L>(acc, 64);
+    double x0[L], beta[L], tc[L], inv[L];
+#pragma unroll
+    for (int l = 0; l < L; ++l) x0[l] = cq[l * n + c];
+    const bool zero = !(acc[0] > 0.0);
+    if (zero) {
+      md::copy<L>(x0, beta);
+      md::zero<L>(tc);
+      md::zero<L>(inv);
+      if (lane == 0) set_status(status, MD_ESINGULAR);
+    } else {
+      reflector<L>(acc, x0, beta, tc, inv);  // every lane computes the same scalars
+    }
+    for (int i = c + lane; i < n; i += 64) {
+      double vi[L];
+      if (i == c) {
+        md::zero<L>(vi);
+        vi[0] = 1.0;
+#pragma unroll
+        for (int l = 0; l < L; ++l) cq[l * n + i] = beta[l];
+      } else {
+        double xi[L];
+#pragma unroll
+        for (int l = 0; l < L; ++l) xi[l] = cq[l * n + i];
+        MD<L>::mul(xi, inv, vi);
+#pragma unroll
+        for (int l = 0; l < L; ++l) cq[l * n + i] = vi[l];
+      }
+#pragma unroll
+      for (int l = 0; l < L; ++l) vboard[(size_t)c * L * n + (size_t)l * n + i] = vi[l];
+    }
+    if (lane == 0) {
+#pragma unroll
+      for (int l = 0; l < L; ++l) {
+        tboard[(size_t)c * L + l] = tc[l];
+        tau[(size_t)l * n + c] = tc[l];
+      }
+    }
+    wave_sync();
+    if (lane == 0) {
+      __atomic_thread_fence(__ATOMIC_RELEASE);  // board writes before the flag (agent scope)
+      __hip_atomic_store(&flags[c], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  };
+
+  // apply H_c (v in vsh, tau tc) to owned column q, rows c..n-1, with a team of T lanes
+  auto apply = [&](int q, int c, const double (&tc)[L], int tlane, int width) {
+    double *cq = col(q);
+    double dot[L];
+    md::zero<L>(dot);
+    for (int i = c + tlane; i < n; i += width) {
+      double vi[L], x[L];
+#pragma unroll
+      for (int l = 0; l < L; ++l) {
+        vi[l] = vsh[l * n + i];
+        x[l] = cq[l * n + i];
+      }
+      MD<L>::fma(dot, vi, x);
+    }
+    team_sum<L>(dot, width);
+    double wj[L];
+    MD<L>::mul(dot, tc, wj);
+    for (int i = c + tlane; i < n; i += width) {
+      double vi[L], x[L];
+#pragma unroll
+      for (int l = 0; l < L; ++l) {
+        vi[l] = vsh[l * n + i];
+        x[l] = cq[l * n + i];
+      }
+      MD<L>::fms(x, vi, wj);
+#pragma unroll
+      for (int l = 0; l < L; ++l) cq[l * n + i] = x[l];
+    }
+  };
+
+  if (g == 0 && w == 0) publish(0, 0);  // column 0 belongs to workgroup 0
+  bool ok = true;
+  for (int c = 0; c < n; ++c) {
+    // reflector c into vsh
+    if (tid == 0) sh_ok = (c % G == g) ? 1 : (wait_flag(&flags[c], status) ? 1 : 0);
+    __syncthreads();
+    ok = sh_ok != 0;
+    if (!ok) break;
+    for (int i = c + tid; i < n; i += blockDim.x)
+#pragma unroll
+      for (int l = 0; l < L; ++l) vsh[l * n + i] = vboard[(size_t)c * L * n + (size_t)l * n + i];
+    if (tid == 0)
+#pragma unroll
+      for (int l = 0; l < L; ++l) sh_tau[l] = tboard[(size_t)c * L + l];
+    __syncthreads();
+    double tc[L];
+#pragma unroll
+    for (int l = 0; l < L; ++l) tc[l] = sh_tau[l];
+    const bool ahead = (c + 1 < n) && ((c + 1) % G == g);
+    const int qa = ahead ? (c + 1 - g) / G : -1;
+    if (ahead && w == 0) {  // look-ahead: update column c+1, publish reflector c+1
+      apply(qa, c, tc, lane, 64);
+      wave_sync();
+      publish(qa, c + 1);
+    }
+    // the other owned columns: A columns j > c (except the look-ahead one) and all Q^T columns
+    // teams 0..3 form wavefront 0, busy with the look-ahead column
+    const int t0 = ahead ? team - 4 : team, nt = ahead ? (blockDim.x / T) - 4 : blockDim.x / T;
+    if (!(ahead && w == 0)) {
+      int k = 0;
+      for (int q = 0; q < ncol; ++q) {
+        const int J = g + q * G;
+        if (J < n && J <= c) continue;  // finished columns of R
+        if (q == qa) continue;
+        if (k % nt == t0) apply(q, c, tc, tl, T);
+        ++k;
       }
     }
     __syncthreads();
   }
+  if (ok) {  // write back the owned columns
+    for (int q = 0; q < ncol; ++q) {
+      const int J = g + q * G;
+      const double *cq = col(q);
+      for (int i = tid; i < n; i += blockDim.x)
+#pragma unroll
+        for (int l = 0; l < L; ++l) {
+          if (J < n) a[(size_t)l * nn + (size_t)i * n + J] = cq[l * n + i];
+          else qt[(size_t)l * nn + (size_t)i * n + (J - n)] = cq[l * n + i];
+        }
+    }
+  }
+}
+
+__global__ void zero_i32_kernel(int *p, int count) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < count) p[q] = 0;
 }
 
 // 1 / R_ii for the back substitutions.  A diagonal entry below
@@ -166,11 +479,40 @@ __global__ void invdiag_kernel(int n, const double *qr, double *invd, int32_t *s
   st<L>(invd, n, i, q);
 }
 
+// Back substitution R z = y in place on y [L][n] in LDS, one wavefront:
+// column-oriented, z_i = y_i / R_ii with the precomputed reciprocal, then
+// y_p -= R_pi z_i for p < i.
+template <int L>
+__device__ void back_subst(int n, const double *qr, const double *invd, double *y, int lane) {
+  const size_t nn = (size_t)n * n;
+  for (int i = n - 1; i >= 0; --i) {
+    double zi[L], yi[L], di[L];
+#pragma unroll
+    for (int l = 0; l < L; ++l) yi[l] = y[l * n + i];
+    ld<L>(invd, n, i, di);
+    MD<L>::mul(yi, di, zi);
+    wave_sync();
+    if (lane == 0)
+#pragma unroll
+      for (int l = 0; l < L; ++l) y[l * n + i] = zi[l];
+    for (int p = lane; p < i; p += 64) {
+      double yp[L], rpi[L];
+#pragma unroll
+      for (int l = 0; l < L; ++l) yp[l] = y[l * n + p];
+      ld<L>(qr, nn, (size_t)p * n + i, rpi);
+      MD<L>::fms(yp, rpi, zi);
+#pragma unroll
+      for (int l = 0; l < L; ++l) y[l * n + p] = yp[l];
+    }
+    wave_sync();
+  }
+}
+
 // Column c of M = R^{-1} Q^T: y = H_{n-1} ... H_0 e_c (Q^T applied to e_c),
 // then z = R^{-1} y by column-oriented back substitution.  One wavefront per
 // column, y kept in LDS.
 template <int L>
-__global__ void __launch_bounds__(64) form_m_kernel(int n, const double *qr, const double *tau, const double *invd,
+__global__ void __launch_bounds__(64, 1) form_m_kernel(int n, const double *qr, const double *tau, const double *invd,
                                                     double *M) {
   extern __shared__ double y[];  // [L][n]
   const int c = blockIdx.x, lane = threadIdx.x;
@@ -218,28 +560,31 @@ __global__ void __launch_bounds__(64) form_m_kernel(int n, const double *qr, con
     }
     wave_sync();
   }
-  // back substitution R z = y, z overwrites y
-  for (int i = n - 1; i >= 0; --i) {
-    double zi[L], yi[L], di[L];
+  back_subst<L>(n, qr, invd, y, lane);
+  for (int i = lane; i < n; i += 64) {
+    double zi[L];
 #pragma unroll
-    for (int l = 0; l < L; ++l) yi[l] = y[l * n + i];
-    ld<L>(invd, n, i, di);
-    MD<L>::mul(yi, di, zi);
-    wave_sync();
-    if (lane == 0)
-#pragma unroll
-      for (int l = 0; l < L; ++l) y[l * n + i] = zi[l];
-    for (int p = lane; p < i; p += 64) {
-      double yp[L], rpi[L];
-#pragma unroll
-      for (int l = 0; l < L; ++l) yp[l] = y[l * n + p];
-      ld<L>(qr, nn, (size_t)p * n + i, rpi);
-      MD<L>::fms(yp, rpi, zi);
-#pragma unroll
-      for (int l = 0; l < L; ++l) y[l * n + p] = yp[l];
-    }
-    wave_sync();
+    for (int l = 0; l < L; ++l) zi[l] = y[l * n + i];
+    st<L>(M, nn, (size_t)i * n + c, zi);
   }
+}
+
+// Column c of M = R^{-1} Q^T from an explicit Q^T (rows of the QR kernel's
+// augmented part): one wavefront per column.
+template <int L>
+__global__ void __launch_bounds__(64, 1) m_from_qt_kernel(int n, const double *qr, const double *qt, const double *invd,
+                                                       double *M) {
+  extern __shared__ double y[];  // [L][n]
+  const int c = blockIdx.x, lane = threadIdx.x;
+  const size_t nn = (size_t)n * n;
+  for (int i = lane; i < n; i += 64) {
+    double v[L];
+    ld<L>(qt, nn, (size_t)i * n + c, v);
+#pragma unroll
+    for (int l = 0; l < L; ++l) y[l * n + i] = v[l];
+  }
+  wave_sync();
+  back_subst<L>(n, qr, invd, y, lane);
   for (int i = lane; i < n; i += 64) {
     double zi[L];
 #pragma unroll
@@ -259,77 +604,196 @@ __global__ void extract_coeff_kernel(int n, int D, int k, const double *A, doubl
   st<L>(out, nn, q, v);
 }
 
-// N = M B with B given as coefficient kb of the series matrix A; teams of 16
-// lanes per output entry.
+// out[l][c][r] = in[l][r][c] for r < rows, c < cols (limb strides in_ls, out_ls):
+// series-major arrays [..][D] to coefficient-major [D][..] and back, through a
+// 32 x 32 LDS tile so that reads and writes are both coalesced.
+__global__ void __launch_bounds__(256) transpose_kernel(const double *in, double *out, size_t rows, int cols,
+                                                        size_t in_ls, size_t out_ls) {
+  __shared__ double tile[32][33];
+  const int l = blockIdx.z;
+  const size_t r0 = (size_t)blockIdx.x * 32;
+  const int c0 = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  for (int yy = ty; yy < 32; yy += 8) {
+    const size_t r = r0 + yy;
+    const int c = c0 + tx;
+    if (r < rows && c < cols) tile[yy][tx] = in[(size_t)l * in_ls + r * cols + c];
+  }
+  __syncthreads();
+  for (int yy = ty; yy < 32; yy += 8) {
+    const int c = c0 + yy;
+    const size_t r = r0 + tx;
+    if (r < rows && c < cols) out[(size_t)l * out_ls + (size_t)c * rows + r] = tile[tx][yy];
+  }
+}
+
+// N = M B for dense n x n matrices (B with limb stride b_ls); teams of 16
+// lanes per output entry, level-sum accumulation.
 template <int L>
-__global__ void __launch_bounds__(256) gemm_series_kernel(int n, int D, int kb, const double *M, const double *A,
-                                                          double *N) {
+__global__ void __launch_bounds__(256) gemm_kernel(int n, const double *M, const double *B, size_t b_ls, double *N) {
   const int T = 16;
   const size_t task = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) / T;
   const int tl = threadIdx.x & (T - 1);
-  const size_t nn = (size_t)n * n, nnD = nn * D;
+  const size_t nn = (size_t)n * n;
   const bool live = task < nn;
   const size_t tk = live ? task : 0;
   const int i = (int)(tk / n), j = (int)(tk - (size_t)i * n);
-  double acc[L];
+  double acc[L], r[L];
   md::zero<L>(acc);
   for (int v = tl; v < n; v += T) {
     double m[L], b[L];
     ld<L>(M, nn, (size_t)i * n + v, m);
-    ld<L>(A, nnD, ((size_t)v * n + j) * D + kb, b);
-    MD<L>::fma(acc, m, b);
+    ld<L>(B, b_ls, (size_t)v * n + j, b);
+    MD<L>::fma_lazy(acc, m, b);
   }
-  team_sum<L>(acc, T);
-  if (live && tl == 0) st<L>(N, nn, (size_t)i * n + j, acc);
+  MD<L>::renorm(acc, r);
+  team_sum<L>(r, T);
+  if (live && tl == 0) st<L>(N, nn, (size_t)i * n + j, r);
 }
 
-// One stage k of the block Toeplitz solve; see the file comment.
+// One stage k of the block Toeplitz solve (see the file comment), on
+// coefficient-major arrays: At [L][D][n][n] (At[k] = A_k), rT, dxT [L][D][n].
+// Blocks 0 .. ceil(n/4)-1: one wavefront per row i computes
+//     dx_k(i) = sum_v M(i,v) r_k(v) - N(i,v) dx_{k-1}(v);
+// the other blocks: teams of 16 lanes per (m, i), m = k+1..D-1, push
+//     r_m(i) -= sum_v A_{m-k+1}(i,v) dx_{k-1}(v).
 template <int L>
 __global__ void __launch_bounds__(256) stage_kernel(int n, int D, int k, const double *M, const double *N,
-                                                    const double *A, double *r, double *dx) {
-  const int T = 16;
-  const size_t task = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) / T;
-  const int tl = threadIdx.x & (T - 1);
+                                                    const double *At, double *rT, double *dxT) {
   const size_t nn = (size_t)n * n, nD = (size_t)n * D, nnD = nn * D;
-  // stage 0 has no previous update to push into later right-hand sides
-  const size_t ntask = (k == 0) ? (size_t)n : (size_t)n * (D - k);
-  const bool live = task < ntask;
-  const size_t tk = live ? task : 0;
-  double acc[L];
+  const int crit_blocks = (n + 3) / 4;
+  double acc[L], r[L];
   md::zero<L>(acc);
-  if (tk < (size_t)n) {  // dx_k(i) = M r_k - N dx_{k-1}
-    const int i = (int)tk;
-    for (int v = tl; v < n; v += T) {
+  if ((int)blockIdx.x < crit_blocks) {
+    const int lane = threadIdx.x & 63;
+    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int i = row < n ? row : 0;
+    for (int v = lane; v < n; v += 64) {
       double m[L], rv[L];
       ld<L>(M, nn, (size_t)i * n + v, m);
-      ld<L>(r, nD, (size_t)v * D + k, rv);
-      MD<L>::fma(acc, m, rv);
+      ld<L>(rT, nD, (size_t)k * n + v, rv);
+      MD<L>::fma_lazy(acc, m, rv);
       if (k > 0) {
         double nv[L], xv[L];
         ld<L>(N, nn, (size_t)i * n + v, nv);
-        ld<L>(dx, nD, (size_t)v * D + k - 1, xv);
-        MD<L>::fms(acc, nv, xv);
+        ld<L>(dxT, nD, (size_t)(k - 1) * n + v, xv);
+        md::neg<L>(nv, nv);
+        MD<L>::fma_lazy(acc, nv, xv);
       }
     }
-    team_sum<L>(acc, T);
-    if (live && tl == 0) st<L>(dx, nD, (size_t)i * D + k, acc);
-  } else {  // r_m(i) -= A_{m-k+1} dx_{k-1}, m = k+1..D-1
-    const size_t t2 = tk - n;
-    const int i = (int)(t2 % n), mm = k + 1 + (int)(t2 / n), jj = mm - k + 1;
+    MD<L>::renorm(acc, r);
+    team_sum<L>(r, 64);
+    if (row < n && lane == 0) st<L>(dxT, nD, (size_t)k * n + i, r);
+    return;
+  }
+  if (k == 0) return;  // stage 0 has no previous update to push
+  const int T = 16;
+  const size_t task = ((size_t)(blockIdx.x - crit_blocks) * blockDim.x + threadIdx.x) / T;
+  const int tl = threadIdx.x & (T - 1);
+  const size_t ntask = (size_t)n * (D - k - 1);
+  const bool live = task < ntask;
+  const size_t tk = live ? task : 0;
+  const int mm = k + 1 + (int)(tk / n), i = (int)(tk % n), jj = mm - k + 1;
+  if (live) {
     for (int v = tl; v < n; v += T) {
       double av[L], xv[L];
-      ld<L>(A, nnD, ((size_t)i * n + v) * D + jj, av);
-      ld<L>(dx, nD, (size_t)v * D + k - 1, xv);
-      MD<L>::fma(acc, av, xv);
-    }
-    team_sum<L>(acc, T);
-    if (live && tl == 0) {
-      double rv[L], s[L];
-      ld<L>(r, nD, (size_t)i * D + mm, rv);
-      MD<L>::sub(rv, acc, s);
-      st<L>(r, nD, (size_t)i * D + mm, s);
+      ld<L>(At, nnD, (size_t)jj * nn + (size_t)i * n + v, av);
+      ld<L>(dxT, nD, (size_t)(k - 1) * n + v, xv);
+      MD<L>::fma_lazy(acc, av, xv);
     }
   }
+  MD<L>::renorm(acc, r);
+  team_sum<L>(r, T);
+  if (live && tl == 0) {
+    double rv[L], s2[L];
+    ld<L>(rT, nD, (size_t)mm * n + i, rv);
+    MD<L>::sub(rv, r, s2);
+    st<L>(rT, nD, (size_t)mm * n + i, s2);
+  }
+}
+
+// out[l][s][i] = in[l][i][D-1-s] and back (coefficients in reverse order):
+// the transposed block Toeplitz system runs the stage recurrence from the
+// last coefficient to the first.
+__global__ void series_to_rev_kernel(int n, int D, int L, const double *in, double *out) {
+  const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t nD = (size_t)n * D;
+  if (q >= nD * L) return;
+  const size_t l = q / nD, r = q - l * nD;
+  const int s = (int)(r / n), i = (int)(r - (size_t)s * n);
+  out[q] = in[l * nD + (size_t)i * D + (D - 1 - s)];
+}
+
+__global__ void rev_to_series_kernel(int n, int D, int L, const double *in, double *out) {
+  const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t nD = (size_t)n * D;
+  if (q >= nD * L) return;
+  const size_t l = q / nD, r = q - l * nD;
+  const int i = (int)(r / D), k = (int)(r - (size_t)i * D);
+  out[q] = in[l * nD + (size_t)(D - 1 - k) * n + i];
+}
+
+// grad[m] = -sum_k lambda_{row(m),k} val_m[k] (val: coefficient-free monomial
+// values [L][m][D]), one thread per monomial, fixed order.
+template <int L>
+__global__ void coef_grad_kernel(int n, int D, int m, const int32_t *row_of, const double *lambda, const double *val,
+                                 double *grad) {
+  const int mj = blockIdx.x * blockDim.x + threadIdx.x;
+  if (mj >= m) return;
+  const size_t nD = (size_t)n * D, mD = (size_t)m * D;
+  const int i = row_of[mj];
+  double acc[L], r[L];
+  md::zero<L>(acc);
+  for (int k = 0; k < D; ++k) {
+    double a[L], b[L];
+    ld<L>(lambda, nD, (size_t)i * D + k, a);
+    ld<L>(val, mD, (size_t)mj * D + k, b);
+    MD<L>::fma_lazy(acc, a, b);
+  }
+  MD<L>::renorm(acc, r);
+  md::neg<L>(r, r);
+  st<L>(grad, m, mj, r);
+}
+
+// c = [1, 0, ..., 0] in every element (unit coefficients).
+__global__ void unit_md_kernel(int L, int m, double *c) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < L * m) c[q] = (q < m) ? 1.0 : 0.0;
+}
+
+// c = sum_q a[q] * b[q] over count elements (one workgroup, fixed order).
+template <int L>
+__global__ void __launch_bounds__(256) dot_kernel(int64_t count, const double *a, const double *b, double *c) {
+  __shared__ double part[256][L];
+  double acc[L], r[L];
+  md::zero<L>(acc);
+  for (int64_t q = threadIdx.x; q < count; q += blockDim.x) {
+    double x[L], y[L];
+    ld<L>(a, count, q, x);
+    ld<L>(b, count, q, y);
+    MD<L>::fma_lazy(acc, x, y);
+  }
+  MD<L>::renorm(acc, r);
+#pragma unroll
+  for (int l = 0; l < L; ++l) part[threadIdx.x][l] = r[l];
+  __syncthreads();
+  for (int half = 128; half > 0; half >>= 1) {
+    if ((int)threadIdx.x < half) {
+      double u[L], v[L], s[L];
+#pragma unroll
+      for (int l = 0; l < L; ++l) {
+        u[l] = part[threadIdx.x][l];
+        v[l] = part[threadIdx.x + half][l];
+      }
+      MD<L>::add(u, v, s);
+#pragma unroll
+      for (int l = 0; l < L; ++l) part[threadIdx.x][l] = s[l];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int l = 0; l < L; ++l) c[l] = part[0][l];
 }
 
 // x := x + dx, one thread per (i, s).
@@ -366,7 +830,7 @@ __global__ void norms_kernel(int n, int D, const double *b, const double *dx, do
 }
 
 template <int L>
-__global__ void arith_kernel(int op, int64_t count, const double *a, const double *b, double *c) {
+__global__ void __launch_bounds__(256) arith_kernel(int op, int64_t count, const double *a, const double *b, double *c) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= count) return;
   double x[L], y[L], r[L];
@@ -401,8 +865,68 @@ hipError_t launch_status_init(int32_t *status, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_qr(int L, int n, double *a, double *tau, int32_t *status, hipStream_t st) {
-  MD_DISPATCH(L, hipLaunchKernelGGL(qr_kernel<LL>, dim3(1), dim3(256), 0, st, n, a, tau, status));
+// Workgroups of the QR: enough teams for the trailing columns, few enough for
+// a cheap grid barrier (all of them must be resident at once).
+int qr_workgroups(int n, bool with_qt) {
+  const int cols = n + (with_qt ? n : 0);
+  int G = (cols + 15) / 16;
+  return G < 1 ? 1 : (G > 16 ? 16 : G);
+}
+
+hipError_t launch_qr(int L, int n, double *a, double *tau, double *qt, int32_t *status, unsigned *bar,
+                     hipStream_t st) {
+  const int G = qr_workgroups(n, qt != nullptr);
+  hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, st, bar);
+  MD_DISPATCH(L, hipLaunchKernelGGL(qr_kernel<LL>, dim3(G), dim3(256), (size_t)LL * n * sizeof(double), st, n, a,
+                                    tau, qt, status, bar));
+  return hipGetLastError();
+}
+
+// Workgroups of the LDS-resident QR: at most 16 columns and about 120 KB of
+// columns per workgroup; 0 if that needs more than 64 workgroups.
+int qr_lds_workgroups(int L, int n, bool with_qt) {
+  const long cols = with_qt ? 2L * n : n;
+  long G = (cols + 15) / 16;
+  const long bytes = cols * (long)L * n * 8;
+  const long need = (bytes + 120L * 1024 - 1) / (120L * 1024);
+  if (need > G) G = need;
+  if (G < 1) G = 1;
+  return G > 64 ? 0 : (int)G;
+}
+
+size_t qr_lds_bytes(int L, int n, int G, bool with_qt) {
+  const int cols = with_qt ? 2 * n : n;
+  const int ncol = (cols + G - 1) / G;
+  return ((size_t)ncol + 1) * L * n * sizeof(double);
+}
+
+hipError_t launch_qr_lds(int L, int n, double *a, double *tau, double *qt, int32_t *status, int *flags,
+                         double *vboard, double *tboard, hipStream_t st) {
+  const int G = qr_lds_workgroups(L, n, qt != nullptr);
+  if (G == 0) return hipErrorInvalidValue;
+  const size_t lds = qr_lds_bytes(L, n, G, qt != nullptr);
+  hipLaunchKernelGGL(zero_i32_kernel, dim3((n + 255) / 256), dim3(256), 0, st, flags, n);
+  MD_DISPATCH(L, {
+    static bool attr = false;
+    if (!attr) {
+      // the kernel also has static LDS: leave room for it below the 160 KB of a CU
+      (void)hipFuncSetAttribute((const void *)qr_lds_kernel<LL>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                150 * 1024);
+      (void)hipGetLastError();
+      attr = true;
+    }
+    hipLaunchKernelGGL(qr_lds_kernel<LL>, dim3(G), dim3(256), lds, st, n, a, tau, qt, status, flags, vboard, tboard);
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_m_from_qt(int L, int n, const double *qr, const double *qt, double *invd, double *M,
+                            int32_t *status, hipStream_t st) {
+  MD_DISPATCH(L, {
+    hipLaunchKernelGGL(invdiag_kernel<LL>, dim3((n + 63) / 64), dim3(64), 0, st, n, qr, invd, status);
+    hipLaunchKernelGGL(m_from_qt_kernel<LL>, dim3(n), dim3(64), (size_t)LL * n * sizeof(double), st, n, qr, qt,
+                       (const double *)invd, M);
+  });
   return hipGetLastError();
 }
 
@@ -423,20 +947,28 @@ hipError_t launch_extract(int L, int n, int D, int k, const double *A, double *o
   return hipGetLastError();
 }
 
-hipError_t launch_gemm_series(int L, int n, int D, int kb, const double *M, const double *A, double *N,
-                              hipStream_t st) {
-  const size_t threads = (size_t)n * n * 16;
-  MD_DISPATCH(L, hipLaunchKernelGGL(gemm_series_kernel<LL>, dim3((threads + 255) / 256), dim3(256), 0, st, n, D, kb,
-                                    M, A, N));
+hipError_t launch_transpose(int L, const double *in, double *out, size_t rows, int cols, size_t in_ls,
+                            size_t out_ls, hipStream_t st) {
+  // L counts batches: limbs, or limbs times coefficients for per-coefficient matrices
+  dim3 grid((unsigned)((rows + 31) / 32), (unsigned)((cols + 31) / 32), (unsigned)L);
+  hipLaunchKernelGGL(transpose_kernel, grid, dim3(256), 0, st, in, out, rows, cols, in_ls, out_ls);
   return hipGetLastError();
 }
 
-hipError_t launch_stages(int L, int n, int D, const double *M, const double *N, const double *A, double *r,
-                         double *dx, hipStream_t st) {
+hipError_t launch_gemm(int L, int n, const double *M, const double *B, size_t b_ls, double *N, hipStream_t st) {
+  const size_t threads = (size_t)n * n * 16;
+  MD_DISPATCH(L, hipLaunchKernelGGL(gemm_kernel<LL>, dim3((threads + 255) / 256), dim3(256), 0, st, n, M, B, b_ls,
+                                    N));
+  return hipGetLastError();
+}
+
+hipError_t launch_stages(int L, int n, int D, const double *M, const double *N, const double *At, double *rT,
+                         double *dxT, hipStream_t st) {
+  const int crit_blocks = (n + 3) / 4;
   for (int k = 0; k < D; ++k) {
-    const size_t threads = (size_t)n * (k == 0 ? 1 : D - k) * 16;
-    MD_DISPATCH(L, hipLaunchKernelGGL(stage_kernel<LL>, dim3((threads + 255) / 256), dim3(256), 0, st, n, D, k, M, N,
-                                      A, r, dx));
+    const size_t bulk = (k == 0) ? 0 : (size_t)n * (D - k - 1) * 16;
+    const unsigned blocks = (unsigned)(crit_blocks + (bulk + 255) / 256);
+    MD_DISPATCH(L, hipLaunchKernelGGL(stage_kernel<LL>, dim3(blocks), dim3(256), 0, st, n, D, k, M, N, At, rT, dxT));
   }
   return hipGetLastError();
 }
@@ -446,6 +978,35 @@ hipError_t launch_update(int L, int n, int D, const double *b, const double *dx,
   const size_t nD = (size_t)n * D;
   MD_DISPATCH(L, hipLaunchKernelGGL(update_kernel<LL>, dim3((nD + 255) / 256), dim3(256), 0, st, n, D, dx, x));
   hipLaunchKernelGGL(norms_kernel, dim3((D + 63) / 64), dim3(64), 0, st, n, D, b, dx, norms, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_series_to_rev(int L, int n, int D, const double *in, double *out, hipStream_t st) {
+  const size_t tot = (size_t)L * n * D;
+  hipLaunchKernelGGL(series_to_rev_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, n, D, L, in, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_rev_to_series(int L, int n, int D, const double *in, double *out, hipStream_t st) {
+  const size_t tot = (size_t)L * n * D;
+  hipLaunchKernelGGL(rev_to_series_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, n, D, L, in, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_coef_grad(int L, int n, int D, int m, const int32_t *row_of, const double *lambda, const double *val,
+                            double *grad, hipStream_t st) {
+  MD_DISPATCH(L, hipLaunchKernelGGL(coef_grad_kernel<LL>, dim3((m + 63) / 64), dim3(64), 0, st, n, D, m, row_of,
+                                    lambda, val, grad));
+  return hipGetLastError();
+}
+
+hipError_t launch_unit_md(int L, int m, double *c, hipStream_t st) {
+  hipLaunchKernelGGL(unit_md_kernel, dim3((L * m + 255) / 256), dim3(256), 0, st, L, m, c);
+  return hipGetLastError();
+}
+
+hipError_t launch_dot(int L, int64_t count, const double *a, const double *b, double *c, hipStream_t st) {
+  MD_DISPATCH(L, hipLaunchKernelGGL(dot_kernel<LL>, dim3(1), dim3(256), 0, st, count, a, b, c));
   return hipGetLastError();
 }
 

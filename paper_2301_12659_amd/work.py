@@ -4,7 +4,9 @@ Counts are the multiple-double operations the method must perform (unpadded
 truncated convolutions: D(D+1)/2 multiply-adds per series product, the
 paper pads to D^2, Section 5.1), expressed as double flops with the
 instruction and flop counts of this library's own generated routines
-(csrc/md_counts.json; a fused multiply-add counts as two flops).
+(csrc/md_counts.json; a fused multiply-add counts as two flops).  A
+convolution output is a multiple-double dot product: its multiply-adds are
+accumulated as level sums ("fma_lazy") and renormalized once ("renorm").
 """
 from __future__ import annotations
 
@@ -59,7 +61,8 @@ def step_work(sys) -> dict:
         conv += n * (maxexp - 2)         # power table
     tri = D * (D + 1) // 2
     w = {}
-    w["convolutions"] = {"fma": conv * tri, "mul": scal * D, "products": conv, "scalar_products": scal}
+    w["convolutions"] = {"fma_lazy": conv * tri, "renorm": conv * D, "mul": scal * D, "products": conv,
+                         "scalar_products": scal}
     # assembly: additions into b and A
     m = len(sys.mon_ptr) - 1
     nnz = len(sys.var)
@@ -72,11 +75,10 @@ def step_work(sys) -> dict:
     w["updates"] = {"fma": upd}
     w["x_update"] = {"add": n * D}
     cost = md_costs(L)
+    ops = ("fma", "fma_lazy", "renorm", "mul", "add")
     for cls, d in w.items():
-        fl = d.get("fma", 0) * cost["fma"]["flops"] + d.get("mul", 0) * cost["mul"]["flops"] + \
-            d.get("add", 0) * cost["add"]["flops"]
-        ins = d.get("fma", 0) * cost["fma"]["instr"] + d.get("mul", 0) * cost["mul"]["instr"] + \
-            d.get("add", 0) * cost["add"]["instr"]
+        fl = sum(d.get(o, 0) * cost[o]["flops"] for o in ops)
+        ins = sum(d.get(o, 0) * cost[o]["instr"] for o in ops)
         d["flops"] = int(fl)
         d["instr"] = int(ins)
     return w

@@ -414,3 +414,79 @@ def test_manufactured_solution_is_a_root():
     # only the rounding of c_{i,0} to four limbs remains
     assert np.max(np.abs(b[0]).max(axis=1) / scale) < 2.0 ** -205
     assert oracle.inexact_inputs() == 0
+
+
+# --------------------------------------------------------------------------
+# 9. the adjoint: transposed block solve and coefficient gradients
+# --------------------------------------------------------------------------
+
+def _dot_exact(a, b):
+    ea, eb = exact(a), exact(b)
+    return sum((ea.flat[q] * eb.flat[q] for q in range(ea.size)), Fraction(0))
+
+
+def test_adjoint_dot_product_identity():
+    """<T^{-1} u, v> = <u, T^{-T} v> for the block Toeplitz T (two different
+    solves: forward block substitution with LU of A_0, backward with LU of A_0^T)."""
+    rng = np.random.default_rng(21)
+    L, n, D = 4, 4, 6
+    A = mdinputs.random_md(rng, L, (D, n, n), -1.0, 1.0)
+    A[0, 0] += 4 * np.eye(n)
+    u = mdinputs.random_md(rng, L, (n, D), -1.0, 1.0)
+    v = mdinputs.random_md(rng, L, (n, D), -1.0, 1.0)
+    K = 16
+    x = oracle.toeplitz_solve(A, u, K=K, prec=900)
+    y = oracle.adjoint_solve(A, v, K=K, prec=900)
+    lhs, rhs = _dot_exact(x, np.concatenate([v, np.zeros((K - L, n, D))])), \
+        _dot_exact(np.concatenate([u, np.zeros((K - L, n, D))]), y)
+    assert abs(lhs - rhs) <= abs(lhs) * Fraction(1, 2 ** 800)
+    # and a transposition slip would be seen
+    At = np.ascontiguousarray(np.swapaxes(A, 2, 3))
+    y2 = oracle.adjoint_solve(At, v, K=K, prec=900)
+    assert abs(_dot_exact(np.concatenate([u, np.zeros((K - L, n, D))]), y2) - lhs) > abs(lhs) * Fraction(1, 2 ** 40)
+
+
+def test_adjoint_gradient_closed_form():
+    """c x^2 = 1 + t: x = sqrt((1+t)/c), dx/dc = -x/(2c), so for L = sum_{k>=2} x_k^2
+    dL/dc = -sum_{k>=2} x_k^2 / c."""
+    L, d = 4, 7
+    D = d + 1
+    c = Fraction(5, 4)
+    sys = make(L, 1, d, [[(c, [(0, 2)])]])
+    cst = series_md([[-1, -1] + [0] * (D - 2)], L)
+    x0 = np.zeros((L, 1, D))
+    x0[0, 0, 0] = 0.9
+    x = oracle.converge(sys, sys.cff, cst, x0, 7, K=18)
+    xr = oracle.round_md(x, L)
+    g = oracle.loss_top_grad(x, 2)
+    out = oracle.newton_step(sys, sys.cff, cst, xr, want_A=True, K=18)
+    lam = oracle.adjoint_solve(oracle.round_md(out["A"], L), oracle.round_md(g, L), K=18)
+    grad = oracle.coef_grad(sys, xr, lam, K=18)
+    ex = exact(x)
+    ref = -sum((ex[0, k] ** 2 for k in range(2, D)), Fraction(0)) / c
+    assert abs(exact(grad)[0] - ref) <= abs(ref) * Fraction(1, 10 ** 55)
+
+
+def test_adjoint_gradient_matches_finite_differences():
+    """Central differences of L(c) = sum_{k>=ktop} x_{i,k}(c)^2 at 1000 bits with
+    h = 2^-150, Newton carried to convergence in the oracle, against the adjoint."""
+    sys = mdinputs.tiny(4, 3, 5, mons=2, kmin=1, kmax=3, exps=(1, 2), seed=4)
+    cst = oracle.manufacture(sys)
+    K, prec, ktop = 24, 1200, 3
+    x = oracle.converge(sys, sys.cff, cst, sys.start(), 6, K=K, prec=prec)
+    out = oracle.newton_step(sys, sys.cff, cst, x, want_A=True, K=K, prec=prec)
+    g = oracle.loss_top_grad(x, ktop)
+    lam = oracle.adjoint_solve(out["A"], g, K=K, prec=prec)
+    grad = exact(oracle.coef_grad(sys, x, lam, K=K, prec=prec))
+    h = Fraction(1, 2 ** 150)
+    for mj in (0, 2, sys.m - 1):
+        vals = []
+        for sgn in (1, -1):
+            cf = np.concatenate([sys.cff, np.zeros((K - sys.L, sys.m))])
+            cf[sys.L, mj] = float(sgn * h)  # c_m +- h as an extra limb, exact
+            cs = np.concatenate([cst, np.zeros((K - sys.L, sys.n, sys.D))])
+            xp = oracle.converge(sys, cf, cs, sys.start(), 7, K=K, prec=prec)
+            ex = exact(xp)
+            vals.append(sum((ex[i, k] ** 2 for i in range(sys.n) for k in range(ktop, sys.D)), Fraction(0)))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        assert abs(fd - grad[mj]) <= abs(grad[mj]) * Fraction(1, 10 ** 70) + Fraction(1, 10 ** 80), mj
