@@ -129,6 +129,24 @@ int md_series_solve(int prec, int n, int d, const double *qr, const double *tau,
 int md_newton_step(const md_plan *plan, const double *cff, const double *cst, double *x, int32_t *dev_status,
                    double *dev_norms, void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* One Newton step in mixed precision.  The introduction (Section 1) recalls
+ * that the early coefficients must be computed more accurately than the late
+ * ones, and Section 1.2 places multiple doubles in the trend of mixed
+ * precision.  Here the residual b = -p(x) (monomial values, forward products
+ * only), the update x := x + dx and the norms are computed at the plan's
+ * precision L, while the Jacobian series (backward and cross products), the
+ * QR of A_0 and the staged solve run at prec_solve limbs (MD_DD or MD_QD,
+ * at most L).  Since b carries all of x's accuracy, repeated steps converge
+ * to the same solution as md_newton_step; each step reduces the error by
+ * about the solve precision times the condition of A_0, so a few more steps
+ * are needed than in the plain iteration.  The Ls-limb truncations of x, cff
+ * and b are their leading limb planes (limb-major storage), so no copies are
+ * made.  Arguments, workspace (md_workspace_size of the plan), status and
+ * norms as md_newton_step; prec_solve == L is md_newton_step.  MD_EINVAL for
+ * a prec_solve that is not a precision or exceeds the plan's. */
+int md_newton_step_mixed(const md_plan *plan, int prec_solve, const double *cff, const double *cst, double *x,
+                         int32_t *dev_status, double *dev_norms, void *ws, size_t ws_bytes, hipStream_t stream);
+
 /* Elementwise multiple-double arithmetic on device arrays of count elements
  * (limb-major [L][count]): op 0 add, 1 sub, 2 mul, 3 div, 4 sqrt (of a),
  * 5 fused c := c + a*b; op 6 is the dot product c[0] = sum_q a[q] b[q]

@@ -42,6 +42,7 @@ _lib.md_qr.argtypes = [_i32, _i32, _vp, _vp, _vp, ctypes.c_size_t, _vp, _vp]
 _lib.md_solve_workspace_size.argtypes = [_i32, _i32, _i32, _szp]
 _lib.md_series_solve.argtypes = [_i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp, _vp]
 _lib.md_newton_step.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
+_lib.md_newton_step_mixed.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
 _lib.md_arith.argtypes = [_i32, _i32, ctypes.c_int64, _vp, _vp, _vp, _vp]
 _lib.md_last_error.restype = ctypes.c_char_p
 _lib.md_adjoint_workspace_size.argtypes = [_i32, _i32, _i32, _szp]
@@ -189,6 +190,15 @@ def newton_step(plan: Plan, cff, cst, x, status, norms, ws, stream=None):
     _check(rc, "md_newton_step")
 
 
+def newton_step_mixed(plan: Plan, prec_solve, cff, cst, x, status, norms, ws, stream=None):
+    L, n, D, m = plan.prec, plan.n, plan.D, plan.m
+    rc = _lib.md_newton_step_mixed(plan._h, int(prec_solve), _ptr(cff, (L, m), "cff"), _ptr(cst, (L, n, D), "cst"),
+                                   _ptr(x, (L, n, D), "x"), _ptr(status, (1,), "status"),
+                                   _ptr(norms, (2, D), "norms"), _ptr(ws, None, "ws"), ws.numel() * 8,
+                                   _stream(stream))
+    _check(rc, "md_newton_step_mixed")
+
+
 def arith(prec, op, a, b, c, stream=None):
     """Elementwise c = a op b on [L, count] md arrays; op "dot" writes sum_q a[q] b[q] to c [L, 1]."""
     L = int(prec)
@@ -258,8 +268,14 @@ class Newton:
         self.status = torch.zeros(1, dtype=torch.int32, device=device)
         self.norms = torch.zeros((2, sys.D), dtype=torch.float64, device=device)
 
-    def step(self, stream=None):
-        newton_step(self.plan, self.cff, self.cst, self.x, self.status, self.norms, self.ws, stream)
+    def step(self, stream=None, prec_solve=None):
+        """One Newton step; prec_solve below the system's precision runs the
+        mixed-precision step (md_newton_step_mixed)."""
+        if prec_solve is None or prec_solve == self.plan.prec:
+            newton_step(self.plan, self.cff, self.cst, self.x, self.status, self.norms, self.ws, stream)
+        else:
+            newton_step_mixed(self.plan, prec_solve, self.cff, self.cst, self.x, self.status, self.norms, self.ws,
+                              stream)
 
     def status_code(self):
         return int(self.status.item())

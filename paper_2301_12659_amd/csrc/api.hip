@@ -362,12 +362,16 @@ int md_series_solve(int prec, int n, int d, const double *qr, const double *tau,
   return series_solve_impl(prec, n, d + 1, qr, tau, A, rhs_dx, ws, st, dev_status);
 }
 
-int md_newton_step(const md_plan *p, const double *cff, const double *cst, double *x, int32_t *dev_status,
-                   double *dev_norms, void *ws, size_t ws_bytes, hipStream_t st) {
-  if (!p || !cst || !x || (p->m > 0 && !cff)) return fail(MD_EINVAL, "NULL argument");
+// One Newton step with the residual b = -p(x) at the plan's precision L and
+// the Jacobian series, the QR of A_0 and the staged solve at Ls <= L limbs.
+// Limb-major storage makes the Ls-limb truncation of x, cff and b their
+// leading Ls limb planes, so the low-precision kernels read the same
+// buffers.  Ls == L is the plain step.
+static int newton_step_impl(const md_plan *p, int Ls, const double *cff, const double *cst, double *x,
+                            int32_t *dev_status, double *dev_norms, void *ws, hipStream_t st) {
   Layout w = newton_layout(p);
-  if (!ws || ws_bytes < w.total) return fail(MD_ENOSPACE, "workspace too small");
   const int L = p->L, n = p->n, D = p->D;
+  const bool mixed = Ls != L;
   hipError_t e;
   if ((e = mdk::launch_status_init(dev_status, st)) != hipSuccess) return hip_fail(e, "status");
   double *b = at(ws, w.b), *A = at(ws, w.A), *qr = at(ws, w.qr), *tau = at(ws, w.tau), *qt = at(ws, w.qt);
@@ -378,9 +382,9 @@ int md_newton_step(const md_plan *p, const double *cff, const double *cst, doubl
   {
     Timed t(MD_CLASS_QR, st);
     eval_args(p, cff, x, ws, 1, a);
-    if ((e = mdk::launch_evaldiff(L, a, p->maxexp, at(ws, w.pw), st)) != hipSuccess)
+    if ((e = mdk::launch_evaldiff(Ls, a, p->maxexp, at(ws, w.pw), st)) != hipSuccess)
       return hip_fail(e, "A_0 pre-pass");
-    if ((e = mdk::launch_assemble_A0(L, n, D, p->nnz, p->d_asm_ptr, p->d_asm_ent, a.der, qr, st)) != hipSuccess)
+    if ((e = mdk::launch_assemble_A0(Ls, n, D, p->nnz, p->d_asm_ptr, p->d_asm_ent, a.der, qr, st)) != hipSuccess)
       return hip_fail(e, "A_0 assembly");
   }
   // 2. fork: QR of A_0 with Q^T, then M = R^{-1} Q^T, on the second stream
@@ -388,41 +392,85 @@ int md_newton_step(const md_plan *p, const double *cff, const double *cst, doubl
   if ((e = hipStreamWaitEvent(p->aux, p->fork, 0)) != hipSuccess) return hip_fail(e, "fork wait");
   {
     Timed t(MD_CLASS_QR, p->aux);
-    if ((e = run_qr(L, n, qr, tau, qt, dev_status, at(ws, w.bar), p->aux)) != hipSuccess) return hip_fail(e, "qr");
+    if ((e = run_qr(Ls, n, qr, tau, qt, dev_status, at(ws, w.bar), p->aux)) != hipSuccess) return hip_fail(e, "qr");
   }
   {
     Timed t(MD_CLASS_QHB_BS, p->aux);
-    if ((e = mdk::launch_m_from_qt(L, n, qr, qt, invd, M, dev_status, p->aux)) != hipSuccess)
+    if ((e = mdk::launch_m_from_qt(Ls, n, qr, qt, invd, M, dev_status, p->aux)) != hipSuccess)
       return hip_fail(e, "M");
   }
   if ((e = hipEventRecord(p->join, p->aux)) != hipSuccess) return hip_fail(e, "join");
-  // 3. the full evaluation and differentiation on the caller's stream
-  int rc = eval_diff_impl(p, cff, cst, x, b, A, ws, st);
-  if (rc != MD_OK) return rc;
+  // 3. the full evaluation and differentiation on the caller's stream; mixed:
+  //    the values at L limbs for b, the derivatives at Ls limbs for A
+  if (!mixed) {
+    int rc = eval_diff_impl(p, cff, cst, x, b, A, ws, st);
+    if (rc != MD_OK) return rc;
+  } else {
+    eval_args(p, cff, x, ws, D, a);
+    a.values_only = 1;
+    {
+      Timed t(MD_CLASS_CONVOLUTIONS, st);
+      if ((e = mdk::launch_evaldiff(L, a, p->maxexp, at(ws, w.pw), st)) != hipSuccess)
+        return hip_fail(e, "residual evaluation");
+    }
+    {
+      Timed t(MD_CLASS_ASSEMBLY, st);
+      if ((e = mdk::launch_assemble_b(L, n, D, p->m, p->d_poly_ptr, cst, a.val, b, st)) != hipSuccess)
+        return hip_fail(e, "residual assembly");
+    }
+    a.values_only = 0;
+    {
+      Timed t(MD_CLASS_CONVOLUTIONS, st);
+      if ((e = mdk::launch_evaldiff(Ls, a, p->maxexp, at(ws, w.pw), st)) != hipSuccess)
+        return hip_fail(e, "Jacobian evaluation");
+    }
+    {
+      Timed t(MD_CLASS_ASSEMBLY, st);
+      if ((e = mdk::launch_assemble_A(Ls, n, D, p->nnz, p->d_asm_ptr, p->d_asm_ent, a.der, A, st)) != hipSuccess)
+        return hip_fail(e, "Jacobian assembly");
+    }
+  }
   const size_t nn = (size_t)n * n, nD = (size_t)n * D;
   double *At = at(ws, w.At), *dxT = at(ws, w.dxT);
   {
     Timed t(MD_CLASS_UPDATES, st);
-    if ((e = mdk::launch_transpose(L, A, At, nn, D, nn * D, nn * D, st)) != hipSuccess) return hip_fail(e, "A^T");
-    if ((e = mdk::launch_transpose(L, b, r, n, D, nD, nD, st)) != hipSuccess) return hip_fail(e, "b^T");
+    if ((e = mdk::launch_transpose(Ls, A, At, nn, D, nn * D, nn * D, st)) != hipSuccess) return hip_fail(e, "A^T");
+    if ((e = mdk::launch_transpose(Ls, b, r, n, D, nD, nD, st)) != hipSuccess) return hip_fail(e, "b^T");
   }
   // 4. join, N = M A_1, the staged solve
   if ((e = hipStreamWaitEvent(st, p->join, 0)) != hipSuccess) return hip_fail(e, "join wait");
   if (D > 1) {
     Timed t(MD_CLASS_GEMM, st);
-    if ((e = mdk::launch_gemm(L, n, M, At + nn, nn * D, N, st)) != hipSuccess) return hip_fail(e, "gemm");
+    if ((e = mdk::launch_gemm(Ls, n, M, At + nn, nn * D, N, st)) != hipSuccess) return hip_fail(e, "gemm");
   }
   {
     Timed t(MD_CLASS_UPDATES, st);
-    if ((e = mdk::launch_stages(L, n, D, M, N, At, r, dxT, st)) != hipSuccess) return hip_fail(e, "stages");
-    if ((e = mdk::launch_transpose(L, dxT, dx, D, n, nD, nD, st)) != hipSuccess) return hip_fail(e, "dx");
+    if ((e = mdk::launch_stages(Ls, n, D, M, N, At, r, dxT, st)) != hipSuccess) return hip_fail(e, "stages");
+    if ((e = mdk::launch_transpose(Ls, dxT, dx, D, n, nD, nD, st)) != hipSuccess) return hip_fail(e, "dx");
   }
   {
     Timed t(MD_CLASS_X_UPDATE, st);
-    if ((e = mdk::launch_update(L, n, D, b, dx, x, dev_norms, dev_status, st)) != hipSuccess)
-      return hip_fail(e, "update");
+    e = mixed ? mdk::launch_update_mixed(L, Ls, n, D, b, dx, x, dev_norms, dev_status, st)
+              : mdk::launch_update(L, n, D, b, dx, x, dev_norms, dev_status, st);
+    if (e != hipSuccess) return hip_fail(e, "update");
   }
   return MD_OK;
+}
+
+int md_newton_step(const md_plan *p, const double *cff, const double *cst, double *x, int32_t *dev_status,
+                   double *dev_norms, void *ws, size_t ws_bytes, hipStream_t st) {
+  if (!p || !cst || !x || (p->m > 0 && !cff)) return fail(MD_EINVAL, "NULL argument");
+  if (!ws || ws_bytes < newton_layout(p).total) return fail(MD_ENOSPACE, "workspace too small");
+  return newton_step_impl(p, p->L, cff, cst, x, dev_status, dev_norms, ws, st);
+}
+
+int md_newton_step_mixed(const md_plan *p, int prec_solve, const double *cff, const double *cst, double *x,
+                         int32_t *dev_status, double *dev_norms, void *ws, size_t ws_bytes, hipStream_t st) {
+  if (!p || !cst || !x || (p->m > 0 && !cff)) return fail(MD_EINVAL, "NULL argument");
+  if (!valid_prec(prec_solve) || prec_solve > p->L)
+    return fail(MD_EINVAL, "solve precision must be dd, qd or od and at most the plan's");
+  if (!ws || ws_bytes < newton_layout(p).total) return fail(MD_ENOSPACE, "workspace too small");
+  return newton_step_impl(p, prec_solve, cff, cst, x, dev_status, dev_norms, ws, st);
 }
 
 int md_adjoint_workspace_size(int prec, int n, int d, size_t *bytes) {

@@ -32,17 +32,55 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
-// Sum of an md value over `width` consecutive lanes (width a power of two <= 64),
-// butterfly order, result in every lane of the team.
+// Lane exchange by a DPP move (data-parallel primitive: a VALU operand
+// permutation, no LDS round trip) of both halves of a double.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// DPP controls: quad permutations [1,0,3,2] (xor 1) and [2,3,0,1] (xor 2),
+// half-row mirror (lane i <-> 7-i in a group of 8), row mirror (i <-> 15-i in
+// a row of 16).
+enum : int { DPP_XOR1 = 0xB1, DPP_XOR2 = 0x4E, DPP_HALF_MIRROR = 0x141, DPP_MIRROR = 0x140 };
+
+template <int L, int CTRL>
+__device__ __forceinline__ void team_step_dpp(double (&v)[L]) {
+  double o[L], s[L];
+#pragma unroll
+  for (int l = 0; l < L; ++l) o[l] = dpp_f64<CTRL>(v[l]);
+  MD<L>::add(v, o, s);
+  md::copy<L>(s, v);
+}
+
+template <int L>
+__device__ __forceinline__ void team_step_xor(double (&v)[L], int off) {
+  double o[L], s[L];
+#pragma unroll
+  for (int l = 0; l < L; ++l) o[l] = __shfl_xor(v[l], off, 64);
+  MD<L>::add(v, o, s);
+  md::copy<L>(s, v);
+}
+
+// Sum of an md value over `width` consecutive lanes (width a power of two <=
+// 64, teams aligned to their width), result in every lane of the team.  The
+// first four levels stay inside a row of 16 lanes and use DPP: exchanges
+// xor 1 and xor 2, then the two mirrors, which pair each lane with one in the
+// other half of its group of 8 (16); the partial sums are uniform over each
+// half by then, so that pairing completes the sum of the group.  Levels 16
+// and 32 cross rows and use the LDS permute.  All lanes of a team must be
+// active.
 template <int L>
 __device__ __forceinline__ void team_sum(double (&v)[L], int width) {
-  for (int off = width >> 1; off > 0; off >>= 1) {
-    double o[L], s[L];
-#pragma unroll
-    for (int l = 0; l < L; ++l) o[l] = __shfl_xor(v[l], off, 64);
-    MD<L>::add(v, o, s);
-    md::copy<L>(s, v);
-  }
+  if (width >= 2) team_step_dpp<L, DPP_XOR1>(v);
+  if (width >= 4) team_step_dpp<L, DPP_XOR2>(v);
+  if (width >= 8) team_step_dpp<L, DPP_HALF_MIRROR>(v);
+  if (width >= 16) team_step_dpp<L, DPP_MIRROR>(v);
+  if (width >= 32) team_step_xor<L>(v, 16);
+  if (width >= 64) team_step_xor<L>(v, 32);
 }
 
 // Record a device-side condition; the first error wins.

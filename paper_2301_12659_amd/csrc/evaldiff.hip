@@ -163,8 +163,9 @@ __global__ void __launch_bounds__(256, (L == 8) ? 1 : 2) evaldiff_kernel(EvalArg
   auto xoff = [&](int v) { return (size_t)v * D; };
   auto der_off = [&](int j) { return (size_t)(e0 + j) * D; };  // j: 0-based entry
 
+  const bool derivs = a.values_only == 0;
   // ---- backward chain: b_q for q = 2..k-1 parked in the slot of entry k-q (0-based k-q-1+... )
-  if (k >= 3) {
+  if (derivs && k >= 3) {
     double *B = buf[0], *X = buf[1], *Wb = buf[2];
     load_series(B, a.x, nD, xoff(a.var[e0 + k - 1]), L, Dc, lane, G);  // b_1 = x_{v_k}
     for (int q = 2; q <= k - 1; ++q) {
@@ -213,7 +214,9 @@ __global__ void __launch_bounds__(256, (L == 8) ? 1 : 2) evaldiff_kernel(EvalArg
   for (int j = 1; j <= k; ++j) {
     const int ej = j - 1;  // 0-based entry of v_j
     const int aj = a.exp[e0 + ej];
-    if (j < k) {
+    if (!derivs) {
+      // values only: the forward product below
+    } else if (j < k) {
       if (k - j == 1)
         load_series(V, a.x, nD, xoff(a.var[e0 + k - 1]), L, Dc, lane, G);  // b_1 = x_{v_k}
       else
@@ -406,6 +409,30 @@ hipError_t launch_assemble_A0(int L, int n, int D, int nnz, const int32_t *asm_p
 size_t evaldiff_lds_bytes(int L, int D) {
   const int G = worker_lanes(D);
   return (size_t)(256 / G) * 3 * L * (D + 1) * sizeof(double);
+}
+
+hipError_t launch_assemble_b(int L, int n, int D, int m, const int32_t *poly_ptr, const double *cst,
+                             const double *val, double *b, hipStream_t st) {
+  const size_t nD = (size_t)n * D;
+  switch (L) {
+    case 2: hipLaunchKernelGGL(assemble_b_kernel<2>, dim3((nD + 255) / 256), dim3(256), 0, st, n, D, m, poly_ptr, cst, val, b); break;
+    case 4: hipLaunchKernelGGL(assemble_b_kernel<4>, dim3((nD + 255) / 256), dim3(256), 0, st, n, D, m, poly_ptr, cst, val, b); break;
+    case 8: hipLaunchKernelGGL(assemble_b_kernel<8>, dim3((nD + 255) / 256), dim3(256), 0, st, n, D, m, poly_ptr, cst, val, b); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_assemble_A(int L, int n, int D, int nnz, const int32_t *asm_ptr, const int32_t *asm_ent,
+                             const double *der, double *A, hipStream_t st) {
+  const size_t nnD = (size_t)n * n * D;
+  switch (L) {
+    case 2: hipLaunchKernelGGL(assemble_A_kernel<2>, dim3((nnD + 255) / 256), dim3(256), 0, st, n, D, nnz, asm_ptr, asm_ent, der, A); break;
+    case 4: hipLaunchKernelGGL(assemble_A_kernel<4>, dim3((nnD + 255) / 256), dim3(256), 0, st, n, D, nnz, asm_ptr, asm_ent, der, A); break;
+    case 8: hipLaunchKernelGGL(assemble_A_kernel<8>, dim3((nnD + 255) / 256), dim3(256), 0, st, n, D, nnz, asm_ptr, asm_ent, der, A); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 template <int L>

@@ -11,6 +11,7 @@ struct EvalArgs {
   const int32_t *mon_ptr, *var, *exp, *order;
   const double *cff, *x, *pw;  // pw: powers x^p for p = 2..maxexp-1, [p-2][L][n][D]
   double *val, *der;           // val [L][m][D], der [L][nnz][D]
+  int values_only = 0;         // 1: monomial values only (no backward or cross products, der untouched)
 };
 
 // evaldiff.hip
@@ -19,6 +20,10 @@ hipError_t launch_assemble(int L, int n, int D, int m, int nnz, const int32_t *p
                            const int32_t *asm_ent, const double *cst, const double *val, const double *der,
                            double *b, double *A, hipStream_t st);
 size_t evaldiff_lds_bytes(int L, int D);
+hipError_t launch_assemble_b(int L, int n, int D, int m, const int32_t *poly_ptr, const double *cst,
+                             const double *val, double *b, hipStream_t st);
+hipError_t launch_assemble_A(int L, int n, int D, int nnz, const int32_t *asm_ptr, const int32_t *asm_ent,
+                             const double *der, double *A, hipStream_t st);
 hipError_t launch_assemble_A0(int L, int n, int D, int nnz, const int32_t *asm_ptr, const int32_t *asm_ent,
                               const double *der, double *a0, hipStream_t st);
 
@@ -41,6 +46,8 @@ hipError_t launch_stages(int L, int n, int D, const double *M, const double *N, 
                          double *dxT, hipStream_t st);
 hipError_t launch_update(int L, int n, int D, const double *b, const double *dx, double *x, double *norms,
                          int32_t *status, hipStream_t st);
+hipError_t launch_update_mixed(int L, int Ldx, int n, int D, const double *b, const double *dx, double *x,
+                               double *norms, int32_t *status, hipStream_t st);
 hipError_t launch_arith(int L, int op, int64_t count, const double *a, const double *b, double *c, hipStream_t st);
 hipError_t launch_copy(const double *src, double *dst, size_t count, hipStream_t st);
 hipError_t launch_series_to_rev(int L, int n, int D, const double *in, double *out, hipStream_t st);

@@ -28,33 +28,15 @@ __global__ void status_init_kernel(int32_t *status) {
 
 // ----------------------------------------------------------------- QR
 
-// Newton iteration counts from a double start (53 correct bits, doubling).
-template <int L> struct NewtonIters {
-  static constexpr int value = (L == 2) ? 2 : (L == 4) ? 3 : 4;
-};
-
 // Householder reflector of a column with squared norm nrm2 and leading entry
 // x0: beta = -sign(x0) ||x|| (sign(0) = +1), v = x / (x0 - beta) with v_0 = 1,
-// tau = (beta - x0) / beta.  Division-free: 1/||x|| by Newton's iteration
-// y := y + y (1 - a y^2) / 2 and 1/(x0 - beta) by r := r + r (1 - v0 r).
+// tau = (beta - x0) / beta.  Division-free: y = 1/||x|| and 1/(x0 - beta) by
+// the Newton steps above.
 template <int L>
 __device__ void reflector(const double (&nrm2)[L], const double (&x0)[L], double (&beta)[L], double (&tau)[L],
                           double (&inv)[L]) {
-  double y[L], t[L], u[L], one[L];
-  md::zero<L>(y);
-  md::zero<L>(one);
-  one[0] = 1.0;
-  y[0] = 1.0 / ::sqrt(nrm2[0]);
-#pragma unroll
-  for (int it = 0; it < NewtonIters<L>::value; ++it) {
-    MD<L>::mul(y, y, t);
-    MD<L>::mul(nrm2, t, u);
-    MD<L>::sub(one, u, t);
-    md::scale2<L>(t, 0.5);
-    MD<L>::mul(y, t, u);
-    MD<L>::add(y, u, t);
-    md::copy<L>(t, y);
-  }
+  double y[L];
+  md::rsqrt_newton<L>(nrm2, y);
   double alpha[L], v0[L];
   MD<L>::mul(nrm2, y, alpha);  // ||x||
   const bool nonneg = x0[0] >= 0.0;
@@ -63,18 +45,7 @@ __device__ void reflector(const double (&nrm2)[L], const double (&x0)[L], double
   MD<L>::sub(x0, beta, v0);
   MD<L>::mul(v0, y, tau);      // tau = -v0 / beta and 1/beta = -+ y
   if (!nonneg) md::neg<L>(tau, tau);
-  double r[L];
-  md::zero<L>(r);
-  r[0] = 1.0 / v0[0];
-#pragma unroll
-  for (int it = 0; it < NewtonIters<L>::value; ++it) {
-    MD<L>::mul(v0, r, t);
-    MD<L>::sub(one, t, u);
-    MD<L>::mul(r, u, t);
-    MD<L>::add(r, t, u);
-    md::copy<L>(u, r);
-  }
-  md::copy<L>(r, inv);
+  md::recip_newton<L>(v0, inv);
 }
 
 // Unblocked Householder QR in one workgroup of 1024 threads; a [L][n][n]
@@ -96,14 +67,18 @@ __device__ __forceinline__ bool grid_barrier(unsigned *counter, unsigned target,
   if (threadIdx.x == 0) {
     ok = 1;
     __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    // relaxed polling (an acquire load would invalidate the caches on every
+    // poll), one acquire fence once the count is reached
     long spins = 0;
-    while (__hip_atomic_load(counter, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
-      if (++spins > (1L << 24)) {
+    while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins > (1L << 22)) {
         set_status(status, MD_EHIP);
         ok = 0;
         break;
       }
     }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
   __syncthreads();
   return ok != 0;
@@ -262,14 +237,19 @@ __global__ void __launch_bounds__(256) qr_kernel(int n, double *a, double *tau, 
 
 // Bounded wait for a published flag (agent scope).  Returns false on time-out
 // (the status word then holds MD_EHIP and the caller's result is garbage).
+// The flag is polled with relaxed loads and a short sleep (an acquire load
+// would invalidate the caches on every poll, and a busy loop takes issue
+// slots from the waves sharing the CU); one acquire fence follows.
 __device__ __forceinline__ bool wait_flag(const int *flag, int32_t *status) {
   long spins = 0;
-  while (__hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0) {
-    if (++spins > (1L << 24)) {
+  while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+    __builtin_amdgcn_s_sleep(1);
+    if (++spins > (1L << 22)) {
       set_status(status, MD_EHIP);
       return false;
     }
   }
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   return true;
 }
 
@@ -287,6 +267,9 @@ template <int L>
 __global__ void __launch_bounds__(256) qr_lds_kernel(int n, double *a, double *tau, double *qt, int32_t *status,
                                                      int *flags, double *vboard, double *tboard) {
   extern __shared__ double lds[];
+  // this launch runs beside the evaluation kernel and is on the critical
+  // path: its wavefronts get the highest issue priority on a shared CU
+  __builtin_amdgcn_s_setprio(3);
   const int G = gridDim.x, g = blockIdx.x;
   const int ncols_total = qt ? 2 * n : n;  // [A_0 | I] or A_0 alone
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -362,8 +345,8 @@ __global__ void __launch_bounds__(256) qr_lds_kernel(int n, double *a, double *t
     }
     wave_sync();
     if (lane == 0) {
-      __atomic_thread_fence(__ATOMIC_RELEASE);  // board writes before the flag (agent scope)
-      __hip_atomic_store(&flags[c], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // board writes before the flag
+      __hip_atomic_store(&flags[c], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   };
 
@@ -796,15 +779,17 @@ __global__ void __launch_bounds__(256) dot_kernel(int64_t count, const double *a
     for (int l = 0; l < L; ++l) c[l] = part[0][l];
 }
 
-// x := x + dx, one thread per (i, s).
-template <int L>
+// x := x + dx, one thread per (i, s); dx may carry fewer limbs (Ldx <= L),
+// the update of a mixed-precision step.
+template <int L, int Ldx = L>
 __global__ void update_kernel(int n, int D, const double *dx, double *x) {
   const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t nD = (size_t)n * D;
   if (q >= nD) return;
-  double a[L], b[L], s[L];
+  double a[L], b[L], s[L], d[Ldx];
   ld<L>(x, nD, q, a);
-  ld<L>(dx, nD, q, b);
+  ld<Ldx>(dx, nD, q, d);
+  md::widen<Ldx>(d, b);
   MD<L>::add(a, b, s);
   st<L>(x, nD, q, s);
 }
@@ -977,6 +962,18 @@ hipError_t launch_update(int L, int n, int D, const double *b, const double *dx,
                          int32_t *status, hipStream_t st) {
   const size_t nD = (size_t)n * D;
   MD_DISPATCH(L, hipLaunchKernelGGL(update_kernel<LL>, dim3((nD + 255) / 256), dim3(256), 0, st, n, D, dx, x));
+  hipLaunchKernelGGL(norms_kernel, dim3((D + 63) / 64), dim3(64), 0, st, n, D, b, dx, norms, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_update_mixed(int L, int Ldx, int n, int D, const double *b, const double *dx, double *x,
+                               double *norms, int32_t *status, hipStream_t st) {
+  const size_t nD = (size_t)n * D;
+  const dim3 grid((nD + 255) / 256);
+  if (L == 4 && Ldx == 2) hipLaunchKernelGGL((update_kernel<4, 2>), grid, dim3(256), 0, st, n, D, dx, x);
+  else if (L == 8 && Ldx == 2) hipLaunchKernelGGL((update_kernel<8, 2>), grid, dim3(256), 0, st, n, D, dx, x);
+  else if (L == 8 && Ldx == 4) hipLaunchKernelGGL((update_kernel<8, 4>), grid, dim3(256), 0, st, n, D, dx, x);
+  else return hipErrorInvalidValue;
   hipLaunchKernelGGL(norms_kernel, dim3((D + 63) / 64), dim3(64), 0, st, n, D, b, dx, norms, status);
   return hipGetLastError();
 }

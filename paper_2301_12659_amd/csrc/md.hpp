@@ -118,4 +118,95 @@ template <int L> MD_INLINE void sqrt(const double (&a)[L], double (&y)[L]) {
   }
 }
 
+// Leading P limbs of an L-limb expansion (its truncation, within about
+// 2^(-53 P) relatively), and the way back with zero limbs.
+template <int P, int L>
+MD_INLINE void head(const double (&a)[L], double (&h)[P]) {
+#pragma unroll
+  for (int i = 0; i < P; ++i) h[i] = a[i];
+}
+template <int P, int L>
+MD_INLINE void widen(const double (&h)[P], double (&a)[L]) {
+#pragma unroll
+  for (int i = 0; i < L; ++i) a[i] = (i < P) ? h[i] : 0.0;
+}
+
+// c = x e at H limbs (H = 1: one double multiplication), widened to P limbs.
+template <int P, int H>
+MD_INLINE void correction(const double (&x)[P], const double (&e)[P], double (&c)[P]) {
+  if constexpr (H == 1) {
+    zero<P>(c);
+    c[0] = x[0] * e[0];
+  } else {
+    double xh[H], eh[H], ch[H];
+    head<H>(x, xh);
+    head<H>(e, eh);
+    MD<H>::mul(xh, eh, ch);
+    widen<H>(ch, c);
+  }
+}
+
+// Newton steps for 1/sqrt(a) and 1/v with precision doubling.  A step
+// y := y + y (1 - a y^2) / 2 (or r := r + r (1 - v r)) doubles the number of
+// correct bits, so the step that brings y from P/2 to P correct limbs runs at
+// P limbs; its residual 1 - a y^2 is below about 2^(-26.5 P), so the
+// correction y (1 - a y^2) / 2 needs only H = P/2 limbs of it, provided the
+// residual's leading H limbs are its leading H * 53 bits.  The sums here
+// leave zero limbs inside an expansion after a deep cancellation (a zero
+// limb 1 or 2 followed by significant ones), so a truncated residual can
+// hold fewer bits: at 2 and 4 limbs the last step below repairs that, at 8
+// limbs the correction is taken at full width.  After the doublings (53
+// bits from the double start, then 2, 4, 8 limbs) a last step at L limbs
+// with a one-limb correction brings the result to a few units in its last
+// limb.
+template <int L, int P, int H>
+MD_INLINE void rsqrt_step(const double (&a)[L], double (&y)[L]) {
+  double ap[P], yp[P], t[P], u[P], e[P], c[P], one[P];
+  head<P>(a, ap);
+  head<P>(y, yp);
+  zero<P>(one);
+  one[0] = 1.0;
+  MD<P>::mul(yp, yp, t);
+  MD<P>::mul(ap, t, u);
+  MD<P>::sub(one, u, e);
+  correction<P, H>(yp, e, c);
+  scale2<P>(c, 0.5);
+  MD<P>::add(yp, c, t);
+  widen<P>(t, y);
+}
+
+template <int L, int P, int H>
+MD_INLINE void recip_step(const double (&v)[L], double (&r)[L]) {
+  double vp[P], rp[P], t[P], e[P], c[P], one[P];
+  head<P>(v, vp);
+  head<P>(r, rp);
+  zero<P>(one);
+  one[0] = 1.0;
+  MD<P>::mul(vp, rp, t);
+  MD<P>::sub(one, t, e);
+  correction<P, H>(rp, e, c);
+  MD<P>::add(rp, c, t);
+  widen<P>(t, r);
+}
+
+template <int L>
+MD_INLINE void rsqrt_newton(const double (&a)[L], double (&y)[L]) {
+  zero<L>(y);
+  y[0] = 1.0 / ::sqrt(a[0]);
+  rsqrt_step<L, 2, 1>(a, y);
+  if constexpr (L >= 4) rsqrt_step<L, 4, 2>(a, y);
+  if constexpr (L >= 8) rsqrt_step<L, 8, 8>(a, y);
+  rsqrt_step<L, L, 1>(a, y);
+}
+
+template <int L>
+MD_INLINE void recip_newton(const double (&v)[L], double (&r)[L]) {
+  zero<L>(r);
+  r[0] = 1.0 / v[0];
+  recip_step<L, 2, 1>(v, r);
+  if constexpr (L >= 4) recip_step<L, 4, 2>(v, r);
+  if constexpr (L >= 8) recip_step<L, 8, 8>(v, r);
+  recip_step<L, L, 1>(v, r);
+}
+
 }  // namespace md
