@@ -81,7 +81,7 @@ size_t qr_scratch_bytes(int L, int n) {
 
 // Workspace regions, in doubles, each aligned to 256 bytes.
 struct Layout {
-  size_t val, der, pw, unit, b, A, qr, tau, qt, bar, invd, M, N, At, r, dxT, dx, total;
+  size_t val, der, pw, unit, b, A, qr, tau, qt, bar, invd, M, N, At, r, dxT, dx, sync, total;
 };
 
 Layout newton_layout(const md_plan *p) {
@@ -105,18 +105,20 @@ Layout newton_layout(const md_plan *p) {
   w.bar = take(qr_scratch_bytes(L, n) / sizeof(double) + 1);
   w.invd = take(L * n);
   w.M = take(L * n * n);
-  w.N = take(L * n * n);
+  w.N = take(2 * L * n * n);  // N = M A_1 and P = M A_2
   w.At = take(L * n * n * D);
   w.r = take(L * n * D);
   w.dxT = take(L * n * D);
   w.dx = take(L * n * D);
+  w.sync = take(mdk::stages_sync_ints(p->D) / 2 + 1);
   w.total = off;
   return w;
 }
 
 size_t solve_bytes(int L, int n, int D) {
-  return align_up((size_t)L * n * sizeof(double)) + 2 * align_up((size_t)L * n * n * sizeof(double)) +
-         align_up((size_t)L * n * n * D * sizeof(double)) + 2 * align_up((size_t)L * n * D * sizeof(double));
+  return align_up((size_t)L * n * sizeof(double)) + align_up((size_t)L * n * n * sizeof(double)) +
+         align_up((size_t)2 * L * n * n * sizeof(double)) + align_up((size_t)L * n * n * D * sizeof(double)) +
+         2 * align_up((size_t)L * n * D * sizeof(double)) + align_up((size_t)mdk::stages_sync_ints(D) * sizeof(int));
 }
 
 double *at(void *ws, size_t byte_off) { return reinterpret_cast<double *>(static_cast<char *>(ws) + byte_off); }
@@ -145,8 +147,9 @@ int series_solve_impl(int L, int n, int D, const double *qr, const double *tau, 
     return p;
   };
   const size_t nn = (size_t)n * n, nD = (size_t)n * D;
-  double *invd = take((size_t)L * n), *M = take((size_t)L * nn), *N = take((size_t)L * nn);
+  double *invd = take((size_t)L * n), *M = take((size_t)L * nn), *N = take((size_t)2 * L * nn);
   double *At = take((size_t)L * nn * D), *rT = take((size_t)L * nD), *dxT = take((size_t)L * nD);
+  int *sync = reinterpret_cast<int *>(take(mdk::stages_sync_ints(D) / 2 + 1));
   hipError_t e;
   {
     Timed t(MD_CLASS_QHB_BS, st);
@@ -159,11 +162,13 @@ int series_solve_impl(int L, int n, int D, const double *qr, const double *tau, 
   }
   if (D > 1) {
     Timed t(MD_CLASS_GEMM, st);
-    if ((e = mdk::launch_gemm(L, n, M, At + nn, nn * D, N, st)) != hipSuccess) return hip_fail(e, "gemm");
+    if ((e = mdk::launch_gemm(L, n, M, At + nn, nn * D, N, mdk::stages_products(L, n, D), st)) != hipSuccess)
+      return hip_fail(e, "gemm");
   }
   {
     Timed t(MD_CLASS_UPDATES, st);
-    if ((e = mdk::launch_stages(L, n, D, M, N, At, rT, dxT, st)) != hipSuccess) return hip_fail(e, "stages");
+    if ((e = mdk::launch_stages(L, n, D, M, N, At, rT, dxT, sync, status, st)) != hipSuccess)
+      return hip_fail(e, "stages");
     if ((e = mdk::launch_transpose(L, dxT, rhs_dx, D, n, nD, nD, st)) != hipSuccess) return hip_fail(e, "dx");
   }
   return MD_OK;
@@ -441,11 +446,14 @@ static int newton_step_impl(const md_plan *p, int Ls, const double *cff, const d
   if ((e = hipStreamWaitEvent(st, p->join, 0)) != hipSuccess) return hip_fail(e, "join wait");
   if (D > 1) {
     Timed t(MD_CLASS_GEMM, st);
-    if ((e = mdk::launch_gemm(Ls, n, M, At + nn, nn * D, N, st)) != hipSuccess) return hip_fail(e, "gemm");
+    if ((e = mdk::launch_gemm(Ls, n, M, At + nn, nn * D, N, mdk::stages_products(Ls, n, D), st)) != hipSuccess)
+      return hip_fail(e, "gemm");
   }
   {
     Timed t(MD_CLASS_UPDATES, st);
-    if ((e = mdk::launch_stages(Ls, n, D, M, N, At, r, dxT, st)) != hipSuccess) return hip_fail(e, "stages");
+    if ((e = mdk::launch_stages(Ls, n, D, M, N, At, r, dxT, reinterpret_cast<int *>(at(ws, w.sync)), dev_status,
+                                st)) != hipSuccess)
+      return hip_fail(e, "stages");
     if ((e = mdk::launch_transpose(Ls, dxT, dx, D, n, nD, nD, st)) != hipSuccess) return hip_fail(e, "dx");
   }
   {
@@ -477,7 +485,9 @@ int md_adjoint_workspace_size(int prec, int n, int d, size_t *bytes) {
   if (!bytes || !valid_prec(prec) || n < 1 || n > MD_MAX_DIM || d < 0 || d + 1 > MD_MAX_COEFFS)
     return fail(MD_EINVAL, "bad argument");
   const size_t L = prec, nn = (size_t)n * n, nD = (size_t)n * (d + 1);
-  *bytes = align_up(L * n * 8) + 3 * align_up(L * nn * 8) + 2 * align_up(L * nn * (d + 1) * 8) + 2 * align_up(L * nD * 8);
+  *bytes = align_up(L * n * 8) + 2 * align_up(L * nn * 8) + align_up(2 * L * nn * 8) +
+           2 * align_up(L * nn * (d + 1) * 8) + 2 * align_up(L * nD * 8) +
+           align_up((size_t)mdk::stages_sync_ints(d + 1) * sizeof(int));
   return MD_OK;
 }
 
@@ -495,17 +505,21 @@ int md_adjoint_solve(int prec, int n, int d, const double *qr, const double *tau
     off += align_up(doubles * sizeof(double));
     return p;
   };
-  double *invd = take((size_t)L * n), *M = take((size_t)L * nn), *Mt = take((size_t)L * nn), *Nt = take((size_t)L * nn);
+  double *invd = take((size_t)L * n), *M = take((size_t)L * nn), *Mt = take((size_t)L * nn),
+         *Nt = take((size_t)2 * L * nn);
   double *At = take((size_t)L * nn * D), *AtT = take((size_t)L * nn * D), *rho = take((size_t)L * nD),
          *lamT = take((size_t)L * nD);
+  int *sync = reinterpret_cast<int *>(take(mdk::stages_sync_ints(D) / 2 + 1));
   hipError_t e;
   if ((e = mdk::launch_form_m(L, n, qr, tau, invd, M, dev_status, st)) != hipSuccess) return hip_fail(e, "form M");
   if ((e = mdk::launch_transpose(L, M, Mt, n, n, nn, nn, st)) != hipSuccess) return hip_fail(e, "M^T");
   if ((e = mdk::launch_transpose(L, A, At, nn, D, nn * D, nn * D, st)) != hipSuccess) return hip_fail(e, "A^T");
   if ((e = mdk::launch_transpose(L * D, At, AtT, n, n, nn, nn, st)) != hipSuccess) return hip_fail(e, "A_k^T");
-  if (D > 1 && (e = mdk::launch_gemm(L, n, Mt, AtT + nn, nn * D, Nt, st)) != hipSuccess) return hip_fail(e, "gemm");
+  if ((e = mdk::launch_gemm(L, n, Mt, AtT + nn, nn * D, Nt, mdk::stages_products(L, n, D), st)) != hipSuccess)
+    return hip_fail(e, "gemm");
   if ((e = mdk::launch_series_to_rev(L, n, D, g_lambda, rho, st)) != hipSuccess) return hip_fail(e, "reverse");
-  if ((e = mdk::launch_stages(L, n, D, Mt, Nt, AtT, rho, lamT, st)) != hipSuccess) return hip_fail(e, "stages");
+  if ((e = mdk::launch_stages(L, n, D, Mt, Nt, AtT, rho, lamT, sync, dev_status, st)) != hipSuccess)
+    return hip_fail(e, "stages");
   if ((e = mdk::launch_rev_to_series(L, n, D, lamT, g_lambda, st)) != hipSuccess) return hip_fail(e, "reverse");
   return MD_OK;
 }

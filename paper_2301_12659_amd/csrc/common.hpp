@@ -25,6 +25,29 @@ __device__ __forceinline__ void st(double *base, size_t stride, size_t q, const 
   for (int l = 0; l < L; ++l) base[(size_t)l * stride + q] = v[l];
 }
 
+// Agent-scope relaxed loads and stores (no fences).  They bypass the caches
+// that are not coherent across the chip (global_load/store with sc1), so a
+// value handed from one workgroup of a running kernel to another is seen
+// without cache maintenance: the writer stores with st_agent, waits for its
+// stores (wait_vm), then raises a flag; the reader polls the flag and then
+// loads with ld_agent.  A release or acquire fence would instead write back
+// or invalidate a whole L2 at every hand-over.
+template <int L>
+__device__ __forceinline__ void ld_agent(const double *base, size_t stride, size_t q, double (&v)[L]) {
+#pragma unroll
+  for (int l = 0; l < L; ++l) v[l] = __hip_atomic_load(base + (size_t)l * stride + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int L>
+__device__ __forceinline__ void st_agent(double *base, size_t stride, size_t q, const double (&v)[L]) {
+#pragma unroll
+  for (int l = 0; l < L; ++l) __hip_atomic_store(base + (size_t)l * stride + q, v[l], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wait until this wave's outstanding memory operations have completed (for
+// agent-scope stores: performed at the agent's coherence point).
+__device__ __forceinline__ void wait_vm() { __builtin_amdgcn_s_waitcnt(0); }
+
 // Order this wave's LDS and global memory operations (all lanes of a worker
 // group live in one wavefront, so no workgroup barrier is needed).
 __device__ __forceinline__ void wave_sync() {

@@ -41,9 +41,18 @@ hipError_t launch_form_m(int L, int n, const double *qr, const double *tau, doub
 hipError_t launch_extract(int L, int n, int D, int k, const double *A, double *out, hipStream_t st);
 hipError_t launch_transpose(int L, const double *in, double *out, size_t rows, int cols, size_t in_ls,
                             size_t out_ls, hipStream_t st);
-hipError_t launch_gemm(int L, int n, const double *M, const double *B, size_t b_ls, double *N, hipStream_t st);
-hipError_t launch_stages(int L, int n, int D, const double *M, const double *N, const double *At, double *rT,
-                         double *dxT, hipStream_t st);
+// out + c L n^2 = M (B + c n^2) for c < count (B with limb stride b_ls).
+hipError_t launch_gemm(int L, int n, const double *M, const double *B, size_t b_ls, double *out, int count,
+                       hipStream_t st);
+// Staged solve of the block Toeplitz system on coefficient-major arrays.
+// NP holds N = M A_1 and, when stages_products() is 2, P = M A_2 after it
+// (L n^2 doubles each); sync is scratch of stages_sync_ints(D) ints.  One
+// persistent launch when stages_persistent(), else one launch per stage.
+bool stages_persistent(int L, int n, int D);
+int stages_sync_ints(int D);
+int stages_products(int L, int n, int D);
+hipError_t launch_stages(int L, int n, int D, const double *M, const double *NP, const double *At, double *rT,
+                         double *dxT, int *sync, int32_t *status, hipStream_t st);
 hipError_t launch_update(int L, int n, int D, const double *b, const double *dx, double *x, double *norms,
                          int32_t *status, hipStream_t st);
 hipError_t launch_update_mixed(int L, int Ldx, int n, int D, const double *b, const double *dx, double *x,

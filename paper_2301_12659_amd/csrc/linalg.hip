@@ -15,6 +15,8 @@
 // only work that waits for dx_{k-1} is one matrix-vector product per row; in
 // the same launch every later right-hand side r_m (m > k) receives its term
 // A_{m-k+1} dx_{k-1}.  Every stage is one launch over the whole GPU.
+#include <algorithm>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -409,13 +411,17 @@ __global__ void __launch_bounds__(256) qr_lds_kernel(int n, double *a, double *t
     // teams 0..3 form wavefront 0, busy with the look-ahead column
     const int t0 = ahead ? team - 4 : team, nt = ahead ? (blockDim.x / T) - 4 : blockDim.x / T;
     if (!(ahead && w == 0)) {
-      int k = 0;
-      for (int q = 0; q < ncol; ++q) {
-        const int J = g + q * G;
-        if (J < n && J <= c) continue;  // finished columns of R
-        if (q == qa) continue;
-        if (k % nt == t0) apply(q, c, tc, tl, T);
-        ++k;
+      // live columns: owned A columns J > c (a suffix q >= q0 of the owned
+      // ones) and every owned Q^T column, without the look-ahead column qa.
+      // Team t0 takes the live columns t0, t0 + nt, ...: the teams of one
+      // wavefront step through their columns together (no serialization of
+      // the teams of a wavefront by divergent branches)
+      const int q0 = (c >= g) ? (c - g) / G + 1 : 0;
+      const int nlive = ncol - q0 - (ahead ? 1 : 0);
+      for (int k = t0; k < nlive; k += nt) {
+        int q = q0 + k;
+        if (ahead && q >= qa) ++q;
+        apply(q, c, tc, tl, T);
       }
     }
     __syncthreads();
@@ -615,6 +621,10 @@ __global__ void __launch_bounds__(256) transpose_kernel(const double *in, double
 template <int L>
 __global__ void __launch_bounds__(256) gemm_kernel(int n, const double *M, const double *B, size_t b_ls, double *N) {
   const int T = 16;
+  // blockIdx.y selects the product: B + y n^2 (the next series coefficient)
+  // into N + y L n^2
+  B += (size_t)blockIdx.y * n * n;
+  N += (size_t)blockIdx.y * L * n * n;
   const size_t task = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) / T;
   const int tl = threadIdx.x & (T - 1);
   const size_t nn = (size_t)n * n;
@@ -692,6 +702,193 @@ __global__ void __launch_bounds__(256) stage_kernel(int n, int D, int k, const d
     ld<L>(rT, nD, (size_t)mm * n + i, rv);
     MD<L>::sub(rv, r, s2);
     st<L>(rT, nD, (size_t)mm * n + i, s2);
+  }
+}
+
+// Bounded wait until *ctr >= target (relaxed polling with a short sleep, one
+// agent-scope acquire fence after).  On time-out the status word gets MD_EHIP.
+template <int SLEEP = 1>
+__device__ __forceinline__ bool wait_geq(const int *ctr, int target, int32_t *status) {
+  long spins = 0;
+  while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    __builtin_amdgcn_s_sleep(SLEEP);
+    if (++spins > (1L << 22)) {
+      set_status(status, MD_EHIP);
+      return false;
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return true;
+}
+
+// Counters of the persistent staged solve, one per 256 bytes so that the
+// polls of one do not contend with the updates of another.
+constexpr int SYNC_STRIDE = 64;
+
+// The whole staged solve in one launch, for n <= 64.  With P = M A_2 the
+// recurrence is reassociated once more,
+//     dx_k = M r'_k - N dx_{k-1} - P dx_{k-2},  r'_k = b_k - sum_{j>=3} A_j dx_{k-j},
+// so that a stage only needs right-hand-side terms at least two stages old.
+// Solver workgroups 0 .. Gs-1 (Gs = ceil(n/4)): wavefront w of solver s owns
+// row i = 4 s + w and keeps M(i,.), N(i,.), P(i,.) in registers (lane v holds
+// column v); stage k is one dot product of length 3n per row.  (One
+// workgroup cannot carry the stage: its n x 3n multiply-adds would keep one
+// CU busy for several microseconds.)  After its rows of dx_k are in dxT,
+// solver s sets its flag to k + 1; a wavefront waits for all solvers with
+// one lane per flag and a vote.  The last workgroup (a forwarder) turns the
+// flags into one count, which the updaters poll with a longer sleep (they
+// have two stages of slack).  Updater (g, b) owns the rows 16 b .. 16 b + 15
+// (one team of 16 lanes per row) of the coefficients m = 3 + g + j Gm; in
+// round q, once dx_q is out, it applies r'_m -= A_{m-q} dx_q to its
+// m >= q + 3 and adds 1 to their round counters; stage k waits for the
+// counter of m = k to reach Bm (k - 2).  Every (m, i) has one owner, so
+// rounds never update it concurrently.  Everything handed between
+// workgroups (dx, r', flags) goes through agent-scope loads and stores and a
+// wait for the stores before the flag, never through fences: a fence would
+// write back or invalidate a whole L2 at every hand-over, hundreds of them
+// per stage.  Counters sit 256 bytes apart.  All workgroups must be
+// resident together; waits are bounded and report MD_EHIP.
+template <int L>
+__global__ void __launch_bounds__(256) stages_persistent_kernel(int n, int D, int Gs, int Gm, const double *M,
+                                                                const double *NP, const double *At, double *rT,
+                                                                double *dxT, int *sync, int32_t *status) {
+  __shared__ int sh_ok;
+  __shared__ double xq[L * 64];  // dx_q of an updater round
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const size_t nn = (size_t)n * n, nD = (size_t)n * D, nnD = nn * D;
+  const int Bm = (n + 15) / 16;
+  int *const forwarded = sync + SYNC_STRIDE;
+  auto rounds = [&](int m) { return sync + (size_t)(2 + m) * SYNC_STRIDE; };
+  auto solved = [&](int s) { return sync + (size_t)(2 + D + s) * SYNC_STRIDE; };  // stages done by solver s
+  auto poll = [&](const int *p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); };
+  // bounded wait until *p >= target by one thread
+  auto wait_one = [&](const int *p, int target, int sleep16) {
+    long spins = 0;
+    while (poll(p) < target) {
+      if (sleep16) __builtin_amdgcn_s_sleep(16);
+      else __builtin_amdgcn_s_sleep(1);
+      if (++spins > (1L << 22)) {
+        set_status(status, MD_EHIP);
+        return false;
+      }
+    }
+    return true;
+  };
+  // wavefront-wide wait until every solver has published stage k - 1: lane
+  // s polls solver s's flag, the wavefront votes
+  auto wait_solvers = [&](int k) {
+    long spins = 0;
+    while (true) {
+      const int f = lane < Gs ? poll(solved(lane)) : k;
+      if (__all(f >= k)) break;
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins > (1L << 22)) {
+        if (lane == 0) set_status(status, MD_EHIP);
+        return false;
+      }
+    }
+    return true;
+  };
+  if ((int)blockIdx.x < Gs) {
+    const int i = blockIdx.x * 4 + wv;
+    const bool row = i < n, col = lane < n;
+    const int ii = row ? i : 0, v = col ? lane : 0;
+    double m[L], nv[L], pv[L];
+    md::zero<L>(m);
+    md::zero<L>(nv);
+    md::zero<L>(pv);
+    if (col) {
+      ld<L>(M, nn, (size_t)ii * n + v, m);
+      if (D > 1) ld<L>(NP, nn, (size_t)ii * n + v, nv);
+      if (D > 2) ld<L>(NP + (size_t)L * nn, nn, (size_t)ii * n + v, pv);
+      md::neg<L>(nv, nv);
+      md::neg<L>(pv, pv);
+    }
+    double x1[L], x2[L];  // dx_{k-1}(v), dx_{k-2}(v)
+    md::zero<L>(x1);
+    md::zero<L>(x2);
+    for (int k = 0; k < D; ++k) {
+      if (wv == 0) {
+        bool ok = (k >= 1) ? wait_solvers(k) : true;
+        if (lane == 0) {
+          if (ok && k >= 3) ok = wait_one(rounds(k), Bm * (k - 2), 0);
+          sh_ok = ok ? 1 : 0;
+        }
+      }
+      __syncthreads();
+      if (!sh_ok) return;
+      double acc[L], r[L], a[L];
+      md::zero<L>(acc);
+      if (col) {
+        md::copy<L>(x1, x2);
+        if (k >= 1) ld_agent<L>(dxT, nD, (size_t)(k - 1) * n + v, x1);
+        ld_agent<L>(rT, nD, (size_t)k * n + v, a);
+        MD<L>::fma_lazy(acc, m, a);
+        if (k >= 1) MD<L>::fma_lazy(acc, nv, x1);
+        if (k >= 2) MD<L>::fma_lazy(acc, pv, x2);
+      }
+      MD<L>::renorm(acc, r);
+      team_sum<L>(r, 64);
+      if (row && lane == 0) st_agent<L>(dxT, nD, (size_t)k * n + i, r);
+      wait_vm();
+      __syncthreads();
+      if (tid == 64) __hip_atomic_store(solved(blockIdx.x), k + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    return;
+  }
+  if ((int)blockIdx.x == gridDim.x - 1) {  // forwarder
+    if (wv == 0)
+      for (int k = 1; k + 2 < D; ++k) {
+        if (!wait_solvers(k)) break;
+        if (lane == 0) __hip_atomic_store(forwarded, k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    return;
+  }
+  const int u = blockIdx.x - Gs, g = u / Bm, b = u - g * Bm;
+  const int team = tid / 16, tl = tid & 15;
+  const int i = b * 16 + team;
+  const int m_last = 3 + g + ((D - 1 - (3 + g)) / Gm) * Gm;  // largest owned coefficient
+  for (int q = 0; q + 3 <= m_last; ++q) {
+    if (tid == 0) sh_ok = wait_one(forwarded, q + 1, 1) ? 1 : 0;
+    __syncthreads();
+    if (!sh_ok) return;
+    for (int e = tid; e < L * n; e += blockDim.x) {
+      const int l = e / n, vv = e - l * n;
+      xq[l * 64 + vv] = __hip_atomic_load(dxT + (size_t)l * nD + (size_t)q * n + vv, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    int m0 = 3 + g;
+    while (m0 < q + 3) m0 += Gm;
+    for (int mm = m0; mm < D; mm += Gm) {
+      const double *Aj = At + (size_t)(mm - q) * nn;
+      double acc[L], r[L], rv[L];
+      md::zero<L>(acc);
+      // r'_m(i) was last written by this same lane (an earlier round) or by
+      // an earlier kernel
+      if (i < n && tl == 0) ld_agent<L>(rT, nD, (size_t)mm * n + i, rv);
+      if (i < n) {
+        for (int vv = tl; vv < n; vv += 16) {
+          double a[L], x[L];
+          ld<L>(Aj, nnD, (size_t)i * n + vv, a);
+#pragma unroll
+          for (int l = 0; l < L; ++l) x[l] = xq[l * 64 + vv];
+          MD<L>::fma_lazy(acc, a, x);
+        }
+      }
+      MD<L>::renorm(acc, r);
+      team_sum<L>(r, 16);
+      if (i < n && tl == 0) {
+        double s2[L];
+        MD<L>::sub(rv, r, s2);
+        st_agent<L>(rT, nD, (size_t)mm * n + i, s2);
+      }
+    }
+    wait_vm();
+    __syncthreads();
+    if (tid == 0)
+      for (int mm = m0; mm < D; mm += Gm)
+        __hip_atomic_fetch_add(rounds(mm), 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -795,23 +992,40 @@ __global__ void update_kernel(int n, int D, const double *dx, double *x) {
 }
 
 // norms[k] = max_i |b_{i,k}|, norms[D+k] = max_i |dx_{i,k}| (leading limbs);
-// a non-finite update is reported.
-__global__ void norms_kernel(int n, int D, const double *b, const double *dx, double *norms, int32_t *status) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= D) return;
+// a non-finite update is reported.  One workgroup of 256 threads per
+// coefficient k, rows strided over the threads, maxima reduced in LDS.
+__global__ void __launch_bounds__(256) norms_kernel(int n, int D, const double *b, const double *dx, double *norms,
+                                                    int32_t *status) {
+  __shared__ double sb[256], sx[256];
+  __shared__ int sf[256];
+  const int k = blockIdx.x, t = threadIdx.x;
   double nb = 0.0, nx = 0.0;
-  bool finite = true;
-  for (int i = 0; i < n; ++i) {
+  int finite = 1;
+  for (int i = t; i < n; i += blockDim.x) {
     const double bi = b[(size_t)i * D + k], xi = dx[(size_t)i * D + k];
-    finite = finite && isfinite(bi) && isfinite(xi);
+    finite &= (isfinite(bi) && isfinite(xi)) ? 1 : 0;
     nb = fmax(nb, fabs(bi));
     nx = fmax(nx, fabs(xi));
   }
-  if (norms) {
-    norms[k] = nb;
-    norms[D + k] = nx;
+  sb[t] = nb;
+  sx[t] = nx;
+  sf[t] = finite;
+  __syncthreads();
+  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+    if (t < h) {
+      sb[t] = fmax(sb[t], sb[t + h]);
+      sx[t] = fmax(sx[t], sx[t + h]);
+      sf[t] &= sf[t + h];
+    }
+    __syncthreads();
   }
-  if (!finite) set_status(status, MD_ENONFINITE);
+  if (t == 0) {
+    if (norms) {
+      norms[k] = sb[0];
+      norms[D + k] = sx[0];
+    }
+    if (!sf[0]) set_status(status, MD_ENONFINITE);
+  }
 }
 
 template <int L>
@@ -940,20 +1154,42 @@ hipError_t launch_transpose(int L, const double *in, double *out, size_t rows, i
   return hipGetLastError();
 }
 
-hipError_t launch_gemm(int L, int n, const double *M, const double *B, size_t b_ls, double *N, hipStream_t st) {
+hipError_t launch_gemm(int L, int n, const double *M, const double *B, size_t b_ls, double *N, int count,
+                       hipStream_t st) {
+  if (count <= 0) return hipSuccess;
   const size_t threads = (size_t)n * n * 16;
-  MD_DISPATCH(L, hipLaunchKernelGGL(gemm_kernel<LL>, dim3((threads + 255) / 256), dim3(256), 0, st, n, M, B, b_ls,
-                                    N));
+  MD_DISPATCH(L, hipLaunchKernelGGL(gemm_kernel<LL>, dim3((threads + 255) / 256, count), dim3(256), 0, st, n, M, B,
+                                    b_ls, N));
   return hipGetLastError();
 }
 
-hipError_t launch_stages(int L, int n, int D, const double *M, const double *N, const double *At, double *rT,
-                         double *dxT, hipStream_t st) {
+bool stages_persistent(int L, int n, int D) { return L <= 4 && n <= 64 && D >= 1; }
+
+int stages_sync_ints(int D) { return (D + 2 + 64) * SYNC_STRIDE; }
+
+int stages_products(int L, int n, int D) { return stages_persistent(L, n, D) ? std::min(2, D - 1) : std::min(1, D - 1); }
+
+hipError_t launch_stages(int L, int n, int D, const double *M, const double *NP, const double *At, double *rT,
+                         double *dxT, int *sync, int32_t *status, hipStream_t st) {
+  if (stages_persistent(L, n, D)) {
+    const int Gs = (n + 3) / 4, Bm = (n + 15) / 16;
+    const int Gm = D > 3 ? std::min(D - 3, 60) : 0;  // coefficient groups of the updaters
+    const int G = Gs + Gm * Bm + 1;                  // at most 16 + 240 + 1 workgroups of 256 threads
+    hipLaunchKernelGGL(zero_i32_kernel, dim3((stages_sync_ints(D) + 255) / 256), dim3(256), 0, st, sync,
+                       stages_sync_ints(D));
+    if (L == 2)
+      hipLaunchKernelGGL(stages_persistent_kernel<2>, dim3(G), dim3(256), 0, st, n, D, Gs, Gm, M, NP, At, rT, dxT,
+                         sync, status);
+    else
+      hipLaunchKernelGGL(stages_persistent_kernel<4>, dim3(G), dim3(256), 0, st, n, D, Gs, Gm, M, NP, At, rT, dxT,
+                         sync, status);
+    return hipGetLastError();
+  }
   const int crit_blocks = (n + 3) / 4;
   for (int k = 0; k < D; ++k) {
     const size_t bulk = (k == 0) ? 0 : (size_t)n * (D - k - 1) * 16;
     const unsigned blocks = (unsigned)(crit_blocks + (bulk + 255) / 256);
-    MD_DISPATCH(L, hipLaunchKernelGGL(stage_kernel<LL>, dim3(blocks), dim3(256), 0, st, n, D, k, M, N, At, rT, dxT));
+    MD_DISPATCH(L, hipLaunchKernelGGL(stage_kernel<LL>, dim3(blocks), dim3(256), 0, st, n, D, k, M, NP, At, rT, dxT));
   }
   return hipGetLastError();
 }
@@ -962,7 +1198,7 @@ hipError_t launch_update(int L, int n, int D, const double *b, const double *dx,
                          int32_t *status, hipStream_t st) {
   const size_t nD = (size_t)n * D;
   MD_DISPATCH(L, hipLaunchKernelGGL(update_kernel<LL>, dim3((nD + 255) / 256), dim3(256), 0, st, n, D, dx, x));
-  hipLaunchKernelGGL(norms_kernel, dim3((D + 63) / 64), dim3(64), 0, st, n, D, b, dx, norms, status);
+  hipLaunchKernelGGL(norms_kernel, dim3(D), dim3(256), 0, st, n, D, b, dx, norms, status);
   return hipGetLastError();
 }
 
@@ -974,7 +1210,7 @@ hipError_t launch_update_mixed(int L, int Ldx, int n, int D, const double *b, co
   else if (L == 8 && Ldx == 2) hipLaunchKernelGGL((update_kernel<8, 2>), grid, dim3(256), 0, st, n, D, dx, x);
   else if (L == 8 && Ldx == 4) hipLaunchKernelGGL((update_kernel<8, 4>), grid, dim3(256), 0, st, n, D, dx, x);
   else return hipErrorInvalidValue;
-  hipLaunchKernelGGL(norms_kernel, dim3((D + 63) / 64), dim3(64), 0, st, n, D, b, dx, norms, status);
+  hipLaunchKernelGGL(norms_kernel, dim3(D), dim3(256), 0, st, n, D, b, dx, norms, status);
   return hipGetLastError();
 }
 
