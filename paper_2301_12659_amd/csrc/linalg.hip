@@ -237,11 +237,24 @@ __global__ void __launch_bounds__(256) qr_kernel(int n, double *a, double *tau, 
   }
 }
 
+// Lanes of a butterfly over `rows` values held one per lane from lane 0
+// (at most 64; more rows than lanes use all 64): the smallest power of two
+// that covers them, so that short columns take fewer levels.
+__device__ __forceinline__ int red_width(int rows) {
+  int w = 1;
+  while (w < rows && w < 64) w <<= 1;
+  return w;
+}
+
 // Bounded wait for a published flag (agent scope).  Returns false on time-out
 // (the status word then holds MD_EHIP and the caller's result is garbage).
 // The flag is polled with relaxed loads and a short sleep (an acquire load
 // would invalidate the caches on every poll, and a busy loop takes issue
-// slots from the waves sharing the CU); one acquire fence follows.
+// slots from the waves sharing the CU); one acquire fence follows.  (Here a
+// release fence on the writer's side and an acquire fence on the reader's
+// are cheaper than agent-scope accesses to the board: only a few
+// workgroups take part, and the write-through stores would put a round trip
+// to memory on the critical path of every column.)
 __device__ __forceinline__ bool wait_flag(const int *flag, int32_t *status) {
   long spins = 0;
   while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
@@ -300,14 +313,18 @@ __global__ void __launch_bounds__(256) qr_lds_kernel(int n, double *a, double *t
   auto publish = [&](int q, int c) {
     double *cq = col(q);
     double acc[L];
-    md::zero<L>(acc);
-    for (int i = c + lane; i < n; i += 64) {
-      double xi[L];
+    {
+      double u[L];
+      md::zero<L>(u);
+      for (int i = c + lane; i < n; i += 64) {
+        double xi[L];
 #pragma unroll
-      for (int l = 0; l < L; ++l) xi[l] = cq[l * n + i];
-      MD<L>::fma(acc, xi, xi);
+        for (int l = 0; l < L; ++l) xi[l] = cq[l * n + i];
+        MD<L>::fma_lazy(u, xi, xi);
+      }
+      team_sum_lazy<L>(u, red_width(n - c));
+      MD<L>::renorm(u, acc);
     }
-    team_sum<L>(acc, 64);
     double x0[L], beta[L], tc[L], inv[L];
 #pragma unroll
     for (int l = 0; l < L; ++l) x0[l] = cq[l * n + c];
@@ -356,17 +373,21 @@ __global__ void __launch_bounds__(256) qr_lds_kernel(int n, double *a, double *t
   auto apply = [&](int q, int c, const double (&tc)[L], int tlane, int width) {
     double *cq = col(q);
     double dot[L];
-    md::zero<L>(dot);
-    for (int i = c + tlane; i < n; i += width) {
-      double vi[L], x[L];
+    {
+      double u[L];
+      md::zero<L>(u);
+      for (int i = c + tlane; i < n; i += width) {
+        double vi[L], x[L];
 #pragma unroll
-      for (int l = 0; l < L; ++l) {
-        vi[l] = vsh[l * n + i];
-        x[l] = cq[l * n + i];
+        for (int l = 0; l < L; ++l) {
+          vi[l] = vsh[l * n + i];
+          x[l] = cq[l * n + i];
+        }
+        MD<L>::fma_lazy(u, vi, x);
       }
-      MD<L>::fma(dot, vi, x);
+      team_sum_lazy<L>(u, width == 64 ? red_width(n - c) : width);
+      MD<L>::renorm(u, dot);
     }
-    team_sum<L>(dot, width);
     double wj[L];
     MD<L>::mul(dot, tc, wj);
     for (int i = c + tlane; i < n; i += width) {
@@ -582,6 +603,69 @@ __global__ void __launch_bounds__(64, 1) m_from_qt_kernel(int n, const double *q
   }
 }
 
+// Column c of M = R^{-1} Q^T for n <= 64, one wavefront per column with
+// row p in lane p.  The reciprocals 1/R_ii are formed here (lane i; the
+// singularity test of invdiag_kernel, reported by workgroup 0) and kept in
+// LDS, and the column R(., i-1) of the next step is loaded while step i
+// computes, so that no step waits for device memory.
+template <int L>
+__global__ void __launch_bounds__(64, 1) m_from_qt_small_kernel(int n, const double *qr, const double *qt, double *M,
+                                                             int32_t *status) {
+  __shared__ double dinv[L * 64], zs[L];
+  const int c = blockIdx.x, lane = threadIdx.x;
+  const size_t nn = (size_t)n * n;
+  const bool on = lane < n;
+  const int p = on ? lane : 0;
+  double rpp[L];
+  ld<L>(qr, nn, (size_t)p * n + p, rpp);
+  double rmax = on ? fabs(rpp[0]) : 0.0;
+  for (int off = 32; off > 0; off >>= 1) rmax = fmax(rmax, __shfl_xor(rmax, off, 64));
+  {
+    double q[L], one[L];
+    md::zero<L>(one);
+    one[0] = 1.0;
+    const bool sing = on && !(fabs(rpp[0]) > ldexp((double)n, -53 * L) * rmax);
+    if (sing || !on) {
+      md::zero<L>(q);
+    } else {
+      md::recip_newton<L>(rpp, q);
+    }
+    if (sing && c == 0) set_status(status, MD_ESINGULAR);
+#pragma unroll
+    for (int l = 0; l < L; ++l) dinv[l * 64 + lane] = q[l];
+  }
+  double y[L], rn[L];
+  md::zero<L>(y);
+  if (on) ld<L>(qt, nn, (size_t)p * n + c, y);
+  md::zero<L>(rn);
+  if (lane < n - 1) ld<L>(qr, nn, (size_t)p * n + (n - 1), rn);  // R(p, n-1), p < n-1
+  wave_sync();
+  for (int i = n - 1; i >= 0; --i) {
+    double rc[L];
+    md::copy<L>(rn, rc);
+    md::zero<L>(rn);
+    if (i >= 1 && lane < i - 1) ld<L>(qr, nn, (size_t)p * n + (i - 1), rn);  // next column, rows above its diagonal
+    if (lane == i) {
+      double d[L], z[L];
+#pragma unroll
+      for (int l = 0; l < L; ++l) d[l] = dinv[l * 64 + i];
+      MD<L>::mul(y, d, z);
+      md::copy<L>(z, y);
+#pragma unroll
+      for (int l = 0; l < L; ++l) zs[l] = z[l];
+    }
+    wave_sync();
+    if (lane < i) {
+      double z[L];
+#pragma unroll
+      for (int l = 0; l < L; ++l) z[l] = zs[l];
+      MD<L>::fms(y, rc, z);
+    }
+    wave_sync();
+  }
+  if (on) st<L>(M, nn, (size_t)p * n + c, y);
+}
+
 // Dense copy of the series coefficient k of A: out[i][j] = A[i][j][k].
 template <int L>
 __global__ void extract_coeff_kernel(int n, int D, int k, const double *A, double *out) {
@@ -639,8 +723,8 @@ __global__ void __launch_bounds__(256) gemm_kernel(int n, const double *M, const
     ld<L>(B, b_ls, (size_t)v * n + j, b);
     MD<L>::fma_lazy(acc, m, b);
   }
+  team_sum_lazy<L>(acc, T);
   MD<L>::renorm(acc, r);
-  team_sum<L>(r, T);
   if (live && tl == 0) st<L>(N, nn, (size_t)i * n + j, r);
 }
 
@@ -674,8 +758,8 @@ __global__ void __launch_bounds__(256) stage_kernel(int n, int D, int k, const d
         MD<L>::fma_lazy(acc, nv, xv);
       }
     }
+    team_sum_lazy<L>(acc, 64);
     MD<L>::renorm(acc, r);
-    team_sum<L>(r, 64);
     if (row < n && lane == 0) st<L>(dxT, nD, (size_t)k * n + i, r);
     return;
   }
@@ -695,8 +779,8 @@ __global__ void __launch_bounds__(256) stage_kernel(int n, int D, int k, const d
       MD<L>::fma_lazy(acc, av, xv);
     }
   }
+  team_sum_lazy<L>(acc, T);
   MD<L>::renorm(acc, r);
-  team_sum<L>(r, T);
   if (live && tl == 0) {
     double rv[L], s2[L];
     ld<L>(rT, nD, (size_t)mm * n + i, rv);
@@ -827,8 +911,8 @@ __global__ void __launch_bounds__(256) stages_persistent_kernel(int n, int D, in
         if (k >= 1) MD<L>::fma_lazy(acc, nv, x1);
         if (k >= 2) MD<L>::fma_lazy(acc, pv, x2);
       }
+      team_sum_lazy<L>(acc, 64);
       MD<L>::renorm(acc, r);
-      team_sum<L>(r, 64);
       if (row && lane == 0) st_agent<L>(dxT, nD, (size_t)k * n + i, r);
       wait_vm();
       __syncthreads();
@@ -876,8 +960,8 @@ __global__ void __launch_bounds__(256) stages_persistent_kernel(int n, int D, in
           MD<L>::fma_lazy(acc, a, x);
         }
       }
+      team_sum_lazy<L>(acc, 16);
       MD<L>::renorm(acc, r);
-      team_sum<L>(r, 16);
       if (i < n && tl == 0) {
         double s2[L];
         MD<L>::sub(rv, r, s2);
@@ -1121,6 +1205,10 @@ hipError_t launch_qr_lds(int L, int n, double *a, double *tau, double *qt, int32
 
 hipError_t launch_m_from_qt(int L, int n, const double *qr, const double *qt, double *invd, double *M,
                             int32_t *status, hipStream_t st) {
+  if (n <= 64) {
+    MD_DISPATCH(L, hipLaunchKernelGGL(m_from_qt_small_kernel<LL>, dim3(n), dim3(64), 0, st, n, qr, qt, M, status));
+    return hipGetLastError();
+  }
   MD_DISPATCH(L, {
     hipLaunchKernelGGL(invdiag_kernel<LL>, dim3((n + 63) / 64), dim3(64), 0, st, n, qr, invd, status);
     hipLaunchKernelGGL(m_from_qt_kernel<LL>, dim3(n), dim3(64), (size_t)LL * n * sizeof(double), st, n, qr, qt,
