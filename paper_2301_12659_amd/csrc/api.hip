@@ -15,7 +15,7 @@
 
 
 struct md_plan {
-  int L, n, d, D, m, nnz, maxexp;
+  int L, n, d, D, m, nnz, maxexp, maxk;
   int32_t *d_poly_ptr = nullptr, *d_mon_ptr = nullptr, *d_var = nullptr, *d_exp = nullptr;
   int32_t *d_order = nullptr, *d_asm_ptr = nullptr, *d_asm_ent = nullptr, *d_row_of = nullptr;
   // second stream of the Newton step: QR of A_0 and M run beside the full
@@ -209,8 +209,9 @@ int md_plan_create(int prec, int n, int d, int m, const int32_t *poly_ptr, const
   for (int j = 0; j < m; ++j)
     if (mon_ptr[j + 1] < mon_ptr[j]) return fail(MD_EINVAL, "mon_ptr not monotone");
   const int nnz = mon_ptr[m];
-  int maxexp = 1;
-  for (int j = 0; j < m; ++j)
+  int maxexp = 1, maxk = 0;
+  for (int j = 0; j < m; ++j) {
+    maxk = std::max(maxk, (int)(mon_ptr[j + 1] - mon_ptr[j]));
     for (int q = mon_ptr[j]; q < mon_ptr[j + 1]; ++q) {
       if (var[q] < 0 || var[q] >= n) return fail(MD_EINVAL, "variable index out of range");
       if (q > mon_ptr[j] && var[q] <= var[q - 1])
@@ -218,6 +219,7 @@ int md_plan_create(int prec, int n, int d, int m, const int32_t *poly_ptr, const
       if (exp[q] < 1 || exp[q] > MD_MAX_EXPONENT) return fail(MD_EINVAL, "exponent out of range");
       maxexp = std::max(maxexp, (int)exp[q]);
     }
+  }
   md_plan *p = new md_plan();
   p->L = prec;
   p->n = n;
@@ -226,6 +228,7 @@ int md_plan_create(int prec, int n, int d, int m, const int32_t *poly_ptr, const
   p->m = m;
   p->nnz = nnz;
   p->maxexp = maxexp;
+  p->maxk = maxk;
   // work order: most expensive monomials first, so that workers of one
   // wavefront get similar work
   std::vector<int32_t> order(m);
@@ -382,13 +385,15 @@ static int newton_step_impl(const md_plan *p, int Ls, const double *cff, const d
   double *b = at(ws, w.b), *A = at(ws, w.A), *qr = at(ws, w.qr), *tau = at(ws, w.tau), *qt = at(ws, w.qt);
   double *invd = at(ws, w.invd), *M = at(ws, w.M), *N = at(ws, w.N), *r = at(ws, w.r), *dx = at(ws, w.dx);
   mdk::EvalArgs a;
-  // 1. pre-pass: coefficient 0 of every product gives A_0, bit for bit the
-  //    coefficient 0 of the full evaluation (same kernel, same operations)
+  // 1. pre-pass: coefficient 0 of every derivative product gives A_0 (the
+  //    same products as the full evaluation, rounded in another order: the
+  //    solve uses this A_0 throughout, for M and for the stages)
   {
     Timed t(MD_CLASS_QR, st);
     eval_args(p, cff, x, ws, 1, a);
-    if ((e = mdk::launch_evaldiff(Ls, a, p->maxexp, at(ws, w.pw), st)) != hipSuccess)
-      return hip_fail(e, "A_0 pre-pass");
+    e = (p->maxk <= mdk::evaldiff0_max_support(Ls)) ? mdk::launch_evaldiff0(Ls, a, st)
+                                                    : mdk::launch_evaldiff(Ls, a, p->maxexp, at(ws, w.pw), st);
+    if (e != hipSuccess) return hip_fail(e, "A_0 pre-pass");
     if ((e = mdk::launch_assemble_A0(Ls, n, D, p->nnz, p->d_asm_ptr, p->d_asm_ent, a.der, qr, st)) != hipSuccess)
       return hip_fail(e, "A_0 assembly");
   }

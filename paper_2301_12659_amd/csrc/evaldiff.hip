@@ -265,6 +265,84 @@ __global__ void __launch_bounds__(256, (L == 8) ? 1 : 2) evaldiff_kernel(EvalArg
   store_series(a.val, mD, (size_t)mono * D, U, L, Dc, lane, G);
 }
 
+// Coefficient 0 of every derivative product (the entries of A_0), one
+// thread per monomial, for supports of at most EVAL0_MAXK variables.  The
+// same products as evaldiff_kernel restricted to the constant coefficients,
+// which are plain multiple-double products: f_0 = c * CF(0), forward
+// products f_j = f_{j-1} x_{v_j}(0) kept in registers, then the backward
+// products b formed on the way back, d/dx_{v_j} = a_j f_{j-1} b_{k-j}.  The
+// loads of the k constant coefficients are issued before the products, so
+// the thread waits for memory once.
+constexpr int EVAL0_MAXK = 8;
+
+template <int L>
+__global__ void __launch_bounds__(256) evaldiff0_kernel(EvalArgs a) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= a.m) return;
+  const int mono = t;
+  const int e0 = a.mon_ptr[mono], k = a.mon_ptr[mono + 1] - e0;
+  const size_t nD = (size_t)a.n * a.D, zD = (size_t)a.nnz * a.D;
+  if (k == 0) return;  // no derivatives
+  double xs[EVAL0_MAXK][L];
+  int ex[EVAL0_MAXK];
+#pragma unroll
+  for (int j = 0; j < EVAL0_MAXK; ++j) {
+    md::zero<L>(xs[j]);
+    ex[j] = 1;
+    if (j < k) {
+      ld<L>(a.x, nD, (size_t)a.var[e0 + j] * a.D, xs[j]);
+      ex[j] = a.exp[e0 + j];
+    }
+  }
+  double f[EVAL0_MAXK][L];  // f[j] = f_j for j < k (f_0 = c CF)
+  ld<L>(a.cff, a.m, mono, f[0]);
+#pragma unroll
+  for (int j = 0; j < EVAL0_MAXK; ++j) {  // common factor: x^(a-1) for exponents >= 2
+    if (j < k)
+      for (int p = 1; p < ex[j]; ++p) {
+        double r[L];
+        MD<L>::mul(f[0], xs[j], r);
+        md::copy<L>(r, f[0]);
+      }
+  }
+#pragma unroll
+  for (int j = 1; j < EVAL0_MAXK; ++j)
+    if (j < k) MD<L>::mul(f[j - 1], xs[j - 1], f[j]);
+  double b[L];  // backward product b_{k-j}, b_0 = 1
+  md::zero<L>(b);
+  b[0] = 1.0;
+#pragma unroll
+  for (int j = EVAL0_MAXK; j >= 1; --j) {
+    if (j > k) continue;
+    double d[L];
+    if (j == k) md::copy<L>(f[j - 1], d);
+    else MD<L>::mul(f[j - 1], b, d);
+    md::mul_int<L>(d, ex[j - 1]);
+#pragma unroll
+    for (int l = 0; l < L; ++l) a.der[(size_t)l * zD + (size_t)(e0 + j - 1) * a.D] = d[l];
+    if (j > 1) {
+      double r[L];
+      if (j == k) md::copy<L>(xs[j - 1], r);
+      else MD<L>::mul(b, xs[j - 1], r);
+      md::copy<L>(r, b);
+    }
+  }
+}
+
+hipError_t launch_evaldiff0(int L, const EvalArgs &a, hipStream_t st) {
+  const dim3 grid((a.m + 255) / 256);
+  switch (L) {
+    case 2: hipLaunchKernelGGL(evaldiff0_kernel<2>, grid, dim3(256), 0, st, a); break;
+    case 4: hipLaunchKernelGGL(evaldiff0_kernel<4>, grid, dim3(256), 0, st, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// Octo doubles would spill the registers of this kernel: they take the
+// general kernel with one coefficient.
+int evaldiff0_max_support(int L) { return L <= 4 ? EVAL0_MAXK : 0; }
+
 // Powers x_v^p, p = 2..maxexp-1, for the common factors of exponents >= 3.
 template <int L>
 __global__ void __launch_bounds__(256, (L == 8) ? 1 : 2) power_kernel(int n, int D, int Dc, int maxp, const double *x, double *pw) {

@@ -16,6 +16,11 @@ struct EvalArgs {
 
 // evaldiff.hip
 hipError_t launch_evaldiff(int L, const EvalArgs &a, int maxexp, double *pw, hipStream_t st);
+// Coefficient 0 of the derivative products only (der[.][.][0]), one thread
+// per monomial; for plans whose supports have at most
+// evaldiff0_max_support(L) variables (none for octo doubles).
+hipError_t launch_evaldiff0(int L, const EvalArgs &a, hipStream_t st);
+int evaldiff0_max_support(int L);
 hipError_t launch_assemble(int L, int n, int D, int m, int nnz, const int32_t *poly_ptr, const int32_t *asm_ptr,
                            const int32_t *asm_ent, const double *cst, const double *val, const double *der,
                            double *b, double *A, hipStream_t st);
