@@ -147,6 +147,53 @@ int md_newton_step(const md_plan *plan, const double *cff, const double *cst, do
 int md_newton_step_mixed(const md_plan *plan, int prec_solve, const double *cff, const double *cst, double *x,
                          int32_t *dev_status, double *dev_norms, void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* Batches of independent systems ("paths"; the paper tracks many solution
+ * paths of a homotopy, Section 1), one Newton step of every path per call,
+ * in one persistent launch.  A path p has n_p (1..128) variables and
+ * polynomials, truncation degree d_p (D_p = d_p + 1 <= MD_MAX_COEFFS) and
+ * m_p monomials with exponents 1 or 2; precision double or quad double.
+ *
+ * md_batch_create: poly_ptr, mon_ptr, var and exp are the tables of
+ * md_plan_create for each path, concatenated in path order (poly_ptr: n_p + 1
+ * entries per path, each starting at 0; mon_ptr: m_p + 1 entries per path,
+ * each starting at 0; var, exp: mon_ptr_p[m_p] entries per path, variable
+ * indices local to the path).  Host pointers, copied.  MD_EINVAL on any
+ * inconsistency.
+ *
+ * Packed device arrays: x and cst are [L][X] with path p's series block
+ * [n_p][D_p] at element x_off[p] of each limb plane (X = x_total); cff is
+ * [L][C] with path p's coefficients at cff_off[p] (C = cff_total), all from
+ * md_batch_offsets.
+ *
+ * md_batch_newton_step: x := x + dx for every path, as md_newton_step
+ * (prec_solve below the batch's precision: md_newton_step_mixed).
+ * dev_status[p] is the path's status (MD_OK, MD_ESINGULAR, MD_ENONFINITE),
+ * dev_norms[2p] = max |b| and dev_norms[2p+1] = max |dx| over the path's
+ * series (leading limbs).  The workspace (md_batch_workspace_size) holds a
+ * queue counter and one slot of intermediates per concurrent workgroup.
+ * The call is asynchronous; it captures its launches in a graph on the
+ * second call with the same arguments and replays the graph afterwards.
+ * Not thread safe per batch.
+ *
+ * md_batch_autotune: for every size bucket of (n, D) present, times the
+ * batched step of that bucket's paths with reduction teams of 4, 8 and 16
+ * lanes on a scratch copy of x (x_scratch, [L][X]) and keeps the fastest;
+ * chosen[9] (optional) receives the choice per bucket.  md_batch_set_tiles
+ * sets them directly. */
+typedef struct md_batch md_batch;
+int md_batch_create(int prec, int npaths, const int32_t *n, const int32_t *d, const int32_t *m,
+                    const int32_t *poly_ptr, const int32_t *mon_ptr, const int32_t *var, const int32_t *exp,
+                    md_batch **out);
+int md_batch_destroy(md_batch *batch);
+int md_batch_offsets(const md_batch *batch, int64_t *x_off, int64_t *cff_off, int64_t *x_total, int64_t *cff_total);
+int md_batch_workspace_size(const md_batch *batch, size_t *bytes);
+int md_batch_newton_step(md_batch *batch, int prec_solve, const double *cff, const double *cst, double *x,
+                         int32_t *dev_status, double *dev_norms, void *ws, size_t ws_bytes, hipStream_t stream);
+int md_batch_autotune(md_batch *batch, int prec_solve, const double *cff, const double *cst, const double *x,
+                      double *x_scratch, int32_t *dev_status, double *dev_norms, void *ws, size_t ws_bytes,
+                      hipStream_t stream, int32_t *chosen);
+int md_batch_set_tiles(md_batch *batch, const int32_t *tiles);
+
 /* Elementwise multiple-double arithmetic on device arrays of count elements
  * (limb-major [L][count]): op 0 add, 1 sub, 2 mul, 3 div, 4 sqrt (of a),
  * 5 fused c := c + a*b; op 6 is the dot product c[0] = sum_q a[q] b[q]

@@ -128,6 +128,42 @@ def _supports(rng, n, n_mon_per_poly, kmin, kmax, exps):
             np.asarray(var, np.int32), np.asarray(ex, np.int32))
 
 
+def _supports_vectorized(rng, n, mons, kmin, kmax, exps):
+    """As _supports with a fixed number of monomials per polynomial, drawn
+    with array operations (another random stream; used for large batches)."""
+    m = n * mons
+    k = np.minimum(rng.integers(kmin, kmax + 1, size=m), n)
+    keys = rng.random((m, n))
+    pick = np.argsort(keys, axis=1)[:, :kmax]
+    es_all = rng.choice(np.asarray(exps), size=(m, kmax))
+    mask = np.arange(kmax)[None, :] < k[:, None]
+    picked = np.where(mask, pick, n)  # n sorts after every variable
+    order = np.argsort(picked, axis=1)
+    vs = np.take_along_axis(picked, order, axis=1)
+    es = np.take_along_axis(es_all, order, axis=1)
+    var = vs[vs < n].astype(np.int32)
+    ex = es[vs < n].astype(np.int32)
+    mon_ptr = np.concatenate([[0], np.cumsum(k)]).astype(np.int32)
+    poly_ptr = (np.arange(n + 1) * mons).astype(np.int32)
+    return poly_ptr, mon_ptr, var, ex
+
+
+def _jacobian0_vectorized(poly_ptr, mon_ptr, var, exp, cff_hi, x0_hi) -> np.ndarray:
+    """jacobian0_estimate with array operations, for points without zero
+    entries: d/dx_a of c prod x_b^e_b is e_a c prod x_b^e_b / x_a."""
+    n = len(poly_ptr) - 1
+    m = len(mon_ptr) - 1
+    mono = np.repeat(np.arange(m), np.diff(mon_ptr))
+    row = np.repeat(np.arange(n), np.diff(poly_ptr))[mono]
+    xe = x0_hi[var] ** exp
+    logp = np.zeros(m)
+    np.add.at(logp, mono, np.log(xe))
+    val = cff_hi[mono] * np.exp(logp[mono]) * exp / x0_hi[var]
+    J = np.zeros((n, n))
+    np.add.at(J, (row, var), val)
+    return J
+
+
 def jacobian0_estimate(poly_ptr, mon_ptr, var, exp, cff_hi, x0_hi) -> np.ndarray:
     """Float64 estimate of the Jacobian at the point x0 (leading limbs only).
 
@@ -175,7 +211,8 @@ def _append_boost(poly_ptr, mon_ptr, var, exp, cff, L, s):
 
 def make_system(name: str, L: int, n: int, d: int, mons_per_poly, kmin: int, kmax: int,
                 exps, seed: int, cond_max: float | None, boost: bool, steps: int = 1,
-                damping: float = 1.0, max_tries: int = 64, boost_gamma: float = 0.125) -> System:
+                damping: float = 1.0, max_tries: int = 64, boost_gamma: float = 0.125,
+                vectorized: bool = False) -> System:
     """Draw a system and its manufactured solution.
 
     Without ``boost`` the system is redrawn (from a derived seed) until the
@@ -191,11 +228,14 @@ def make_system(name: str, L: int, n: int, d: int, mons_per_poly, kmin: int, kma
             per = mons_per_poly
         else:
             per = (lambda i, _c=int(mons_per_poly): _c)
-        pp, mp, var, ex = _supports(rng, n, lambda i: per(i) if not callable(mons_per_poly) else int(mons_per_poly(rng)), kmin, kmax, exps)
+        if vectorized:
+            pp, mp, var, ex = _supports_vectorized(rng, n, int(mons_per_poly), kmin, kmax, exps)
+        else:
+            pp, mp, var, ex = _supports(rng, n, lambda i: per(i) if not callable(mons_per_poly) else int(mons_per_poly(rng)), kmin, kmax, exps)
         m = len(mp) - 1
         cff = random_md(rng, L, (m,), -1.0, 1.0)
         xstar = random_series(rng, L, n, D, 0.5, 1.5, damping)
-        J = jacobian0_estimate(pp, mp, var, ex, cff[0], xstar[0, :, 0])
+        J = (_jacobian0_vectorized if vectorized else jacobian0_estimate)(pp, mp, var, ex, cff[0], xstar[0, :, 0])
         bidx = None
         if boost:
             rowsum = np.abs(J).sum(axis=1) + 1.0
@@ -265,6 +305,29 @@ def tiny(L: int, n: int, d: int, mons: int = 3, kmin: int = 1, kmax: int = 3, ex
     """Small systems for parity tests that the oracle finishes in seconds."""
     return make_system(f"tiny_L{L}_n{n}_d{d}", L, n, d, mons, kmin, kmax, exps, seed, cond_max,
                        boost=boost, steps=1, damping=damping, boost_gamma=BOOST_GAMMA)
+
+
+def batch_paths(count: int = 2048, L: int = 4, seed: int = 7, n_range=(16, 96), d_choices=(15, 31, 63),
+                mons_range=(8, 32), k_range=(2, 5), exps=(1,)) -> list:
+    """Independent systems of uneven size for the batched step: path j has n
+    uniform in n_range, d from d_choices, a per-path number of monomials per
+    polynomial uniform in mons_range, monomials of k_range variables with the
+    given exponents, a diagonal boost, damped manufactured solutions."""
+    rng = np.random.default_rng([seed, 31337])
+    out = []
+    for j in range(count):
+        n = int(rng.integers(n_range[0], n_range[1] + 1))
+        d = int(rng.choice(d_choices))
+        mons = int(rng.integers(mons_range[0], mons_range[1] + 1))
+        out.append(make_system(f"path{j}", L, n, d, mons, k_range[0], k_range[1], exps, seed * 100003 + j, 1e3,
+                               boost=True, steps=6, damping=DAMPING, boost_gamma=BOOST_GAMMA, vectorized=True))
+    return out
+
+
+def small_batch(L: int = 4, seed: int = 9) -> list:
+    """A few small paths for parity tests (the oracle finishes each in seconds):
+    n in 3..12, d in {0, 3, 7, 15}, several size buckets."""
+    return batch_paths(8, L, seed, (3, 12), (0, 3, 7, 15), (2, 5), (1, 3), (1, 2))
 
 
 PRESETS = {

@@ -49,6 +49,14 @@ _lib.md_adjoint_workspace_size.argtypes = [_i32, _i32, _i32, _szp]
 _lib.md_adjoint_solve.argtypes = [_i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp, _vp]
 _lib.md_coef_grad.argtypes = [_vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
 _lib.md_timing_enable.argtypes = [_i32]
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_lib.md_batch_create.argtypes = [_i32, _i32, _i32p, _i32p, _i32p, _i32p, _i32p, _i32p, _i32p, ctypes.POINTER(_vp)]
+_lib.md_batch_destroy.argtypes = [_vp]
+_lib.md_batch_offsets.argtypes = [_vp, _i64p, _i64p, _i64p, _i64p]
+_lib.md_batch_workspace_size.argtypes = [_vp, _szp]
+_lib.md_batch_newton_step.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
+_lib.md_batch_autotune.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp, _i32p]
+_lib.md_batch_set_tiles.argtypes = [_vp, _i32p]
 _lib.md_timing_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
 
 # Kernel classes of md_timing_read (the paper's kernel types, Table 4).
@@ -130,6 +138,96 @@ class Plan:
     def close(self):
         if getattr(self, "_h", None):
             _lib.md_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """md_batch: many independent systems (paths) stepped together.
+
+    `systems` are objects with L, n, d, poly_ptr, mon_ptr, var, exp (the
+    mdinputs.System fields); all share the precision `prec`.  Device arrays
+    are packed: x and cst [L, x_total], cff [L, cff_total]; pack/unpack
+    convert from and to per-path arrays."""
+
+    BUCKETS = 9
+
+    def __init__(self, systems, prec=None):
+        self.prec = int(prec if prec is not None else systems[0].L)
+        self.P = len(systems)
+        n = np.array([s.n for s in systems], dtype=np.int32)
+        d = np.array([s.d for s in systems], dtype=np.int32)
+        m = np.array([len(s.mon_ptr) - 1 for s in systems], dtype=np.int32)
+        cat = lambda f: np.concatenate([np.asarray(getattr(s, f), dtype=np.int32) for s in systems])
+        self._keep = [_i32arr(n), _i32arr(d), _i32arr(m), _i32arr(cat("poly_ptr")), _i32arr(cat("mon_ptr")),
+                      _i32arr(cat("var")), _i32arr(cat("exp"))]
+        h = _vp()
+        rc = _lib.md_batch_create(self.prec, self.P, *[k[1] for k in self._keep], ctypes.byref(h))
+        _check(rc, "md_batch_create")
+        self._h = h
+        self.n, self.D, self.m = n.tolist(), (d + 1).tolist(), m.tolist()
+        xo = (ctypes.c_int64 * self.P)()
+        co = (ctypes.c_int64 * self.P)()
+        xt, ct = ctypes.c_int64(), ctypes.c_int64()
+        _check(_lib.md_batch_offsets(self._h, xo, co, ctypes.byref(xt), ctypes.byref(ct)), "md_batch_offsets")
+        self.x_off, self.cff_off = list(xo), list(co)
+        self.x_total, self.cff_total = int(xt.value), int(ct.value)
+
+    def workspace_bytes(self):
+        v = ctypes.c_size_t()
+        _check(_lib.md_batch_workspace_size(self._h, ctypes.byref(v)), "md_batch_workspace_size")
+        return int(v.value)
+
+    def pack_series(self, arrays):
+        """[L, n_p, D_p] per path -> [L, x_total] (numpy)."""
+        out = np.zeros((self.prec, self.x_total))
+        for p, a in enumerate(arrays):
+            sz = self.n[p] * self.D[p]
+            out[:, self.x_off[p]:self.x_off[p] + sz] = np.asarray(a)[:self.prec].reshape(self.prec, sz)
+        return out
+
+    def unpack_series(self, packed):
+        packed = np.asarray(packed)
+        return [packed[:, self.x_off[p]:self.x_off[p] + self.n[p] * self.D[p]].reshape(-1, self.n[p], self.D[p])
+                for p in range(self.P)]
+
+    def pack_cff(self, arrays):
+        out = np.zeros((self.prec, self.cff_total))
+        for p, a in enumerate(arrays):
+            out[:, self.cff_off[p]:self.cff_off[p] + self.m[p]] = np.asarray(a)[:self.prec]
+        return out
+
+    def step(self, cff, cst, x, status, norms, ws, prec_solve=None, stream=None):
+        L = self.prec
+        rc = _lib.md_batch_newton_step(self._h, int(prec_solve or L), _ptr(cff, (L, self.cff_total), "cff"),
+                                       _ptr(cst, (L, self.x_total), "cst"), _ptr(x, (L, self.x_total), "x"),
+                                       _ptr(status, (self.P,), "status"), _ptr(norms, (2 * self.P,), "norms"),
+                                       _ptr(ws, None, "ws"), ws.numel() * 8, _stream(stream))
+        _check(rc, "md_batch_newton_step")
+
+    def autotune(self, cff, cst, x, x_scratch, status, norms, ws, prec_solve=None, stream=None):
+        L = self.prec
+        chosen = (ctypes.c_int32 * self.BUCKETS)()
+        rc = _lib.md_batch_autotune(self._h, int(prec_solve or L), _ptr(cff, (L, self.cff_total), "cff"),
+                                    _ptr(cst, (L, self.x_total), "cst"), _ptr(x, (L, self.x_total), "x"),
+                                    _ptr(x_scratch, (L, self.x_total), "x_scratch"),
+                                    _ptr(status, (self.P,), "status"), _ptr(norms, (2 * self.P,), "norms"),
+                                    _ptr(ws, None, "ws"), ws.numel() * 8, _stream(stream), chosen)
+        _check(rc, "md_batch_autotune")
+        return list(chosen)
+
+    def set_tiles(self, tiles):
+        arr, ptr = _i32arr(tiles)
+        _check(_lib.md_batch_set_tiles(self._h, ptr), "md_batch_set_tiles")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.md_batch_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -28,7 +28,7 @@ FLAGS = [
     "-Wno-unused-command-line-argument",
 ]
 
-SOURCES = ["evaldiff.hip", "linalg.hip", "api.hip"]
+SOURCES = ["evaldiff.hip", "linalg.hip", "api.hip", "batch.hip"]
 
 
 def _compile(src: str) -> str:

@@ -177,6 +177,10 @@ int series_solve_impl(int L, int n, int D, const double *qr, const double *tau, 
 }  // namespace
 
 namespace mdk {
+// The library's error message for calls implemented in other files.
+int api_fail(int code, const char *msg) { return fail(code, msg); }
+int api_hip_fail(hipError_t e, const char *what) { return hip_fail(e, what); }
+bool api_timing_enabled() { return g_timing; }
 __global__ void copy_kernel(const double *src, double *dst, size_t count) {
   const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q < count) dst[q] = src[q];

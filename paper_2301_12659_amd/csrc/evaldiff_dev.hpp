@@ -1,0 +1,246 @@
+// Device routines of the evaluation and differentiation by convolutions,
+// shared by the single-system kernels (evaldiff.hip) and the batched Newton
+// step (batch.hip).  The method and the work decomposition are described at
+// the top of evaldiff.hip.
+#pragma once
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace mdk {
+
+// Lanes per output pair (S) and per half (G2) of a worker for D coefficients.
+__host__ __device__ inline int pair_lanes(int D) {
+  int h = (D + 1) / 2, g = 1;
+  while (g < h) g <<= 1;
+  return g;
+}
+__host__ __device__ inline int split_factor(int D) { return 2 * pair_lanes(D) <= 64 ? 2 : 1; }
+__host__ __device__ inline int worker_lanes(int D) { return split_factor(D) * pair_lanes(D); }
+
+// LDS series layout: [L][D + 1]; entry D of every limb is zero and is what
+// masked terms read.
+
+// Truncated product W = scale * (U * V) (all in LDS).
+template <int L>
+__device__ void conv(const double *U, const double *V, double *W, int D, int lane, int scale) {
+  const int Dp = D + 1, G2 = pair_lanes(D), S = split_factor(D);
+  const int h = lane / G2, p = lane - h * G2;
+  const bool act = p < (D + 1) / 2;
+  const int o1 = p, o2 = D - 1 - p;
+  const int H = (D + S) / S;  // terms per half: ceil((D + 1) / S)
+  const int t0 = h * H;
+  double acc[L];
+  md::zero<L>(acc);
+  for (int tt = 0; tt < H; ++tt) {
+    const int t = t0 + tt;
+    const bool ph1 = t <= o1;
+    int i = ph1 ? t : t - o1 - 1;
+    int j = (ph1 ? o1 : o2) - i;
+    if (!act || t > D) {  // reads the zero padding
+      i = D;
+      j = 0;
+    }
+    double u[L], v[L];
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+      u[l] = U[l * Dp + i];
+      v[l] = V[l * Dp + j];
+    }
+    MD<L>::fma_lazy(acc, u, v);
+    if (t == o1) {  // first output complete (always in the first half)
+      if (act) {
+        double r[L];
+        MD<L>::renorm(acc, r);
+        md::mul_int<L>(r, scale);
+#pragma unroll
+        for (int l = 0; l < L; ++l) W[l * Dp + o1] = r[l];
+      }
+      md::zero<L>(acc);
+    }
+  }
+  double r[L];
+  MD<L>::renorm(acc, r);
+  if (S == 2) {  // add the second half's part of the second output
+    double o[L], s[L];
+#pragma unroll
+    for (int l = 0; l < L; ++l) o[l] = __shfl_xor(r[l], G2, 64);
+    MD<L>::add(r, o, s);
+    md::copy<L>(s, r);
+  }
+  if (h == 0 && act && o2 > o1) {
+    md::mul_int<L>(r, scale);
+#pragma unroll
+    for (int l = 0; l < L; ++l) W[l * Dp + o2] = r[l];
+  }
+}
+
+// W = scale * c * V for a scalar c (registers) and a series V.
+template <int L>
+__device__ void scal(const double (&c)[L], const double *V, double *W, int D, int lane, int G, int scale) {
+  const int Dp = D + 1;
+  for (int s = lane; s < D; s += G) {
+    double v[L], r[L];
+#pragma unroll
+    for (int l = 0; l < L; ++l) v[l] = V[l * Dp + s];
+    MD<L>::mul(c, v, r);
+    md::mul_int<L>(r, scale);
+#pragma unroll
+    for (int l = 0; l < L; ++l) W[l * Dp + s] = r[l];
+  }
+}
+
+// LDS <- global series (limb stride gstride, element offset off), D entries.
+__device__ __forceinline__ void load_series(double *S, const double *g, size_t gstride, size_t off, int L, int D,
+                                            int lane, int G) {
+  for (int q = lane; q < L * D; q += G) {
+    const int l = q / D, s = q - l * D;
+    S[l * (D + 1) + s] = g[(size_t)l * gstride + off + s];
+  }
+}
+
+__device__ __forceinline__ void store_series(double *g, size_t gstride, size_t off, const double *S, int L, int D,
+                                             int lane, int G) {
+  for (int q = lane; q < L * D; q += G) {
+    const int l = q / D, s = q - l * D;
+    g[(size_t)l * gstride + off + s] = S[l * (D + 1) + s];
+  }
+}
+
+// Zero the padding entries of a worker's three buffers.
+__device__ __forceinline__ void zero_pads(double *buf0, int L, int D, int lane, int G) {
+  for (int q = lane; q < 3 * L; q += G) buf0[q * (D + 1) + D] = 0.0;
+}
+
+// One worker (G lanes of one wavefront, worker_lanes(a.Dc) of them) evaluates
+// and differentiates monomial `mono` with the three LDS series buffers at
+// buf0 (3 L (Dc + 1) doubles).  The products are described at the top of
+// evaldiff.hip.
+template <int L>
+__device__ void eval_monomial(const EvalArgs &a, int mono, int lane, double *buf0) {
+  const int D = a.D;    // coefficients stored per series (global stride)
+  const int Dc = a.Dc;  // coefficients computed: D, or 1 for the A_0 pre-pass
+  const int G = worker_lanes(Dc);
+  const int Dp = Dc + 1;
+  double *buf[3] = {buf0, buf0 + L * Dp, buf0 + 2 * L * Dp};
+  zero_pads(buf[0], L, Dc, lane, G);
+  const int e0 = a.mon_ptr[mono], k = a.mon_ptr[mono + 1] - e0;
+  const size_t nD = (size_t)a.n * D, mD = (size_t)a.m * D, zD = (size_t)a.nnz * D;
+  const size_t xls = a.x_ls ? a.x_ls : nD;  // limb stride of x
+  double c[L];
+  ld<L>(a.cff, a.cff_ls ? a.cff_ls : (size_t)a.m, mono, c);
+
+  if (k == 0) {  // constant monomial
+    for (int s = lane; s < Dc; s += G) {
+#pragma unroll
+      for (int l = 0; l < L; ++l) a.val[(size_t)l * mD + (size_t)mono * D + s] = (s == 0) ? c[l] : 0.0;
+    }
+    return;
+  }
+  auto xoff = [&](int v) { return (size_t)v * D; };
+  auto der_off = [&](int j) { return (size_t)(e0 + j) * D; };  // j: 0-based entry
+
+  const bool derivs = a.values_only == 0;
+  // ---- backward chain: b_q for q = 2..k-1 parked in the slot of entry k-q (0-based k-q-1+... )
+  if (derivs && k >= 3) {
+    double *B = buf[0], *X = buf[1], *Wb = buf[2];
+    load_series(B, a.x, xls, xoff(a.var[e0 + k - 1]), L, Dc, lane, G);  // b_1 = x_{v_k}
+    for (int q = 2; q <= k - 1; ++q) {
+      load_series(X, a.x, xls, xoff(a.var[e0 + k - q]), L, Dc, lane, G);  // x_{v_{k-q+1}}
+      wave_sync();
+      conv<L>(B, X, Wb, Dc, lane, 1);
+      wave_sync();
+      // b_q is consumed by the cross product of forward step j = k - q (1-based),
+      // i.e. entry k - q - 1 (0-based)
+      store_series(a.der, zD, der_off(k - q - 1), Wb, L, Dc, lane, G);
+      double *t = B;
+      B = Wb;
+      Wb = t;
+      wave_sync();
+    }
+  }
+
+  // ---- common factor and f_0
+  double *U = buf[0], *V = buf[1], *W = buf[2];
+  bool f0_scalar = true;
+  for (int j = 0; j < k; ++j) {
+    const int p = a.exp[e0 + j] - 1;
+    if (p < 1) continue;
+    const int v = a.var[e0 + j];
+    const double *src = (p == 1) ? a.x : a.pw + (size_t)(p - 2) * L * nD;
+    const size_t sls = (p == 1) ? xls : nD;
+    if (f0_scalar) {
+      load_series(U, src, sls, xoff(v), L, Dc, lane, G);
+      f0_scalar = false;
+      wave_sync();
+    } else {
+      load_series(V, src, sls, xoff(v), L, Dc, lane, G);
+      wave_sync();
+      conv<L>(U, V, W, Dc, lane, 1);
+      wave_sync();
+      double *t = U;
+      U = W;
+      W = t;
+    }
+  }
+  if (!f0_scalar) {  // f_0 = c * CF in place
+    scal<L>(c, U, U, Dc, lane, G, 1);
+    wave_sync();
+  }
+
+  // ---- forward chain with the cross products
+  for (int j = 1; j <= k; ++j) {
+    const int ej = j - 1;  // 0-based entry of v_j
+    const int aj = a.exp[e0 + ej];
+    if (!derivs) {
+      // values only: the forward product below
+    } else if (j < k) {
+      if (k - j == 1)
+        load_series(V, a.x, xls, xoff(a.var[e0 + k - 1]), L, Dc, lane, G);  // b_1 = x_{v_k}
+      else
+        load_series(V, a.der, zD, der_off(ej), L, Dc, lane, G);  // b_{k-j}
+      wave_sync();
+      if (f0_scalar && j == 1)
+        scal<L>(c, V, W, Dc, lane, G, aj);
+      else
+        conv<L>(U, V, W, Dc, lane, aj);
+      wave_sync();
+      store_series(a.der, zD, der_off(ej), W, L, Dc, lane, G);
+    } else {  // d/dx_{v_k} = a_k f_{k-1}
+      if (f0_scalar && j == 1) {
+        for (int s = lane; s < Dc; s += G) {
+          double r[L];
+#pragma unroll
+          for (int l = 0; l < L; ++l) r[l] = (s == 0) ? c[l] : 0.0;
+          md::mul_int<L>(r, aj);
+#pragma unroll
+          for (int l = 0; l < L; ++l) a.der[(size_t)l * zD + der_off(ej) + s] = r[l];
+        }
+      } else {
+        for (int s = lane; s < Dc; s += G) {
+          double r[L];
+#pragma unroll
+          for (int l = 0; l < L; ++l) r[l] = U[l * Dp + s];
+          md::mul_int<L>(r, aj);
+#pragma unroll
+          for (int l = 0; l < L; ++l) a.der[(size_t)l * zD + der_off(ej) + s] = r[l];
+        }
+      }
+    }
+    wave_sync();
+    // f_j = f_{j-1} * x_{v_j}
+    load_series(V, a.x, xls, xoff(a.var[e0 + ej]), L, Dc, lane, G);
+    wave_sync();
+    if (f0_scalar && j == 1)
+      scal<L>(c, V, W, Dc, lane, G, 1);
+    else
+      conv<L>(U, V, W, Dc, lane, 1);
+    wave_sync();
+    double *t = U;
+    U = W;
+    W = t;
+  }
+  store_series(a.val, mD, (size_t)mono * D, U, L, Dc, lane, G);
+}
+
+
+}  // namespace mdk

@@ -12,6 +12,7 @@ struct EvalArgs {
   const double *cff, *x, *pw;  // pw: powers x^p for p = 2..maxexp-1, [p-2][L][n][D]
   double *val, *der;           // val [L][m][D], der [L][nnz][D]
   int values_only = 0;         // 1: monomial values only (no backward or cross products, der untouched)
+  size_t x_ls = 0, cff_ls = 0; // limb strides of x and cff when not n D and m (packed batches)
 };
 
 // evaldiff.hip
@@ -70,5 +71,10 @@ hipError_t launch_coef_grad(int L, int n, int D, int m, const int32_t *row_of, c
                             double *grad, hipStream_t st);
 hipError_t launch_unit_md(int L, int m, double *c, hipStream_t st);
 hipError_t launch_dot(int L, int64_t count, const double *a, const double *b, double *c, hipStream_t st);
+
+// api.hip: record the message returned by md_last_error and return the code.
+int api_fail(int code, const char *msg);
+int api_hip_fail(hipError_t e, const char *what);
+bool api_timing_enabled();
 
 }  // namespace mdk
