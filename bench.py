@@ -69,6 +69,58 @@ def _err_vs(mdn, torch, x, ref):
     return float((diff.amax(dim=-1) / mag).max().item())
 
 
+def _bench_batch(mdn, torch, np, mdinputs, npaths, steps):
+    """The batched workload: npaths independent quad-double paths, n in
+    16..96, d in {15, 31, 63}, 8..32 monomials per polynomial of 2..5
+    variables with exponent 1, manufactured solutions (constants evaluated on
+    the GPU); plain steps and qd residual / dd solve steps, each a graph
+    replay of one persistent launch."""
+    paths = mdinputs.batch_paths(npaths, 4)
+    b = mdn.Batch(paths)
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    # c_{i,0} = -p_i(x*) with zero constant, path by path on the GPU
+    cst_parts = []
+    for s in paths:
+        plan = mdn.Plan.from_system(s)
+        ws1 = mdn.workspace(plan.workspace_bytes())
+        bb = torch.empty((4, s.n, s.D), dtype=torch.float64, device="cuda")
+        AA = torch.empty((4, s.n, s.n, s.D), dtype=torch.float64, device="cuda")
+        mdn.eval_diff(plan, dev(s.cff), torch.zeros_like(bb), dev(s.xstar), bb, AA, ws1)
+        cst_parts.append(bb.cpu().numpy())
+        del AA, ws1
+        plan.close()
+    cff = dev(b.pack_cff([s.cff for s in paths]))
+    cst = dev(b.pack_series(cst_parts))
+    x0 = dev(b.pack_series([s.start() for s in paths]))
+    status = torch.zeros(npaths, dtype=torch.int32, device="cuda")
+    norms = torch.zeros(2 * npaths, dtype=torch.float64, device="cuda")
+    ws = mdn.workspace(b.workspace_bytes())
+    x = x0.clone()
+    t0 = time.perf_counter()
+    tiles = b.autotune(cff, cst, x, torch.empty_like(x), status, norms, ws)
+    tune_s = time.perf_counter() - t0
+    res = {"workload": f"{npaths} quad-double paths, n 16..96, d in {{15,31,63}}, 8..32 monomials per polynomial, "
+                       "2..5 variables, exponent 1, manufactured solutions, seed 7",
+           "paths": npaths, "total_unknown_series": int(sum(s.n for s in paths)),
+           "tiles_per_bucket": tiles, "autotune_s": round(tune_s, 2)}
+    for name, ls in (("plain_qd", 4), ("mixed_qd_dd", 2)):
+        x.copy_(x0)
+        for _ in range(2):  # eager, then captured
+            b.step(cff, cst, x, status, norms, ws, prec_solve=ls)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            b.step(cff, cst, x, status, norms, ws, prec_solve=ls)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        bad = int((status != 0).sum().item())
+        res[name] = {"ms_per_batched_step": round(ms, 3), "path_steps_per_s": round(npaths * 1000.0 / ms, 1),
+                     "paths_not_ok": bad}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -76,6 +128,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--batch-paths", type=int, default=2048,
+                    help="paths of the batched workload (0 skips it)")
+    ap.add_argument("--batch-steps", type=int, default=4)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -191,6 +246,9 @@ def main():
         "err_vs_manufactured": err_manufactured,
         "wall_s_timed": round(wall, 3),
     }
+
+    if args.batch_paths > 0:
+        out["batched"] = _bench_batch(mdn, torch, np, mdinputs, args.batch_paths, args.batch_steps)
 
     if not args.no_cpu_baseline:
         import oracle
