@@ -28,7 +28,7 @@ PEAK_FP64_TFLOPS = 78.6  # MI355X FP64 vector, FMA = 2 flops
 # sources the evaluation/differentiation kernel is compiled from; the HBM
 # traffic recorded from hardware counters is reported only while they are
 # unchanged since the counters were taken
-_EVALDIFF_SOURCES = ("evaldiff.hip", "common.hpp", "kernels.hpp", "md.hpp", "md_gen.inc")
+_EVALDIFF_SOURCES = ("evaldiff.hip", "evaldiff_dev.hpp", "common.hpp", "kernels.hpp", "md.hpp", "md_gen.inc")
 _TRAFFIC_FILE = os.path.join(ROOT, "profiles", "evaldiff_kernel_medium_qd_hbm_traffic.md")
 
 
