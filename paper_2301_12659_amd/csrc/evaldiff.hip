@@ -259,6 +259,8 @@ hipError_t launch_assemble_A0(int L, int n, int D, int nnz, const int32_t *asm_p
   return hipGetLastError();
 }
 
+int evaldiff_workers_per_block(int D) { return 256 / worker_lanes(D); }
+
 size_t evaldiff_lds_bytes(int L, int D) {
   const int G = worker_lanes(D);
   return (size_t)(256 / G) * 3 * L * (D + 1) * sizeof(double);

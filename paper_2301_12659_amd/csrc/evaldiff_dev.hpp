@@ -29,8 +29,8 @@ __device__ void conv(const double *U, const double *V, double *W, int D, int lan
   const int o1 = p, o2 = D - 1 - p;
   const int H = (D + S) / S;  // terms per half: ceil((D + 1) / S)
   const int t0 = h * H;
-  double acc[L];
-  md::zero<L>(acc);
+  double acc0[L];
+  md::zero<L>(acc0);
   for (int tt = 0; tt < H; ++tt) {
     const int t = t0 + tt;
     const bool ph1 = t <= o1;
@@ -46,27 +46,26 @@ __device__ void conv(const double *U, const double *V, double *W, int D, int lan
       u[l] = U[l * Dp + i];
       v[l] = V[l * Dp + j];
     }
-    MD<L>::fma_lazy(acc, u, v);
+    MD<L>::fma_lazy(acc0, u, v);
     if (t == o1) {  // first output complete (always in the first half)
       if (act) {
         double r[L];
-        MD<L>::renorm(acc, r);
+        MD<L>::renorm(acc0, r);
         md::mul_int<L>(r, scale);
 #pragma unroll
         for (int l = 0; l < L; ++l) W[l * Dp + o1] = r[l];
       }
-      md::zero<L>(acc);
+      md::zero<L>(acc0);
     }
   }
-  double r[L];
-  MD<L>::renorm(acc, r);
-  if (S == 2) {  // add the second half's part of the second output
-    double o[L], s[L];
+  if (S == 2) {  // add the second half's part of the second output, still as level sums
+    double o[L];
 #pragma unroll
-    for (int l = 0; l < L; ++l) o[l] = __shfl_xor(r[l], G2, 64);
-    MD<L>::add(r, o, s);
-    md::copy<L>(s, r);
+    for (int l = 0; l < L; ++l) o[l] = __shfl_xor(acc0[l], G2, 64);
+    MD<L>::add_lazy(acc0, o);
   }
+  double r[L];
+  MD<L>::renorm(acc0, r);
   if (h == 0 && act && o2 > o1) {
     md::mul_int<L>(r, scale);
 #pragma unroll

@@ -26,6 +26,7 @@ hipError_t launch_assemble(int L, int n, int D, int m, int nnz, const int32_t *p
                            const int32_t *asm_ent, const double *cst, const double *val, const double *der,
                            double *b, double *A, hipStream_t st);
 size_t evaldiff_lds_bytes(int L, int D);
+int evaldiff_workers_per_block(int D);  // monomials per 256-thread workgroup
 hipError_t launch_assemble_b(int L, int n, int D, int m, const int32_t *poly_ptr, const double *cst,
                              const double *val, double *b, hipStream_t st);
 hipError_t launch_assemble_A(int L, int n, int D, int nnz, const int32_t *asm_ptr, const int32_t *asm_ent,
