@@ -291,15 +291,22 @@ __global__ void __launch_bounds__(256) qr_lds_kernel(int n, double *a, double *t
   constexpr int T = 16;
   const int team = tid / T, tl = tid % T;
   const size_t nn = (size_t)n * n;
-  const int ncol = (ncols_total - g + G - 1) / G;  // owned columns J = g + q G
+  // columns are owned in pairs: J belongs to workgroup (J / 2) mod G, so that
+  // every second reflector is used by the workgroup that computed it, from
+  // its LDS, without a hand-over
+  auto owner = [&](int J) { return (J >> 1) % G; };
+  auto gcol = [&](int q) { return 2 * (g + (q >> 1) * G) + (q & 1); };  // local index -> J
+  auto lcol = [&](int J) { return 2 * ((J >> 1) / G) + (J & 1); };       // J -> local index
+  int ncol = 0;
+  while (gcol(ncol) < ncols_total) ++ncol;
   double *cols = lds;                          // [ncol][L][n]
   double *vsh = lds + (size_t)ncol * L * n;    // [L][n] current reflector
-  __shared__ double sh_tau[L];
+  __shared__ double sh_tau[L], sh_tau_own[L];
   __shared__ int sh_ok;
   auto col = [&](int q) { return cols + (size_t)q * L * n; };
   // load the owned columns of [A_0 | I]
   for (int q = 0; q < ncol; ++q) {
-    const int J = g + q * G;
+    const int J = gcol(q);
     double *cq = col(q);
     for (int i = tid; i < n; i += blockDim.x)
 #pragma unroll
@@ -360,6 +367,7 @@ __global__ void __launch_bounds__(256) qr_lds_kernel(int n, double *a, double *t
       for (int l = 0; l < L; ++l) {
         tboard[(size_t)c * L + l] = tc[l];
         tau[(size_t)l * n + c] = tc[l];
+        sh_tau_own[l] = tc[l];
       }
     }
     wave_sync();
@@ -405,24 +413,37 @@ __global__ void __launch_bounds__(256) qr_lds_kernel(int n, double *a, double *t
 
   if (g == 0 && w == 0) publish(0, 0);  // column 0 belongs to workgroup 0
   bool ok = true;
+  int q0 = 0;  // owned columns J <= c: a prefix of the local order
   for (int c = 0; c < n; ++c) {
-    // reflector c into vsh
-    if (tid == 0) sh_ok = (c % G == g) ? 1 : (wait_flag(&flags[c], status) ? 1 : 0);
+    // reflector c into vsh: from this workgroup's own column, or from the board
+    const bool own = owner(c) == g;
+    if (tid == 0) sh_ok = own ? 1 : (wait_flag(&flags[c], status) ? 1 : 0);
     __syncthreads();
     ok = sh_ok != 0;
     if (!ok) break;
-    for (int i = c + tid; i < n; i += blockDim.x)
+    if (own) {
+      const double *cc = col(lcol(c));
+      for (int i = c + tid; i < n; i += blockDim.x)
 #pragma unroll
-      for (int l = 0; l < L; ++l) vsh[l * n + i] = vboard[(size_t)c * L * n + (size_t)l * n + i];
-    if (tid == 0)
+        for (int l = 0; l < L; ++l) vsh[l * n + i] = (i == c) ? (l == 0 ? 1.0 : 0.0) : cc[l * n + i];
+      if (tid == 0)
 #pragma unroll
-      for (int l = 0; l < L; ++l) sh_tau[l] = tboard[(size_t)c * L + l];
+        for (int l = 0; l < L; ++l) sh_tau[l] = sh_tau_own[l];
+    } else {
+      for (int i = c + tid; i < n; i += blockDim.x)
+#pragma unroll
+        for (int l = 0; l < L; ++l) vsh[l * n + i] = vboard[(size_t)c * L * n + (size_t)l * n + i];
+      if (tid == 0)
+#pragma unroll
+        for (int l = 0; l < L; ++l) sh_tau[l] = tboard[(size_t)c * L + l];
+    }
     __syncthreads();
     double tc[L];
 #pragma unroll
     for (int l = 0; l < L; ++l) tc[l] = sh_tau[l];
-    const bool ahead = (c + 1 < n) && ((c + 1) % G == g);
-    const int qa = ahead ? (c + 1 - g) / G : -1;
+    while (q0 < ncol && gcol(q0) <= c) ++q0;
+    const bool ahead = (c + 1 < n) && owner(c + 1) == g;
+    const int qa = ahead ? lcol(c + 1) : -1;
     if (ahead && w == 0) {  // look-ahead: update column c+1, publish reflector c+1
       apply(qa, c, tc, lane, 64);
       wave_sync();
@@ -437,7 +458,6 @@ __global__ void __launch_bounds__(256) qr_lds_kernel(int n, double *a, double *t
       // Team t0 takes the live columns t0, t0 + nt, ...: the teams of one
       // wavefront step through their columns together (no serialization of
       // the teams of a wavefront by divergent branches)
-      const int q0 = (c >= g) ? (c - g) / G + 1 : 0;
       const int nlive = ncol - q0 - (ahead ? 1 : 0);
       for (int k = t0; k < nlive; k += nt) {
         int q = q0 + k;
@@ -449,7 +469,7 @@ __global__ void __launch_bounds__(256) qr_lds_kernel(int n, double *a, double *t
   }
   if (ok) {  // write back the owned columns
     for (int q = 0; q < ncol; ++q) {
-      const int J = g + q * G;
+      const int J = gcol(q);
       const double *cq = col(q);
       for (int i = tid; i < n; i += blockDim.x)
 #pragma unroll
@@ -1167,19 +1187,19 @@ hipError_t launch_qr(int L, int n, double *a, double *tau, double *qt, int32_t *
 
 // Workgroups of the LDS-resident QR: at most 16 columns and about 120 KB of
 // columns per workgroup; 0 if that needs more than 64 workgroups.
+size_t qr_lds_bytes(int L, int n, int G, bool with_qt);
+
 int qr_lds_workgroups(int L, int n, bool with_qt) {
-  const long cols = with_qt ? 2L * n : n;
-  long G = (cols + 15) / 16;
-  const long bytes = cols * (long)L * n * 8;
-  const long need = (bytes + 120L * 1024 - 1) / (120L * 1024);
-  if (need > G) G = need;
-  if (G < 1) G = 1;
-  return G > 64 ? 0 : (int)G;
+  const int cols = with_qt ? 2 * n : n;
+  int G = std::max(1, (cols + 15) / 16);  // about 16 columns per workgroup
+  while (G <= 64 && qr_lds_bytes(L, n, G, with_qt) > 140 * 1024) ++G;
+  return G > 64 ? 0 : G;
 }
 
 size_t qr_lds_bytes(int L, int n, int G, bool with_qt) {
   const int cols = with_qt ? 2 * n : n;
-  const int ncol = (cols + G - 1) / G;
+  const int pairs = (cols + 1) / 2;
+  const int ncol = 2 * ((pairs + G - 1) / G);  // columns are owned in pairs
   return ((size_t)ncol + 1) * L * n * sizeof(double);
 }
 
