@@ -64,6 +64,8 @@ def lib():
         L.ora_arith.argtypes = [ci, ci, ci, dp, dp, dp, ci, ci, dp]
         L.ora_adjoint_solve.argtypes = [ci, ci, ci, ci, dp, dp, ci, dp]
         L.ora_coef_grad.argtypes = [ci, ci, ci, ci, i32p, i32p, i32p, i32p, ci, dp, ci, dp, ci, dp]
+        L.ora_window_step.argtypes = [ci, ci, ci, ci, i32p, i32p, i32p, i32p, ci, dp, dp, dp, dp, ci, ci, dp, dp,
+                                      dp, dp]
         _lib = L
     return _lib
 
@@ -288,6 +290,50 @@ def coef_grad(sys, x, lam, K=None, prec=None):
                              lam.shape[0], _d(_c64(lam)), K, _d(out))
     _check(rc, "ora_coef_grad")
     return out
+
+
+def window_step(sys, cff, cst, x, lo, hi, x_kept=None, K=None, prec=None):
+    """One step of the staggered method (Sections 4 and 5.3) on the problem
+    truncated at order ``hi``: b = -p(x) mod t^hi, A = p'(x) mod t^hi, the
+    block solve with dx_k = 0 for k < lo, and x_k + dx_k for k < hi.  With
+    ``x_kept`` the diagonal block is A_0 at x_kept's leading coefficients (the
+    factorization kept from an earlier step: a chord step), else at x.
+
+    Returns a dict of expansions x, dx, b of shape [K, n, D]: coefficients at
+    and above hi are x's own (dx and b zero there), and ``scale`` [D], the
+    size max_i (|c_{i,0,k}| + sum_m |value_{m,k}|) of the terms of b_k (zero
+    at and above hi)."""
+    L0 = cff.shape[0]
+    L, (cff, cst, x) = _common(cff, cst, x)
+    K = K or 4 * L0 + 2
+    prec = prec or prec_bits(L0)
+    n, D = sys.n, sys.D
+    if not (0 <= lo < hi <= D):
+        raise ValueError("need 0 <= lo < hi <= D")
+    xt = _c64(x[:, :, :hi])
+    ct = _c64(cst[:, :, :hi])
+    xs = None
+    if x_kept is not None:
+        xs = _c64(_pad(x_kept, L)[:L, :, 0])
+    pp, mp, var, ex = _sys_args(sys)
+    out = {k: np.zeros((K, n, hi)) for k in ("x", "dx", "b")}
+    sc = np.zeros(hi)
+    null = ctypes.POINTER(ctypes.c_double)()
+    rc = lib().ora_window_step(prec, n, hi, sys.m, _i(pp), _i(mp), _i(var), _i(ex), L, _d(cff), _d(ct), _d(xt),
+                               _d(xs) if xs is not None else null, lo, K, _d(out["x"]), _d(out["dx"]),
+                               _d(out["b"]), _d(sc))
+    _check(rc, "ora_window_step")
+    res = {}
+    for k in ("dx", "b"):
+        full = np.zeros((K, n, D))
+        full[:, :, :hi] = out[k]
+        res[k] = full
+    xf = np.zeros((K, n, D))
+    xf[:L] = x  # coefficients at and above hi: x itself (an exact expansion)
+    xf[:, :, :hi] = out["x"]
+    res["x"] = xf
+    res["scale"] = np.concatenate([sc, np.zeros(D - hi)])
+    return res
 
 
 def converge(sys, cff, cst, x0, steps, K=None, prec=None):

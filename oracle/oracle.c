@@ -123,9 +123,10 @@ static void mono_series(mpfr_t *out, mpfr_t coef, const int32_t *vars, const int
 
 /* Evaluate rows [r0, r1): b = -(c_0 + sum_m value_m), A_k[i][j] = sum_m (d/dx_j value_m)_k.
  * b is [rows][D], A is [D][rows][n] (row-major per matrix), scale[rows] gets
- * max_s (|c_{i,0,s}| + sum_m |value_{m,s}|). */
-static void eval_rows(const sys_t *S, mpfr_t *const *X, mpfr_t *const *C, mpfr_t *cff, int r0,
-                      int r1, mpfr_t *b, mpfr_t *A, mpfr_t *scale, mpfr_prec_t prec) {
+ * max_s (|c_{i,0,s}| + sum_m |value_{m,s}|); terms (NULL to skip) gets each
+ * |c_{i,0,s}| + sum_m |value_{m,s}| itself, [rows][D]. */
+static void eval_rows_terms(const sys_t *S, mpfr_t *const *X, mpfr_t *const *C, mpfr_t *cff, int r0,
+                            int r1, mpfr_t *b, mpfr_t *A, mpfr_t *scale, mpfr_t *terms, mpfr_prec_t prec) {
   const int D = S->D, n = S->n, rows = r1 - r0;
   for (size_t q = 0; q < (size_t)D * rows * n; ++q) mpfr_set_zero(A[q], 1);
 #pragma omp parallel num_threads(ora_get_threads())
@@ -163,6 +164,8 @@ static void eval_rows(const sys_t *S, mpfr_t *const *X, mpfr_t *const *C, mpfr_t
       for (int s = 0; s < D; ++s) mpfr_neg(b[(size_t)ri * D + s], b[(size_t)ri * D + s], MPFR_RNDN);
       mpfr_set_zero(scale[ri], 1);
       for (int s = 0; s < D; ++s) mpfr_max(scale[ri], scale[ri], absacc[s], MPFR_RNDN);
+      if (terms)
+        for (int s = 0; s < D; ++s) mpfr_set(terms[(size_t)ri * D + s], absacc[s], MPFR_RNDN);
     }
     vfree(val, D);
     vfree(tmp, D);
@@ -170,6 +173,11 @@ static void eval_rows(const sys_t *S, mpfr_t *const *X, mpfr_t *const *C, mpfr_t
     mpfr_clear(t);
     mpfr_clear(c2);
   }
+}
+
+static void eval_rows(const sys_t *S, mpfr_t *const *X, mpfr_t *const *C, mpfr_t *cff, int r0,
+                      int r1, mpfr_t *b, mpfr_t *A, mpfr_t *scale, mpfr_prec_t prec) {
+  eval_rows_terms(S, X, C, cff, r0, r1, b, A, scale, NULL, prec);
 }
 
 static int check_sys(const sys_t *S) {
@@ -283,17 +291,25 @@ static void lu_solve(mpfr_t *LU, int n, const int *perm, mpfr_t *y, mpfr_t *w, m
 
 /* Block forward substitution on the lower triangular block Toeplitz system
  * (Section 2): dx_k = A_0^{-1} (b_k - sum_{j=1..k} A_j dx_{k-j}).
- * A is [D][n][n] row-major, b and dx are [n][D]. */
-static int toeplitz_solve(mpfr_t *A, mpfr_t *b, mpfr_t *dx, int n, int D, mpfr_prec_t prec) {
+ * A is [D][n][n] row-major, b and dx are [n][D].  The diagonal block is A0:
+ * A itself for Newton's method, or the leading matrix taken at an earlier
+ * point when the factorization of the first stage is kept (Section 5.3, a
+ * chord step).  Stages below lo are not solved: dx_k = 0 for k < lo
+ * (Section 4, a coefficient whose residual vanishes gets no update); the
+ * sums still run over every j, with those zeros. */
+static int toeplitz_solve_window(mpfr_t *A, mpfr_t *A0, mpfr_t *b, mpfr_t *dx, int n, int D, int lo,
+                                 mpfr_prec_t prec) {
   mpfr_t *LU = vnew((size_t)n * n, prec);
   int *perm = (int *)malloc(n * sizeof(int));
-  for (size_t q = 0; q < (size_t)n * n; ++q) mpfr_set(LU[q], A[q], MPFR_RNDN);
+  for (size_t q = 0; q < (size_t)n * n; ++q) mpfr_set(LU[q], A0[q], MPFR_RNDN);
   int rc = lu_factor(LU, n, perm, prec);
   if (rc == ORA_OK) {
     mpfr_t *r = vnew(n, prec), *w = vnew(n, prec);
     mpfr_t t;
     mpfr_init2(t, prec);
-    for (int k = 0; k < D; ++k) {
+    for (int k = 0; k < lo && k < D; ++k)
+      for (int i = 0; i < n; ++i) mpfr_set_zero(dx[(size_t)i * D + k], 1);
+    for (int k = lo; k < D; ++k) {
 #pragma omp parallel for schedule(static) num_threads(ora_get_threads())
       for (int i = 0; i < n; ++i) {
         mpfr_t u;
@@ -316,6 +332,10 @@ static int toeplitz_solve(mpfr_t *A, mpfr_t *b, mpfr_t *dx, int n, int D, mpfr_p
   vfree(LU, (size_t)n * n);
   free(perm);
   return rc;
+}
+
+static int toeplitz_solve(mpfr_t *A, mpfr_t *b, mpfr_t *dx, int n, int D, mpfr_prec_t prec) {
+  return toeplitz_solve_window(A, A, b, dx, n, D, 0, prec);
 }
 
 /* ---------------------------- exported API ------------------------------ */
@@ -391,6 +411,78 @@ int ora_newton_step(int prec_bits, int n, int D, int m, const int32_t *pp, const
   vfree(A, (size_t)D * n * n);
   vfree(sc, n);
   vfree(dx, (size_t)n * D);
+  free_inputs(&S, X, C, F);
+  return rc;
+}
+
+/* One step of the staggered method (Sections 4 and 5.3).  The caller passes
+ * series truncated at the step's order, D coefficients (x, cst [L][n][D]), so
+ * b = -p(x) mod t^D and A = p'(x) mod t^D.  The diagonal block of the solve
+ * is A_0 taken at the leading coefficients xs0 [L][n] (the point where the
+ * factorization was computed; NULL: x's own, Newton's method); stages below
+ * lo get no update.  Outputs (K-double expansions, NULL to skip): x + dx,
+ * dx, b as [K][n][D]; scale[D] (doubles) gets max_i (|c_{i,0,k}| +
+ * sum_m |value_{m,k}|), the size of the terms that cancel in b_k. */
+int ora_window_step(int prec_bits, int n, int D, int m, const int32_t *pp, const int32_t *mp,
+                    const int32_t *var, const int32_t *ex, int L, const double *cff,
+                    const double *cst, const double *x, const double *xs0, int lo, int K,
+                    double *x_out, double *dx_out, double *b_out, double *scale_out) {
+  sys_t S = {n, D, m, pp, mp, var, ex};
+  if (check_sys(&S) || K < 1 || L < 1 || lo < 0 || lo >= D) return ORA_EINVAL;
+  mpfr_prec_t prec = prec_bits;
+  mpfr_t **X, **C, *F;
+  load_inputs(&S, L, cff, cst, x, &X, &C, &F, prec);
+  const size_t nD = (size_t)n * D, nn = (size_t)n * n;
+  mpfr_t *b = vnew(nD, prec), *A = vnew((size_t)D * nn, prec), *sc = vnew(n, prec);
+  mpfr_t *terms = vnew(nD, prec), *dx = vnew(nD, prec);
+  eval_rows_terms(&S, X, C, F, 0, n, b, A, sc, terms, prec);
+  mpfr_t *A0 = A;
+  mpfr_t *As = NULL, *bs = NULL, *scs = NULL;
+  if (xs0) {  /* A_0 at the kept point: the Jacobian of the order-1 truncation there */
+    sys_t S1 = {n, 1, m, pp, mp, var, ex};
+    mpfr_t **X1, **C1, *F1;
+    load_inputs(&S1, L, cff, NULL, xs0, &X1, &C1, &F1, prec);
+    As = vnew(nn, prec);
+    bs = vnew(n, prec);
+    scs = vnew(n, prec);
+    eval_rows(&S1, X1, C1, F1, 0, n, bs, As, scs, prec);
+    free_inputs(&S1, X1, C1, F1);
+    A0 = As;
+  }
+  int rc = toeplitz_solve_window(A, A0, b, dx, n, D, lo, prec);
+  if (rc == ORA_OK) {
+    mpfr_t tmp, xn, mx;
+    mpfr_init2(tmp, prec);
+    mpfr_init2(xn, prec);
+    mpfr_init2(mx, prec);
+    for (int i = 0; i < n; ++i)
+      for (int s2 = 0; s2 < D; ++s2) {
+        size_t q = (size_t)i * D + s2;
+        mpfr_add(xn, X[i][s2], dx[q], MPFR_RNDN);
+        if (x_out) exp_put(x_out + q, nD, K, xn, tmp);
+        if (dx_out) exp_put(dx_out + q, nD, K, dx[q], tmp);
+        if (b_out) exp_put(b_out + q, nD, K, b[q], tmp);
+      }
+    if (scale_out)
+      for (int s2 = 0; s2 < D; ++s2) {
+        mpfr_set_zero(mx, 1);
+        for (int i = 0; i < n; ++i) mpfr_max(mx, mx, terms[(size_t)i * D + s2], MPFR_RNDN);
+        scale_out[s2] = mpfr_get_d(mx, MPFR_RNDN);
+      }
+    mpfr_clear(tmp);
+    mpfr_clear(xn);
+    mpfr_clear(mx);
+  }
+  if (As) {
+    vfree(As, nn);
+    vfree(bs, n);
+    vfree(scs, n);
+  }
+  vfree(b, nD);
+  vfree(A, (size_t)D * nn);
+  vfree(sc, n);
+  vfree(terms, nD);
+  vfree(dx, nD);
   free_inputs(&S, X, C, F);
   return rc;
 }

@@ -490,3 +490,131 @@ def test_adjoint_gradient_matches_finite_differences():
             vals.append(sum((ex[i, k] ** 2 for i in range(sys.n) for k in range(ktop, sys.D)), Fraction(0)))
         fd = (vals[0] - vals[1]) / (2 * h)
         assert abs(fd - grad[mj]) <= abs(grad[mj]) * Fraction(1, 10 ** 70) + Fraction(1, 10 ** 80), mj
+
+
+# --------------------------------------------------------------------------
+# 10. the staggered step: order truncation, stage window, kept factorization
+#     (Sections 4 and 5.3)
+# --------------------------------------------------------------------------
+
+def _sympy_window(sys, cst, x, lo, hi, x_kept=None):
+    """Exact window step with sympy: b and A of the order-hi truncation, the
+    block system over stages lo..hi-1 only (dx_k = 0 below lo), its diagonal
+    block the Jacobian at x_kept's leading coefficients (x's own if None)."""
+    t = sympy.Symbol("t")
+    n = sys.n
+    X = sympy.symbols(f"y0:{n}")
+    cfv = [md_value(sys.cff[:, j]) for j in range(sys.m)]
+    xs = [sum(sympy.Rational(md_value(x[:, i, s])) * t ** s for s in range(hi)) for i in range(n)]
+    cs = [sum(sympy.Rational(md_value(cst[:, i, s])) * t ** s for s in range(hi)) for i in range(n)]
+    P = []
+    for i in range(n):
+        expr = 0
+        for mj in range(sys.poly_ptr[i], sys.poly_ptr[i + 1]):
+            term = sympy.Rational(cfv[mj])
+            for q in range(sys.mon_ptr[mj], sys.mon_ptr[mj + 1]):
+                term *= X[sys.var[q]] ** int(sys.exp[q])
+            expr += term
+        P.append(expr)
+
+    def trunc(e):
+        poly = sympy.Poly(sympy.expand(e), t)
+        return [poly.coeff_monomial(t ** s) for s in range(hi)]
+
+    sub = dict(zip(X, xs))
+    b = [[-c for c in trunc(cs[i] + P[i].subs(sub))] for i in range(n)]
+    A = [[trunc(sympy.diff(P[i], X[j]).subs(sub)) for j in range(n)] for i in range(n)]
+    if x_kept is None:
+        A0 = [[A[i][j][0] for j in range(n)] for i in range(n)]
+    else:
+        sub0 = {X[v]: sympy.Rational(md_value(x_kept[:, v, 0])) for v in range(n)}
+        A0 = [[sympy.diff(P[i], X[j]).subs(sub0) for j in range(n)] for i in range(n)]
+    W = hi - lo
+    T = sympy.zeros(n * W, n * W)
+    rhs = sympy.zeros(n * W, 1)
+    for kk in range(W):
+        for i in range(n):
+            rhs[kk * n + i] = b[i][lo + kk]
+            for jj in range(kk + 1):
+                for v in range(n):
+                    T[kk * n + i, jj * n + v] = A0[i][v] if jj == kk else A[i][v][kk - jj]
+    sol = T.LUsolve(rhs)
+    dx = [[sol[(s - lo) * n + i] if lo <= s < hi else 0 for s in range(sys.D)] for i in range(n)]
+    return b, dx
+
+
+@pytest.mark.parametrize("lo,hi,kept", [(0, 4, False), (1, 3, False), (2, 4, False), (0, 2, True), (1, 4, True),
+                                        (3, 4, True)])
+def test_window_step_brute_force_sympy(lo, hi, kept):
+    sys = mdinputs.tiny(2, 3, 3, mons=2, kmin=1, kmax=3, exps=(1, 2), seed=4)
+    x = mdinputs.random_point(sys, 4)
+    cst = mdinputs.random_constant(sys, 4)
+    xk = mdinputs.random_point(sys, 5) if kept else None
+    b, dx = _sympy_window(sys, cst, x, lo, hi, xk)
+    out = oracle.window_step(sys, sys.cff, cst, x, lo, hi, x_kept=xk, prec=700, K=16)
+    eb, edx, ex = exact(out["b"]), exact(out["dx"]), exact(out["x"])
+    tol = Fraction(1, 2 ** 600)
+    for i in range(sys.n):
+        for s in range(sys.D):
+            want_dx = Fraction(str(dx[i][s]))
+            assert abs(edx[i, s] - want_dx) <= tol * (1 + abs(want_dx))
+            want_x = md_value(x[:, i, s]) + want_dx
+            assert abs(ex[i, s] - want_x) <= tol * (1 + abs(want_x))
+            if s < hi:
+                want_b = Fraction(str(b[i][s]))
+                assert abs(eb[i, s] - want_b) <= tol * (1 + abs(want_b))
+            else:
+                assert eb[i, s] == 0 and ex[i, s] == md_value(x[:, i, s])
+
+
+def test_window_step_truncation_is_the_leading_part_of_newton():
+    """Coefficient k of the Newton update depends on the coefficients 0..k
+    only, so the step of the order-hi truncation is the leading part of the
+    full step; exact data make every residual product exact."""
+    L, n, d = 2, 4, 11
+    sys = _exact_data_system(L, n, d, seed=3)
+    cst = oracle.manufacture(sys, Lout=L)
+    x = sys.start()
+    x[:, :, 1:4] = sys.xstar[:, :, 1:4] * 0.5
+    full = oracle.newton_step(sys, sys.cff, cst, x)
+    for hi in (1, 5, 12):
+        w = oracle.window_step(sys, sys.cff, cst, x, 0, hi)
+        assert np.array_equal(exact(w["dx"])[:, :hi], exact(full["dx"])[:, :hi])
+        assert np.array_equal(exact(w["x"])[:, hi:], exact(x[:, :, hi:]))
+
+
+def test_chord_step_fixed_point_and_zero_window():
+    """At an exact root b = 0, so the chord step (any kept A_0) leaves x
+    unchanged; with x_k exact below lo, the window from lo is Newton's step
+    (Section 4: dx_k = 0 where b_k = 0)."""
+    L, n, d = 2, 4, 9
+    sys = _exact_data_system(L, n, d, seed=11)
+    cst = oracle.manufacture(sys, Lout=L)
+    kept = sys.xstar.copy()
+    kept[:, :, 0] *= 1.0 + 2.0 ** -20
+    w = oracle.window_step(sys, sys.cff, cst, sys.xstar, 0, sys.D, x_kept=kept)
+    assert not np.any(w["dx"]) and np.array_equal(exact(w["x"]), exact(sys.xstar))
+    lo = 4
+    x = sys.xstar.copy()
+    x[:, :, lo:] = 0.0
+    newton = oracle.newton_step(sys, sys.cff, cst, x)
+    win = oracle.window_step(sys, sys.cff, cst, x, lo, sys.D)
+    assert np.array_equal(exact(win["dx"]), exact(newton["dx"]))
+    assert not np.any(exact(newton["dx"])[:, :lo])
+
+
+def test_chord_step_contracts_linearly():
+    """A chord step (A_0 kept from a point sigma away) reduces an error delta
+    to about sigma * delta, where Newton's step reaches delta^2."""
+    sys = mdinputs.tiny(4, 4, 5, mons=3, seed=6)
+    cst = oracle.manufacture(sys)
+    delta, sigma = 1e-12, 1e-4
+    rng = np.random.default_rng(0)
+    x = sys.xstar.copy()
+    x[0] += delta * rng.uniform(0.5, 1.0, size=x.shape[1:])
+    kept = sys.xstar.copy()
+    kept[0, :, 0] *= 1.0 + sigma
+    chord = oracle.absdiff(oracle.window_step(sys, sys.cff, cst, x, 0, sys.D, x_kept=kept)["x"], sys.xstar).max()
+    newton = oracle.absdiff(oracle.newton_step(sys, sys.cff, cst, x)["x"], sys.xstar).max()
+    assert 1e-3 * sigma * delta < chord < 1e3 * sigma * delta
+    assert newton < 1e-3 * chord
