@@ -147,6 +147,60 @@ int md_newton_step(const md_plan *plan, const double *cff, const double *cst, do
 int md_newton_step_mixed(const md_plan *plan, int prec_solve, const double *cff, const double *cst, double *x,
                          int32_t *dev_status, double *dev_norms, void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* One step of the staggered method (Section 4) on a window of the series.
+ * The problem is truncated at order hi: b = -p(x) and A = p'(x) are computed
+ * for the coefficients 0..hi-1 only (x's coefficients from hi on are not
+ * read and not changed).  Once x_k is correct, b_k vanishes and dx_k need
+ * not be computed, so only the stages lo..hi-1 are solved, with dx_k = 0
+ * below lo:  A_0 dx_k = b_k - sum_{j=1..k-lo} A_j dx_{k-j},  lo <= k < hi;
+ * x_k := x_k + dx_k for lo <= k < hi.  keep_factorization = 1 skips the QR
+ * of A_0 and uses the factorization (as M = A_0^{-1}) that the last step
+ * without it left in ws, computed at that step's x (Section 5.3: the QR is
+ * done once, in the first stage); this makes a chord step.  It is the
+ * caller's to ensure that such a step has run on the same plan, ws and
+ * prec_solve; the result is undefined otherwise.  prec_solve as for
+ * md_newton_step_mixed (the plan's precision: a plain step).  Status and
+ * workspace as md_newton_step; dev_norms [2][D]: max |b_k| for k < hi, max
+ * |dx_k| for lo <= k < hi, zero elsewhere.  lo = 0, hi = D,
+ * keep_factorization = 0 is md_newton_step_mixed.  MD_EINVAL unless
+ * 0 <= lo < hi <= D. */
+int md_newton_step_window(const md_plan *plan, int prec_solve, int lo, int hi, int keep_factorization,
+                          const double *cff, const double *cst, double *x, int32_t *dev_status, double *dev_norms,
+                          void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* The order schedule of the staggered method (Section 4): the next order
+ * after d, d + 1 + d/2 (integer division), capped at D.  Host only. */
+int md_stagger_next_order(int d, int D);
+
+/* Result of md_newton_staggered. */
+typedef struct md_stagger_report {
+  int32_t steps;          /* steps taken */
+  int32_t converged;      /* 1: every coefficient met the tolerance */
+  int32_t lo, hi;         /* window of the last step */
+  int32_t factorizations; /* QR factorizations of A_0 computed */
+} md_stagger_report;
+
+/* Newton's method with the staggered progression of the order (Section 4),
+ * driven from the host: the first step solves for x_0 alone (order 1; x_0
+ * should carry about half the working precision, as the paper assumes), each
+ * following step raises the order hi by md_stagger_next_order, and the stages
+ * below lo are dropped once their residuals vanish: after each step, lo is
+ * the number of leading coefficients k with max_i |b_{i,k}| <= tol * s_k,
+ * where s_k = max_i (|c_{i,0,k}| + sum_m |value_{m,k}|) is the size of the
+ * terms that cancel in b_k (leading limbs).  refactor_every_step = 0 factors
+ * A_0 once, at the first step (Section 5.3), and makes every later step a
+ * chord step; 1 factors at every step (Newton's method).  Stops when hi = D
+ * and every coefficient meets the tolerance (converged = 1) or after
+ * max_steps steps (converged = 0).  windows (host, nullable): [max_steps][2]
+ * gets (lo, hi) of every step.  The host waits for the stream after every
+ * step (a few doubles are read back).  Arguments and workspace as
+ * md_newton_step_window; dev_norms [2][D] is required.  A step whose status
+ * is not MD_OK ends the run with that code. */
+int md_newton_staggered(const md_plan *plan, int prec_solve, int refactor_every_step, int max_steps, double tol,
+                        const double *cff, const double *cst, double *x, int32_t *windows,
+                        md_stagger_report *report, int32_t *dev_status, double *dev_norms, void *ws,
+                        size_t ws_bytes, hipStream_t stream);
+
 /* Batches of independent systems ("paths"; the paper tracks many solution
  * paths of a homotopy, Section 1), one Newton step of every path per call,
  * in one persistent launch.  A path p has n_p (1..128) variables and

@@ -43,6 +43,19 @@ _lib.md_solve_workspace_size.argtypes = [_i32, _i32, _i32, _szp]
 _lib.md_series_solve.argtypes = [_i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp, _vp]
 _lib.md_newton_step.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
 _lib.md_newton_step_mixed.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
+_lib.md_newton_step_window.argtypes = [_vp, _i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t,
+                                       _vp]
+_lib.md_stagger_next_order.argtypes = [_i32, _i32]
+
+
+class StaggerReport(ctypes.Structure):
+    """md_stagger_report: steps, converged, lo, hi, factorizations."""
+    _fields_ = [("steps", ctypes.c_int32), ("converged", ctypes.c_int32), ("lo", ctypes.c_int32),
+                ("hi", ctypes.c_int32), ("factorizations", ctypes.c_int32)]
+
+
+_lib.md_newton_staggered.argtypes = [_vp, _i32, _i32, _i32, ctypes.c_double, _vp, _vp, _vp, _i32p,
+                                     ctypes.POINTER(StaggerReport), _vp, _vp, _vp, ctypes.c_size_t, _vp]
 _lib.md_arith.argtypes = [_i32, _i32, ctypes.c_int64, _vp, _vp, _vp, _vp]
 _lib.md_last_error.restype = ctypes.c_char_p
 _lib.md_adjoint_workspace_size.argtypes = [_i32, _i32, _i32, _szp]
@@ -297,6 +310,43 @@ def newton_step_mixed(plan: Plan, prec_solve, cff, cst, x, status, norms, ws, st
     _check(rc, "md_newton_step_mixed")
 
 
+def newton_step_window(plan: Plan, prec_solve, lo, hi, keep_factorization, cff, cst, x, status, norms, ws,
+                       stream=None):
+    """md_newton_step_window: one staggered step on the window lo..hi-1."""
+    L, n, D, m = plan.prec, plan.n, plan.D, plan.m
+    rc = _lib.md_newton_step_window(plan._h, int(prec_solve), int(lo), int(hi), int(bool(keep_factorization)),
+                                    _ptr(cff, (L, m), "cff"), _ptr(cst, (L, n, D), "cst"), _ptr(x, (L, n, D), "x"),
+                                    _ptr(status, (1,), "status"), _ptr(norms, (2, D), "norms"), _ptr(ws, None, "ws"),
+                                    ws.numel() * 8, _stream(stream))
+    _check(rc, "md_newton_step_window")
+
+
+def stagger_next_order(d, D):
+    """The order after d in the staggered schedule, d + 1 + d // 2, capped at D."""
+    return int(_lib.md_stagger_next_order(int(d), int(D)))
+
+
+def newton_staggered(plan: Plan, prec_solve, refactor_every_step, max_steps, tol, cff, cst, x, status, norms, ws,
+                     stream=None):
+    """md_newton_staggered; returns (StaggerReport, [(lo, hi) per step])."""
+    L, n, D, m = plan.prec, plan.n, plan.D, plan.m
+    win = (ctypes.c_int32 * (2 * int(max_steps)))()
+    rep = StaggerReport()
+    rc = _lib.md_newton_staggered(plan._h, int(prec_solve), int(bool(refactor_every_step)), int(max_steps),
+                                  float(tol), _ptr(cff, (L, m), "cff"), _ptr(cst, (L, n, D), "cst"),
+                                  _ptr(x, (L, n, D), "x"), win, ctypes.byref(rep), _ptr(status, (1,), "status"),
+                                  _ptr(norms, (2, D), "norms"), _ptr(ws, None, "ws"), ws.numel() * 8,
+                                  _stream(stream))
+    _check(rc, "md_newton_staggered")
+    return rep, [(win[2 * q], win[2 * q + 1]) for q in range(rep.steps)]
+
+
+def default_stagger_tol(prec):
+    """Residual tolerance of the staggered driver relative to the size of the
+    cancelling terms: 2^8 units in the last place of the multiple double."""
+    return 2.0 ** (8 - 53 * int(prec))
+
+
 def arith(prec, op, a, b, c, stream=None):
     """Elementwise c = a op b on [L, count] md arrays; op "dot" writes sum_q a[q] b[q] to c [L, 1]."""
     L = int(prec)
@@ -374,6 +424,20 @@ class Newton:
         else:
             newton_step_mixed(self.plan, prec_solve, self.cff, self.cst, self.x, self.status, self.norms, self.ws,
                               stream)
+
+    def step_window(self, lo, hi, keep_factorization=False, stream=None, prec_solve=None):
+        """One step of the staggered method on the window lo..hi-1 (md_newton_step_window)."""
+        ps = self.plan.prec if prec_solve is None else prec_solve
+        newton_step_window(self.plan, ps, lo, hi, keep_factorization, self.cff, self.cst, self.x, self.status,
+                           self.norms, self.ws, stream)
+
+    def staggered(self, max_steps=40, tol=None, refactor_every_step=False, stream=None, prec_solve=None):
+        """Newton's method with the staggered order schedule (md_newton_staggered);
+        returns (StaggerReport, [(lo, hi) per step])."""
+        ps = self.plan.prec if prec_solve is None else prec_solve
+        tol = default_stagger_tol(ps) if tol is None else tol
+        return newton_staggered(self.plan, ps, refactor_every_step, max_steps, tol, self.cff, self.cst, self.x,
+                                self.status, self.norms, self.ws, stream)
 
     def status_code(self):
         return int(self.status.item())

@@ -81,7 +81,7 @@ size_t qr_scratch_bytes(int L, int n) {
 
 // Workspace regions, in doubles, each aligned to 256 bytes.
 struct Layout {
-  size_t val, der, pw, unit, b, A, qr, tau, qt, bar, invd, M, N, At, r, dxT, dx, sync, total;
+  size_t val, der, pw, unit, b, A, qr, tau, qt, bar, invd, M, N, At, r, dxT, dx, sync, scale, total;
 };
 
 Layout newton_layout(const md_plan *p) {
@@ -111,6 +111,7 @@ Layout newton_layout(const md_plan *p) {
   w.dxT = take(L * n * D);
   w.dx = take(L * n * D);
   w.sync = take(mdk::stages_sync_ints(p->D) / 2 + 1);
+  w.scale = take(D);  // term sizes of b_k for the staggered driver
   w.total = off;
   return w;
 }
@@ -343,11 +344,12 @@ static void eval_args(const md_plan *p, const double *cff, const double *x, void
   a.der = at(ws, w.der);
 }
 
-static int eval_diff_impl(const md_plan *p, const double *cff, const double *cst, const double *x, double *b,
+// b and A for the first Dc coefficients (the problem truncated at order Dc).
+static int eval_diff_impl(const md_plan *p, int Dc, const double *cff, const double *cst, const double *x, double *b,
                           double *A, void *ws, hipStream_t st) {
   Layout w = newton_layout(p);
   mdk::EvalArgs a;
-  eval_args(p, cff, x, ws, p->D, a);
+  eval_args(p, cff, x, ws, Dc, a);
   hipError_t e;
   {
     Timed t(MD_CLASS_CONVOLUTIONS, st);
@@ -356,8 +358,8 @@ static int eval_diff_impl(const md_plan *p, const double *cff, const double *cst
   if (e != hipSuccess) return hip_fail(e, "eval/diff launch");
   {
     Timed t(MD_CLASS_ASSEMBLY, st);
-    e = mdk::launch_assemble(p->L, p->n, p->D, p->m, p->nnz, p->d_poly_ptr, p->d_asm_ptr, p->d_asm_ent, cst, a.val,
-                             a.der, b, A, st);
+    e = mdk::launch_assemble(p->L, p->n, p->D, Dc, p->m, p->nnz, p->d_poly_ptr, p->d_asm_ptr, p->d_asm_ent, cst,
+                             a.val, a.der, b, A, st);
   }
   if (e != hipSuccess) return hip_fail(e, "assembly launch");
   return MD_OK;
@@ -367,7 +369,7 @@ int md_eval_diff(const md_plan *p, const double *cff, const double *cst, const d
                  void *ws, size_t ws_bytes, hipStream_t st) {
   if (!p || !cst || !x || !b || !A || (p->m > 0 && !cff)) return fail(MD_EINVAL, "NULL argument");
   if (!ws || ws_bytes < newton_layout(p).total) return fail(MD_ENOSPACE, "workspace too small");
-  return eval_diff_impl(p, cff, cst, x, b, A, ws, st);
+  return eval_diff_impl(p, p->D, cff, cst, x, b, A, ws, st);
 }
 
 int md_qr_workspace_size(int prec, int n, size_t *bytes) {
@@ -405,48 +407,63 @@ int md_series_solve(int prec, int n, int d, const double *qr, const double *tau,
 // Limb-major storage makes the Ls-limb truncation of x, cff and b their
 // leading Ls limb planes, so the low-precision kernels read the same
 // buffers.  Ls == L is the plain step.
-static int newton_step_impl(const md_plan *p, int Ls, const double *cff, const double *cst, double *x,
-                            int32_t *dev_status, double *dev_norms, void *ws, hipStream_t st) {
+//
+// The staggered method (Section 4) runs the step on a window: the problem
+// truncated at order hi (coefficients 0..hi-1 evaluated, those from hi on
+// left as they are) with the stages lo..hi-1 solved, dx_k = 0 below lo.
+// The window's block system is the block Toeplitz solve of hi - lo stages on
+// b_lo..b_{hi-1} with A_0..A_{hi-lo-1}, so strided transposes pack it into
+// the compact coefficient-major arrays of the stage kernels.  keep_m skips
+// the pre-pass, the QR and M and uses the M = A_0^{-1} that the last step
+// without keep_m left in the workspace (the factorization of the first
+// stage, Section 5.3: a chord step).  scale (nullable, D doubles) receives
+// the size of the terms of each b_k.
+static int newton_step_impl(const md_plan *p, int Ls, int lo, int hi, bool keep_m, const double *cff,
+                            const double *cst, double *x, int32_t *dev_status, double *dev_norms, double *scale,
+                            void *ws, hipStream_t st) {
   Layout w = newton_layout(p);
-  const int L = p->L, n = p->n, D = p->D;
+  const int L = p->L, n = p->n, D = p->D, W = hi - lo;
   const bool mixed = Ls != L;
   hipError_t e;
   if ((e = mdk::launch_status_init(dev_status, st)) != hipSuccess) return hip_fail(e, "status");
   double *b = at(ws, w.b), *A = at(ws, w.A), *qr = at(ws, w.qr), *tau = at(ws, w.tau), *qt = at(ws, w.qt);
   double *invd = at(ws, w.invd), *M = at(ws, w.M), *N = at(ws, w.N), *r = at(ws, w.r), *dx = at(ws, w.dx);
   mdk::EvalArgs a;
-  // 1. pre-pass: coefficient 0 of every derivative product gives A_0 (the
-  //    same products as the full evaluation, rounded in another order: the
-  //    solve uses this A_0 throughout, for M and for the stages)
-  {
-    Timed t(MD_CLASS_QR, st);
-    eval_args(p, cff, x, ws, 1, a);
-    e = (p->maxk <= mdk::evaldiff0_max_support(Ls)) ? mdk::launch_evaldiff0(Ls, a, st)
-                                                    : mdk::launch_evaldiff(Ls, a, p->maxexp, at(ws, w.pw), st);
-    if (e != hipSuccess) return hip_fail(e, "A_0 pre-pass");
-    if ((e = mdk::launch_assemble_A0(Ls, n, D, p->nnz, p->d_asm_ptr, p->d_asm_ent, a.der, qr, st)) != hipSuccess)
-      return hip_fail(e, "A_0 assembly");
+  if (!keep_m) {
+    // 1. pre-pass: coefficient 0 of every derivative product gives A_0 (the
+    //    same products as the full evaluation, rounded in another order: the
+    //    solve uses this A_0 throughout, for M and for the stages)
+    {
+      Timed t(MD_CLASS_QR, st);
+      eval_args(p, cff, x, ws, 1, a);
+      e = (p->maxk <= mdk::evaldiff0_max_support(Ls)) ? mdk::launch_evaldiff0(Ls, a, st)
+                                                      : mdk::launch_evaldiff(Ls, a, p->maxexp, at(ws, w.pw), st);
+      if (e != hipSuccess) return hip_fail(e, "A_0 pre-pass");
+      if ((e = mdk::launch_assemble_A0(Ls, n, D, p->nnz, p->d_asm_ptr, p->d_asm_ent, a.der, qr, st)) != hipSuccess)
+        return hip_fail(e, "A_0 assembly");
+    }
+    // 2. fork: QR of A_0 with Q^T, then M = R^{-1} Q^T, on the second stream
+    if ((e = hipEventRecord(p->fork, st)) != hipSuccess) return hip_fail(e, "fork");
+    if ((e = hipStreamWaitEvent(p->aux, p->fork, 0)) != hipSuccess) return hip_fail(e, "fork wait");
+    {
+      Timed t(MD_CLASS_QR, p->aux);
+      if ((e = run_qr(Ls, n, qr, tau, qt, dev_status, at(ws, w.bar), p->aux)) != hipSuccess) return hip_fail(e, "qr");
+    }
+    {
+      Timed t(MD_CLASS_QHB_BS, p->aux);
+      if ((e = mdk::launch_m_from_qt(Ls, n, qr, qt, invd, M, dev_status, p->aux)) != hipSuccess)
+        return hip_fail(e, "M");
+    }
+    if ((e = hipEventRecord(p->join, p->aux)) != hipSuccess) return hip_fail(e, "join");
   }
-  // 2. fork: QR of A_0 with Q^T, then M = R^{-1} Q^T, on the second stream
-  if ((e = hipEventRecord(p->fork, st)) != hipSuccess) return hip_fail(e, "fork");
-  if ((e = hipStreamWaitEvent(p->aux, p->fork, 0)) != hipSuccess) return hip_fail(e, "fork wait");
-  {
-    Timed t(MD_CLASS_QR, p->aux);
-    if ((e = run_qr(Ls, n, qr, tau, qt, dev_status, at(ws, w.bar), p->aux)) != hipSuccess) return hip_fail(e, "qr");
-  }
-  {
-    Timed t(MD_CLASS_QHB_BS, p->aux);
-    if ((e = mdk::launch_m_from_qt(Ls, n, qr, qt, invd, M, dev_status, p->aux)) != hipSuccess)
-      return hip_fail(e, "M");
-  }
-  if ((e = hipEventRecord(p->join, p->aux)) != hipSuccess) return hip_fail(e, "join");
-  // 3. the full evaluation and differentiation on the caller's stream; mixed:
-  //    the values at L limbs for b, the derivatives at Ls limbs for A
+  // 3. the evaluation and differentiation of the first hi coefficients on the
+  //    caller's stream; mixed: the values at L limbs for b, the derivatives
+  //    at Ls limbs for A
   if (!mixed) {
-    int rc = eval_diff_impl(p, cff, cst, x, b, A, ws, st);
+    int rc = eval_diff_impl(p, hi, cff, cst, x, b, A, ws, st);
     if (rc != MD_OK) return rc;
   } else {
-    eval_args(p, cff, x, ws, D, a);
+    eval_args(p, cff, x, ws, hi, a);
     a.values_only = 1;
     {
       Timed t(MD_CLASS_CONVOLUTIONS, st);
@@ -455,7 +472,7 @@ static int newton_step_impl(const md_plan *p, int Ls, const double *cff, const d
     }
     {
       Timed t(MD_CLASS_ASSEMBLY, st);
-      if ((e = mdk::launch_assemble_b(L, n, D, p->m, p->d_poly_ptr, cst, a.val, b, st)) != hipSuccess)
+      if ((e = mdk::launch_assemble_b(L, n, D, hi, p->m, p->d_poly_ptr, cst, a.val, b, st)) != hipSuccess)
         return hip_fail(e, "residual assembly");
     }
     a.values_only = 0;
@@ -466,35 +483,44 @@ static int newton_step_impl(const md_plan *p, int Ls, const double *cff, const d
     }
     {
       Timed t(MD_CLASS_ASSEMBLY, st);
-      if ((e = mdk::launch_assemble_A(Ls, n, D, p->nnz, p->d_asm_ptr, p->d_asm_ent, a.der, A, st)) != hipSuccess)
+      if ((e = mdk::launch_assemble_A(Ls, n, D, hi, p->nnz, p->d_asm_ptr, p->d_asm_ent, a.der, A, st)) != hipSuccess)
         return hip_fail(e, "Jacobian assembly");
     }
   }
-  const size_t nn = (size_t)n * n, nD = (size_t)n * D;
+  if (scale) {
+    Timed t(MD_CLASS_ASSEMBLY, st);
+    if ((e = mdk::launch_term_scale(n, D, hi, p->m, p->d_poly_ptr, cst, at(ws, w.val), scale, st)) != hipSuccess)
+      return hip_fail(e, "term scale");
+  }
+  const size_t nn = (size_t)n * n, nD = (size_t)n * D, nW = (size_t)n * W;
   double *At = at(ws, w.At), *dxT = at(ws, w.dxT);
   {
+    // coefficient-major A_0..A_{W-1} [Ls][W][n][n] and b_lo..b_{hi-1} [Ls][W][n]
     Timed t(MD_CLASS_UPDATES, st);
-    if ((e = mdk::launch_transpose(Ls, A, At, nn, D, nn * D, nn * D, st)) != hipSuccess) return hip_fail(e, "A^T");
-    if ((e = mdk::launch_transpose(Ls, b, r, n, D, nD, nD, st)) != hipSuccess) return hip_fail(e, "b^T");
+    if ((e = mdk::launch_transpose_ld(Ls, A, D, At, nn, nn, W, nn * D, nn * W, st)) != hipSuccess)
+      return hip_fail(e, "A^T");
+    if ((e = mdk::launch_transpose_ld(Ls, b + lo, D, r, n, n, W, nD, nW, st)) != hipSuccess)
+      return hip_fail(e, "b^T");
   }
-  // 4. join, N = M A_1, the staged solve
-  if ((e = hipStreamWaitEvent(st, p->join, 0)) != hipSuccess) return hip_fail(e, "join wait");
-  if (D > 1) {
+  // 4. join, N = M A_1 (and P = M A_2), the staged solve of the window
+  if (!keep_m && (e = hipStreamWaitEvent(st, p->join, 0)) != hipSuccess) return hip_fail(e, "join wait");
+  if (W > 1) {
     Timed t(MD_CLASS_GEMM, st);
-    if ((e = mdk::launch_gemm(Ls, n, M, At + nn, nn * D, N, mdk::stages_products(Ls, n, D), st)) != hipSuccess)
+    if ((e = mdk::launch_gemm(Ls, n, M, At + nn, nn * W, N, mdk::stages_products(Ls, n, W), st)) != hipSuccess)
       return hip_fail(e, "gemm");
   }
   {
     Timed t(MD_CLASS_UPDATES, st);
-    if ((e = mdk::launch_stages(Ls, n, D, M, N, At, r, dxT, reinterpret_cast<int *>(at(ws, w.sync)), dev_status,
+    if ((e = mdk::launch_stages(Ls, n, W, M, N, At, r, dxT, reinterpret_cast<int *>(at(ws, w.sync)), dev_status,
                                 st)) != hipSuccess)
       return hip_fail(e, "stages");
-    if ((e = mdk::launch_transpose(Ls, dxT, dx, D, n, nD, nD, st)) != hipSuccess) return hip_fail(e, "dx");
+    if ((e = mdk::launch_transpose_ld(Ls, dxT, n, dx + lo, D, W, n, nW, nD, st)) != hipSuccess)
+      return hip_fail(e, "dx");
   }
   {
     Timed t(MD_CLASS_X_UPDATE, st);
-    e = mixed ? mdk::launch_update_mixed(L, Ls, n, D, b, dx, x, dev_norms, dev_status, st)
-              : mdk::launch_update(L, n, D, b, dx, x, dev_norms, dev_status, st);
+    e = mixed ? mdk::launch_update_mixed(L, Ls, n, D, lo, hi, b, dx, x, dev_norms, dev_status, st)
+              : mdk::launch_update(L, n, D, lo, hi, b, dx, x, dev_norms, dev_status, st);
     if (e != hipSuccess) return hip_fail(e, "update");
   }
   return MD_OK;
@@ -504,7 +530,7 @@ int md_newton_step(const md_plan *p, const double *cff, const double *cst, doubl
                    double *dev_norms, void *ws, size_t ws_bytes, hipStream_t st) {
   if (!p || !cst || !x || (p->m > 0 && !cff)) return fail(MD_EINVAL, "NULL argument");
   if (!ws || ws_bytes < newton_layout(p).total) return fail(MD_ENOSPACE, "workspace too small");
-  return newton_step_impl(p, p->L, cff, cst, x, dev_status, dev_norms, ws, st);
+  return newton_step_impl(p, p->L, 0, p->D, false, cff, cst, x, dev_status, dev_norms, nullptr, ws, st);
 }
 
 int md_newton_step_mixed(const md_plan *p, int prec_solve, const double *cff, const double *cst, double *x,
@@ -513,7 +539,73 @@ int md_newton_step_mixed(const md_plan *p, int prec_solve, const double *cff, co
   if (!valid_prec(prec_solve) || prec_solve > p->L)
     return fail(MD_EINVAL, "solve precision must be dd, qd or od and at most the plan's");
   if (!ws || ws_bytes < newton_layout(p).total) return fail(MD_ENOSPACE, "workspace too small");
-  return newton_step_impl(p, prec_solve, cff, cst, x, dev_status, dev_norms, ws, st);
+  return newton_step_impl(p, prec_solve, 0, p->D, false, cff, cst, x, dev_status, dev_norms, nullptr, ws, st);
+}
+
+int md_newton_step_window(const md_plan *p, int prec_solve, int lo, int hi, int keep_factorization,
+                          const double *cff, const double *cst, double *x, int32_t *dev_status, double *dev_norms,
+                          void *ws, size_t ws_bytes, hipStream_t st) {
+  if (!p || !cst || !x || (p->m > 0 && !cff)) return fail(MD_EINVAL, "NULL argument");
+  if (!valid_prec(prec_solve) || prec_solve > p->L)
+    return fail(MD_EINVAL, "solve precision must be dd, qd or od and at most the plan's");
+  if (lo < 0 || hi > p->D || lo >= hi) return fail(MD_EINVAL, "window must satisfy 0 <= lo < hi <= D");
+  if (!ws || ws_bytes < newton_layout(p).total) return fail(MD_ENOSPACE, "workspace too small");
+  return newton_step_impl(p, prec_solve, lo, hi, keep_factorization != 0, cff, cst, x, dev_status, dev_norms,
+                          nullptr, ws, st);
+}
+
+int md_stagger_next_order(int d, int D) { return std::min(D, d + 1 + d / 2); }
+
+int md_newton_staggered(const md_plan *p, int prec_solve, int refactor_every_step, int max_steps, double tol,
+                        const double *cff, const double *cst, double *x, int32_t *windows,
+                        md_stagger_report *report, int32_t *dev_status, double *dev_norms, void *ws,
+                        size_t ws_bytes, hipStream_t st) {
+  if (!p || !cst || !x || !dev_status || !dev_norms || !report || (p->m > 0 && !cff))
+    return fail(MD_EINVAL, "NULL argument");
+  if (!valid_prec(prec_solve) || prec_solve > p->L)
+    return fail(MD_EINVAL, "solve precision must be dd, qd or od and at most the plan's");
+  if (max_steps < 1 || !(tol >= 0.0)) return fail(MD_EINVAL, "max_steps must be positive and tol non-negative");
+  if (!ws || ws_bytes < newton_layout(p).total) return fail(MD_ENOSPACE, "workspace too small");
+  const Layout w = newton_layout(p);
+  const int D = p->D;
+  double *scale = at(ws, w.scale);
+  std::vector<double> h(3 * (size_t)D);  // max |b_k|, max |dx_k|, s_k
+  int32_t status = MD_OK;
+  *report = md_stagger_report{0, 0, 0, 1, 0};
+  int lo = 0, hi = 1;
+  for (int step = 0; step < max_steps; ++step) {
+    const bool keep = !refactor_every_step && step > 0;
+    int rc = newton_step_impl(p, prec_solve, lo, hi, keep, cff, cst, x, dev_status, dev_norms, scale, ws, st);
+    if (rc != MD_OK) return rc;
+    report->steps = step + 1;
+    report->lo = lo;
+    report->hi = hi;
+    if (!keep) report->factorizations++;
+    if (windows) {
+      windows[2 * step] = lo;
+      windows[2 * step + 1] = hi;
+    }
+    hipError_t e;
+    if ((e = hipMemcpyAsync(h.data(), dev_norms, 2 * (size_t)D * sizeof(double), hipMemcpyDeviceToHost, st)) !=
+            hipSuccess ||
+        (e = hipMemcpyAsync(h.data() + 2 * (size_t)D, scale, (size_t)D * sizeof(double), hipMemcpyDeviceToHost,
+                            st)) != hipSuccess ||
+        (e = hipMemcpyAsync(&status, dev_status, sizeof(int32_t), hipMemcpyDeviceToHost, st)) != hipSuccess ||
+        (e = hipStreamSynchronize(st)) != hipSuccess)
+      return hip_fail(e, "reading the norms");
+    if (status != MD_OK) return fail(status, "a step of the staggered method failed (status " +
+                                                 std::to_string(status) + ")");
+    // leading coefficients whose residual vanished, relative to its terms
+    int k = 0;
+    while (k < hi && h[k] <= tol * h[2 * (size_t)D + k]) ++k;
+    if (hi == D && k == D) {
+      report->converged = 1;
+      break;
+    }
+    lo = k;
+    hi = md_stagger_next_order(hi, D);
+  }
+  return MD_OK;
 }
 
 int md_adjoint_workspace_size(int prec, int n, int d, size_t *bytes) {

@@ -22,15 +22,19 @@ hipError_t launch_evaldiff(int L, const EvalArgs &a, int maxexp, double *pw, hip
 // evaldiff0_max_support(L) variables (none for octo doubles).
 hipError_t launch_evaldiff0(int L, const EvalArgs &a, hipStream_t st);
 int evaldiff0_max_support(int L);
-hipError_t launch_assemble(int L, int n, int D, int m, int nnz, const int32_t *poly_ptr, const int32_t *asm_ptr,
-                           const int32_t *asm_ent, const double *cst, const double *val, const double *der,
-                           double *b, double *A, hipStream_t st);
+// The assembly kernels fill the first Dc coefficients of series stored with D.
+hipError_t launch_assemble(int L, int n, int D, int Dc, int m, int nnz, const int32_t *poly_ptr,
+                           const int32_t *asm_ptr, const int32_t *asm_ent, const double *cst, const double *val,
+                           const double *der, double *b, double *A, hipStream_t st);
 size_t evaldiff_lds_bytes(int L, int D);
 int evaldiff_workers_per_block(int D);  // monomials per 256-thread workgroup
-hipError_t launch_assemble_b(int L, int n, int D, int m, const int32_t *poly_ptr, const double *cst,
+hipError_t launch_assemble_b(int L, int n, int D, int Dc, int m, const int32_t *poly_ptr, const double *cst,
                              const double *val, double *b, hipStream_t st);
-hipError_t launch_assemble_A(int L, int n, int D, int nnz, const int32_t *asm_ptr, const int32_t *asm_ent,
+hipError_t launch_assemble_A(int L, int n, int D, int Dc, int nnz, const int32_t *asm_ptr, const int32_t *asm_ent,
                              const double *der, double *A, hipStream_t st);
+// scale[k] = max_i (|c_{i,0,k}| + sum_m |value_{m,k}|) for k < Dc, 0 above (scale[D]).
+hipError_t launch_term_scale(int n, int D, int Dc, int m, const int32_t *poly_ptr, const double *cst,
+                             const double *val, double *scale, hipStream_t st);
 hipError_t launch_assemble_A0(int L, int n, int D, int nnz, const int32_t *asm_ptr, const int32_t *asm_ent,
                               const double *der, double *a0, hipStream_t st);
 
@@ -48,6 +52,10 @@ hipError_t launch_form_m(int L, int n, const double *qr, const double *tau, doub
 hipError_t launch_extract(int L, int n, int D, int k, const double *A, double *out, hipStream_t st);
 hipError_t launch_transpose(int L, const double *in, double *out, size_t rows, int cols, size_t in_ls,
                             size_t out_ls, hipStream_t st);
+// The same with row strides: out[l][c][r] at out + l out_ls + c out_ld + r from
+// in + l in_ls + r in_ld + c (a window of the coefficients of series).
+hipError_t launch_transpose_ld(int L, const double *in, size_t in_ld, double *out, size_t out_ld, size_t rows,
+                               int cols, size_t in_ls, size_t out_ls, hipStream_t st);
 // out + c L n^2 = M (B + c n^2) for c < count (B with limb stride b_ls).
 hipError_t launch_gemm(int L, int n, const double *M, const double *B, size_t b_ls, double *out, int count,
                        hipStream_t st);
@@ -60,10 +68,12 @@ int stages_sync_ints(int D);
 int stages_products(int L, int n, int D);
 hipError_t launch_stages(int L, int n, int D, const double *M, const double *NP, const double *At, double *rT,
                          double *dxT, int *sync, int32_t *status, hipStream_t st);
-hipError_t launch_update(int L, int n, int D, const double *b, const double *dx, double *x, double *norms,
-                         int32_t *status, hipStream_t st);
-hipError_t launch_update_mixed(int L, int Ldx, int n, int D, const double *b, const double *dx, double *x,
-                               double *norms, int32_t *status, hipStream_t st);
+// x_k += dx_k for lo <= k < hi; norms[2][D]: max |b_k| for k < hi and
+// max |dx_k| for lo <= k < hi, zero elsewhere.
+hipError_t launch_update(int L, int n, int D, int lo, int hi, const double *b, const double *dx, double *x,
+                         double *norms, int32_t *status, hipStream_t st);
+hipError_t launch_update_mixed(int L, int Ldx, int n, int D, int lo, int hi, const double *b, const double *dx,
+                               double *x, double *norms, int32_t *status, hipStream_t st);
 hipError_t launch_arith(int L, int op, int64_t count, const double *a, const double *b, double *c, hipStream_t st);
 hipError_t launch_copy(const double *src, double *dst, size_t count, hipStream_t st);
 hipError_t launch_series_to_rev(int L, int n, int D, const double *in, double *out, hipStream_t st);

@@ -697,11 +697,12 @@ __global__ void extract_coeff_kernel(int n, int D, int k, const double *A, doubl
   st<L>(out, nn, q, v);
 }
 
-// out[l][c][r] = in[l][r][c] for r < rows, c < cols (limb strides in_ls, out_ls):
-// series-major arrays [..][D] to coefficient-major [D][..] and back, through a
-// 32 x 32 LDS tile so that reads and writes are both coalesced.
+// out[l][c][r] = in[l][r][c] for r < rows, c < cols (row strides in_ld,
+// out_ld; limb strides in_ls, out_ls): series-major arrays [..][D] to
+// coefficient-major [D][..] and back, also for a window of the coefficients,
+// through a 32 x 32 LDS tile so that reads and writes are both coalesced.
 __global__ void __launch_bounds__(256) transpose_kernel(const double *in, double *out, size_t rows, int cols,
-                                                        size_t in_ls, size_t out_ls) {
+                                                        size_t in_ld, size_t out_ld, size_t in_ls, size_t out_ls) {
   __shared__ double tile[32][33];
   const int l = blockIdx.z;
   const size_t r0 = (size_t)blockIdx.x * 32;
@@ -710,13 +711,13 @@ __global__ void __launch_bounds__(256) transpose_kernel(const double *in, double
   for (int yy = ty; yy < 32; yy += 8) {
     const size_t r = r0 + yy;
     const int c = c0 + tx;
-    if (r < rows && c < cols) tile[yy][tx] = in[(size_t)l * in_ls + r * cols + c];
+    if (r < rows && c < cols) tile[yy][tx] = in[(size_t)l * in_ls + r * in_ld + c];
   }
   __syncthreads();
   for (int yy = ty; yy < 32; yy += 8) {
     const int c = c0 + yy;
     const size_t r = r0 + tx;
-    if (r < rows && c < cols) out[(size_t)l * out_ls + (size_t)c * rows + r] = tile[tx][yy];
+    if (r < rows && c < cols) out[(size_t)l * out_ls + (size_t)c * out_ld + r] = tile[tx][yy];
   }
 }
 
@@ -1080,13 +1081,16 @@ __global__ void __launch_bounds__(256) dot_kernel(int64_t count, const double *a
     for (int l = 0; l < L; ++l) c[l] = part[0][l];
 }
 
-// x := x + dx, one thread per (i, s); dx may carry fewer limbs (Ldx <= L),
-// the update of a mixed-precision step.
+// x := x + dx for the coefficients lo .. lo + W - 1 of every series, one
+// thread per (i, s); dx may carry fewer limbs (Ldx <= L), the update of a
+// mixed-precision step.
 template <int L, int Ldx = L>
-__global__ void update_kernel(int n, int D, const double *dx, double *x) {
-  const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void update_kernel(int n, int D, int lo, int W, const double *dx, double *x) {
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t nD = (size_t)n * D;
-  if (q >= nD) return;
+  if (t >= (size_t)n * W) return;
+  const size_t i = t / W;
+  const size_t q = i * D + lo + (t - i * W);
   double a[L], b[L], s[L], d[Ldx];
   ld<L>(x, nD, q, a);
   ld<Ldx>(dx, nD, q, d);
@@ -1095,18 +1099,20 @@ __global__ void update_kernel(int n, int D, const double *dx, double *x) {
   st<L>(x, nD, q, s);
 }
 
-// norms[k] = max_i |b_{i,k}|, norms[D+k] = max_i |dx_{i,k}| (leading limbs);
-// a non-finite update is reported.  One workgroup of 256 threads per
-// coefficient k, rows strided over the threads, maxima reduced in LDS.
-__global__ void __launch_bounds__(256) norms_kernel(int n, int D, const double *b, const double *dx, double *norms,
-                                                    int32_t *status) {
+// norms[k] = max_i |b_{i,k}| for k < hi, norms[D+k] = max_i |dx_{i,k}| for
+// lo <= k < hi (leading limbs), zero elsewhere; a non-finite residual or
+// update is reported.  One workgroup of 256 threads per coefficient k, rows
+// strided over the threads, maxima reduced in LDS.
+__global__ void __launch_bounds__(256) norms_kernel(int n, int D, int lo, int hi, const double *b, const double *dx,
+                                                    double *norms, int32_t *status) {
   __shared__ double sb[256], sx[256];
   __shared__ int sf[256];
   const int k = blockIdx.x, t = threadIdx.x;
+  const bool has_b = k < hi, has_dx = k >= lo && k < hi;
   double nb = 0.0, nx = 0.0;
   int finite = 1;
   for (int i = t; i < n; i += blockDim.x) {
-    const double bi = b[(size_t)i * D + k], xi = dx[(size_t)i * D + k];
+    const double bi = has_b ? b[(size_t)i * D + k] : 0.0, xi = has_dx ? dx[(size_t)i * D + k] : 0.0;
     finite &= (isfinite(bi) && isfinite(xi)) ? 1 : 0;
     nb = fmax(nb, fabs(bi));
     nx = fmax(nx, fabs(xi));
@@ -1254,12 +1260,18 @@ hipError_t launch_extract(int L, int n, int D, int k, const double *A, double *o
   return hipGetLastError();
 }
 
+hipError_t launch_transpose_ld(int L, const double *in, size_t in_ld, double *out, size_t out_ld, size_t rows,
+                               int cols, size_t in_ls, size_t out_ls, hipStream_t st) {
+  // L counts batches: limbs, or limbs times coefficients for per-coefficient matrices
+  if (rows == 0 || cols <= 0) return hipSuccess;
+  dim3 grid((unsigned)((rows + 31) / 32), (unsigned)((cols + 31) / 32), (unsigned)L);
+  hipLaunchKernelGGL(transpose_kernel, grid, dim3(256), 0, st, in, out, rows, cols, in_ld, out_ld, in_ls, out_ls);
+  return hipGetLastError();
+}
+
 hipError_t launch_transpose(int L, const double *in, double *out, size_t rows, int cols, size_t in_ls,
                             size_t out_ls, hipStream_t st) {
-  // L counts batches: limbs, or limbs times coefficients for per-coefficient matrices
-  dim3 grid((unsigned)((rows + 31) / 32), (unsigned)((cols + 31) / 32), (unsigned)L);
-  hipLaunchKernelGGL(transpose_kernel, grid, dim3(256), 0, st, in, out, rows, cols, in_ls, out_ls);
-  return hipGetLastError();
+  return launch_transpose_ld(L, in, (size_t)cols, out, rows, rows, cols, in_ls, out_ls, st);
 }
 
 hipError_t launch_gemm(int L, int n, const double *M, const double *B, size_t b_ls, double *N, int count,
@@ -1302,23 +1314,27 @@ hipError_t launch_stages(int L, int n, int D, const double *M, const double *NP,
   return hipGetLastError();
 }
 
-hipError_t launch_update(int L, int n, int D, const double *b, const double *dx, double *x, double *norms,
-                         int32_t *status, hipStream_t st) {
-  const size_t nD = (size_t)n * D;
-  MD_DISPATCH(L, hipLaunchKernelGGL(update_kernel<LL>, dim3((nD + 255) / 256), dim3(256), 0, st, n, D, dx, x));
-  hipLaunchKernelGGL(norms_kernel, dim3(D), dim3(256), 0, st, n, D, b, dx, norms, status);
+hipError_t launch_update(int L, int n, int D, int lo, int hi, const double *b, const double *dx, double *x,
+                         double *norms, int32_t *status, hipStream_t st) {
+  if (lo < 0 || hi > D || lo >= hi) return hipErrorInvalidValue;
+  const int W = hi - lo;
+  const size_t nW = (size_t)n * W;
+  MD_DISPATCH(L, hipLaunchKernelGGL(update_kernel<LL>, dim3((nW + 255) / 256), dim3(256), 0, st, n, D, lo, W, dx, x));
+  hipLaunchKernelGGL(norms_kernel, dim3(D), dim3(256), 0, st, n, D, lo, hi, b, dx, norms, status);
   return hipGetLastError();
 }
 
-hipError_t launch_update_mixed(int L, int Ldx, int n, int D, const double *b, const double *dx, double *x,
-                               double *norms, int32_t *status, hipStream_t st) {
-  const size_t nD = (size_t)n * D;
-  const dim3 grid((nD + 255) / 256);
-  if (L == 4 && Ldx == 2) hipLaunchKernelGGL((update_kernel<4, 2>), grid, dim3(256), 0, st, n, D, dx, x);
-  else if (L == 8 && Ldx == 2) hipLaunchKernelGGL((update_kernel<8, 2>), grid, dim3(256), 0, st, n, D, dx, x);
-  else if (L == 8 && Ldx == 4) hipLaunchKernelGGL((update_kernel<8, 4>), grid, dim3(256), 0, st, n, D, dx, x);
+hipError_t launch_update_mixed(int L, int Ldx, int n, int D, int lo, int hi, const double *b, const double *dx,
+                               double *x, double *norms, int32_t *status, hipStream_t st) {
+  if (lo < 0 || hi > D || lo >= hi) return hipErrorInvalidValue;
+  const int W = hi - lo;
+  const size_t nW = (size_t)n * W;
+  const dim3 grid((nW + 255) / 256);
+  if (L == 4 && Ldx == 2) hipLaunchKernelGGL((update_kernel<4, 2>), grid, dim3(256), 0, st, n, D, lo, W, dx, x);
+  else if (L == 8 && Ldx == 2) hipLaunchKernelGGL((update_kernel<8, 2>), grid, dim3(256), 0, st, n, D, lo, W, dx, x);
+  else if (L == 8 && Ldx == 4) hipLaunchKernelGGL((update_kernel<8, 4>), grid, dim3(256), 0, st, n, D, lo, W, dx, x);
   else return hipErrorInvalidValue;
-  hipLaunchKernelGGL(norms_kernel, dim3(D), dim3(256), 0, st, n, D, b, dx, norms, status);
+  hipLaunchKernelGGL(norms_kernel, dim3(D), dim3(256), 0, st, n, D, lo, hi, b, dx, norms, status);
   return hipGetLastError();
 }
 

@@ -79,3 +79,17 @@ def test_convolution_count_is_3k_minus_5():
     s = mdinputs.small_dd()
     w = work.step_work(s)
     assert w["convolutions"]["products"] == 64 * 4  # 8 x 8 monomials of 3 variables
+
+
+def test_stagger_order_schedule():
+    """The order schedule of the staggered method, d := d + 1 + d/2 capped at D
+    (Section 4), from the host-only entry point."""
+    import paper_2301_12659_amd as mdn
+
+    seq = [1]
+    while seq[-1] < 64:
+        seq.append(mdn.stagger_next_order(seq[-1], 64))
+    assert seq == [1, 2, 4, 7, 11, 17, 26, 40, 61, 64]
+    for d in range(0, 130):
+        for D in (1, 16, 64, 128):
+            assert mdn.stagger_next_order(d, D) == min(D, d + 1 + d // 2)
