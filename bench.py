@@ -28,7 +28,7 @@ PEAK_FP64_TFLOPS = 78.6  # MI355X FP64 vector, FMA = 2 flops
 # sources the evaluation/differentiation kernel is compiled from; the HBM
 # traffic recorded from hardware counters is reported only while they are
 # unchanged since the counters were taken
-_EVALDIFF_SOURCES = ("evaldiff.hip", "evaldiff_dev.hpp", "common.hpp", "kernels.hpp", "md.hpp", "md_gen.inc")
+_EVALDIFF_SOURCES = ("evaldiff.hip", "evaldiff_dev.hpp", "evalargs.hpp", "common.hpp", "md.hpp", "md_gen.inc")
 _TRAFFIC_FILE = os.path.join(ROOT, "profiles", "evaldiff_kernel_medium_qd_hbm_traffic.md")
 
 
@@ -121,6 +121,54 @@ def _bench_batch(mdn, torch, np, mdinputs, npaths, steps):
     return res
 
 
+def _bench_staggered(mdn, torch, np, sysm, cst, xstar, repeats):
+    """Time to solution on the medium system from x*(0) with its trailing two
+    limbs dropped (about half the working precision, the start the staggered
+    method assumes): the staggered driver with A_0 factored once and with a
+    factorization at every step, and plain full-order Newton steps, as many
+    as it takes to reach the quad-double tolerance (timed back to back)."""
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    x0 = dev(sysm.half_precision_start())
+    drv = mdn.Newton(sysm, np.zeros((sysm.L, sysm.n, sysm.D)), sysm.half_precision_start())
+    drv.cst.copy_(cst)
+    res = {"start": "x*(0) with its two trailing limbs dropped, higher coefficients zero",
+           "tol": mdn.default_stagger_tol(sysm.L)}
+    for name, refac in (("qr_once", False), ("qr_every_step", True)):
+        times = []
+        for r in range(repeats + 1):  # the first run is not timed
+            drv.x.copy_(x0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rep, win = drv.staggered(max_steps=40, refactor_every_step=refac)
+            torch.cuda.synchronize()
+            if r:
+                times.append(time.perf_counter() - t0)
+        res[name] = {"ms_to_solution": round(1000 * min(times), 3), "steps": rep.steps,
+                     "factorizations": rep.factorizations, "converged": bool(rep.converged),
+                     "err_vs_manufactured": _err_vs(mdn, torch, drv.x, xstar),
+                     "windows": [list(w) for w in win]}
+    drv.x.copy_(x0)
+    k = 0
+    while k < 20:
+        drv.step()
+        k += 1
+        if _err_vs(mdn, torch, drv.x, xstar) <= 1e-60:
+            break
+    times = []
+    for r in range(repeats + 1):
+        drv.x.copy_(x0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(k):
+            drv.step()
+        torch.cuda.synchronize()
+        if r:
+            times.append(time.perf_counter() - t0)
+    res["plain_newton"] = {"ms_to_solution": round(1000 * min(times), 3), "steps": k,
+                           "err_vs_manufactured": _err_vs(mdn, torch, drv.x, xstar)}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -131,6 +179,8 @@ def main():
     ap.add_argument("--batch-paths", type=int, default=2048,
                     help="paths of the batched workload (0 skips it)")
     ap.add_argument("--batch-steps", type=int, default=4)
+    ap.add_argument("--stagger-repeats", type=int, default=3,
+                    help="timed runs of each staggered time-to-solution measurement (0: skip)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -246,6 +296,9 @@ def main():
         "err_vs_manufactured": err_manufactured,
         "wall_s_timed": round(wall, 3),
     }
+
+    if args.stagger_repeats > 0:
+        out["staggered"] = _bench_staggered(mdn, torch, np, sysm, drv.cst, xstar, args.stagger_repeats)
 
     if args.batch_paths > 0:
         out["batched"] = _bench_batch(mdn, torch, np, mdinputs, args.batch_paths, args.batch_steps)

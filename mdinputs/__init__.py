@@ -78,6 +78,14 @@ class System:
         x[:, :, 0] = self.xstar[:, :, 0]
         return x
 
+    def half_precision_start(self) -> np.ndarray:
+        """x*(0) with the trailing half of its limbs dropped (the leading
+        ceil(L/2) limbs kept: about half the working precision correct, the
+        start the staggered method assumes), higher coefficients zero."""
+        x = self.start()
+        x[(self.L + 1) // 2:, :, 0] = 0.0
+        return x
+
 
 def random_md(rng: np.random.Generator, L: int, shape, lo: float, hi: float) -> np.ndarray:
     """Random multiple doubles with every limb populated, limb-major [L, *shape].

@@ -81,7 +81,7 @@ size_t qr_scratch_bytes(int L, int n) {
 
 // Workspace regions, in doubles, each aligned to 256 bytes.
 struct Layout {
-  size_t val, der, pw, unit, b, A, qr, tau, qt, bar, invd, M, N, At, r, dxT, dx, sync, scale, total;
+  size_t val, der, pw, unit, b, A, qr, tau, qt, bar, invd, M, N, At, r, dxT, dx, sync, tsz, scale, total;
 };
 
 Layout newton_layout(const md_plan *p) {
@@ -111,7 +111,8 @@ Layout newton_layout(const md_plan *p) {
   w.dxT = take(L * n * D);
   w.dx = take(L * n * D);
   w.sync = take(mdk::stages_sync_ints(p->D) / 2 + 1);
-  w.scale = take(D);  // term sizes of b_k for the staggered driver
+  w.tsz = take(n * D);  // sizes of the terms of b_{i,k} and their maxima over i, for the staggered driver
+  w.scale = take(D);
   w.total = off;
   return w;
 }
@@ -344,9 +345,10 @@ static void eval_args(const md_plan *p, const double *cff, const double *x, void
   a.der = at(ws, w.der);
 }
 
-// b and A for the first Dc coefficients (the problem truncated at order Dc).
+// b and A for the first Dc coefficients (the problem truncated at order Dc);
+// tsz (nullable) gets the sizes of the terms of b.
 static int eval_diff_impl(const md_plan *p, int Dc, const double *cff, const double *cst, const double *x, double *b,
-                          double *A, void *ws, hipStream_t st) {
+                          double *A, void *ws, hipStream_t st, double *tsz = nullptr) {
   Layout w = newton_layout(p);
   mdk::EvalArgs a;
   eval_args(p, cff, x, ws, Dc, a);
@@ -359,7 +361,7 @@ static int eval_diff_impl(const md_plan *p, int Dc, const double *cff, const dou
   {
     Timed t(MD_CLASS_ASSEMBLY, st);
     e = mdk::launch_assemble(p->L, p->n, p->D, Dc, p->m, p->nnz, p->d_poly_ptr, p->d_asm_ptr, p->d_asm_ent, cst,
-                             a.val, a.der, b, A, st);
+                             a.val, a.der, b, A, st, tsz);
   }
   if (e != hipSuccess) return hip_fail(e, "assembly launch");
   return MD_OK;
@@ -416,8 +418,9 @@ int md_series_solve(int prec, int n, int d, const double *qr, const double *tau,
 // the compact coefficient-major arrays of the stage kernels.  keep_m skips
 // the pre-pass, the QR and M and uses the M = A_0^{-1} that the last step
 // without keep_m left in the workspace (the factorization of the first
-// stage, Section 5.3: a chord step).  scale (nullable, D doubles) receives
-// the size of the terms of each b_k.
+// stage, Section 5.3: a chord step).  With scale (nullable, D doubles) the
+// assembly records the size of the terms of every b_{i,k} and scale[k] gets
+// their maximum over i.
 static int newton_step_impl(const md_plan *p, int Ls, int lo, int hi, bool keep_m, const double *cff,
                             const double *cst, double *x, int32_t *dev_status, double *dev_norms, double *scale,
                             void *ws, hipStream_t st) {
@@ -428,6 +431,7 @@ static int newton_step_impl(const md_plan *p, int Ls, int lo, int hi, bool keep_
   if ((e = mdk::launch_status_init(dev_status, st)) != hipSuccess) return hip_fail(e, "status");
   double *b = at(ws, w.b), *A = at(ws, w.A), *qr = at(ws, w.qr), *tau = at(ws, w.tau), *qt = at(ws, w.qt);
   double *invd = at(ws, w.invd), *M = at(ws, w.M), *N = at(ws, w.N), *r = at(ws, w.r), *dx = at(ws, w.dx);
+  double *tsz = scale ? at(ws, w.tsz) : nullptr;
   mdk::EvalArgs a;
   if (!keep_m) {
     // 1. pre-pass: coefficient 0 of every derivative product gives A_0 (the
@@ -460,7 +464,7 @@ static int newton_step_impl(const md_plan *p, int Ls, int lo, int hi, bool keep_
   //    caller's stream; mixed: the values at L limbs for b, the derivatives
   //    at Ls limbs for A
   if (!mixed) {
-    int rc = eval_diff_impl(p, hi, cff, cst, x, b, A, ws, st);
+    int rc = eval_diff_impl(p, hi, cff, cst, x, b, A, ws, st, tsz);
     if (rc != MD_OK) return rc;
   } else {
     eval_args(p, cff, x, ws, hi, a);
@@ -472,7 +476,7 @@ static int newton_step_impl(const md_plan *p, int Ls, int lo, int hi, bool keep_
     }
     {
       Timed t(MD_CLASS_ASSEMBLY, st);
-      if ((e = mdk::launch_assemble_b(L, n, D, hi, p->m, p->d_poly_ptr, cst, a.val, b, st)) != hipSuccess)
+      if ((e = mdk::launch_assemble_b(L, n, D, hi, p->m, p->d_poly_ptr, cst, a.val, b, st, tsz)) != hipSuccess)
         return hip_fail(e, "residual assembly");
     }
     a.values_only = 0;
@@ -486,11 +490,6 @@ static int newton_step_impl(const md_plan *p, int Ls, int lo, int hi, bool keep_
       if ((e = mdk::launch_assemble_A(Ls, n, D, hi, p->nnz, p->d_asm_ptr, p->d_asm_ent, a.der, A, st)) != hipSuccess)
         return hip_fail(e, "Jacobian assembly");
     }
-  }
-  if (scale) {
-    Timed t(MD_CLASS_ASSEMBLY, st);
-    if ((e = mdk::launch_term_scale(n, D, hi, p->m, p->d_poly_ptr, cst, at(ws, w.val), scale, st)) != hipSuccess)
-      return hip_fail(e, "term scale");
   }
   const size_t nn = (size_t)n * n, nD = (size_t)n * D, nW = (size_t)n * W;
   double *At = at(ws, w.At), *dxT = at(ws, w.dxT);
@@ -519,8 +518,8 @@ static int newton_step_impl(const md_plan *p, int Ls, int lo, int hi, bool keep_
   }
   {
     Timed t(MD_CLASS_X_UPDATE, st);
-    e = mixed ? mdk::launch_update_mixed(L, Ls, n, D, lo, hi, b, dx, x, dev_norms, dev_status, st)
-              : mdk::launch_update(L, n, D, lo, hi, b, dx, x, dev_norms, dev_status, st);
+    e = mixed ? mdk::launch_update_mixed(L, Ls, n, D, lo, hi, b, dx, x, dev_norms, dev_status, st, tsz, scale)
+              : mdk::launch_update(L, n, D, lo, hi, b, dx, x, dev_norms, dev_status, st, tsz, scale);
     if (e != hipSuccess) return hip_fail(e, "update");
   }
   return MD_OK;
@@ -569,8 +568,21 @@ int md_newton_staggered(const md_plan *p, int prec_solve, int refactor_every_ste
   const Layout w = newton_layout(p);
   const int D = p->D;
   double *scale = at(ws, w.scale);
-  std::vector<double> h(3 * (size_t)D);  // max |b_k|, max |dx_k|, s_k
-  int32_t status = MD_OK;
+  // norms, term sizes and status come back through pinned, mapped host
+  // memory written by one small kernel: one wait per step, no copies
+  struct Pinned {
+    double *h = nullptr;
+    ~Pinned() {
+      if (h) (void)hipHostFree(h);
+    }
+  } pin;
+  hipError_t e;
+  double *hdev = nullptr;
+  if ((e = hipHostMalloc((void **)&pin.h, (3 * (size_t)D + 1) * sizeof(double), hipHostMallocCoherent)) !=
+          hipSuccess ||
+      (e = hipHostGetDevicePointer((void **)&hdev, pin.h, 0)) != hipSuccess)
+    return hip_fail(e, "pinned report buffer");
+  const double *h = pin.h;
   *report = md_stagger_report{0, 0, 0, 1, 0};
   int lo = 0, hi = 1;
   for (int step = 0; step < max_steps; ++step) {
@@ -585,14 +597,10 @@ int md_newton_staggered(const md_plan *p, int prec_solve, int refactor_every_ste
       windows[2 * step] = lo;
       windows[2 * step + 1] = hi;
     }
-    hipError_t e;
-    if ((e = hipMemcpyAsync(h.data(), dev_norms, 2 * (size_t)D * sizeof(double), hipMemcpyDeviceToHost, st)) !=
-            hipSuccess ||
-        (e = hipMemcpyAsync(h.data() + 2 * (size_t)D, scale, (size_t)D * sizeof(double), hipMemcpyDeviceToHost,
-                            st)) != hipSuccess ||
-        (e = hipMemcpyAsync(&status, dev_status, sizeof(int32_t), hipMemcpyDeviceToHost, st)) != hipSuccess ||
+    if ((e = mdk::launch_report(D, dev_norms, scale, dev_status, hdev, st)) != hipSuccess ||
         (e = hipStreamSynchronize(st)) != hipSuccess)
       return hip_fail(e, "reading the norms");
+    const int32_t status = (int32_t)h[3 * (size_t)D];
     if (status != MD_OK) return fail(status, "a step of the staggered method failed (status " +
                                                  std::to_string(status) + ")");
     // leading coefficients whose residual vanished, relative to its terms

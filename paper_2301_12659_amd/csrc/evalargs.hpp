@@ -1,0 +1,17 @@
+// Arguments of the evaluation and differentiation kernels (Section 5.1).
+#pragma once
+#include <cstddef>
+#include <cstdint>
+
+namespace mdk {
+
+struct EvalArgs {
+  int n, D, Dc, m, nnz;  // D: coefficients stored per series, Dc <= D: coefficients computed
+  const int32_t *mon_ptr, *var, *exp, *order;
+  const double *cff, *x, *pw;  // pw: powers x^p for p = 2..maxexp-1, [p-2][L][n][D]
+  double *val, *der;           // val [L][m][D], der [L][nnz][D]
+  int values_only = 0;         // 1: monomial values only (no backward or cross products, der untouched)
+  size_t x_ls = 0, cff_ls = 0; // limb strides of x and cff when not n D and m (packed batches)
+};
+
+}  // namespace mdk

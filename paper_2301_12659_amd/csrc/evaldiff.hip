@@ -1,7 +1,8 @@
 // Evaluation and differentiation of a polynomial system at a power series
 // (Section 5.1: reverse mode of algorithmic differentiation with power-series
-// products; Section 6: operands staged through shared memory into registers),
-// and the assembly of b(t) = -p(x(t)) and of the Jacobian series A(t).
+// products; Section 6: operands staged through shared memory into registers).
+// The sums into b(t) = -p(x(t)) and the Jacobian series A(t) are in
+// assemble.hip.
 //
 // Work decomposition.  A "worker" is a group of G lanes of one wavefront; it
 // evaluates and differentiates one whole monomial, product after product,
@@ -144,102 +145,6 @@ __global__ void __launch_bounds__(256, (L == 8) ? 1 : 2) power_kernel(int n, int
   }
 }
 
-// b_i(t) = -(c_{i,0}(t) + sum_{m in P_i} value_m(t)), one thread per (i, s)
-// for the first Dc coefficients s.
-template <int L>
-__global__ void assemble_b_kernel(int n, int D, int Dc, int m, const int32_t *poly_ptr, const double *cst,
-                                  const double *val, double *b) {
-  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const size_t nD = (size_t)n * D, mD = (size_t)m * D;
-  if (t >= (size_t)n * Dc) return;
-  const int i = (int)(t / Dc), s = (int)(t - (size_t)i * Dc);
-  const size_t q = (size_t)i * D + s;
-  double acc[L];
-  ld<L>(cst, nD, q, acc);
-  for (int mj = poly_ptr[i]; mj < poly_ptr[i + 1]; ++mj) {
-    double v[L], r[L];
-    ld<L>(val, mD, (size_t)mj * D + s, v);
-    MD<L>::add(acc, v, r);
-    md::copy<L>(r, acc);
-  }
-  md::neg<L>(acc, acc);
-  st<L>(b, nD, q, acc);
-}
-
-// A[i][j][s] = sum of the derivative series of row i's monomials with respect
-// to x_j, in monomial order; one thread per (i, j, s) for the first Dc
-// coefficients s.
-template <int L>
-__global__ void assemble_A_kernel(int n, int D, int Dc, int nnz, const int32_t *asm_ptr, const int32_t *asm_ent,
-                                  const double *der, double *A) {
-  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const size_t nnD = (size_t)n * n * D, zD = (size_t)nnz * D;
-  if (t >= (size_t)n * n * Dc) return;
-  const size_t ij = t / Dc;
-  const int s = (int)(t - ij * Dc);
-  const size_t q = ij * D + s;
-  const int lo = asm_ptr[ij], hi = asm_ptr[ij + 1];
-  double acc[L];
-  md::zero<L>(acc);
-  if (lo < hi) {
-    ld<L>(der, zD, (size_t)asm_ent[lo] * D + s, acc);
-    for (int t = lo + 1; t < hi; ++t) {
-      double v[L], r[L];
-      ld<L>(der, zD, (size_t)asm_ent[t] * D + s, v);
-      MD<L>::add(acc, v, r);
-      md::copy<L>(r, acc);
-    }
-  }
-  st<L>(A, nnD, q, acc);
-}
-
-// Coefficient 0 of A into a dense row-major matrix a0 [L][n][n], summed in
-// the same order as assemble_A_kernel, so it equals A[i][j][0] bit for bit.
-template <int L>
-__global__ void assemble_A0_kernel(int n, int D, int nnz, const int32_t *asm_ptr, const int32_t *asm_ent,
-                                   const double *der, double *a0) {
-  const size_t ij = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const size_t nn = (size_t)n * n, zD = (size_t)nnz * D;
-  if (ij >= nn) return;
-  const int lo = asm_ptr[ij], hi = asm_ptr[ij + 1];
-  double acc[L];
-  md::zero<L>(acc);
-  if (lo < hi) {
-    ld<L>(der, zD, (size_t)asm_ent[lo] * D, acc);
-    for (int t = lo + 1; t < hi; ++t) {
-      double v[L], r[L];
-      ld<L>(der, zD, (size_t)asm_ent[t] * D, v);
-      MD<L>::add(acc, v, r);
-      md::copy<L>(r, acc);
-    }
-  }
-  st<L>(a0, nn, ij, acc);
-}
-
-// scale[k] = max_i (|c_{i,0,k}| + sum_{m in P_i} |value_{m,k}|) on leading
-// limbs for k < Dc, zero above: the size of the terms that cancel in b_k, so
-// that a residual can be judged against its own rounding.  One workgroup per
-// coefficient, rows strided over its threads.
-__global__ void __launch_bounds__(256) term_scale_kernel(int n, int D, int Dc, int m, const int32_t *poly_ptr,
-                                                         const double *cst, const double *val, double *scale) {
-  __shared__ double part[256];
-  const int k = blockIdx.x, t = threadIdx.x;
-  double mx = 0.0;
-  if (k < Dc)
-    for (int i = t; i < n; i += blockDim.x) {
-      double acc = fabs(cst[(size_t)i * D + k]);
-      for (int mj = poly_ptr[i]; mj < poly_ptr[i + 1]; ++mj) acc += fabs(val[(size_t)mj * D + k]);
-      mx = fmax(mx, acc);
-    }
-  part[t] = mx;
-  __syncthreads();
-  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
-    if (t < h) part[t] = fmax(part[t], part[t + h]);
-    __syncthreads();
-  }
-  if (t == 0) scale[k] = part[0];
-}
-
 // ------------------------------------------------------------------ launchers
 
 template <int L>
@@ -275,64 +180,11 @@ hipError_t launch_evaldiff(int L, const EvalArgs &a, int maxexp, double *pw, hip
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_assemble_A0(int L, int n, int D, int nnz, const int32_t *asm_ptr, const int32_t *asm_ent,
-                              const double *der, double *a0, hipStream_t st) {
-  const size_t nn = (size_t)n * n;
-  switch (L) {
-    case 2: hipLaunchKernelGGL(assemble_A0_kernel<2>, dim3((nn + 255) / 256), dim3(256), 0, st, n, D, nnz, asm_ptr, asm_ent, der, a0); break;
-    case 4: hipLaunchKernelGGL(assemble_A0_kernel<4>, dim3((nn + 255) / 256), dim3(256), 0, st, n, D, nnz, asm_ptr, asm_ent, der, a0); break;
-    case 8: hipLaunchKernelGGL(assemble_A0_kernel<8>, dim3((nn + 255) / 256), dim3(256), 0, st, n, D, nnz, asm_ptr, asm_ent, der, a0); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
-
 int evaldiff_workers_per_block(int D) { return 256 / worker_lanes(D); }
 
 size_t evaldiff_lds_bytes(int L, int D) {
   const int G = worker_lanes(D);
   return (size_t)(256 / G) * 3 * L * (D + 1) * sizeof(double);
-}
-
-hipError_t launch_assemble_b(int L, int n, int D, int Dc, int m, const int32_t *poly_ptr, const double *cst,
-                             const double *val, double *b, hipStream_t st) {
-  if (Dc < 1 || Dc > D) return hipErrorInvalidValue;
-  const unsigned blocks = (unsigned)(((size_t)n * Dc + 255) / 256);
-  switch (L) {
-    case 2: hipLaunchKernelGGL(assemble_b_kernel<2>, dim3(blocks), dim3(256), 0, st, n, D, Dc, m, poly_ptr, cst, val, b); break;
-    case 4: hipLaunchKernelGGL(assemble_b_kernel<4>, dim3(blocks), dim3(256), 0, st, n, D, Dc, m, poly_ptr, cst, val, b); break;
-    case 8: hipLaunchKernelGGL(assemble_b_kernel<8>, dim3(blocks), dim3(256), 0, st, n, D, Dc, m, poly_ptr, cst, val, b); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
-
-hipError_t launch_assemble_A(int L, int n, int D, int Dc, int nnz, const int32_t *asm_ptr, const int32_t *asm_ent,
-                             const double *der, double *A, hipStream_t st) {
-  if (Dc < 1 || Dc > D) return hipErrorInvalidValue;
-  const unsigned blocks = (unsigned)(((size_t)n * n * Dc + 255) / 256);
-  switch (L) {
-    case 2: hipLaunchKernelGGL(assemble_A_kernel<2>, dim3(blocks), dim3(256), 0, st, n, D, Dc, nnz, asm_ptr, asm_ent, der, A); break;
-    case 4: hipLaunchKernelGGL(assemble_A_kernel<4>, dim3(blocks), dim3(256), 0, st, n, D, Dc, nnz, asm_ptr, asm_ent, der, A); break;
-    case 8: hipLaunchKernelGGL(assemble_A_kernel<8>, dim3(blocks), dim3(256), 0, st, n, D, Dc, nnz, asm_ptr, asm_ent, der, A); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
-
-hipError_t launch_assemble(int L, int n, int D, int Dc, int m, int nnz, const int32_t *poly_ptr,
-                           const int32_t *asm_ptr, const int32_t *asm_ent, const double *cst, const double *val,
-                           const double *der, double *b, double *A, hipStream_t st) {
-  hipError_t e = launch_assemble_b(L, n, D, Dc, m, poly_ptr, cst, val, b, st);
-  if (e != hipSuccess) return e;
-  return launch_assemble_A(L, n, D, Dc, nnz, asm_ptr, asm_ent, der, A, st);
-}
-
-hipError_t launch_term_scale(int n, int D, int Dc, int m, const int32_t *poly_ptr, const double *cst,
-                             const double *val, double *scale, hipStream_t st) {
-  if (Dc < 1 || Dc > D) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(term_scale_kernel, dim3(D), dim3(256), 0, st, n, D, Dc, m, poly_ptr, cst, val, scale);
-  return hipGetLastError();
 }
 
 }  // namespace mdk

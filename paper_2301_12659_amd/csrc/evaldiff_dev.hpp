@@ -117,7 +117,7 @@ __device__ __forceinline__ void zero_pads(double *buf0, int L, int D, int lane, 
 template <int L>
 __device__ void eval_monomial(const EvalArgs &a, int mono, int lane, double *buf0) {
   const int D = a.D;    // coefficients stored per series (global stride)
-  const int Dc = a.Dc;  // coefficients computed: D, or 1 for the A_0 pre-pass
+  const int Dc = a.Dc;  // coefficients computed: the order of a truncated problem (1: the A_0 pre-pass)
   const int G = worker_lanes(Dc);
   const int Dp = Dc + 1;
   double *buf[3] = {buf0, buf0 + L * Dp, buf0 + 2 * L * Dp};

@@ -4,16 +4,9 @@
 #include <cstddef>
 #include <cstdint>
 
-namespace mdk {
+#include "evalargs.hpp"
 
-struct EvalArgs {
-  int n, D, Dc, m, nnz;  // D: coefficients stored per series, Dc: coefficients computed (D or 1)
-  const int32_t *mon_ptr, *var, *exp, *order;
-  const double *cff, *x, *pw;  // pw: powers x^p for p = 2..maxexp-1, [p-2][L][n][D]
-  double *val, *der;           // val [L][m][D], der [L][nnz][D]
-  int values_only = 0;         // 1: monomial values only (no backward or cross products, der untouched)
-  size_t x_ls = 0, cff_ls = 0; // limb strides of x and cff when not n D and m (packed batches)
-};
+namespace mdk {
 
 // evaldiff.hip
 hipError_t launch_evaldiff(int L, const EvalArgs &a, int maxexp, double *pw, hipStream_t st);
@@ -22,19 +15,18 @@ hipError_t launch_evaldiff(int L, const EvalArgs &a, int maxexp, double *pw, hip
 // evaldiff0_max_support(L) variables (none for octo doubles).
 hipError_t launch_evaldiff0(int L, const EvalArgs &a, hipStream_t st);
 int evaldiff0_max_support(int L);
-// The assembly kernels fill the first Dc coefficients of series stored with D.
+// The assembly kernels fill the first Dc coefficients of series stored with
+// D; tsz (nullable, [n][D]) gets |c_{i,0,s}| + sum_m |value_{m,s}| (leading
+// limbs), the size of the terms of b_{i,s}.
 hipError_t launch_assemble(int L, int n, int D, int Dc, int m, int nnz, const int32_t *poly_ptr,
                            const int32_t *asm_ptr, const int32_t *asm_ent, const double *cst, const double *val,
-                           const double *der, double *b, double *A, hipStream_t st);
+                           const double *der, double *b, double *A, hipStream_t st, double *tsz = nullptr);
 size_t evaldiff_lds_bytes(int L, int D);
 int evaldiff_workers_per_block(int D);  // monomials per 256-thread workgroup
 hipError_t launch_assemble_b(int L, int n, int D, int Dc, int m, const int32_t *poly_ptr, const double *cst,
-                             const double *val, double *b, hipStream_t st);
+                             const double *val, double *b, hipStream_t st, double *tsz = nullptr);
 hipError_t launch_assemble_A(int L, int n, int D, int Dc, int nnz, const int32_t *asm_ptr, const int32_t *asm_ent,
                              const double *der, double *A, hipStream_t st);
-// scale[k] = max_i (|c_{i,0,k}| + sum_m |value_{m,k}|) for k < Dc, 0 above (scale[D]).
-hipError_t launch_term_scale(int n, int D, int Dc, int m, const int32_t *poly_ptr, const double *cst,
-                             const double *val, double *scale, hipStream_t st);
 hipError_t launch_assemble_A0(int L, int n, int D, int nnz, const int32_t *asm_ptr, const int32_t *asm_ent,
                               const double *der, double *a0, hipStream_t st);
 
@@ -69,11 +61,18 @@ int stages_products(int L, int n, int D);
 hipError_t launch_stages(int L, int n, int D, const double *M, const double *NP, const double *At, double *rT,
                          double *dxT, int *sync, int32_t *status, hipStream_t st);
 // x_k += dx_k for lo <= k < hi; norms[2][D]: max |b_k| for k < hi and
-// max |dx_k| for lo <= k < hi, zero elsewhere.
+// max |dx_k| for lo <= k < hi, zero elsewhere; with tsz ([n][D] term sizes
+// from the assembly) scale[k] = max_i tsz[i][k] for k < hi, zero above.
 hipError_t launch_update(int L, int n, int D, int lo, int hi, const double *b, const double *dx, double *x,
-                         double *norms, int32_t *status, hipStream_t st);
+                         double *norms, int32_t *status, hipStream_t st, const double *tsz = nullptr,
+                         double *scale = nullptr);
 hipError_t launch_update_mixed(int L, int Ldx, int n, int D, int lo, int hi, const double *b, const double *dx,
-                               double *x, double *norms, int32_t *status, hipStream_t st);
+                               double *x, double *norms, int32_t *status, hipStream_t st,
+                               const double *tsz = nullptr, double *scale = nullptr);
+// out[0 .. 3D]: norms[2][D], scale[D] and the status word (as a double),
+// written by one small kernel (out may be mapped host memory).
+hipError_t launch_report(int D, const double *norms, const double *scale, const int32_t *status, double *out,
+                         hipStream_t st);
 hipError_t launch_arith(int L, int op, int64_t count, const double *a, const double *b, double *c, hipStream_t st);
 hipError_t launch_copy(const double *src, double *dst, size_t count, hipStream_t st);
 hipError_t launch_series_to_rev(int L, int n, int D, const double *in, double *out, hipStream_t st);

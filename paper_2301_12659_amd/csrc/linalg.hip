@@ -1104,27 +1104,31 @@ __global__ void update_kernel(int n, int D, int lo, int W, const double *dx, dou
 // update is reported.  One workgroup of 256 threads per coefficient k, rows
 // strided over the threads, maxima reduced in LDS.
 __global__ void __launch_bounds__(256) norms_kernel(int n, int D, int lo, int hi, const double *b, const double *dx,
-                                                    double *norms, int32_t *status) {
-  __shared__ double sb[256], sx[256];
+                                                    double *norms, int32_t *status, const double *tsz,
+                                                    double *scale) {
+  __shared__ double sb[256], sx[256], ss[256];
   __shared__ int sf[256];
   const int k = blockIdx.x, t = threadIdx.x;
   const bool has_b = k < hi, has_dx = k >= lo && k < hi;
-  double nb = 0.0, nx = 0.0;
+  double nb = 0.0, nx = 0.0, ns = 0.0;
   int finite = 1;
   for (int i = t; i < n; i += blockDim.x) {
     const double bi = has_b ? b[(size_t)i * D + k] : 0.0, xi = has_dx ? dx[(size_t)i * D + k] : 0.0;
     finite &= (isfinite(bi) && isfinite(xi)) ? 1 : 0;
     nb = fmax(nb, fabs(bi));
     nx = fmax(nx, fabs(xi));
+    if (tsz && has_b) ns = fmax(ns, tsz[(size_t)i * D + k]);
   }
   sb[t] = nb;
   sx[t] = nx;
+  ss[t] = ns;
   sf[t] = finite;
   __syncthreads();
   for (int h = blockDim.x / 2; h > 0; h >>= 1) {
     if (t < h) {
       sb[t] = fmax(sb[t], sb[t + h]);
       sx[t] = fmax(sx[t], sx[t + h]);
+      ss[t] = fmax(ss[t], ss[t + h]);
       sf[t] &= sf[t + h];
     }
     __syncthreads();
@@ -1134,8 +1138,16 @@ __global__ void __launch_bounds__(256) norms_kernel(int n, int D, int lo, int hi
       norms[k] = sb[0];
       norms[D + k] = sx[0];
     }
+    if (tsz && scale) scale[k] = ss[0];
     if (!sf[0]) set_status(status, MD_ENONFINITE);
   }
+}
+
+// out[0..2D) = norms, out[2D..3D) = scale, out[3D] = status; one workgroup.
+__global__ void __launch_bounds__(256) report_kernel(int D, const double *norms, const double *scale,
+                                                     const int32_t *status, double *out) {
+  for (int t = threadIdx.x; t <= 3 * D; t += blockDim.x)
+    out[t] = (t < 2 * D) ? norms[t] : (t < 3 * D) ? scale[t - 2 * D] : (double)status[0];
 }
 
 template <int L>
@@ -1315,17 +1327,19 @@ hipError_t launch_stages(int L, int n, int D, const double *M, const double *NP,
 }
 
 hipError_t launch_update(int L, int n, int D, int lo, int hi, const double *b, const double *dx, double *x,
-                         double *norms, int32_t *status, hipStream_t st) {
+                         double *norms, int32_t *status, hipStream_t st, const double *tsz, double *scale) {
   if (lo < 0 || hi > D || lo >= hi) return hipErrorInvalidValue;
   const int W = hi - lo;
   const size_t nW = (size_t)n * W;
   MD_DISPATCH(L, hipLaunchKernelGGL(update_kernel<LL>, dim3((nW + 255) / 256), dim3(256), 0, st, n, D, lo, W, dx, x));
-  hipLaunchKernelGGL(norms_kernel, dim3(D), dim3(256), 0, st, n, D, lo, hi, b, dx, norms, status);
+  hipLaunchKernelGGL(norms_kernel, dim3(D), dim3(256), 0, st, n, D, lo, hi, b, dx, norms, status, tsz,
+                     scale);
   return hipGetLastError();
 }
 
 hipError_t launch_update_mixed(int L, int Ldx, int n, int D, int lo, int hi, const double *b, const double *dx,
-                               double *x, double *norms, int32_t *status, hipStream_t st) {
+                               double *x, double *norms, int32_t *status, hipStream_t st, const double *tsz,
+                               double *scale) {
   if (lo < 0 || hi > D || lo >= hi) return hipErrorInvalidValue;
   const int W = hi - lo;
   const size_t nW = (size_t)n * W;
@@ -1334,7 +1348,14 @@ hipError_t launch_update_mixed(int L, int Ldx, int n, int D, int lo, int hi, con
   else if (L == 8 && Ldx == 2) hipLaunchKernelGGL((update_kernel<8, 2>), grid, dim3(256), 0, st, n, D, lo, W, dx, x);
   else if (L == 8 && Ldx == 4) hipLaunchKernelGGL((update_kernel<8, 4>), grid, dim3(256), 0, st, n, D, lo, W, dx, x);
   else return hipErrorInvalidValue;
-  hipLaunchKernelGGL(norms_kernel, dim3(D), dim3(256), 0, st, n, D, lo, hi, b, dx, norms, status);
+  hipLaunchKernelGGL(norms_kernel, dim3(D), dim3(256), 0, st, n, D, lo, hi, b, dx, norms, status, tsz,
+                     scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_report(int D, const double *norms, const double *scale, const int32_t *status, double *out,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(report_kernel, dim3(1), dim3(256), 0, st, D, norms, scale, status, out);
   return hipGetLastError();
 }
 

@@ -21,17 +21,6 @@ def mdn():
     return mdn
 
 
-def half_precision_start(s, seed):
-    """x*(0) with each leading coefficient off by about half the working
-    precision (the paper's assumption on x_0), higher coefficients zero."""
-    L = s.L
-    rng = np.random.default_rng(seed)
-    e = np.zeros((L + 1, s.n, s.D))
-    e[:L, :, 0] = s.xstar[:, :, 0]
-    e[L, :, 0] = s.xstar[0, :, 0] * rng.uniform(-1.0, 1.0, s.n) * 2.0 ** (-26.5 * L)
-    return oracle.round_md(e, L)
-
-
 def rough_point(s, seed, rel=1e-3):
     """x* with every coefficient off by about rel (a residual in every coefficient)."""
     rng = np.random.default_rng(seed)
@@ -105,7 +94,7 @@ def test_driver_replayed_by_the_oracle(mdn, L):
     the GPU ended; both are at the manufactured solution."""
     s = mdinputs.tiny(L, 8, 23, mons=3, kmin=1, kmax=3, exps=(1, 2), seed=40 + L)
     cst = oracle.manufacture(s)
-    x0 = half_precision_start(s, 5)
+    x0 = s.half_precision_start()
     drv = mdn.Newton(s, cst, x0)
     rep, windows = drv.staggered(max_steps=30)
     assert rep.converged == 1 and rep.factorizations == 1, (rep.steps, windows)
@@ -128,7 +117,7 @@ def test_driver_medium_qd(mdn):
     solution; refactoring at every step converges as well."""
     s = mdinputs.medium_qd()
     cst = oracle.manufacture(s)
-    x0 = half_precision_start(s, 6)
+    x0 = s.half_precision_start()
     drv = mdn.Newton(s, cst, x0)
     rep, windows = drv.staggered(max_steps=40)
     assert rep.converged == 1 and rep.factorizations == 1, (rep.steps, windows)

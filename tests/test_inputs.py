@@ -53,3 +53,16 @@ def test_damping_scales_by_powers_of_two():
     r = mdinputs.make_system("t", 2, 4, 7, 2, 1, 2, (1,), 3, None, boost=False, damping=1.0)
     for k in range(8):
         assert np.array_equal(s.xstar[:, :, k], r.xstar[:, :, k] * 0.25 ** k)
+
+
+@pytest.mark.parametrize("L", [2, 4, 8])
+def test_half_precision_start(L):
+    """The staggered method's start: x*(0) with the trailing half of its limbs
+    dropped, off by about half the working precision; zero above coefficient 0."""
+    s = mdinputs.tiny(L, 5, 7, seed=3)
+    x = s.half_precision_start()
+    keep = (L + 1) // 2
+    assert np.array_equal(x[:keep, :, 0], s.xstar[:keep, :, 0])
+    assert not np.any(x[keep:]) and not np.any(x[:, :, 1:])
+    rel = np.abs(s.xstar[keep, :, 0]) / np.abs(s.xstar[0, :, 0])
+    assert np.all(rel < 2.0 ** (-53 * keep + 1))
