@@ -64,6 +64,7 @@ def lib():
         L.ora_arith.argtypes = [ci, ci, ci, dp, dp, dp, ci, ci, dp]
         L.ora_adjoint_solve.argtypes = [ci, ci, ci, ci, dp, dp, ci, dp]
         L.ora_coef_grad.argtypes = [ci, ci, ci, ci, i32p, i32p, i32p, i32p, ci, dp, ci, dp, ci, dp]
+        L.ora_linear_residual.argtypes = [ci, ci, ci, ci, dp, dp, dp, ci, i32p, ci, dp, dp]
         L.ora_window_step.argtypes = [ci, ci, ci, ci, i32p, i32p, i32p, i32p, ci, dp, dp, dp, dp, ci, ci, dp, dp,
                                       dp, dp]
         _lib = L
@@ -181,6 +182,24 @@ def toeplitz_solve(A, rhs, K=None, prec=None):
     rc = lib().ora_toeplitz_solve(prec, n, D, L, _d(A), _d(rhs), K, _d(dx))
     _check(rc, "ora_toeplitz_solve")
     return dx
+
+
+def linear_residual(A, b, dx, rows=None, K=None, prec=None):
+    """r = b - T dx for the block Toeplitz matrix T of A[L, D, n, n] (oracle
+    layout), b and dx [L, n, D], on the rows listed (all rows when None).
+    Returns (r [K, nrows, D] expansions, scale [nrows, D]: |b| plus the sum of
+    the absolute products)."""
+    L0 = max(A.shape[0], b.shape[0], dx.shape[0])
+    L, (A, b, dx) = _common(A, b, dx)
+    _, D, n, _ = A.shape
+    K = K or 4 * L0 + 2
+    prec = prec or prec_bits(L0)
+    rr = np.arange(n, dtype=np.int32) if rows is None else _c32(rows)
+    r = np.zeros((K, len(rr), D))
+    sc = np.zeros((len(rr), D))
+    rc = lib().ora_linear_residual(prec, n, D, L, _d(A), _d(b), _d(dx), len(rr), _i(rr), K, _d(r), _d(sc))
+    _check(rc, "ora_linear_residual")
+    return r, sc
 
 
 def manufacture(sys, Lout=None, prec=None):

@@ -487,6 +487,58 @@ int ora_window_step(int prec_bits, int n, int D, int m, const int32_t *pp, const
   return rc;
 }
 
+/* Residual of the block Toeplitz system (the quantity Newton's loop of
+ * Section 2 monitors; the residual kernels of Section 5.4 and Table 4):
+ *   r_{i,k} = b_{i,k} - sum_{j=0..k} sum_v A_j(i,v) dx_{v,k-j}
+ * for the rows listed in rows[nrows] (every row when rows is NULL).
+ * A is [L][D][n][n] row-major per coefficient, b and dx are [L][n][D].
+ * Outputs: r_out[K][nrows][D] (expansions), scale_out[nrows][D] (doubles):
+ * |b_{i,k}| + sum_j sum_v |A_j(i,v)| |dx_{v,k-j}|, the size of the terms. */
+int ora_linear_residual(int prec_bits, int n, int D, int L, const double *A, const double *b, const double *dx,
+                        int nrows, const int32_t *rows, int K, double *r_out, double *scale_out) {
+  if (n < 1 || D < 1 || K < 1 || L < 1 || nrows < 1) return ORA_EINVAL;
+  for (int q = 0; rows && q < nrows; ++q)
+    if (rows[q] < 0 || rows[q] >= n) return ORA_EINVAL;
+  mpfr_prec_t prec = prec_bits;
+  const size_t nn = (size_t)n * n, tot = (size_t)D * nn, nD = (size_t)n * D, rD = (size_t)nrows * D;
+  mpfr_t *Am = vnew(tot, prec), *bm = vnew(nD, prec), *xm = vnew(nD, prec);
+  for (size_t q = 0; q < tot; ++q) md_get(Am[q], A + q, tot, L);
+  for (size_t q = 0; q < nD; ++q) {
+    md_get(bm[q], b + q, nD, L);
+    md_get(xm[q], dx + q, nD, L);
+  }
+#pragma omp parallel for schedule(dynamic, 1) num_threads(ora_get_threads())
+  for (int ri = 0; ri < nrows; ++ri) {
+    const int i = rows ? rows[ri] : ri;
+    mpfr_t r, t, sc, at;
+    mpfr_init2(r, prec);
+    mpfr_init2(t, prec);
+    mpfr_init2(sc, prec);
+    mpfr_init2(at, prec);
+    for (int k = 0; k < D; ++k) {
+      mpfr_set(r, bm[(size_t)i * D + k], MPFR_RNDN);
+      mpfr_abs(sc, r, MPFR_RNDN);
+      for (int j = 0; j <= k; ++j)
+        for (int v = 0; v < n; ++v) {
+          mpfr_mul(t, Am[(size_t)j * nn + (size_t)i * n + v], xm[(size_t)v * D + (k - j)], MPFR_RNDN);
+          mpfr_sub(r, r, t, MPFR_RNDN);
+          mpfr_abs(at, t, MPFR_RNDN);
+          mpfr_add(sc, sc, at, MPFR_RNDN);
+        }
+      exp_put(r_out + (size_t)ri * D + k, rD, K, r, t);
+      scale_out[(size_t)ri * D + k] = mpfr_get_d(sc, MPFR_RNDN);
+    }
+    mpfr_clear(r);
+    mpfr_clear(t);
+    mpfr_clear(sc);
+    mpfr_clear(at);
+  }
+  vfree(Am, tot);
+  vfree(bm, nD);
+  vfree(xm, nD);
+  return ORA_OK;
+}
+
 /* Solve the block Toeplitz system for given A[L][D][n][n] (row-major) and
  * rhs[L][n][D]; dx[K][n][D].  Used for the standalone series solve. */
 int ora_toeplitz_solve(int prec_bits, int n, int D, int L, const double *A, const double *rhs, int K,

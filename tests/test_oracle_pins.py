@@ -618,3 +618,43 @@ def test_chord_step_contracts_linearly():
     newton = oracle.absdiff(oracle.newton_step(sys, sys.cff, cst, x)["x"], sys.xstar).max()
     assert 1e-3 * sigma * delta < chord < 1e3 * sigma * delta
     assert newton < 1e-3 * chord
+
+
+# --------------------------------------------------------------------------
+# 11. the linear residual b - T dx (Section 5.4, Table 4)
+# --------------------------------------------------------------------------
+
+def test_linear_residual_brute_force():
+    """Exact rationals: r_{i,k} = b_{i,k} - sum_{j<=k} sum_v A_j(i,v) dx_{v,k-j},
+    on all rows and on a sample of rows."""
+    rng = np.random.default_rng(3)
+    L, n, D = 2, 3, 4
+    A = mdinputs.random_md(rng, L, (D, n, n), -1.0, 1.0)
+    b = mdinputs.random_md(rng, L, (n, D), -1.0, 1.0)
+    dx = mdinputs.random_md(rng, L, (n, D), -1.0, 1.0)
+    eA = exact(A)
+    eb, edx = exact(b), exact(dx)
+    for rows in (None, [2, 0]):
+        r, sc = oracle.linear_residual(A, b, dx, rows=rows, prec=700, K=16)
+        er = exact(r)
+        for q, i in enumerate(range(n) if rows is None else rows):
+            for k in range(D):
+                want = eb[i, k] - sum(eA[j, i, v] * edx[v, k - j] for j in range(k + 1) for v in range(n))
+                assert abs(er[q, k] - want) <= Fraction(1, 2 ** 600) * (1 + abs(want))
+                size = abs(eb[i, k]) + sum(abs(eA[j, i, v] * edx[v, k - j]) for j in range(k + 1) for v in range(n))
+                assert sc[q, k] == pytest.approx(float(size), rel=1e-15)
+
+
+def test_linear_residual_of_the_block_solve_vanishes():
+    """The residual of the oracle's own block forward substitution (pinned by
+    the sympy brute force above) is zero to the working bits."""
+    rng = np.random.default_rng(4)
+    L, n, D = 4, 5, 7
+    A = mdinputs.random_md(rng, L, (D, n, n), -1.0, 1.0)
+    A[0, 0] += 4.0 * np.eye(n)  # a well-conditioned A_0 (the added leading limbs keep the limbs nonoverlapping)
+    b = mdinputs.random_md(rng, L, (n, D), -1.0, 1.0)
+    dx = oracle.toeplitz_solve(A, b)
+    r, sc = oracle.linear_residual(A, b, dx)
+    assert np.max(oracle.absdiff(r, np.zeros((1,) + r.shape[1:])) / sc) < 2.0 ** -(4 * 53 * L - 20)
+    r2, _ = oracle.linear_residual(A, b, np.zeros_like(b))
+    assert np.array_equal(exact(r2), exact(b))
