@@ -297,6 +297,26 @@ def main():
         "wall_s_timed": round(wall, 3),
     }
 
+    # the linear residual of the last step's system (monitoring): every
+    # equation, and one sampled equation
+    res_t = {}
+    pb, pA, pdx = mdn.step_arrays(drv.plan, drv.ws)
+    for name, rows in (("all_rows", None), ("one_row", [n // 2])):
+        rws = None if rows is None else torch.tensor(rows, dtype=torch.int32, device="cuda")
+        rr = torch.empty((L, n if rows is None else len(rows), D), dtype=torch.float64, device="cuda")
+        nr = torch.empty(D, dtype=torch.float64, device="cuda")
+        call = lambda: mdn.linear_residual(L, n, D - 1, pA, pb, pdx, rr, rows=rws, norm1=nr)
+        call()
+        torch.cuda.synchronize()
+        r0, r1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        r0.record()
+        for _ in range(20):
+            call()
+        r1.record()
+        torch.cuda.synchronize()
+        res_t[name + "_us"] = round(1000.0 * r0.elapsed_time(r1) / 20, 2)
+    out["residual"] = res_t
+
     if args.stagger_repeats > 0:
         out["staggered"] = _bench_staggered(mdn, torch, np, sysm, drv.cst, xstar, args.stagger_repeats)
 

@@ -201,6 +201,30 @@ int md_newton_staggered(const md_plan *plan, int prec_solve, int refactor_every_
                         md_stagger_report *report, int32_t *dev_status, double *dev_norms, void *ws,
                         size_t ws_bytes, hipStream_t stream);
 
+/* Residual of the lower triangular block Toeplitz system of Section 2 (what
+ * the Newton loop of Section 2 reports; the residual kernels of Section 5.4
+ * and Table 4), in multiple-double precision:
+ *   r_{q,k} = b_{i,k} - sum_{j=0..k} sum_v A_j(i,v) dx_{v,k-j},  i = rows[q],
+ * for q < nrows and k < D = d + 1.  rows (device int32, nrows entries)
+ * selects the equations (Section 7.2 suggests a few random ones instead of
+ * all, as the full residual costs about as much as the staged updates); NULL
+ * takes every row in order (nrows must then be n).  A [L][n][n][D] as
+ * md_eval_diff writes it, b and dx [L][n][D], r [L][nrows][D]; all device
+ * arrays, precision prec = L.  norm1 (device, nullable) [D]: norm1[k] =
+ * sum_q |r_{q,k}| on leading limbs.  A row index outside 0..n-1 sets
+ * *dev_status (nullable) to MD_EINVAL and leaves that row of r unwritten. */
+int md_linear_residual(int prec, int n, int d, const double *A, const double *b, const double *dx, int nrows,
+                       const int32_t *rows, double *r, double *norm1, int32_t *dev_status, hipStream_t stream);
+
+/* Device pointers into ws (the workspace of plan) where the last Newton step
+ * run with it (md_newton_step, md_newton_step_mixed, md_newton_step_window)
+ * left b = -p(x) at the step's input [L][n][D], the Jacobian series A
+ * [L][n][n][D] and dx [L][n][D].  A and dx hold the step's solve precision
+ * (their leading limbs); a window step leaves dx only on its window and b, A
+ * only below its order.  With md_linear_residual they give the residual of
+ * the step's linear system. */
+int md_step_arrays(const md_plan *plan, void *ws, size_t ws_bytes, double **b, double **A, double **dx);
+
 /* Batches of independent systems ("paths"; the paper tracks many solution
  * paths of a homotopy, Section 1), one Newton step of every path per call,
  * in one persistent launch.  A path p has n_p (1..128) variables and

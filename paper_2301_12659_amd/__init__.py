@@ -56,6 +56,9 @@ class StaggerReport(ctypes.Structure):
 
 _lib.md_newton_staggered.argtypes = [_vp, _i32, _i32, _i32, ctypes.c_double, _vp, _vp, _vp, _i32p,
                                      ctypes.POINTER(StaggerReport), _vp, _vp, _vp, ctypes.c_size_t, _vp]
+_lib.md_linear_residual.argtypes = [_i32, _i32, _i32, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _vp]
+_lib.md_step_arrays.argtypes = [_vp, _vp, ctypes.c_size_t, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                                ctypes.POINTER(_vp)]
 _lib.md_arith.argtypes = [_i32, _i32, ctypes.c_int64, _vp, _vp, _vp, _vp]
 _lib.md_last_error.restype = ctypes.c_char_p
 _lib.md_adjoint_workspace_size.argtypes = [_i32, _i32, _i32, _szp]
@@ -321,6 +324,29 @@ def newton_step_window(plan: Plan, prec_solve, lo, hi, keep_factorization, cff, 
     _check(rc, "md_newton_step_window")
 
 
+def linear_residual(prec, n, d, A, b, dx, r, rows=None, norm1=None, status=None, stream=None):
+    """md_linear_residual: r = b - T dx on the rows listed (all when None).
+
+    A [L, n, n, D], b and dx [L, n, D] (tensors, or raw device addresses from
+    step_arrays), r [L, nrows, D]; rows an int32 device tensor; norm1 [D]."""
+    L, D = int(prec), int(d) + 1
+    nrows = n if rows is None else int(rows.numel())
+    raw = lambda t, shape, name: _vp(t) if isinstance(t, int) else _ptr(t, shape, name)
+    rc = _lib.md_linear_residual(L, int(n), int(d), raw(A, (L, n, n, D), "A"), raw(b, (L, n, D), "b"),
+                                 raw(dx, (L, n, D), "dx"), nrows, _ptr(rows, (nrows,), "rows"),
+                                 _ptr(r, (L, nrows, D), "r"), _ptr(norm1, (D,), "norm1"),
+                                 _ptr(status, (1,), "status"), _stream(stream))
+    _check(rc, "md_linear_residual")
+
+
+def step_arrays(plan: Plan, ws):
+    """Device addresses (b, A, dx) where the last Newton step on ws left its arrays."""
+    b, A, dx = _vp(), _vp(), _vp()
+    _check(_lib.md_step_arrays(plan._h, _ptr(ws, None, "ws"), ws.numel() * 8, ctypes.byref(b), ctypes.byref(A),
+                               ctypes.byref(dx)), "md_step_arrays")
+    return int(b.value), int(A.value), int(dx.value)
+
+
 def stagger_next_order(d, D):
     """The order after d in the staggered schedule, d + 1 + d // 2, capped at D."""
     return int(_lib.md_stagger_next_order(int(d), int(D)))
@@ -438,6 +464,23 @@ class Newton:
         tol = default_stagger_tol(ps) if tol is None else tol
         return newton_staggered(self.plan, ps, refactor_every_step, max_steps, tol, self.cff, self.cst, self.x,
                                 self.status, self.norms, self.ws, stream)
+
+    def residual(self, rows=None, prec=None, stream=None):
+        """Residual b - T dx of the last step's linear system (md_step_arrays +
+        md_linear_residual) on the listed rows (all when None), at precision
+        prec (default: the plan's; a mixed step solved at fewer limbs).
+        Returns (r [prec, nrows, D], norm1 [D])."""
+        import torch
+
+        L = self.plan.prec if prec is None else int(prec)
+        n, D = self.plan.n, self.plan.D
+        rws = None if rows is None else torch.as_tensor(np.asarray(rows, dtype=np.int32), device=self.x.device)
+        nrows = n if rws is None else int(rws.numel())
+        b, A, dx = step_arrays(self.plan, self.ws)
+        r = torch.empty((L, nrows, D), dtype=torch.float64, device=self.x.device)
+        norm1 = torch.empty(D, dtype=torch.float64, device=self.x.device)
+        linear_residual(L, n, D - 1, A, b, dx, r, rows=rws, norm1=norm1, status=self.status, stream=stream)
+        return r, norm1
 
     def status_code(self):
         return int(self.status.item())

@@ -616,6 +616,26 @@ int md_newton_staggered(const md_plan *p, int prec_solve, int refactor_every_ste
   return MD_OK;
 }
 
+int md_linear_residual(int prec, int n, int d, const double *A, const double *b, const double *dx, int nrows,
+                       const int32_t *rows, double *r, double *norm1, int32_t *dev_status, hipStream_t st) {
+  if (!valid_prec(prec) || n < 1 || n > MD_MAX_DIM || d < 0 || d + 1 > MD_MAX_COEFFS)
+    return fail(MD_EINVAL, "bad precision, dimension or degree");
+  if (!A || !b || !dx || !r) return fail(MD_EINVAL, "NULL argument");
+  if (nrows < 1 || (!rows && nrows != n)) return fail(MD_EINVAL, "nrows must be positive (n when rows is NULL)");
+  hipError_t e = mdk::launch_residual(prec, n, d + 1, nrows, rows, A, b, dx, r, norm1, dev_status, st);
+  return e == hipSuccess ? MD_OK : hip_fail(e, "residual launch");
+}
+
+int md_step_arrays(const md_plan *p, void *ws, size_t ws_bytes, double **b, double **A, double **dx) {
+  if (!p || !ws || !b || !A || !dx) return fail(MD_EINVAL, "NULL argument");
+  const Layout w = newton_layout(p);
+  if (ws_bytes < w.total) return fail(MD_ENOSPACE, "workspace too small");
+  *b = at(ws, w.b);
+  *A = at(ws, w.A);
+  *dx = at(ws, w.dx);
+  return MD_OK;
+}
+
 int md_adjoint_workspace_size(int prec, int n, int d, size_t *bytes) {
   if (!bytes || !valid_prec(prec) || n < 1 || n > MD_MAX_DIM || d < 0 || d + 1 > MD_MAX_COEFFS)
     return fail(MD_EINVAL, "bad argument");

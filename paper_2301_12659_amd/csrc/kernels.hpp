@@ -82,6 +82,10 @@ hipError_t launch_coef_grad(int L, int n, int D, int m, const int32_t *row_of, c
 hipError_t launch_unit_md(int L, int m, double *c, hipStream_t st);
 hipError_t launch_dot(int L, int64_t count, const double *a, const double *b, double *c, hipStream_t st);
 
+// residual.hip: r [L][nrows][D] = b - T dx on rows (NULL: all), norm1 [D] (nullable).
+hipError_t launch_residual(int L, int n, int D, int nrows, const int32_t *rows, const double *A, const double *b,
+                           const double *dx, double *r, double *norm1, int32_t *status, hipStream_t st);
+
 // api.hip: record the message returned by md_last_error and return the code.
 int api_fail(int code, const char *msg);
 int api_hip_fail(hipError_t e, const char *what);

@@ -1173,14 +1173,6 @@ __global__ void __launch_bounds__(256) arith_kernel(int op, int64_t count, const
 
 // ------------------------------------------------------------------ launchers
 
-#define MD_DISPATCH(L, ...)                          \
-  switch (L) {                                       \
-    case 2: { constexpr int LL = 2; __VA_ARGS__; } break; \
-    case 4: { constexpr int LL = 4; __VA_ARGS__; } break; \
-    case 8: { constexpr int LL = 8; __VA_ARGS__; } break; \
-    default: return hipErrorInvalidValue;            \
-  }
-
 hipError_t launch_status_init(int32_t *status, hipStream_t st) {
   hipLaunchKernelGGL(status_init_kernel, dim3(1), dim3(64), 0, st, status);
   return hipGetLastError();
