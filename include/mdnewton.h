@@ -185,19 +185,25 @@ typedef struct md_stagger_report {
  * should carry about half the working precision, as the paper assumes), each
  * following step raises the order hi by md_stagger_next_order, and the stages
  * below lo are dropped once their residuals vanish: after each step, lo is
- * the number of leading coefficients k with max_i |b_{i,k}| <= tol * s_k,
- * where s_k = max_i (|c_{i,0,k}| + sum_m |value_{m,k}|) is the size of the
- * terms that cancel in b_k (leading limbs).  refactor_every_step = 0 factors
+ * the number of leading coefficients k with |b_{i,k}| <= tol * s_{i,k} for
+ * every equation i, where s_{i,k} = |c_{i,0,k}| + sum_m max_j |f_{m,j,k}| is
+ * the size of the terms whose rounding errors reach b_{i,k}: the constant and,
+ * per monomial, the largest coefficient k of the products f_j along its
+ * forward chain (leading limbs; tol = 0 drops only exactly zero residuals),
+ * or whose relative residual max_i |b_{i,k}| / s_{i,k} did not halve since
+ * the previous step (a Newton or chord step reduces it far more, so it has
+ * reached the level of the rounding errors).  refactor_every_step = 0 factors
  * A_0 once, at the first step (Section 5.3), and makes every later step a
  * chord step; 1 factors at every step (Newton's method).  Stops when hi = D
  * and every coefficient meets the tolerance (converged = 1) or after
  * max_steps steps (converged = 0).  windows (host, nullable): [max_steps][2]
- * gets (lo, hi) of every step.  The host waits for the stream after every
+ * gets (lo, hi) of every step; rel (host, nullable) [D] gets the last step's
+ * max_i |b_{i,k}| / s_{i,k} for k < hi (zero above).  The host waits for the stream after every
  * step (a few doubles are read back).  Arguments and workspace as
  * md_newton_step_window; dev_norms [2][D] is required.  A step whose status
  * is not MD_OK ends the run with that code. */
 int md_newton_staggered(const md_plan *plan, int prec_solve, int refactor_every_step, int max_steps, double tol,
-                        const double *cff, const double *cst, double *x, int32_t *windows,
+                        const double *cff, const double *cst, double *x, int32_t *windows, double *rel,
                         md_stagger_report *report, int32_t *dev_status, double *dev_norms, void *ws,
                         size_t ws_bytes, hipStream_t stream);
 

@@ -17,6 +17,8 @@ exponential-series solutions, Section 3; the sizes below replace them):
 * ``adjoint_qd`` n=32,  degree 31,  quad-double, 32 monomials of 3..5
                  variables with exponents in {1,2}, plus a diagonal boost.
 * ``batched``    many independent paths of uneven size (see ``batched_paths``).
+* ``column_system``  the paper's own one- and two-column triangular systems
+                 with exponential solutions, in closed form (Section 3).
 
 Multiple-double numbers are stored limb-major (structure of arrays by limb),
 shape ``[L, ...]``, as the paper does to keep memory accesses coalesced
@@ -59,6 +61,7 @@ class System:
     seed: int
     steps: int = 1
     boost: np.ndarray | None = None  # index of the boost monomial of each row, or None
+    cst: np.ndarray | None = None  # c_{i,0}(t) [L, n, D] when known in closed form, else None
 
     @property
     def D(self) -> int:
@@ -344,6 +347,81 @@ PRESETS = {
     "large_od": large_od,
     "adjoint_qd": adjoint_qd,
 }
+
+
+def _round_limbs(values, L: int) -> np.ndarray:
+    """Exact rationals to L-limb multiple doubles, limb by limb to nearest."""
+    from fractions import Fraction
+
+    vals = list(values)
+    out = np.zeros((L, len(vals)))
+    for q, v in enumerate(vals):
+        r = Fraction(v)
+        for l in range(L):
+            f = float(r)
+            out[l, q] = f
+            r -= Fraction(f)
+    return out
+
+
+def _exp_coefficients(a, D: int):
+    """a^k / k! for k < D, exact rationals (a a rational)."""
+    from fractions import Fraction
+
+    c = [Fraction(1)]
+    for k in range(1, D):
+        c.append(c[-1] * a / k)
+    return c
+
+
+def column_system(n: int, d: int, L: int, columns: int = 1, seed: int = 0, delta: float = 0.25) -> System:
+    """The paper's test systems (Section 3): x^E = b(t) with E the lower
+    triangular matrix of ones (row i is x_0 x_1 ... x_i), or with two columns
+    c_1 x^{E_1} + c_2 x^{E_2} = b(t), E_1 lower and E_2 the reversed
+    triangle (row i is x_0 ... x_{n-1-i}).  The solution is
+    x_j(t) = exp(alpha_j t) with alpha_j in [-1, -1 + delta] or [1 - delta, 1]
+    (sign and value random, a multiple of 2^-20 so that every sum is exact),
+    so b_i(t) is a sum of c exp(S t) with S a partial sum of the alphas, and
+    both x* and c_{i,0} = -b_i are exact rationals rounded to L limbs.
+    Two-column coefficients: c_1 in [1.5, 2], c_2 in [0.25, 0.5] (doubles),
+    which keeps the 2 x 2 pairs of equations (k, n-1-k) well conditioned."""
+    from fractions import Fraction
+
+    if columns not in (1, 2):
+        raise ValueError("one or two columns")
+    rng = np.random.default_rng([seed, n, d, columns])
+    D = d + 1
+    sign = np.where(rng.random(n) < 0.5, -1, 1)
+    mag = 1.0 - delta * rng.random(n)
+    alpha = [Fraction(int(round(float(s * m) * 2 ** 20)), 2 ** 20) for s, m in zip(sign, mag)]
+    part = [Fraction(0)]
+    for a in alpha:
+        part.append(part[-1] + a)  # part[i + 1] = alpha_0 + ... + alpha_i
+    poly_ptr, mon_ptr, var, exp, cf = [0], [0], [], [], []
+    c1 = rng.uniform(1.5, 2.0, n) if columns == 2 else np.ones(n)
+    c2 = rng.uniform(0.25, 0.5, n)
+    rhs = []
+    for i in range(n):
+        sup = [list(range(i + 1))] + ([list(range(n - i))] if columns == 2 else [])
+        coef = [float(c1[i])] + ([float(c2[i])] if columns == 2 else [])
+        b = [Fraction(0)] * D
+        for vs, c in zip(sup, coef):
+            var.extend(vs)
+            exp.extend([1] * len(vs))
+            mon_ptr.append(len(var))
+            cf.append(c)
+            for k, e in enumerate(_exp_coefficients(part[len(vs)], D)):
+                b[k] += Fraction(c) * e
+        poly_ptr.append(len(cf))
+        rhs.append(b)
+    xs = [_exp_coefficients(a, D) for a in alpha]
+    xstar = _round_limbs([v for row in xs for v in row], L).reshape(L, n, D)
+    cst = _round_limbs([-v for row in rhs for v in row], L).reshape(L, n, D)
+    cff = np.zeros((L, len(cf)))
+    cff[0] = cf
+    return System(f"column{columns}_L{L}_n{n}_d{d}", L, n, d, np.array(poly_ptr, np.int32),
+                  np.array(mon_ptr, np.int32), np.array(var, np.int32), np.array(exp, np.int32), cff, xstar, seed,
+                  steps=1, cst=cst)
 
 
 def random_point(sys: System, seed: int, lo: float = 0.5, hi: float = 1.5) -> np.ndarray:

@@ -55,7 +55,8 @@ class StaggerReport(ctypes.Structure):
 
 
 _lib.md_newton_staggered.argtypes = [_vp, _i32, _i32, _i32, ctypes.c_double, _vp, _vp, _vp, _i32p,
-                                     ctypes.POINTER(StaggerReport), _vp, _vp, _vp, ctypes.c_size_t, _vp]
+                                     ctypes.POINTER(ctypes.c_double), ctypes.POINTER(StaggerReport), _vp, _vp, _vp,
+                                     ctypes.c_size_t, _vp]
 _lib.md_linear_residual.argtypes = [_i32, _i32, _i32, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _vp]
 _lib.md_step_arrays.argtypes = [_vp, _vp, ctypes.c_size_t, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
                                 ctypes.POINTER(_vp)]
@@ -354,23 +355,28 @@ def stagger_next_order(d, D):
 
 def newton_staggered(plan: Plan, prec_solve, refactor_every_step, max_steps, tol, cff, cst, x, status, norms, ws,
                      stream=None):
-    """md_newton_staggered; returns (StaggerReport, [(lo, hi) per step])."""
+    """md_newton_staggered; returns (StaggerReport, [(lo, hi) per step]); the
+    report's `rel` attribute holds the last step's relative residuals [D]."""
     L, n, D, m = plan.prec, plan.n, plan.D, plan.m
     win = (ctypes.c_int32 * (2 * int(max_steps)))()
+    rel = (ctypes.c_double * D)()
     rep = StaggerReport()
     rc = _lib.md_newton_staggered(plan._h, int(prec_solve), int(bool(refactor_every_step)), int(max_steps),
                                   float(tol), _ptr(cff, (L, m), "cff"), _ptr(cst, (L, n, D), "cst"),
-                                  _ptr(x, (L, n, D), "x"), win, ctypes.byref(rep), _ptr(status, (1,), "status"),
-                                  _ptr(norms, (2, D), "norms"), _ptr(ws, None, "ws"), ws.numel() * 8,
-                                  _stream(stream))
+                                  _ptr(x, (L, n, D), "x"), win, rel, ctypes.byref(rep),
+                                  _ptr(status, (1,), "status"), _ptr(norms, (2, D), "norms"), _ptr(ws, None, "ws"),
+                                  ws.numel() * 8, _stream(stream))
     _check(rc, "md_newton_staggered")
+    rep.rel = np.array(rel[:])
     return rep, [(win[2 * q], win[2 * q + 1]) for q in range(rep.steps)]
 
 
-def default_stagger_tol(prec):
+def default_stagger_tol(prec, chain=1):
     """Residual tolerance of the staggered driver relative to the size of the
-    cancelling terms: 2^8 units in the last place of the multiple double."""
-    return 2.0 ** (8 - 53 * int(prec))
+    cancelling terms of each equation: 2^8 units in the last place of the
+    multiple double, times the length of the longest product chain (the
+    largest monomial support), along which rounding errors add up."""
+    return 2.0 ** (8 - 53 * int(prec)) * max(1, int(chain))
 
 
 def arith(prec, op, a, b, c, stream=None):
@@ -461,7 +467,8 @@ class Newton:
         """Newton's method with the staggered order schedule (md_newton_staggered);
         returns (StaggerReport, [(lo, hi) per step])."""
         ps = self.plan.prec if prec_solve is None else prec_solve
-        tol = default_stagger_tol(ps) if tol is None else tol
+        chain = int(np.max(np.diff(self.sys.mon_ptr))) if self.sys.m > 0 else 1
+        tol = default_stagger_tol(ps, chain) if tol is None else tol
         return newton_staggered(self.plan, ps, refactor_every_step, max_steps, tol, self.cff, self.cst, self.x,
                                 self.status, self.norms, self.ws, stream)
 

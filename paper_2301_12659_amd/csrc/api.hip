@@ -81,7 +81,7 @@ size_t qr_scratch_bytes(int L, int n) {
 
 // Workspace regions, in doubles, each aligned to 256 bytes.
 struct Layout {
-  size_t val, der, pw, unit, b, A, qr, tau, qt, bar, invd, M, N, At, r, dxT, dx, sync, tsz, scale, total;
+  size_t val, der, pw, unit, b, A, qr, tau, qt, bar, invd, M, N, At, r, dxT, dx, sync, vsz, tsz, scale, total;
 };
 
 Layout newton_layout(const md_plan *p) {
@@ -111,6 +111,7 @@ Layout newton_layout(const md_plan *p) {
   w.dxT = take(L * n * D);
   w.dx = take(L * n * D);
   w.sync = take(mdk::stages_sync_ints(p->D) / 2 + 1);
+  w.vsz = take((size_t)p->m * D);  // chain maxima of the monomials' forward products
   w.tsz = take(n * D);  // sizes of the terms of b_{i,k} and their maxima over i, for the staggered driver
   w.scale = take(D);
   w.total = off;
@@ -352,6 +353,7 @@ static int eval_diff_impl(const md_plan *p, int Dc, const double *cff, const dou
   Layout w = newton_layout(p);
   mdk::EvalArgs a;
   eval_args(p, cff, x, ws, Dc, a);
+  if (tsz) a.vsize = at(ws, w.vsz);
   hipError_t e;
   {
     Timed t(MD_CLASS_CONVOLUTIONS, st);
@@ -361,7 +363,7 @@ static int eval_diff_impl(const md_plan *p, int Dc, const double *cff, const dou
   {
     Timed t(MD_CLASS_ASSEMBLY, st);
     e = mdk::launch_assemble(p->L, p->n, p->D, Dc, p->m, p->nnz, p->d_poly_ptr, p->d_asm_ptr, p->d_asm_ent, cst,
-                             a.val, a.der, b, A, st, tsz);
+                             a.val, a.der, b, A, st, tsz, a.vsize);
   }
   if (e != hipSuccess) return hip_fail(e, "assembly launch");
   return MD_OK;
@@ -420,7 +422,7 @@ int md_series_solve(int prec, int n, int d, const double *qr, const double *tau,
 // without keep_m left in the workspace (the factorization of the first
 // stage, Section 5.3: a chord step).  With scale (nullable, D doubles) the
 // assembly records the size of the terms of every b_{i,k} and scale[k] gets
-// their maximum over i.
+// max_i |b_{i,k}| / (that size), the residual relative to its own terms.
 static int newton_step_impl(const md_plan *p, int Ls, int lo, int hi, bool keep_m, const double *cff,
                             const double *cst, double *x, int32_t *dev_status, double *dev_norms, double *scale,
                             void *ws, hipStream_t st) {
@@ -469,6 +471,7 @@ static int newton_step_impl(const md_plan *p, int Ls, int lo, int hi, bool keep_
   } else {
     eval_args(p, cff, x, ws, hi, a);
     a.values_only = 1;
+    if (tsz) a.vsize = at(ws, w.vsz);
     {
       Timed t(MD_CLASS_CONVOLUTIONS, st);
       if ((e = mdk::launch_evaldiff(L, a, p->maxexp, at(ws, w.pw), st)) != hipSuccess)
@@ -476,10 +479,12 @@ static int newton_step_impl(const md_plan *p, int Ls, int lo, int hi, bool keep_
     }
     {
       Timed t(MD_CLASS_ASSEMBLY, st);
-      if ((e = mdk::launch_assemble_b(L, n, D, hi, p->m, p->d_poly_ptr, cst, a.val, b, st, tsz)) != hipSuccess)
+      if ((e = mdk::launch_assemble_b(L, n, D, hi, p->m, p->d_poly_ptr, cst, a.val, b, st, tsz, a.vsize)) !=
+          hipSuccess)
         return hip_fail(e, "residual assembly");
     }
     a.values_only = 0;
+    a.vsize = nullptr;
     {
       Timed t(MD_CLASS_CONVOLUTIONS, st);
       if ((e = mdk::launch_evaldiff(Ls, a, p->maxexp, at(ws, w.pw), st)) != hipSuccess)
@@ -556,7 +561,7 @@ int md_newton_step_window(const md_plan *p, int prec_solve, int lo, int hi, int 
 int md_stagger_next_order(int d, int D) { return std::min(D, d + 1 + d / 2); }
 
 int md_newton_staggered(const md_plan *p, int prec_solve, int refactor_every_step, int max_steps, double tol,
-                        const double *cff, const double *cst, double *x, int32_t *windows,
+                        const double *cff, const double *cst, double *x, int32_t *windows, double *rel,
                         md_stagger_report *report, int32_t *dev_status, double *dev_norms, void *ws,
                         size_t ws_bytes, hipStream_t st) {
   if (!p || !cst || !x || !dev_status || !dev_norms || !report || (p->m > 0 && !cff))
@@ -568,7 +573,7 @@ int md_newton_staggered(const md_plan *p, int prec_solve, int refactor_every_ste
   const Layout w = newton_layout(p);
   const int D = p->D;
   double *scale = at(ws, w.scale);
-  // norms, term sizes and status come back through pinned, mapped host
+  // norms, relative residuals and status come back through pinned, mapped host
   // memory written by one small kernel: one wait per step, no copies
   struct Pinned {
     double *h = nullptr;
@@ -583,6 +588,9 @@ int md_newton_staggered(const md_plan *p, int prec_solve, int refactor_every_ste
       (e = hipHostGetDevicePointer((void **)&hdev, pin.h, 0)) != hipSuccess)
     return hip_fail(e, "pinned report buffer");
   const double *h = pin.h;
+  // relative residual of each coefficient at the previous step (infinity:
+  // not yet evaluated), to recognise a residual that no longer decreases
+  std::vector<double> prev((size_t)D, INFINITY);
   *report = md_stagger_report{0, 0, 0, 1, 0};
   int lo = 0, hi = 1;
   for (int step = 0; step < max_steps; ++step) {
@@ -603,9 +611,19 @@ int md_newton_staggered(const md_plan *p, int prec_solve, int refactor_every_ste
     const int32_t status = (int32_t)h[3 * (size_t)D];
     if (status != MD_OK) return fail(status, "a step of the staggered method failed (status " +
                                                  std::to_string(status) + ")");
-    // leading coefficients whose residual vanished, relative to its terms
-    int k = 0;
-    while (k < hi && h[k] <= tol * h[2 * (size_t)D + k]) ++k;
+    if (rel)
+      for (int q = 0; q < D; ++q) rel[q] = h[2 * (size_t)D + q];
+    // leading coefficients that are done: residual within tol of its terms,
+    // or a residual that did not halve since the last step (a Newton or chord
+    // step reduces it far more: it is at the level of the rounding errors).
+    // Coefficients below lo are done and stay frozen, so lo never decreases.
+    int k = lo;
+    while (k < hi) {
+      const double rk = h[2 * (size_t)D + k];
+      if (!(rk <= tol || rk > 0.5 * prev[k])) break;
+      ++k;
+    }
+    for (int q = 0; q < hi; ++q) prev[q] = h[2 * (size_t)D + q];
     if (hi == D && k == D) {
       report->converged = 1;
       break;

@@ -11,11 +11,12 @@ namespace mdk {
 
 // b_i(t) = -(c_{i,0}(t) + sum_{m in P_i} value_m(t)), one thread per (i, s)
 // for the first Dc coefficients s.  tsz (nullable, [n][D]) gets the size of
-// the terms, |c_{i,0,s}| + sum_m |value_{m,s}| on leading limbs, against
-// which the staggered method judges b_{i,s}.
+// the terms whose rounding errors reach b_{i,s}, against which the staggered
+// method judges it: |c_{i,0,s}| + sum_m vsize_{m,s}, the largest product of
+// each monomial's chain (|value_{m,s}| when vsize is null; leading limbs).
 template <int L>
 __global__ void assemble_b_kernel(int n, int D, int Dc, int m, const int32_t *poly_ptr, const double *cst,
-                                  const double *val, double *b, double *tsz) {
+                                  const double *val, double *b, double *tsz, const double *vsize) {
   const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t nD = (size_t)n * D, mD = (size_t)m * D;
   if (t >= (size_t)n * Dc) return;
@@ -27,7 +28,7 @@ __global__ void assemble_b_kernel(int n, int D, int Dc, int m, const int32_t *po
   for (int mj = poly_ptr[i]; mj < poly_ptr[i + 1]; ++mj) {
     double v[L], r[L];
     ld<L>(val, mD, (size_t)mj * D + s, v);
-    size += fabs(v[0]);
+    size += vsize ? vsize[(size_t)mj * D + s] : fabs(v[0]);
     MD<L>::add(acc, v, r);
     md::copy<L>(r, acc);
   }
@@ -101,13 +102,13 @@ hipError_t launch_assemble_A0(int L, int n, int D, int nnz, const int32_t *asm_p
 }
 
 hipError_t launch_assemble_b(int L, int n, int D, int Dc, int m, const int32_t *poly_ptr, const double *cst,
-                             const double *val, double *b, hipStream_t st, double *tsz) {
+                             const double *val, double *b, hipStream_t st, double *tsz, const double *vsize) {
   if (Dc < 1 || Dc > D) return hipErrorInvalidValue;
   const unsigned blocks = (unsigned)(((size_t)n * Dc + 255) / 256);
   switch (L) {
-    case 2: hipLaunchKernelGGL(assemble_b_kernel<2>, dim3(blocks), dim3(256), 0, st, n, D, Dc, m, poly_ptr, cst, val, b, tsz); break;
-    case 4: hipLaunchKernelGGL(assemble_b_kernel<4>, dim3(blocks), dim3(256), 0, st, n, D, Dc, m, poly_ptr, cst, val, b, tsz); break;
-    case 8: hipLaunchKernelGGL(assemble_b_kernel<8>, dim3(blocks), dim3(256), 0, st, n, D, Dc, m, poly_ptr, cst, val, b, tsz); break;
+    case 2: hipLaunchKernelGGL(assemble_b_kernel<2>, dim3(blocks), dim3(256), 0, st, n, D, Dc, m, poly_ptr, cst, val, b, tsz, vsize); break;
+    case 4: hipLaunchKernelGGL(assemble_b_kernel<4>, dim3(blocks), dim3(256), 0, st, n, D, Dc, m, poly_ptr, cst, val, b, tsz, vsize); break;
+    case 8: hipLaunchKernelGGL(assemble_b_kernel<8>, dim3(blocks), dim3(256), 0, st, n, D, Dc, m, poly_ptr, cst, val, b, tsz, vsize); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -128,8 +129,9 @@ hipError_t launch_assemble_A(int L, int n, int D, int Dc, int nnz, const int32_t
 
 hipError_t launch_assemble(int L, int n, int D, int Dc, int m, int nnz, const int32_t *poly_ptr,
                            const int32_t *asm_ptr, const int32_t *asm_ent, const double *cst, const double *val,
-                           const double *der, double *b, double *A, hipStream_t st, double *tsz) {
-  hipError_t e = launch_assemble_b(L, n, D, Dc, m, poly_ptr, cst, val, b, st, tsz);
+                           const double *der, double *b, double *A, hipStream_t st, double *tsz,
+                           const double *vsize) {
+  hipError_t e = launch_assemble_b(L, n, D, Dc, m, poly_ptr, cst, val, b, st, tsz, vsize);
   if (e != hipSuccess) return e;
   return launch_assemble_A(L, n, D, Dc, nnz, asm_ptr, asm_ent, der, A, st);
 }

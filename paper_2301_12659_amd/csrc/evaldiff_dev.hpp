@@ -132,6 +132,7 @@ __device__ void eval_monomial(const EvalArgs &a, int mono, int lane, double *buf
     for (int s = lane; s < Dc; s += G) {
 #pragma unroll
       for (int l = 0; l < L; ++l) a.val[(size_t)l * mD + (size_t)mono * D + s] = (s == 0) ? c[l] : 0.0;
+      if (a.vsize) a.vsize[(size_t)mono * D + s] = (s == 0) ? fabs(c[0]) : 0.0;
     }
     return;
   }
@@ -185,6 +186,19 @@ __device__ void eval_monomial(const EvalArgs &a, int mono, int lane, double *buf
     scal<L>(c, U, U, Dc, lane, G, 1);
     wave_sync();
   }
+  // With vsize: the largest |f_j| of the forward chain at each coefficient
+  // (a lane owns s = lane and s = lane + G; G >= Dc / 2 for Dc <= 128): the
+  // size of the terms whose rounding errors reach the value.
+  const bool track = a.vsize != nullptr;
+  double vmax[2] = {0.0, 0.0};
+  auto track_max = [&](const double *F, bool scalar) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int s = lane + q * G;
+      if (s < Dc) vmax[q] = fmax(vmax[q], scalar ? (s == 0 ? fabs(c[0]) : 0.0) : fabs(F[s]));
+    }
+  };
+  if (track) track_max(U, f0_scalar);
 
   // ---- forward chain with the cross products
   for (int j = 1; j <= k; ++j) {
@@ -237,8 +251,15 @@ __device__ void eval_monomial(const EvalArgs &a, int mono, int lane, double *buf
     double *t = U;
     U = W;
     W = t;
+    if (track) track_max(U, false);
   }
   store_series(a.val, mD, (size_t)mono * D, U, L, Dc, lane, G);
+  if (track)
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int s = lane + q * G;
+      if (s < Dc) a.vsize[(size_t)mono * D + s] = vmax[q];
+    }
 }
 
 

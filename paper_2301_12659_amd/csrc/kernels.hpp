@@ -16,15 +16,18 @@ hipError_t launch_evaldiff(int L, const EvalArgs &a, int maxexp, double *pw, hip
 hipError_t launch_evaldiff0(int L, const EvalArgs &a, hipStream_t st);
 int evaldiff0_max_support(int L);
 // The assembly kernels fill the first Dc coefficients of series stored with
-// D; tsz (nullable, [n][D]) gets |c_{i,0,s}| + sum_m |value_{m,s}| (leading
-// limbs), the size of the terms of b_{i,s}.
+// D; tsz (nullable, [n][D]) gets |c_{i,0,s}| + sum_m vsize_{m,s} (the
+// evaluation's chain maxima; |value_{m,s}| when vsize is null), the size of
+// the terms of b_{i,s}.
 hipError_t launch_assemble(int L, int n, int D, int Dc, int m, int nnz, const int32_t *poly_ptr,
                            const int32_t *asm_ptr, const int32_t *asm_ent, const double *cst, const double *val,
-                           const double *der, double *b, double *A, hipStream_t st, double *tsz = nullptr);
+                           const double *der, double *b, double *A, hipStream_t st, double *tsz = nullptr,
+                           const double *vsize = nullptr);
 size_t evaldiff_lds_bytes(int L, int D);
 int evaldiff_workers_per_block(int D);  // monomials per 256-thread workgroup
 hipError_t launch_assemble_b(int L, int n, int D, int Dc, int m, const int32_t *poly_ptr, const double *cst,
-                             const double *val, double *b, hipStream_t st, double *tsz = nullptr);
+                             const double *val, double *b, hipStream_t st, double *tsz = nullptr,
+                             const double *vsize = nullptr);
 hipError_t launch_assemble_A(int L, int n, int D, int Dc, int nnz, const int32_t *asm_ptr, const int32_t *asm_ent,
                              const double *der, double *A, hipStream_t st);
 hipError_t launch_assemble_A0(int L, int n, int D, int nnz, const int32_t *asm_ptr, const int32_t *asm_ent,
@@ -62,7 +65,8 @@ hipError_t launch_stages(int L, int n, int D, const double *M, const double *NP,
                          double *dxT, int *sync, int32_t *status, hipStream_t st);
 // x_k += dx_k for lo <= k < hi; norms[2][D]: max |b_k| for k < hi and
 // max |dx_k| for lo <= k < hi, zero elsewhere; with tsz ([n][D] term sizes
-// from the assembly) scale[k] = max_i tsz[i][k] for k < hi, zero above.
+// from the assembly) rel[k] = max_i |b_{i,k}| / tsz[i][k] for k < hi, zero
+// above (passed as the scale argument).
 hipError_t launch_update(int L, int n, int D, int lo, int hi, const double *b, const double *dx, double *x,
                          double *norms, int32_t *status, hipStream_t st, const double *tsz = nullptr,
                          double *scale = nullptr);

@@ -1100,12 +1100,14 @@ __global__ void update_kernel(int n, int D, int lo, int W, const double *dx, dou
 }
 
 // norms[k] = max_i |b_{i,k}| for k < hi, norms[D+k] = max_i |dx_{i,k}| for
-// lo <= k < hi (leading limbs), zero elsewhere; a non-finite residual or
-// update is reported.  One workgroup of 256 threads per coefficient k, rows
-// strided over the threads, maxima reduced in LDS.
+// lo <= k < hi (leading limbs), zero elsewhere; with the term sizes tsz of
+// the assembly, rel[k] = max_i |b_{i,k}| / tsz_{i,k} for k < hi (every
+// equation judged against its own terms).  A non-finite residual or update
+// is reported.  One workgroup of 256 threads per coefficient k, rows strided
+// over the threads, maxima reduced in LDS.
 __global__ void __launch_bounds__(256) norms_kernel(int n, int D, int lo, int hi, const double *b, const double *dx,
                                                     double *norms, int32_t *status, const double *tsz,
-                                                    double *scale) {
+                                                    double *rel) {
   __shared__ double sb[256], sx[256], ss[256];
   __shared__ int sf[256];
   const int k = blockIdx.x, t = threadIdx.x;
@@ -1117,7 +1119,10 @@ __global__ void __launch_bounds__(256) norms_kernel(int n, int D, int lo, int hi
     finite &= (isfinite(bi) && isfinite(xi)) ? 1 : 0;
     nb = fmax(nb, fabs(bi));
     nx = fmax(nx, fabs(xi));
-    if (tsz && has_b) ns = fmax(ns, tsz[(size_t)i * D + k]);
+    if (tsz && has_b) {  // |b_{i,k}| relative to the size of its own terms (0/0 = 0)
+      const double t = tsz[(size_t)i * D + k], ab = fabs(bi);
+      ns = fmax(ns, t > 0.0 ? ab / t : (ab > 0.0 ? INFINITY : 0.0));
+    }
   }
   sb[t] = nb;
   sx[t] = nx;
@@ -1138,7 +1143,7 @@ __global__ void __launch_bounds__(256) norms_kernel(int n, int D, int lo, int hi
       norms[k] = sb[0];
       norms[D + k] = sx[0];
     }
-    if (tsz && scale) scale[k] = ss[0];
+    if (tsz && rel) rel[k] = ss[0];
     if (!sf[0]) set_status(status, MD_ENONFINITE);
   }
 }
@@ -1178,20 +1183,37 @@ hipError_t launch_status_init(int32_t *status, hipStream_t st) {
   return hipGetLastError();
 }
 
-// Workgroups of the QR: enough teams for the trailing columns, few enough for
-// a cheap grid barrier (all of them must be resident at once).
+// Workgroups of the QR: a team of 16 lanes per trailing column, at most 16
+// workgroups while that suffices (a cheap grid barrier) and up to 128 for the
+// large systems this kernel serves (n = 1024: 2048 columns of [A_0 | I]);
+// all of them must be resident at once, one per CU at most.
 int qr_workgroups(int n, bool with_qt) {
   const int cols = n + (with_qt ? n : 0);
   int G = (cols + 15) / 16;
-  return G < 1 ? 1 : (G > 16 ? 16 : G);
+  return G < 1 ? 1 : (G > 128 ? 128 : G);
+}
+
+// Dynamic LDS above 64 KB (an octo-double column of 1024 entries) needs the
+// attribute; set once per kernel.
+template <typename K>
+static void allow_large_lds(K kernel) {
+  (void)hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+  (void)hipGetLastError();  // an attribute the runtime refuses must not be reported by the launch
 }
 
 hipError_t launch_qr(int L, int n, double *a, double *tau, double *qt, int32_t *status, unsigned *bar,
                      hipStream_t st) {
   const int G = qr_workgroups(n, qt != nullptr);
   hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, st, bar);
-  MD_DISPATCH(L, hipLaunchKernelGGL(qr_kernel<LL>, dim3(G), dim3(256), (size_t)LL * n * sizeof(double), st, n, a,
-                                    tau, qt, status, bar));
+  MD_DISPATCH(L, {
+    static bool attr = false;
+    if (!attr) {
+      allow_large_lds(qr_kernel<LL>);
+      attr = true;
+    }
+    hipLaunchKernelGGL(qr_kernel<LL>, dim3(G), dim3(256), (size_t)LL * n * sizeof(double), st, n, a, tau, qt, status,
+                       bar);
+  });
   return hipGetLastError();
 }
 
@@ -1240,6 +1262,11 @@ hipError_t launch_m_from_qt(int L, int n, const double *qr, const double *qt, do
     return hipGetLastError();
   }
   MD_DISPATCH(L, {
+    static bool attr = false;
+    if (!attr) {
+      allow_large_lds(m_from_qt_kernel<LL>);
+      attr = true;
+    }
     hipLaunchKernelGGL(invdiag_kernel<LL>, dim3((n + 63) / 64), dim3(64), 0, st, n, qr, invd, status);
     hipLaunchKernelGGL(m_from_qt_kernel<LL>, dim3(n), dim3(64), (size_t)LL * n * sizeof(double), st, n, qr, qt,
                        (const double *)invd, M);
@@ -1250,6 +1277,11 @@ hipError_t launch_m_from_qt(int L, int n, const double *qr, const double *qt, do
 hipError_t launch_form_m(int L, int n, const double *qr, const double *tau, double *invd, double *M, int32_t *status,
                          hipStream_t st) {
   MD_DISPATCH(L, {
+    static bool attr = false;
+    if (!attr) {
+      allow_large_lds(form_m_kernel<LL>);
+      attr = true;
+    }
     hipLaunchKernelGGL(invdiag_kernel<LL>, dim3((n + 63) / 64), dim3(64), 0, st, n, qr, invd, status);
     hipLaunchKernelGGL(form_m_kernel<LL>, dim3(n), dim3(64), (size_t)LL * n * sizeof(double), st, n, qr, tau,
                        (const double *)invd, M);

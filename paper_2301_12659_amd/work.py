@@ -92,3 +92,19 @@ PAPER_MUL_COST = {2: 23, 4: 336, 8: 1742}
 def paper_convention_flops(sys) -> int:
     w = step_work(sys)["convolutions"]
     return int(w["products"] * sys.D * sys.D * PAPER_MUL_COST[sys.L])
+
+
+def convolution_flops(sys, order: int) -> dict:
+    """Evaluation and differentiation of the system at series of `order`
+    coefficients: this library's flops (unpadded convolutions) and the paper's
+    convention (zero-padded order^2 multiplications per product, Table 2)."""
+    conv = scal = 0
+    for j in range(len(sys.mon_ptr) - 1):
+        e = sys.exp[sys.mon_ptr[j]:sys.mon_ptr[j + 1]]
+        c, s = monomial_products(len(e), e)
+        conv += c
+        scal += s
+    cost = md_costs(sys.L)
+    ours = (conv * order * (order + 1) // 2 * cost["fma_lazy"]["flops"] + conv * order * cost["renorm"]["flops"] +
+            scal * order * cost["mul"]["flops"])
+    return {"flops": int(ours), "paper_flops": int(conv * order * order * PAPER_MUL_COST[sys.L]), "products": conv}

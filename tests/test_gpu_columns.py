@@ -1,0 +1,73 @@
+"""The paper's own test systems (Section 3) on the GPU: one and two columns of
+monomials with triangular exponent matrices of ones and exponential
+solutions, whose right-hand sides and solutions are known in closed form."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import mdinputs
+import oracle
+from gpu_helpers import TOL, host, series_err, step_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mdn():
+    import paper_2301_12659_amd as mdn
+
+    return mdn
+
+
+def growth(s):
+    """n max_{i,k} |S_i|^k / k!: the partial sums S_i = alpha_0 + ... + alpha_i
+    are the exponents of the products along the monomial chains, and the
+    coefficients x_k ~ alpha^k / k! are recovered from residual coefficients of
+    size S^k / k! (the systems' inherent loss of accuracy, in units of the
+    working precision)."""
+    S = np.cumsum(s.xstar[0, :, 1])  # coefficient 1 of exp(alpha t) is alpha
+    g, term = 1.0, np.ones_like(S)
+    for k in range(1, s.D):
+        term = term * np.abs(S) / k
+        g = max(g, float(term.max()))
+    return s.n * g
+
+
+@pytest.mark.parametrize("L,n,d,cols,steps", [(4, 48, 31, 1, 8), (2, 33, 15, 2, 7), (8, 16, 23, 1, 8)])
+def test_newton_reaches_the_exponential_solution(mdn, L, n, d, cols, steps):
+    """Newton from x*(0) = 1 doubles the correct coefficients per step and ends
+    at exp(alpha t) to the working precision times the system's growth."""
+    s = mdinputs.column_system(n, d, L, cols, seed=3)
+    drv = mdn.Newton(s, s.cst, s.start())
+    for _ in range(steps):
+        drv.step()
+    assert drv.status_code() == 0
+    assert series_err(host(drv.x), s.xstar) <= TOL[L] * growth(s)
+
+
+def test_column_step_matches_oracle(mdn):
+    """One step of a two-column octo-double system from a perturbed point,
+    against the oracle's step."""
+    s = mdinputs.column_system(12, 9, 8, 2, seed=4)
+    x = s.xstar.copy()
+    x[0] *= 1.0 + 1e-3 * np.random.default_rng(0).uniform(-1, 1, x.shape[1:])
+    drv = mdn.Newton(s, s.cst, x)
+    drv.step()
+    ref = oracle.newton_step(s, s.cff, s.cst, x)["x"]
+    assert step_err(host(drv.x), ref, x) <= TOL[8]
+
+
+def test_staggered_driver_on_a_column_system(mdn):
+    """The staggered driver from x*(0) on one column of 64 quad-double
+    monomials of up to 64 variables, whose high coefficients cannot reach the
+    per-equation tolerance (rounding errors grow along the 64-factor chains):
+    one factorization, converged once the residuals stop decreasing, at the
+    exponential solution within the system's growth."""
+    s = mdinputs.column_system(64, 31, 4, 1, seed=5)
+    drv = mdn.Newton(s, s.cst, s.start())
+    rep, windows = drv.staggered(max_steps=30)
+    assert rep.converged == 1 and rep.factorizations == 1, (rep.steps, windows)
+    los = [lo for lo, _ in windows]
+    assert los == sorted(los)  # a coefficient once done stays frozen
+    assert series_err(host(drv.x), s.xstar) <= TOL[4] * growth(s)

@@ -66,3 +66,34 @@ def test_half_precision_start(L):
     assert not np.any(x[keep:]) and not np.any(x[:, :, 1:])
     rel = np.abs(s.xstar[keep, :, 0]) / np.abs(s.xstar[0, :, 0])
     assert np.all(rel < 2.0 ** (-53 * keep + 1))
+
+
+def test_column_system_exponential_coefficients_match_table1():
+    """x_j(t) = exp(alpha t): with alpha = 1 the coefficients are the printed
+    1/k! of the paper's Table 1 (two significant digits)."""
+    import os
+
+    here = os.path.dirname(os.path.abspath(__file__))
+    coefs = mdinputs._exp_coefficients(1, 128)
+    with open(os.path.join(here, "golden", "table1_inverse_factorials.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            k, val = line.split()[:2]
+            assert float(coefs[int(k)]) == pytest.approx(float(val), rel=0.051)
+
+
+@pytest.mark.parametrize("L,cols", [(2, 1), (4, 2), (8, 1)])
+def test_column_system_solution_is_a_root(L, cols):
+    """The closed-form b(t) of the paper's column systems (Section 3) is
+    p(x*) for the exponential x*: the oracle's residual at x* is only the
+    rounding of c_{i,0} and x* to L limbs."""
+    import oracle
+
+    s = mdinputs.column_system(9, 7, L, cols, seed=2)
+    assert s.m == cols * s.n and np.all(s.exp == 1)
+    rows = [list(s.var[s.mon_ptr[j]:s.mon_ptr[j + 1]]) for j in range(s.m)]
+    assert rows[0] == [0] and rows[cols * 8] == list(range(9))
+    b, _, scale = oracle.eval_diff(s, s.cff, s.cst, s.xstar)
+    assert np.max(np.abs(b[0]).max(axis=1) / scale) < 2.0 ** (-53 * L + 8)
+    np.testing.assert_array_equal(s.start()[0, :, 0], np.ones(9))
