@@ -18,7 +18,8 @@ exponential-series solutions, Section 3; the sizes below replace them):
                  variables with exponents in {1,2}, plus a diagonal boost.
 * ``batched``    many independent paths of uneven size (see ``batched_paths``).
 * ``column_system``  the paper's own one- and two-column triangular systems
-                 with exponential solutions, in closed form (Section 3).
+                 with exponential solutions, in closed form (Section 3);
+                 ``complex_column_system`` the same with complex data.
 
 Multiple-double numbers are stored limb-major (structure of arrays by limb),
 shape ``[L, ...]``, as the paper does to keep memory accesses coalesced
@@ -75,10 +76,15 @@ class System:
     def nnz(self) -> int:
         return int(self.var.shape[0])
 
+    @property
+    def is_complex(self) -> bool:
+        """Complex data: cff [2, L, m], xstar and cst [2, L, n, D] (real plane, imaginary plane)."""
+        return self.xstar.ndim == 4
+
     def start(self) -> np.ndarray:
         """x*(0) as a series: coefficient 0 of x*, all higher coefficients zero."""
         x = np.zeros_like(self.xstar)
-        x[:, :, 0] = self.xstar[:, :, 0]
+        x[..., 0] = self.xstar[..., 0]
         return x
 
     def half_precision_start(self) -> np.ndarray:
@@ -422,6 +428,82 @@ def column_system(n: int, d: int, L: int, columns: int = 1, seed: int = 0, delta
     return System(f"column{columns}_L{L}_n{n}_d{d}", L, n, d, np.array(poly_ptr, np.int32),
                   np.array(mon_ptr, np.int32), np.array(var, np.int32), np.array(exp, np.int32), cff, xstar, seed,
                   steps=1, cst=cst)
+
+
+def _cmul(a, b):
+    """(a0 + i a1)(b0 + i b1) on pairs of exact rationals."""
+    return (a[0] * b[0] - a[1] * b[1], a[0] * b[1] + a[1] * b[0])
+
+
+def _cexp_coefficients(a, D: int):
+    """a^k / k! for k < D, a a pair of exact rationals."""
+    from fractions import Fraction
+
+    c = [(Fraction(1), Fraction(0))]
+    for k in range(1, D):
+        p = _cmul(c[-1], a)
+        c.append((p[0] / k, p[1] / k))
+    return c
+
+
+def complex_column_system(n: int, d: int, L: int, columns: int = 1, seed: int = 0) -> System:
+    """The paper's column systems with complex data (Sections 3 and 5.2):
+    x_j(t) = exp(alpha_j t) with alpha_j = cos(theta_j) + i sin(theta_j),
+    |alpha_j| = 1 up to rounding its parts to multiples of 2^-20, theta_j
+    uniform; b_i(t) = exp(S_i t) (one column) or c_1 exp(S_i t) + c_2
+    exp(S_{n-1-i} t) (two columns, real c as in column_system), S_i the partial
+    sums of the alphas; x* and c_{i,0} = -b_i exact complex rationals rounded
+    to L limbs per part.  cff [2, L, m], xstar and cst [2, L, n, D]."""
+    from fractions import Fraction
+
+    if columns not in (1, 2):
+        raise ValueError("one or two columns")
+    rng = np.random.default_rng([seed, n, d, columns, 7])
+    D = d + 1
+    theta = rng.uniform(0.0, 2.0 * np.pi, n)
+    q = lambda v: Fraction(int(round(float(v) * 2 ** 20)), 2 ** 20)
+    alpha = [(q(np.cos(t)), q(np.sin(t))) for t in theta]
+    part = [(Fraction(0), Fraction(0))]
+    for a in alpha:
+        part.append((part[-1][0] + a[0], part[-1][1] + a[1]))
+    poly_ptr, mon_ptr, var, exp, cf = [0], [0], [], [], []
+    c1 = rng.uniform(1.5, 2.0, n) if columns == 2 else np.ones(n)
+    c2 = rng.uniform(0.25, 0.5, n)
+    re_b, im_b = [], []
+    for i in range(n):
+        sup = [list(range(i + 1))] + ([list(range(n - i))] if columns == 2 else [])
+        coef = [float(c1[i])] + ([float(c2[i])] if columns == 2 else [])
+        b = [(Fraction(0), Fraction(0)) for _ in range(D)]
+        for vs, c in zip(sup, coef):
+            var.extend(vs)
+            exp.extend([1] * len(vs))
+            mon_ptr.append(len(var))
+            cf.append(c)
+            for k, e in enumerate(_cexp_coefficients(part[len(vs)], D)):
+                b[k] = (b[k][0] + Fraction(c) * e[0], b[k][1] + Fraction(c) * e[1])
+        poly_ptr.append(len(cf))
+        re_b.append([-v[0] for v in b])
+        im_b.append([-v[1] for v in b])
+    xs = [_cexp_coefficients(a, D) for a in alpha]
+    xstar = np.stack([_round_limbs([v[0] for row in xs for v in row], L).reshape(L, n, D),
+                      _round_limbs([v[1] for row in xs for v in row], L).reshape(L, n, D)])
+    cst = np.stack([_round_limbs([v for row in re_b for v in row], L).reshape(L, n, D),
+                    _round_limbs([v for row in im_b for v in row], L).reshape(L, n, D)])
+    cff = np.zeros((2, L, len(cf)))
+    cff[0, 0] = cf
+    return System(f"ccolumn{columns}_L{L}_n{n}_d{d}", L, n, d, np.array(poly_ptr, np.int32),
+                  np.array(mon_ptr, np.int32), np.array(var, np.int32), np.array(exp, np.int32), cff, xstar, seed,
+                  steps=1, cst=cst)
+
+
+def complex_random(sys: System, seed: int, lo: float = -1.0, hi: float = 1.0):
+    """Random complex data for a system's tables: (cff [2, L, m], cst [2, L, n, D], x [2, L, n, D])."""
+    rng = np.random.default_rng([seed, 31337])
+    L, n, D, m = sys.L, sys.n, sys.D, sys.m
+    cff = np.stack([random_md(rng, L, (m,), lo, hi) for _ in range(2)])
+    cst = np.stack([random_md(rng, L, (n, D), lo, hi) for _ in range(2)])
+    x = np.stack([random_md(rng, L, (n, D), lo, hi) for _ in range(2)])
+    return cff, cst, x
 
 
 def random_point(sys: System, seed: int, lo: float = 0.5, hi: float = 1.5) -> np.ndarray:

@@ -64,6 +64,7 @@ def lib():
         L.ora_arith.argtypes = [ci, ci, ci, dp, dp, dp, ci, ci, dp]
         L.ora_adjoint_solve.argtypes = [ci, ci, ci, ci, dp, dp, ci, dp]
         L.ora_coef_grad.argtypes = [ci, ci, ci, ci, i32p, i32p, i32p, i32p, ci, dp, ci, dp, ci, dp]
+        L.ora_complex_step.argtypes = [ci, ci, ci, ci, i32p, i32p, i32p, i32p, ci, dp, dp, dp, ci, dp, dp, dp, dp]
         L.ora_linear_residual.argtypes = [ci, ci, ci, ci, dp, dp, dp, ci, i32p, ci, dp, dp]
         L.ora_window_step.argtypes = [ci, ci, ci, ci, i32p, i32p, i32p, i32p, ci, dp, dp, dp, dp, ci, ci, dp, dp,
                                       dp, dp]
@@ -200,6 +201,31 @@ def linear_residual(A, b, dx, rows=None, K=None, prec=None):
     rc = lib().ora_linear_residual(prec, n, D, L, _d(A), _d(b), _d(dx), len(rr), _i(rr), K, _d(r), _d(sc))
     _check(rc, "ora_linear_residual")
     return r, sc
+
+
+def complex_step(sys, cff, cst, x, K=None, prec=None, step=True):
+    """Complex data (Section 5.2): cff [2, L, m], cst and x [2, L, n, D] (real
+    plane, imaginary plane).  Returns a dict of expansions b [2, K, n, D],
+    A [2, K, D, n, n] and, with step, x + dx and dx [2, K, n, D] (one Newton
+    step by complex LU and block forward substitution)."""
+    L0 = cff.shape[1]
+    L = max(cff.shape[1], cst.shape[1], x.shape[1])
+    pad = lambda a: np.stack([_pad(a[0], L), _pad(a[1], L)])
+    cff, cst, x = pad(cff), pad(cst), pad(x)
+    K = K or 4 * L0 + 2
+    prec = prec or prec_bits(L0)
+    n, D = sys.n, sys.D
+    pp, mp, var, ex = _sys_args(sys)
+    out = {"b": np.zeros((2, K, n, D)), "A": np.zeros((2, K, D, n, n))}
+    null = ctypes.POINTER(ctypes.c_double)()
+    if step:
+        out["x"] = np.zeros((2, K, n, D))
+        out["dx"] = np.zeros((2, K, n, D))
+    rc = lib().ora_complex_step(prec, n, D, sys.m, _i(pp), _i(mp), _i(var), _i(ex), L, _d(cff), _d(cst), _d(x), K,
+                                _d(out["b"]), _d(out["A"]), _d(out["x"]) if step else null,
+                                _d(out["dx"]) if step else null)
+    _check(rc, "ora_complex_step")
+    return out
 
 
 def manufacture(sys, Lout=None, prec=None):

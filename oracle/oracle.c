@@ -539,6 +539,311 @@ int ora_linear_residual(int prec_bits, int n, int D, int L, const double *A, con
   return ORA_OK;
 }
 
+/* ------------------ complex data (Section 5.2: complex series) ------------
+ * A complex number is a pair of MPFR numbers, a complex array a pair of
+ * arrays.  Inputs are [2][L][...]: the real plane, then the imaginary plane;
+ * outputs [2][K][...].  The product is the textbook one,
+ * (a + ib)(c + id) = (ac - bd) + i(ad + bc). */
+
+/* r = a * b (r must not alias a or b). */
+static void cmul(mpfr_t rr, mpfr_t ri, mpfr_t ar, mpfr_t ai, mpfr_t br, mpfr_t bi, mpfr_t t1, mpfr_t t2) {
+  mpfr_mul(t1, ar, br, MPFR_RNDN);
+  mpfr_mul(t2, ai, bi, MPFR_RNDN);
+  mpfr_sub(rr, t1, t2, MPFR_RNDN);
+  mpfr_mul(t1, ar, bi, MPFR_RNDN);
+  mpfr_mul(t2, ai, br, MPFR_RNDN);
+  mpfr_add(ri, t1, t2, MPFR_RNDN);
+}
+
+/* Truncated complex product c = a * b mod t^D (c must not alias a or b). */
+static void cser_mul(mpfr_t *cr, mpfr_t *ci, mpfr_t *ar, mpfr_t *ai, mpfr_t *br, mpfr_t *bi, int D, mpfr_t *w) {
+  for (int s = 0; s < D; ++s) {
+    mpfr_set_zero(cr[s], 1);
+    mpfr_set_zero(ci[s], 1);
+    for (int i = 0; i <= s; ++i) {
+      cmul(w[0], w[1], ar[i], ai[i], br[s - i], bi[s - i], w[2], w[3]);
+      mpfr_add(cr[s], cr[s], w[0], MPFR_RNDN);
+      mpfr_add(ci[s], ci[s], w[1], MPFR_RNDN);
+    }
+  }
+}
+
+/* out = coef * prod_l x_{var_l}^{e_l} mod t^D with entry `skip` (if >= 0)
+ * lowered by one; tmp a scratch pair of series, w four scratch numbers. */
+static void cmono_series(mpfr_t *outr, mpfr_t *outi, mpfr_t cr, mpfr_t ci, const int32_t *vars, const int32_t *exps,
+                         int k, int skip, mpfr_t *const *Xr, mpfr_t *const *Xi, int D, mpfr_t *tr, mpfr_t *ti,
+                         mpfr_t *w) {
+  for (int s = 0; s < D; ++s) {
+    mpfr_set_zero(outr[s], 1);
+    mpfr_set_zero(outi[s], 1);
+  }
+  mpfr_set(outr[0], cr, MPFR_RNDN);
+  mpfr_set(outi[0], ci, MPFR_RNDN);
+  for (int l = 0; l < k; ++l) {
+    int e = exps[l] - (l == skip ? 1 : 0);
+    for (int r = 0; r < e; ++r) {
+      cser_mul(tr, ti, outr, outi, Xr[vars[l]], Xi[vars[l]], D, w);
+      for (int s = 0; s < D; ++s) {
+        mpfr_swap(outr[s], tr[s]);
+        mpfr_swap(outi[s], ti[s]);
+      }
+    }
+  }
+}
+
+/* b = -(c_0 + sum_m value_m) and A_k[i][j] = sum_m (d/dx_j value_m)_k on every
+ * row; b [2][n][D], A [2][D][n][n]. */
+static void ceval_rows(const sys_t *S, mpfr_t *const *Xr, mpfr_t *const *Xi, mpfr_t *const *Cr, mpfr_t *const *Ci,
+                       mpfr_t *Fr, mpfr_t *Fi, mpfr_t *br, mpfr_t *bi, mpfr_t *Ar, mpfr_t *Ai, mpfr_prec_t prec) {
+  const int D = S->D, n = S->n;
+  for (size_t q = 0; q < (size_t)D * n * n; ++q) {
+    mpfr_set_zero(Ar[q], 1);
+    mpfr_set_zero(Ai[q], 1);
+  }
+#pragma omp parallel num_threads(ora_get_threads())
+  {
+    mpfr_t *vr = vnew(D, prec), *vi = vnew(D, prec), *tr = vnew(D, prec), *ti = vnew(D, prec), *w = vnew(4, prec);
+    mpfr_t c2r, c2i;
+    mpfr_init2(c2r, prec);
+    mpfr_init2(c2i, prec);
+#pragma omp for schedule(dynamic, 1)
+    for (int i = 0; i < n; ++i) {
+      for (int s = 0; s < D; ++s) {
+        mpfr_set(br[(size_t)i * D + s], Cr[i][s], MPFR_RNDN);
+        mpfr_set(bi[(size_t)i * D + s], Ci[i][s], MPFR_RNDN);
+      }
+      for (int mj = S->pp[i]; mj < S->pp[i + 1]; ++mj) {
+        const int32_t *vs = S->var + S->mp[mj], *es = S->ex + S->mp[mj];
+        int k = S->mp[mj + 1] - S->mp[mj];
+        cmono_series(vr, vi, Fr[mj], Fi[mj], vs, es, k, -1, Xr, Xi, D, tr, ti, w);
+        for (int s = 0; s < D; ++s) {
+          mpfr_add(br[(size_t)i * D + s], br[(size_t)i * D + s], vr[s], MPFR_RNDN);
+          mpfr_add(bi[(size_t)i * D + s], bi[(size_t)i * D + s], vi[s], MPFR_RNDN);
+        }
+        for (int l = 0; l < k; ++l) {  /* d/dx_j (c x^a) = c a_j x^{a - e_j} */
+          mpfr_mul_si(c2r, Fr[mj], es[l], MPFR_RNDN);
+          mpfr_mul_si(c2i, Fi[mj], es[l], MPFR_RNDN);
+          cmono_series(vr, vi, c2r, c2i, vs, es, k, l, Xr, Xi, D, tr, ti, w);
+          for (int s = 0; s < D; ++s) {
+            size_t q = ((size_t)s * n + i) * n + vs[l];
+            mpfr_add(Ar[q], Ar[q], vr[s], MPFR_RNDN);
+            mpfr_add(Ai[q], Ai[q], vi[s], MPFR_RNDN);
+          }
+        }
+      }
+      for (int s = 0; s < D; ++s) {
+        mpfr_neg(br[(size_t)i * D + s], br[(size_t)i * D + s], MPFR_RNDN);
+        mpfr_neg(bi[(size_t)i * D + s], bi[(size_t)i * D + s], MPFR_RNDN);
+      }
+    }
+    vfree(vr, D);
+    vfree(vi, D);
+    vfree(tr, D);
+    vfree(ti, D);
+    vfree(w, 4);
+    mpfr_clear(c2r);
+    mpfr_clear(c2i);
+  }
+}
+
+/* Complex Gaussian elimination with partial pivoting (largest |re| + |im|)
+ * on an n x n row-major pair; returns ORA_ESINGULAR on a zero pivot. */
+static int clu_factor(mpfr_t *Mr, mpfr_t *Mi, int n, int *perm, mpfr_prec_t prec) {
+  mpfr_t t, best, den, qr, qi, w[4];
+  mpfr_inits2(prec, t, best, den, qr, qi, w[0], w[1], w[2], w[3], (mpfr_ptr)0);
+  int rc = ORA_OK;
+  for (int i = 0; i < n; ++i) perm[i] = i;
+  for (int c = 0; c < n && rc == ORA_OK; ++c) {
+    int piv = c;
+    mpfr_set_zero(best, 1);
+    for (int r = c; r < n; ++r) {
+      mpfr_abs(t, Mr[(size_t)r * n + c], MPFR_RNDN);
+      mpfr_abs(den, Mi[(size_t)r * n + c], MPFR_RNDN);
+      mpfr_add(t, t, den, MPFR_RNDN);
+      if (mpfr_cmp(t, best) > 0) {
+        mpfr_set(best, t, MPFR_RNDN);
+        piv = r;
+      }
+    }
+    if (mpfr_zero_p(best)) {
+      rc = ORA_ESINGULAR;
+      break;
+    }
+    if (piv != c) {
+      for (int j = 0; j < n; ++j) {
+        mpfr_swap(Mr[(size_t)c * n + j], Mr[(size_t)piv * n + j]);
+        mpfr_swap(Mi[(size_t)c * n + j], Mi[(size_t)piv * n + j]);
+      }
+      int tp = perm[c];
+      perm[c] = perm[piv];
+      perm[piv] = tp;
+    }
+    mpfr_t *pr = &Mr[(size_t)c * n + c], *pi = &Mi[(size_t)c * n + c];
+    mpfr_sqr(den, *pr, MPFR_RNDN);
+    mpfr_sqr(t, *pi, MPFR_RNDN);
+    mpfr_add(den, den, t, MPFR_RNDN);
+    for (int r = c + 1; r < n; ++r) {
+      /* l = M[r][c] / p = a conj(p) / |p|^2, a conj(p) = (ar pr + ai pi) + i (ai pr - ar pi) */
+      mpfr_mul(w[0], Mr[(size_t)r * n + c], *pr, MPFR_RNDN);
+      mpfr_mul(w[1], Mi[(size_t)r * n + c], *pi, MPFR_RNDN);
+      mpfr_add(qr, w[0], w[1], MPFR_RNDN);
+      mpfr_mul(w[0], Mi[(size_t)r * n + c], *pr, MPFR_RNDN);
+      mpfr_mul(w[1], Mr[(size_t)r * n + c], *pi, MPFR_RNDN);
+      mpfr_sub(qi, w[0], w[1], MPFR_RNDN);
+      mpfr_div(qr, qr, den, MPFR_RNDN);
+      mpfr_div(qi, qi, den, MPFR_RNDN);
+      mpfr_set(Mr[(size_t)r * n + c], qr, MPFR_RNDN);
+      mpfr_set(Mi[(size_t)r * n + c], qi, MPFR_RNDN);
+      for (int j = c + 1; j < n; ++j) {
+        cmul(w[2], w[3], qr, qi, Mr[(size_t)c * n + j], Mi[(size_t)c * n + j], w[0], w[1]);
+        mpfr_sub(Mr[(size_t)r * n + j], Mr[(size_t)r * n + j], w[2], MPFR_RNDN);
+        mpfr_sub(Mi[(size_t)r * n + j], Mi[(size_t)r * n + j], w[3], MPFR_RNDN);
+      }
+    }
+  }
+  mpfr_clears(t, best, den, qr, qi, w[0], w[1], w[2], w[3], (mpfr_ptr)0);
+  return rc;
+}
+
+/* Solve (LU) y = rhs in place (y [n] pairs), with the row order of perm. */
+static void clu_solve(mpfr_t *LUr, mpfr_t *LUi, int n, const int *perm, mpfr_t *yr, mpfr_t *yi, mpfr_prec_t prec) {
+  mpfr_t *zr = vnew(n, prec), *zi = vnew(n, prec), *w = vnew(6, prec);
+  for (int i = 0; i < n; ++i) {
+    mpfr_set(zr[i], yr[perm[i]], MPFR_RNDN);
+    mpfr_set(zi[i], yi[perm[i]], MPFR_RNDN);
+  }
+  for (int i = 0; i < n; ++i) /* forward, unit lower */
+    for (int j = 0; j < i; ++j) {
+      cmul(w[0], w[1], LUr[(size_t)i * n + j], LUi[(size_t)i * n + j], zr[j], zi[j], w[2], w[3]);
+      mpfr_sub(zr[i], zr[i], w[0], MPFR_RNDN);
+      mpfr_sub(zi[i], zi[i], w[1], MPFR_RNDN);
+    }
+  for (int i = n - 1; i >= 0; --i) { /* backward */
+    for (int j = i + 1; j < n; ++j) {
+      cmul(w[0], w[1], LUr[(size_t)i * n + j], LUi[(size_t)i * n + j], zr[j], zi[j], w[2], w[3]);
+      mpfr_sub(zr[i], zr[i], w[0], MPFR_RNDN);
+      mpfr_sub(zi[i], zi[i], w[1], MPFR_RNDN);
+    }
+    /* z_i / U_ii = z_i conj(u) / |u|^2 */
+    mpfr_t *ur = &LUr[(size_t)i * n + i], *ui = &LUi[(size_t)i * n + i];
+    mpfr_sqr(w[4], *ur, MPFR_RNDN);
+    mpfr_sqr(w[5], *ui, MPFR_RNDN);
+    mpfr_add(w[4], w[4], w[5], MPFR_RNDN);
+    mpfr_mul(w[0], zr[i], *ur, MPFR_RNDN);
+    mpfr_mul(w[1], zi[i], *ui, MPFR_RNDN);
+    mpfr_add(w[2], w[0], w[1], MPFR_RNDN);
+    mpfr_mul(w[0], zi[i], *ur, MPFR_RNDN);
+    mpfr_mul(w[1], zr[i], *ui, MPFR_RNDN);
+    mpfr_sub(w[3], w[0], w[1], MPFR_RNDN);
+    mpfr_div(zr[i], w[2], w[4], MPFR_RNDN);
+    mpfr_div(zi[i], w[3], w[4], MPFR_RNDN);
+  }
+  for (int i = 0; i < n; ++i) {
+    mpfr_set(yr[i], zr[i], MPFR_RNDN);
+    mpfr_set(yi[i], zi[i], MPFR_RNDN);
+  }
+  vfree(zr, n);
+  vfree(zi, n);
+  vfree(w, 6);
+}
+
+/* Block forward substitution on the complex block Toeplitz system (Section
+ * 2): dx_k = A_0^{-1} (b_k - sum_{j=1..k} A_j dx_{k-j}). */
+static int ctoeplitz_solve(mpfr_t *Ar, mpfr_t *Ai, mpfr_t *br, mpfr_t *bi, mpfr_t *xr, mpfr_t *xi, int n, int D,
+                           mpfr_prec_t prec) {
+  const size_t nn = (size_t)n * n;
+  mpfr_t *LUr = vnew(nn, prec), *LUi = vnew(nn, prec), *rr = vnew(n, prec), *ri = vnew(n, prec), *w = vnew(4, prec);
+  int *perm = (int *)malloc(n * sizeof(int));
+  for (size_t q = 0; q < nn; ++q) {
+    mpfr_set(LUr[q], Ar[q], MPFR_RNDN);
+    mpfr_set(LUi[q], Ai[q], MPFR_RNDN);
+  }
+  int rc = clu_factor(LUr, LUi, n, perm, prec);
+  for (int k = 0; k < D && rc == ORA_OK; ++k) {
+    for (int i = 0; i < n; ++i) {
+      mpfr_set(rr[i], br[(size_t)i * D + k], MPFR_RNDN);
+      mpfr_set(ri[i], bi[(size_t)i * D + k], MPFR_RNDN);
+      for (int j = 1; j <= k; ++j)
+        for (int v = 0; v < n; ++v) {
+          size_t a = (size_t)j * nn + (size_t)i * n + v, x = (size_t)v * D + (k - j);
+          cmul(w[0], w[1], Ar[a], Ai[a], xr[x], xi[x], w[2], w[3]);
+          mpfr_sub(rr[i], rr[i], w[0], MPFR_RNDN);
+          mpfr_sub(ri[i], ri[i], w[1], MPFR_RNDN);
+        }
+    }
+    clu_solve(LUr, LUi, n, perm, rr, ri, prec);
+    for (int i = 0; i < n; ++i) {
+      mpfr_set(xr[(size_t)i * D + k], rr[i], MPFR_RNDN);
+      mpfr_set(xi[(size_t)i * D + k], ri[i], MPFR_RNDN);
+    }
+  }
+  vfree(LUr, nn);
+  vfree(LUi, nn);
+  vfree(rr, n);
+  vfree(ri, n);
+  vfree(w, 4);
+  free(perm);
+  return rc;
+}
+
+/* Complex evaluation, differentiation and (optionally) one Newton step.
+ * Inputs [2][L][...]: cff [m], cst and x [n][D].  Outputs (NULL to skip) as
+ * [2][K][...] expansions: b [n][D], A [D][n][n], x + dx and dx [n][D]. */
+int ora_complex_step(int prec_bits, int n, int D, int m, const int32_t *pp, const int32_t *mp, const int32_t *var,
+                     const int32_t *ex, int L, const double *cff, const double *cst, const double *x, int K,
+                     double *b_out, double *A_out, double *x_out, double *dx_out) {
+  sys_t S = {n, D, m, pp, mp, var, ex};
+  if (check_sys(&S) || K < 1 || L < 1) return ORA_EINVAL;
+  mpfr_prec_t prec = prec_bits;
+  const size_t nD = (size_t)n * D, nn = (size_t)n * n, DA = (size_t)D * nn;
+  mpfr_t **Xr, **Cr, *Fr, **Xi, **Ci, *Fi;
+  load_inputs(&S, L, cff, cst, x, &Xr, &Cr, &Fr, prec);
+  load_inputs(&S, L, cff + (size_t)L * m, cst + (size_t)L * nD, x + (size_t)L * nD, &Xi, &Ci, &Fi, prec);
+  mpfr_t *br = vnew(nD, prec), *bi = vnew(nD, prec), *Ar = vnew(DA, prec), *Ai = vnew(DA, prec);
+  ceval_rows(&S, Xr, Xi, Cr, Ci, Fr, Fi, br, bi, Ar, Ai, prec);
+  mpfr_t tmp;
+  mpfr_init2(tmp, prec);
+  int rc = ORA_OK;
+  for (size_t q = 0; b_out && q < nD; ++q) {
+    exp_put(b_out + q, nD, K, br[q], tmp);
+    exp_put(b_out + (size_t)K * nD + q, nD, K, bi[q], tmp);
+  }
+  for (size_t q = 0; A_out && q < DA; ++q) {
+    exp_put(A_out + q, DA, K, Ar[q], tmp);
+    exp_put(A_out + (size_t)K * DA + q, DA, K, Ai[q], tmp);
+  }
+  if (x_out || dx_out) {
+    mpfr_t *dxr = vnew(nD, prec), *dxi = vnew(nD, prec), xn;
+    mpfr_init2(xn, prec);
+    rc = ctoeplitz_solve(Ar, Ai, br, bi, dxr, dxi, n, D, prec);
+    for (int i = 0; i < n && rc == ORA_OK; ++i)
+      for (int s2 = 0; s2 < D; ++s2) {
+        size_t q = (size_t)i * D + s2;
+        if (x_out) {
+          mpfr_add(xn, Xr[i][s2], dxr[q], MPFR_RNDN);
+          exp_put(x_out + q, nD, K, xn, tmp);
+          mpfr_add(xn, Xi[i][s2], dxi[q], MPFR_RNDN);
+          exp_put(x_out + (size_t)K * nD + q, nD, K, xn, tmp);
+        }
+        if (dx_out) {
+          exp_put(dx_out + q, nD, K, dxr[q], tmp);
+          exp_put(dx_out + (size_t)K * nD + q, nD, K, dxi[q], tmp);
+        }
+      }
+    vfree(dxr, nD);
+    vfree(dxi, nD);
+    mpfr_clear(xn);
+  }
+  mpfr_clear(tmp);
+  vfree(br, nD);
+  vfree(bi, nD);
+  vfree(Ar, DA);
+  vfree(Ai, DA);
+  free_inputs(&S, Xr, Cr, Fr);
+  free_inputs(&S, Xi, Ci, Fi);
+  return rc;
+}
+
 /* Solve the block Toeplitz system for given A[L][D][n][n] (row-major) and
  * rhs[L][n][D]; dx[K][n][D].  Used for the standalone series solve. */
 int ora_toeplitz_solve(int prec_bits, int n, int D, int L, const double *A, const double *rhs, int K,

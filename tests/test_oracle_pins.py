@@ -658,3 +658,98 @@ def test_linear_residual_of_the_block_solve_vanishes():
     assert np.max(oracle.absdiff(r, np.zeros((1,) + r.shape[1:])) / sc) < 2.0 ** -(4 * 53 * L - 20)
     r2, _ = oracle.linear_residual(A, b, np.zeros_like(b))
     assert np.array_equal(exact(r2), exact(b))
+
+
+# --------------------------------------------------------------------------
+# 12. complex data (Section 5.2)
+# --------------------------------------------------------------------------
+
+def _cval(a, idx):
+    """Exact complex value of entry idx of a complex md array [2, L, ...]."""
+    return sympy.Rational(md_value(a[(0, slice(None)) + idx])) + sympy.I * sympy.Rational(md_value(a[(1, slice(None)) + idx]))
+
+
+def test_complex_step_brute_force_sympy():
+    """Exact complex rationals: b = -(c_0 + p(x)), A = p'(x) and one Newton step
+    by solving the full block system exactly."""
+    s = mdinputs.tiny(2, 2, 2, mons=2, kmin=1, kmax=2, exps=(1, 2), seed=8)
+    cff, cst, x = mdinputs.complex_random(s, 8)
+    t = sympy.Symbol("t")
+    n, D = s.n, s.D
+    X = sympy.symbols(f"y0:{n}")
+    xs = [sum(_cval(x, (i, k)) * t ** k for k in range(D)) for i in range(n)]
+    P = []
+    for i in range(n):
+        e = sum(_cval(cst, (i, k)) * t ** k for k in range(D))
+        for mj in range(s.poly_ptr[i], s.poly_ptr[i + 1]):
+            term = _cval(cff, (mj,))
+            for q in range(s.mon_ptr[mj], s.mon_ptr[mj + 1]):
+                term *= X[s.var[q]] ** int(s.exp[q])
+            e += term
+        P.append(e)
+    sub = dict(zip(X, xs))
+    trunc = lambda e: [sympy.expand(e).coeff(t, k) for k in range(D)]
+    b = [[-c for c in trunc(P[i].subs(sub))] for i in range(n)]
+    A = [[trunc(sympy.diff(P[i], X[j]).subs(sub)) for j in range(n)] for i in range(n)]
+    T = sympy.zeros(n * D, n * D)
+    rhs = sympy.zeros(n * D, 1)
+    for k in range(D):
+        for i in range(n):
+            rhs[k * n + i] = b[i][k]
+            for j in range(k + 1):
+                for v in range(n):
+                    T[k * n + i, j * n + v] = A[i][v][k - j]
+    sol = T.LUsolve(rhs)
+    out = oracle.complex_step(s, cff, cst, x, prec=700, K=16)
+    tol = Fraction(1, 2 ** 600)
+    close = lambda got_re, got_im, want: (abs(got_re - Fraction(str(sympy.re(want)))) <= tol * (1 + abs(got_re)) and
+                                          abs(got_im - Fraction(str(sympy.im(want)))) <= tol * (1 + abs(got_im)))
+    ebr, ebi = exact(out["b"][0]), exact(out["b"][1])
+    eAr, eAi = exact(out["A"][0]), exact(out["A"][1])
+    exr, exi = exact(out["x"][0]), exact(out["x"][1])
+    for i in range(n):
+        for k in range(D):
+            assert close(ebr[i, k], ebi[i, k], sympy.nsimplify(b[i][k]))
+            assert close(exr[i, k], exi[i, k], sympy.expand(_cval(x, (i, k)) + sol[k * n + i]))
+            for j in range(n):
+                assert close(eAr[k, i, j], eAi[k, i, j], sympy.expand(A[i][j][k]))
+
+
+def test_complex_real_case_and_conjugation():
+    """With zero imaginary parts the complex oracle is the real one: b and A
+    exactly (the same products), the step to the working bits (a complex
+    division z conj(u) / |u|^2 rounds otherwise than z / u), with exactly
+    zero imaginary outputs; conjugating every input conjugates every output
+    exactly."""
+    s = mdinputs.tiny(4, 4, 5, mons=3, kmin=1, kmax=3, exps=(1, 2), seed=9)
+    cff, cst, x = mdinputs.complex_random(s, 9)
+    real = oracle.newton_step(s, cff[0], cst[0], x[0], want_A=True)
+    z = lambda a: np.stack([a[0], np.zeros_like(a[0])])
+    c = oracle.complex_step(s, z(cff), z(cst), z(x))
+    for key in ("b", "A"):
+        assert np.array_equal(exact(c[key][0]), exact(real[key])) and not np.any(c[key][1])
+    for key in ("x", "dx"):
+        assert not np.any(c[key][1])
+        assert np.max(oracle.absdiff(c[key][0], real[key])) <= 2.0 ** -(4 * 53 * 4 - 40) * np.abs(real[key][0]).max()
+    conj = lambda a: np.stack([a[0], -a[1]])
+    o1 = oracle.complex_step(s, cff, cst, x)
+    o2 = oracle.complex_step(s, conj(cff), conj(cst), conj(x))
+    for key in ("b", "A", "x", "dx"):
+        assert np.array_equal(o2[key][0], o1[key][0]) and np.array_equal(o2[key][1], -o1[key][1])
+
+
+@pytest.mark.parametrize("cols", [1, 2])
+def test_complex_column_system_closed_form(cols):
+    """The complex column systems (|alpha| = 1, Section 3): the closed-form
+    right-hand side vanishes at x* to the rounding of the data, and Newton
+    from x*(0) reaches x* with exact data (error at the oracle's working
+    bits after log2(D) + 1 steps)."""
+    s = mdinputs.complex_column_system(6, 7, 4, cols, seed=2)
+    out = oracle.complex_step(s, s.cff, s.cst, s.xstar, step=False)
+    b = np.abs(out["b"][:, 0])
+    assert b.max() < 2.0 ** -200
+    x = s.start()
+    for _ in range(4):
+        x = oracle.complex_step(s, s.cff, s.cst, x)["x"]
+    err = max(oracle.absdiff(x[0], s.xstar[0]).max(), oracle.absdiff(x[1], s.xstar[1]).max())
+    assert err < 2.0 ** -200
