@@ -169,6 +169,47 @@ def _bench_staggered(mdn, torch, np, sysm, cst, xstar, repeats):
     return res
 
 
+def _bench_complex(mdn, torch, np, mdinputs, sysm):
+    """Complex data (Section 5.2) on the medium system's tables: the
+    evaluation with the 4M products side by side and the complex Newton step
+    (real form of dimension 2n), timed with HIP events; right-hand side
+    manufactured on the GPU at a complex x*."""
+    from paper_2301_12659_amd import work
+
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    cff, _, _ = mdinputs.complex_random(sysm, 70)
+    cff[:, :, sysm.boost] = np.stack([4.0 * sysm.cff[:, sysm.boost], np.zeros_like(sysm.cff[:, sysm.boost])])
+    xs = np.stack([sysm.xstar, 0.5 * mdinputs.random_series(np.random.default_rng(71), sysm.L, sysm.n, sysm.D,
+                                                              damping=mdinputs.DAMPING)])
+    drv = mdn.ComplexNewton(sysm, cff, np.zeros_like(xs), xs)
+    b, _ = drv.eval_diff()
+    drv.cst.copy_(b)
+    x0 = dev(np.concatenate([xs[..., :1], np.zeros_like(xs[..., 1:])], axis=-1))
+    res = {"workload": "medium_qd tables with complex coefficients and a complex x* (imaginary part damped like "
+                       "the real one, boost four times the real system's), seed 70"}
+    for name, fn, reps in (("evaluation", lambda: drv.eval_diff(), 20), ("newton_step", lambda: drv.step(), 10)):
+        drv.x.copy_(x0)
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        res[name + "_ms"] = round(e0.elapsed_time(e1) / reps, 4)
+    f = work.convolution_flops(sysm, sysm.D)["flops"] * 4  # four real products per complex one
+    res["evaluation_tflops"] = round(f / (res["evaluation_ms"] * 1e-3) / 1e12, 3)
+    drv.x.copy_(x0)
+    for _ in range(8):
+        drv.step()
+    xsd = dev(xs)
+    res["err_vs_manufactured_after_8_steps"] = max(_err_vs(mdn, torch, drv.x[0].contiguous(), xsd[0].contiguous()),
+                                                   _err_vs(mdn, torch, drv.x[1].contiguous(), xsd[1].contiguous()))
+    res["status"] = drv.status_code()
+    return res
+
+
 # The paper's printed figures for its own workloads (context only: other
 # hardware).  Table 5: seconds of 24 Newton steps on the V100, octo double,
 # n = 1024, order 64, one and two columns of monomials; Table 6: gigaflops of
@@ -446,6 +487,8 @@ def main():
         torch.cuda.synchronize()
         res_t[name + "_us"] = round(1000.0 * r0.elapsed_time(r1) / 20, 2)
     out["residual"] = res_t
+
+    out["complex"] = _bench_complex(mdn, torch, np, mdinputs, sysm)
 
     if args.stagger_repeats > 0:
         out["staggered"] = _bench_staggered(mdn, torch, np, sysm, drv.cst, xstar, args.stagger_repeats)

@@ -231,6 +231,27 @@ int md_linear_residual(int prec, int n, int d, const double *A, const double *b,
  * the step's linear system. */
 int md_step_arrays(const md_plan *plan, void *ws, size_t ws_bytes, double **b, double **A, double **dx);
 
+/* Complex data (Section 5.2).  Complex multiple-double arrays are
+ * [2][L][...]: the real plane, then the imaginary plane, each laid out as the
+ * real array (cff [2][L][m], cst and x [2][L][n][D], b [2][L][n][D], A
+ * [2][L][n][n][D]).  The evaluation forms the four real products of every
+ * complex convolution (the 4M method) side by side on the lanes of a worker.
+ * Exponents must be 1 or 2 (MD_EINVAL otherwise).  md_complex_workspace_size
+ * gives the bytes of ws for both calls.
+ *
+ * md_eval_diff_complex: b = -p(x) and A = p'(x) as md_eval_diff.
+ * md_newton_step_complex: one Newton step (Section 2) in place on x; the
+ * complex block Toeplitz system is solved through its real form of dimension
+ * 2n, [[Re A_k, -Im A_k], [Im A_k, Re A_k]], by the real QR and staged solve
+ * (2n <= MD_MAX_DIM); *dev_status as md_newton_step; dev_norms [2][D]
+ * (nullable): the larger of the real and imaginary parts' max |b_k| and
+ * max |dx_k|. */
+int md_complex_workspace_size(const md_plan *plan, size_t *bytes);
+int md_eval_diff_complex(const md_plan *plan, const double *cff, const double *cst, const double *x, double *b,
+                         double *A, void *ws, size_t ws_bytes, hipStream_t stream);
+int md_newton_step_complex(const md_plan *plan, const double *cff, const double *cst, double *x, int32_t *dev_status,
+                           double *dev_norms, void *ws, size_t ws_bytes, hipStream_t stream);
+
 /* Batches of independent systems ("paths"; the paper tracks many solution
  * paths of a homotopy, Section 1), one Newton step of every path per call,
  * in one persistent launch.  A path p has n_p (1..128) variables and

@@ -60,6 +60,9 @@ _lib.md_newton_staggered.argtypes = [_vp, _i32, _i32, _i32, ctypes.c_double, _vp
 _lib.md_linear_residual.argtypes = [_i32, _i32, _i32, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _vp]
 _lib.md_step_arrays.argtypes = [_vp, _vp, ctypes.c_size_t, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
                                 ctypes.POINTER(_vp)]
+_lib.md_complex_workspace_size.argtypes = [_vp, _szp]
+_lib.md_eval_diff_complex.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
+_lib.md_newton_step_complex.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
 _lib.md_arith.argtypes = [_i32, _i32, ctypes.c_int64, _vp, _vp, _vp, _vp]
 _lib.md_last_error.restype = ctypes.c_char_p
 _lib.md_adjoint_workspace_size.argtypes = [_i32, _i32, _i32, _szp]
@@ -348,6 +351,32 @@ def step_arrays(plan: Plan, ws):
     return int(b.value), int(A.value), int(dx.value)
 
 
+def complex_workspace_bytes(plan: Plan):
+    v = ctypes.c_size_t()
+    _check(_lib.md_complex_workspace_size(plan._h, ctypes.byref(v)), "md_complex_workspace_size")
+    return int(v.value)
+
+
+def eval_diff_complex(plan: Plan, cff, cst, x, b, A, ws, stream=None):
+    """md_eval_diff_complex: complex arrays [2, L, ...] (real plane, imaginary plane)."""
+    L, n, D, m = plan.prec, plan.n, plan.D, plan.m
+    rc = _lib.md_eval_diff_complex(plan._h, _ptr(cff, (2, L, m), "cff"), _ptr(cst, (2, L, n, D), "cst"),
+                                   _ptr(x, (2, L, n, D), "x"), _ptr(b, (2, L, n, D), "b"),
+                                   _ptr(A, (2, L, n, n, D), "A"), _ptr(ws, None, "ws"), ws.numel() * 8,
+                                   _stream(stream))
+    _check(rc, "md_eval_diff_complex")
+
+
+def newton_step_complex(plan: Plan, cff, cst, x, status, norms, ws, stream=None):
+    """md_newton_step_complex: one Newton step on complex data, x [2, L, n, D] in place."""
+    L, n, D, m = plan.prec, plan.n, plan.D, plan.m
+    rc = _lib.md_newton_step_complex(plan._h, _ptr(cff, (2, L, m), "cff"), _ptr(cst, (2, L, n, D), "cst"),
+                                     _ptr(x, (2, L, n, D), "x"), _ptr(status, (1,), "status"),
+                                     _ptr(norms, (2, D), "norms"), _ptr(ws, None, "ws"), ws.numel() * 8,
+                                     _stream(stream))
+    _check(rc, "md_newton_step_complex")
+
+
 def stagger_next_order(d, D):
     """The order after d in the staggered schedule, d + 1 + d // 2, capped at D."""
     return int(_lib.md_stagger_next_order(int(d), int(D)))
@@ -488,6 +517,38 @@ class Newton:
         norm1 = torch.empty(D, dtype=torch.float64, device=self.x.device)
         linear_residual(L, n, D - 1, A, b, dx, r, rows=rws, norm1=norm1, status=self.status, stream=stream)
         return r, norm1
+
+    def status_code(self):
+        return int(self.status.item())
+
+
+class ComplexNewton:
+    """Device copies of a system with complex data (cff [2, L, m], cst and x
+    [2, L, n, D]) and its workspace; md_newton_step_complex in place."""
+
+    def __init__(self, sys, cff, cst, x0, device="cuda"):
+        import torch
+
+        self.sys = sys
+        self.plan = Plan.from_system(sys)
+        t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=device)
+        self.cff, self.cst, self.x = t(cff), t(cst), t(x0)
+        self.ws = workspace(complex_workspace_bytes(self.plan), device)
+        self.status = torch.zeros(1, dtype=torch.int32, device=device)
+        self.norms = torch.zeros((2, sys.D), dtype=torch.float64, device=device)
+
+    def step(self, stream=None):
+        newton_step_complex(self.plan, self.cff, self.cst, self.x, self.status, self.norms, self.ws, stream)
+
+    def eval_diff(self, x=None, stream=None):
+        """(b, A) at x (default: the current iterate)."""
+        import torch
+
+        L, n, D = self.plan.prec, self.plan.n, self.plan.D
+        b = torch.empty((2, L, n, D), dtype=torch.float64, device=self.x.device)
+        A = torch.empty((2, L, n, n, D), dtype=torch.float64, device=self.x.device)
+        eval_diff_complex(self.plan, self.cff, self.cst, self.x if x is None else x, b, A, self.ws, stream)
+        return b, A
 
     def status_code(self):
         return int(self.status.item())

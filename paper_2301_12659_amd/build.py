@@ -28,7 +28,7 @@ FLAGS = [
     "-Wno-unused-command-line-argument",
 ]
 
-SOURCES = ["evaldiff.hip", "assemble.hip", "linalg.hip", "residual.hip", "api.hip", "batch.hip"]
+SOURCES = ["evaldiff.hip", "assemble.hip", "linalg.hip", "residual.hip", "complex.hip", "api.hip", "batch.hip"]
 
 
 def _compile(src: str) -> str:

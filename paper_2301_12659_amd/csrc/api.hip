@@ -654,6 +654,127 @@ int md_step_arrays(const md_plan *p, void *ws, size_t ws_bytes, double **b, doub
   return MD_OK;
 }
 
+// Workspace of the complex step: complex monomial values and derivative
+// series, b and A, the real form of the block system (2n) with its QR and the
+// real staged-solve workspace, dx, and the norms of the imaginary parts.
+struct CLayout {
+  size_t val, der, b, A, At, bt, a0, tau, qrs, solve, dx, nt, total;
+};
+
+static CLayout complex_layout(const md_plan *p) {
+  const size_t L = p->L, n = p->n, D = p->D, N = 2 * n;
+  CLayout w{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += align_up(bytes);
+    return o;
+  };
+  const size_t d8 = sizeof(double);
+  w.val = take(2 * L * p->m * D * d8 + d8);
+  w.der = take(2 * L * p->nnz * D * d8 + d8);
+  w.b = take(2 * L * n * D * d8);
+  w.A = take(2 * L * n * n * D * d8);
+  w.At = take(L * N * N * D * d8);
+  w.bt = take(L * N * D * d8);
+  w.a0 = take(L * N * N * d8);
+  w.tau = take(L * N * d8);
+  w.qrs = take(qr_scratch_bytes((int)L, (int)N));
+  w.solve = take(solve_bytes((int)L, (int)N, (int)D));
+  w.dx = take(2 * L * n * D * d8);
+  w.nt = take(2 * D * d8);
+  w.total = off;
+  return w;
+}
+
+static int complex_eval_impl(const md_plan *p, const double *cff, const double *cst, const double *x, double *b,
+                             double *A, void *ws, hipStream_t st) {
+  const CLayout w = complex_layout(p);
+  const size_t L = p->L, n = p->n, D = p->D;
+  mdk::EvalArgs a;
+  a.n = p->n;
+  a.D = p->D;
+  a.Dc = p->D;
+  a.m = p->m;
+  a.nnz = p->nnz;
+  a.mon_ptr = p->d_mon_ptr;
+  a.var = p->d_var;
+  a.exp = p->d_exp;
+  a.order = p->d_order;
+  a.cff = cff;
+  a.x = x;
+  a.pw = x;  // not read: exponents are at most 2
+  a.val = at(ws, w.val);
+  a.der = at(ws, w.der);
+  hipError_t e;
+  {
+    Timed t(MD_CLASS_CONVOLUTIONS, st);
+    if ((e = mdk::launch_evaldiff_complex(p->L, a, st)) != hipSuccess) return hip_fail(e, "complex evaluation");
+  }
+  {
+    Timed t(MD_CLASS_ASSEMBLY, st);
+    const size_t nD = n * D, nnD = n * n * D, mD = (size_t)p->m * D, zD = (size_t)p->nnz * D;
+    for (int part = 0; part < 2; ++part)
+      if ((e = mdk::launch_assemble(p->L, p->n, p->D, p->D, p->m, p->nnz, p->d_poly_ptr, p->d_asm_ptr, p->d_asm_ent,
+                                    cst + part * L * nD, a.val + part * L * mD, a.der + part * L * zD,
+                                    b + part * L * nD, A + part * L * nnD, st)) != hipSuccess)
+        return hip_fail(e, "complex assembly");
+  }
+  return MD_OK;
+}
+
+int md_complex_workspace_size(const md_plan *p, size_t *bytes) {
+  if (!p || !bytes) return fail(MD_EINVAL, "NULL argument");
+  *bytes = complex_layout(p).total;
+  return MD_OK;
+}
+
+int md_eval_diff_complex(const md_plan *p, const double *cff, const double *cst, const double *x, double *b,
+                         double *A, void *ws, size_t ws_bytes, hipStream_t st) {
+  if (!p || !cst || !x || !b || !A || (p->m > 0 && !cff)) return fail(MD_EINVAL, "NULL argument");
+  if (p->maxexp > 2) return fail(MD_EINVAL, "complex data: exponents must be 1 or 2");
+  if (!ws || ws_bytes < complex_layout(p).total) return fail(MD_ENOSPACE, "workspace too small");
+  return complex_eval_impl(p, cff, cst, x, b, A, ws, st);
+}
+
+int md_newton_step_complex(const md_plan *p, const double *cff, const double *cst, double *x, int32_t *dev_status,
+                           double *dev_norms, void *ws, size_t ws_bytes, hipStream_t st) {
+  if (!p || !cst || !x || (p->m > 0 && !cff)) return fail(MD_EINVAL, "NULL argument");
+  if (p->maxexp > 2) return fail(MD_EINVAL, "complex data: exponents must be 1 or 2");
+  if (2 * p->n > MD_MAX_DIM) return fail(MD_EINVAL, "complex data: 2n must be at most MD_MAX_DIM");
+  const CLayout w = complex_layout(p);
+  if (!ws || ws_bytes < w.total) return fail(MD_ENOSPACE, "workspace too small");
+  const int L = p->L, n = p->n, D = p->D, N = 2 * n;
+  const size_t nD = (size_t)n * D;
+  hipError_t e;
+  if ((e = mdk::launch_status_init(dev_status, st)) != hipSuccess) return hip_fail(e, "status");
+  double *b = at(ws, w.b), *A = at(ws, w.A), *At = at(ws, w.At), *bt = at(ws, w.bt), *a0 = at(ws, w.a0);
+  double *tau = at(ws, w.tau), *dx = at(ws, w.dx);
+  int rc = complex_eval_impl(p, cff, cst, x, b, A, ws, st);
+  if (rc != MD_OK) return rc;
+  {
+    Timed t(MD_CLASS_UPDATES, st);
+    if ((e = mdk::launch_complex_embed(L, n, D, A, b, At, bt, st)) != hipSuccess) return hip_fail(e, "real form");
+    if ((e = mdk::launch_extract(L, N, D, 0, At, a0, st)) != hipSuccess) return hip_fail(e, "A_0");
+  }
+  {
+    Timed t(MD_CLASS_QR, st);
+    if ((e = run_qr(L, N, a0, tau, nullptr, dev_status, at(ws, w.qrs), st)) != hipSuccess) return hip_fail(e, "qr");
+  }
+  if ((rc = series_solve_impl(L, N, D, a0, tau, At, bt, at(ws, w.solve), st, dev_status)) != MD_OK) return rc;
+  {
+    Timed t(MD_CLASS_X_UPDATE, st);
+    if ((e = mdk::launch_complex_unpack(L, n, D, bt, dx, st)) != hipSuccess) return hip_fail(e, "dx");
+    double *nt = dev_norms ? at(ws, w.nt) : nullptr;
+    if ((e = mdk::launch_update(L, n, D, 0, D, b, dx, x, dev_norms, dev_status, st)) != hipSuccess ||
+        (e = mdk::launch_update(L, n, D, 0, D, b + (size_t)L * nD, dx + (size_t)L * nD, x + (size_t)L * nD, nt,
+                                dev_status, st)) != hipSuccess)
+      return hip_fail(e, "update");
+    if (dev_norms && (e = mdk::launch_max(2 * D, nt, dev_norms, st)) != hipSuccess) return hip_fail(e, "norms");
+  }
+  return MD_OK;
+}
+
 int md_adjoint_workspace_size(int prec, int n, int d, size_t *bytes) {
   if (!bytes || !valid_prec(prec) || n < 1 || n > MD_MAX_DIM || d < 0 || d + 1 > MD_MAX_COEFFS)
     return fail(MD_EINVAL, "bad argument");

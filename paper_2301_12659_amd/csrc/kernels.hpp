@@ -86,6 +86,15 @@ hipError_t launch_coef_grad(int L, int n, int D, int m, const int32_t *row_of, c
 hipError_t launch_unit_md(int L, int m, double *c, hipStream_t st);
 hipError_t launch_dot(int L, int64_t count, const double *a, const double *b, double *c, hipStream_t st);
 
+// complex.hip: complex arrays [2][L][...] (real plane, imaginary plane).
+hipError_t launch_evaldiff_complex(int L, const EvalArgs &a, hipStream_t st);
+// At [L][2n][2n][D] = [[Re A, -Im A], [Im A, Re A]], bt [L][2n][D] = [Re b; Im b].
+hipError_t launch_complex_embed(int L, int n, int D, const double *A, const double *b, double *At, double *bt,
+                                hipStream_t st);
+// dx [2][L][n][D] from dxt [L][2n][D].
+hipError_t launch_complex_unpack(int L, int n, int D, const double *dxt, double *dx, hipStream_t st);
+hipError_t launch_max(int count, const double *b, double *a, hipStream_t st);
+
 // residual.hip: r [L][nrows][D] = b - T dx on rows (NULL: all), norm1 [D] (nullable).
 hipError_t launch_residual(int L, int n, int D, int nrows, const int32_t *rows, const double *A, const double *b,
                            const double *dx, double *r, double *norm1, int32_t *status, hipStream_t st);
