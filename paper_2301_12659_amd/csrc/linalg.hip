@@ -857,7 +857,7 @@ template <int L>
 __global__ void __launch_bounds__(256) stages_persistent_kernel(int n, int D, int Gs, int Gm, const double *M,
                                                                 const double *NP, const double *At, double *rT,
                                                                 double *dxT, int *sync, int32_t *status) {
-  __shared__ int sh_ok;
+  __shared__ int sh_ok, sh_dead;  // sh_dead: a solver wavefront's wait timed out
   __shared__ double xq[L * 64];  // dx_q of an updater round
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const size_t nn = (size_t)n * n, nD = (size_t)n * D, nnD = nn * D;
@@ -909,28 +909,46 @@ __global__ void __launch_bounds__(256) stages_persistent_kernel(int n, int D, in
       md::neg<L>(nv, nv);
       md::neg<L>(pv, pv);
     }
-    double x1[L], x2[L];  // dx_{k-1}(v), dx_{k-2}(v)
+    // wavefront-wide wait until the updaters have finished round target of
+    // coefficient mm (all lanes poll the same counter)
+    auto wait_rounds = [&](int mm, int target) {
+      long spins = 0;
+      while (true) {
+        const int f = poll(rounds(mm));
+        if (__all(f >= target)) break;
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > (1L << 22)) {
+          if (lane == 0) set_status(status, MD_EHIP);
+          return false;
+        }
+      }
+      return true;
+    };
+    // Only N dx_{k-1} waits for the previous stage: M r'_k (final once the
+    // updaters have applied every dx_q, q <= k - 3) and P dx_{k-2} are
+    // accumulated into the lane's level sums while the solvers wait for each
+    // other, so a stage's critical path holds one multiply-add per lane.
+    if (tid == 0) sh_dead = 0;
+    double pre[L], x1[L];  // the terms of the coming stage known in advance; dx_{k-1}(v)
+    md::zero<L>(pre);
     md::zero<L>(x1);
-    md::zero<L>(x2);
+    if (col) {
+      double a[L];
+      ld_agent<L>(rT, nD, (size_t)v, a);
+      MD<L>::fma_lazy(pre, m, a);
+    }
     for (int k = 0; k < D; ++k) {
       if (wv == 0) {
-        bool ok = (k >= 1) ? wait_solvers(k) : true;
-        if (lane == 0) {
-          if (ok && k >= 3) ok = wait_one(rounds(k), Bm * (k - 2), 0);
-          sh_ok = ok ? 1 : 0;
-        }
+        const bool ok = (k >= 1) ? wait_solvers(k) : true;
+        if (lane == 0) sh_ok = (ok && !sh_dead) ? 1 : 0;
       }
       __syncthreads();
       if (!sh_ok) return;
-      double acc[L], r[L], a[L];
-      md::zero<L>(acc);
-      if (col) {
-        md::copy<L>(x1, x2);
-        if (k >= 1) ld_agent<L>(dxT, nD, (size_t)(k - 1) * n + v, x1);
-        ld_agent<L>(rT, nD, (size_t)k * n + v, a);
-        MD<L>::fma_lazy(acc, m, a);
-        if (k >= 1) MD<L>::fma_lazy(acc, nv, x1);
-        if (k >= 2) MD<L>::fma_lazy(acc, pv, x2);
+      double acc[L], r[L];
+      md::copy<L>(pre, acc);
+      if (col && k >= 1) {
+        ld_agent<L>(dxT, nD, (size_t)(k - 1) * n + v, x1);
+        MD<L>::fma_lazy(acc, nv, x1);
       }
       team_sum_lazy<L>(acc, 64);
       MD<L>::renorm(acc, r);
@@ -938,6 +956,16 @@ __global__ void __launch_bounds__(256) stages_persistent_kernel(int n, int D, in
       wait_vm();
       __syncthreads();
       if (tid == 64) __hip_atomic_store(solved(blockIdx.x), k + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (k + 1 < D) {  // M r'_{k+1} + P dx_{k-1}
+        if (k + 1 >= 3 && !wait_rounds(k + 1, Bm * (k - 1)) && lane == 0) sh_dead = 1;
+        md::zero<L>(pre);
+        if (col) {
+          double a[L];
+          ld_agent<L>(rT, nD, (size_t)(k + 1) * n + v, a);
+          MD<L>::fma_lazy(pre, m, a);
+          if (k >= 1) MD<L>::fma_lazy(pre, pv, x1);
+        }
+      }
     }
     return;
   }
