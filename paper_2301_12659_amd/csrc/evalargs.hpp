@@ -13,6 +13,7 @@ struct EvalArgs {
   int values_only = 0;         // 1: monomial values only (no backward or cross products, der untouched)
   size_t x_ls = 0, cff_ls = 0; // limb strides of x and cff when not n D and m (packed batches)
   double *vsize = nullptr;     // [m][D], nullable: max_j |f_j| over each monomial's forward chain (leading limbs)
+  int beside_qr = 0;           // 1: runs beside the QR (one wavefront per monomial, more issue slots for the QR)
 };
 
 }  // namespace mdk

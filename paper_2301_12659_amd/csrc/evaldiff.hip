@@ -30,6 +30,160 @@
 
 namespace mdk {
 
+// Two wavefronts per monomial when a worker fills a wavefront (worker width
+// 64: orders 33 and up).  Wavefront B forms the backward chain while
+// wavefront A forms the common factor; then at every forward step A forms
+// f_j = f_{j-1} * x_{v_j} while B forms the cross product f_{j-1} * b_{k-j}
+// of the same f_{j-1}, so the chain of dependent products shortens from
+// 3k - 5 to about 2k - 2 and every monomial has two wavefronts to interleave.
+// One workgroup of 128 threads per monomial, a workgroup barrier per step;
+// the products are the single-wavefront routines of eval_monomial.
+template <int L>
+__device__ void eval_monomial_pair(const EvalArgs &a, int mono, double *buf0) {
+  const int D = a.D, Dc = a.Dc, Dp = Dc + 1, G = 64;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const bool isA = tid < 64;
+  for (int q = tid; q < 6 * L; q += 128) buf0[(size_t)q * Dp + Dc] = 0.0;
+  const int e0 = a.mon_ptr[mono], k = a.mon_ptr[mono + 1] - e0;
+  const size_t nD = (size_t)a.n * D, mD = (size_t)a.m * D, zD = (size_t)a.nnz * D;
+  const size_t xls = a.x_ls ? a.x_ls : nD;
+  double c[L];
+  ld<L>(a.cff, a.cff_ls ? a.cff_ls : (size_t)a.m, mono, c);
+  if (k == 0) {  // constant monomial (the whole workgroup leaves)
+    if (isA)
+      for (int s = lane; s < Dc; s += G) {
+#pragma unroll
+        for (int l = 0; l < L; ++l) a.val[(size_t)l * mD + (size_t)mono * D + s] = (s == 0) ? c[l] : 0.0;
+        if (a.vsize) a.vsize[(size_t)mono * D + s] = (s == 0) ? fabs(c[0]) : 0.0;
+      }
+    return;
+  }
+  auto xoff = [&](int v) { return (size_t)v * D; };
+  auto der_off = [&](int j) { return (size_t)(e0 + j) * D; };
+  const bool derivs = a.values_only == 0;
+  double *U = buf0, *V = buf0 + (size_t)L * Dp, *W = buf0 + 2 * (size_t)L * Dp;  // A's buffers
+  double *Bq = buf0 + 3 * (size_t)L * Dp, *Xq = buf0 + 4 * (size_t)L * Dp, *Wq = buf0 + 5 * (size_t)L * Dp;  // B's
+  bool f0_scalar = true;
+  for (int j = 0; j < k; ++j) f0_scalar = f0_scalar && a.exp[e0 + j] < 2;
+  __syncthreads();
+  if (!isA) {
+    // backward chain: b_1 = x_{v_k}, b_q = b_{q-1} * x_{v_{k-q+1}}, parked in the slot of entry k - q - 1
+    if (derivs && k >= 3) {
+      double *B = Bq, *X = Xq, *Wb = Wq;
+      load_series(B, a.x, xls, xoff(a.var[e0 + k - 1]), L, Dc, lane, G);
+      for (int q = 2; q <= k - 1; ++q) {
+        load_series(X, a.x, xls, xoff(a.var[e0 + k - q]), L, Dc, lane, G);
+        wave_sync();
+        conv<L>(B, X, Wb, Dc, lane, 1);
+        wave_sync();
+        store_series(a.der, zD, der_off(k - q - 1), Wb, L, Dc, lane, G);
+        double *t = B;
+        B = Wb;
+        Wb = t;
+        wave_sync();
+      }
+    }
+  } else if (!f0_scalar) {
+    // common factor and f_0 = c * CF
+    bool first = true;
+    for (int j = 0; j < k; ++j) {
+      const int p = a.exp[e0 + j] - 1;
+      if (p < 1) continue;
+      const int v = a.var[e0 + j];
+      const double *src = (p == 1) ? a.x : a.pw + (size_t)(p - 2) * L * nD;
+      const size_t sls = (p == 1) ? xls : nD;
+      if (first) {
+        load_series(U, src, sls, xoff(v), L, Dc, lane, G);
+        first = false;
+        wave_sync();
+      } else {
+        load_series(V, src, sls, xoff(v), L, Dc, lane, G);
+        wave_sync();
+        conv<L>(U, V, W, Dc, lane, 1);
+        wave_sync();
+        double *t = U;
+        U = W;
+        W = t;
+      }
+    }
+    scal<L>(c, U, U, Dc, lane, G, 1);
+    wave_sync();
+  }
+  // A's buffer rotation above happened in A only: share the result's place
+  __shared__ int sh_u;
+  if (tid == 0) sh_u = (int)((U - buf0) / ((size_t)L * Dp));
+  __syncthreads();
+  U = buf0 + (size_t)sh_u * L * Dp;
+  V = buf0 + (size_t)((sh_u + 1) % 3) * L * Dp;
+  W = buf0 + (size_t)((sh_u + 2) % 3) * L * Dp;
+  const bool track = a.vsize != nullptr;
+  double vmax[2] = {0.0, 0.0};
+  auto track_max = [&](const double *F, bool scalar) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int s = lane + q * G;
+      if (s < Dc) vmax[q] = fmax(vmax[q], scalar ? (s == 0 ? fabs(c[0]) : 0.0) : fabs(F[s]));
+    }
+  };
+  if (track && isA) track_max(U, f0_scalar);
+  // forward chain (A) beside the cross products (B)
+  for (int j = 1; j <= k; ++j) {
+    const int ej = j - 1;
+    const int aj = a.exp[e0 + ej];
+    if (isA) {
+      load_series(V, a.x, xls, xoff(a.var[e0 + ej]), L, Dc, lane, G);
+      wave_sync();
+      if (f0_scalar && j == 1)
+        scal<L>(c, V, W, Dc, lane, G, 1);
+      else
+        conv<L>(U, V, W, Dc, lane, 1);
+    } else if (derivs) {
+      if (j < k) {
+        if (k - j == 1)
+          load_series(Xq, a.x, xls, xoff(a.var[e0 + k - 1]), L, Dc, lane, G);  // b_1 = x_{v_k}
+        else
+          load_series(Xq, a.der, zD, der_off(ej), L, Dc, lane, G);  // b_{k-j}
+        wave_sync();
+        if (f0_scalar && j == 1)
+          scal<L>(c, Xq, Wq, Dc, lane, G, aj);
+        else
+          conv<L>(U, Xq, Wq, Dc, lane, aj);
+        wave_sync();
+        store_series(a.der, zD, der_off(ej), Wq, L, Dc, lane, G);
+      } else {  // d/dx_{v_k} = a_k f_{k-1}
+        for (int s = lane; s < Dc; s += G) {
+          double r[L];
+#pragma unroll
+          for (int l = 0; l < L; ++l) r[l] = (f0_scalar && j == 1) ? ((s == 0) ? c[l] : 0.0) : U[l * Dp + s];
+          md::mul_int<L>(r, aj);
+#pragma unroll
+          for (int l = 0; l < L; ++l) a.der[(size_t)l * zD + der_off(ej) + s] = r[l];
+        }
+      }
+    }
+    __syncthreads();  // f_{j-1} read by both, f_j complete
+    double *t = U;
+    U = W;
+    W = t;
+    if (track && isA) track_max(U, false);
+  }
+  if (isA) {
+    store_series(a.val, mD, (size_t)mono * D, U, L, Dc, lane, G);
+    if (track)
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int s = lane + q * G;
+        if (s < Dc) a.vsize[(size_t)mono * D + s] = vmax[q];
+      }
+  }
+}
+
+template <int L>
+__global__ void __launch_bounds__(128) evaldiff_pair_kernel(EvalArgs a) {
+  extern __shared__ double lds[];
+  eval_monomial_pair<L>(a, a.order[blockIdx.x], lds);
+}
+
 template <int L>
 __global__ void __launch_bounds__(256, (L == 8) ? 1 : 2) evaldiff_kernel(EvalArgs a) {
   extern __shared__ double lds[];
@@ -165,8 +319,13 @@ hipError_t launch_evaldiff_T(const EvalArgs &a, int maxexp, double *pw_mut, hipS
     hipLaunchKernelGGL(power_kernel<L>, dim3(blocks), dim3(256), lds, st, a.n, a.D, a.Dc, maxexp - 1, a.x, pw_mut);
   }
   if (a.m > 0) {
-    const int blocks = (a.m + wpb - 1) / wpb;
-    hipLaunchKernelGGL(evaldiff_kernel<L>, dim3(blocks), dim3(256), lds, st, a);
+    if (G == 64 && !a.beside_qr) {  // two wavefronts per monomial
+      hipLaunchKernelGGL(evaldiff_pair_kernel<L>, dim3(a.m), dim3(128), (size_t)6 * L * (a.Dc + 1) * sizeof(double),
+                         st, a);
+    } else {
+      const int blocks = (a.m + wpb - 1) / wpb;
+      hipLaunchKernelGGL(evaldiff_kernel<L>, dim3(blocks), dim3(256), lds, st, a);
+    }
   }
   return hipGetLastError();
 }
@@ -180,7 +339,7 @@ hipError_t launch_evaldiff(int L, const EvalArgs &a, int maxexp, double *pw, hip
   return hipErrorInvalidValue;
 }
 
-int evaldiff_workers_per_block(int D) { return 256 / worker_lanes(D); }
+int evaldiff_workers_per_block(int D) { return worker_lanes(D) == 64 ? 1 : 256 / worker_lanes(D); }
 
 size_t evaldiff_lds_bytes(int L, int D) {
   const int G = worker_lanes(D);
