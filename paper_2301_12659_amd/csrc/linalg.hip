@@ -33,12 +33,13 @@ __global__ void status_init_kernel(int32_t *status) {
 // Householder reflector of a column with squared norm nrm2 and leading entry
 // x0: beta = -sign(x0) ||x|| (sign(0) = +1), v = x / (x0 - beta) with v_0 = 1,
 // tau = (beta - x0) / beta.  Division-free: y = 1/||x|| and 1/(x0 - beta) by
-// the Newton steps above.
+// the shortened Newton doublings (the reflector is on the chain of every
+// column of the factorization).
 template <int L>
 __device__ void reflector(const double (&nrm2)[L], const double (&x0)[L], double (&beta)[L], double (&tau)[L],
                           double (&inv)[L]) {
   double y[L];
-  md::rsqrt_newton<L>(nrm2, y);
+  md::rsqrt_short<L>(nrm2, y);
   double alpha[L], v0[L];
   MD<L>::mul(nrm2, y, alpha);  // ||x||
   const bool nonneg = x0[0] >= 0.0;
@@ -47,7 +48,7 @@ __device__ void reflector(const double (&nrm2)[L], const double (&x0)[L], double
   MD<L>::sub(x0, beta, v0);
   MD<L>::mul(v0, y, tau);      // tau = -v0 / beta and 1/beta = -+ y
   if (!nonneg) md::neg<L>(tau, tau);
-  md::recip_newton<L>(v0, inv);
+  md::recip_short<L>(v0, inv);
 }
 
 // Unblocked Householder QR in one workgroup of 1024 threads; a [L][n][n]
@@ -623,15 +624,23 @@ __global__ void __launch_bounds__(64, 1) m_from_qt_kernel(int n, const double *q
   }
 }
 
+// Lane i's double in every lane (i uniform over the wavefront).
+__device__ __forceinline__ double read_lane(double x, int i) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)b, i);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), i);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
 // Column c of M = R^{-1} Q^T for n <= 64, one wavefront per column with
 // row p in lane p.  The reciprocals 1/R_ii are formed here (lane i; the
 // singularity test of invdiag_kernel, reported by workgroup 0) and kept in
-// LDS, and the column R(., i-1) of the next step is loaded while step i
-// computes, so that no step waits for device memory.
+// the lane's registers, the column R(., i-1) of the next step is loaded while
+// step i computes, so that no step waits for device memory, and z_i reaches
+// the other lanes by lane reads (no LDS round trip on the chain).
 template <int L>
 __global__ void __launch_bounds__(64, 1) m_from_qt_small_kernel(int n, const double *qr, const double *qt, double *M,
                                                              int32_t *status) {
-  __shared__ double dinv[L * 64], zs[L];
   const int c = blockIdx.x, lane = threadIdx.x;
   const size_t nn = (size_t)n * n;
   const bool on = lane < n;
@@ -640,48 +649,29 @@ __global__ void __launch_bounds__(64, 1) m_from_qt_small_kernel(int n, const dou
   ld<L>(qr, nn, (size_t)p * n + p, rpp);
   double rmax = on ? fabs(rpp[0]) : 0.0;
   for (int off = 32; off > 0; off >>= 1) rmax = fmax(rmax, __shfl_xor(rmax, off, 64));
+  double dq[L];  // 1 / R_pp in lane p
   {
-    double q[L], one[L];
-    md::zero<L>(one);
-    one[0] = 1.0;
     const bool sing = on && !(fabs(rpp[0]) > ldexp((double)n, -53 * L) * rmax);
-    if (sing || !on) {
-      md::zero<L>(q);
-    } else {
-      md::recip_newton<L>(rpp, q);
-    }
+    if (sing || !on) md::zero<L>(dq);
+    else md::recip_newton<L>(rpp, dq);
     if (sing && c == 0) set_status(status, MD_ESINGULAR);
-#pragma unroll
-    for (int l = 0; l < L; ++l) dinv[l * 64 + lane] = q[l];
   }
   double y[L], rn[L];
   md::zero<L>(y);
   if (on) ld<L>(qt, nn, (size_t)p * n + c, y);
   md::zero<L>(rn);
   if (lane < n - 1) ld<L>(qr, nn, (size_t)p * n + (n - 1), rn);  // R(p, n-1), p < n-1
-  wave_sync();
   for (int i = n - 1; i >= 0; --i) {
     double rc[L];
     md::copy<L>(rn, rc);
     md::zero<L>(rn);
     if (i >= 1 && lane < i - 1) ld<L>(qr, nn, (size_t)p * n + (i - 1), rn);  // next column, rows above its diagonal
-    if (lane == i) {
-      double d[L], z[L];
+    double zl[L], z[L];
+    MD<L>::mul(y, dq, zl);  // meaningful in lane i
 #pragma unroll
-      for (int l = 0; l < L; ++l) d[l] = dinv[l * 64 + i];
-      MD<L>::mul(y, d, z);
-      md::copy<L>(z, y);
-#pragma unroll
-      for (int l = 0; l < L; ++l) zs[l] = z[l];
-    }
-    wave_sync();
-    if (lane < i) {
-      double z[L];
-#pragma unroll
-      for (int l = 0; l < L; ++l) z[l] = zs[l];
-      MD<L>::fms(y, rc, z);
-    }
-    wave_sync();
+    for (int l = 0; l < L; ++l) z[l] = read_lane(zl[l], i);
+    if (lane == i) md::copy<L>(z, y);
+    else if (lane < i) MD<L>::fms(y, rc, z);
   }
   if (on) st<L>(M, nn, (size_t)p * n + c, y);
 }

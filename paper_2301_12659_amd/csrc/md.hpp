@@ -209,4 +209,35 @@ MD_INLINE void recip_newton(const double (&v)[L], double (&r)[L]) {
   recip_step<L, L, 1>(v, r);
 }
 
+// The same doublings with every correction at full width and no repair
+// step, for double and quad doubles: the residual is never truncated, so a
+// zero limb inside it costs nothing, and the last doubling leaves a relative
+// error of about 2^(-53 L + 6) instead of a few units in the last limb, for
+// one full-precision step less.  Used where the result is on a chain of
+// dependent operations (the reflector of a Householder step).  Octo doubles
+// keep the full sequence (a shortened one would stop near 2^(-412)).
+template <int L>
+MD_INLINE void rsqrt_short(const double (&a)[L], double (&y)[L]) {
+  if constexpr (L >= 8) {
+    rsqrt_newton<L>(a, y);
+  } else {
+    zero<L>(y);
+    y[0] = 1.0 / ::sqrt(a[0]);
+    rsqrt_step<L, 2, (L == 2 ? 2 : 1)>(a, y);
+    if constexpr (L == 4) rsqrt_step<L, 4, 4>(a, y);
+  }
+}
+
+template <int L>
+MD_INLINE void recip_short(const double (&v)[L], double (&r)[L]) {
+  if constexpr (L >= 8) {
+    recip_newton<L>(v, r);
+  } else {
+    zero<L>(r);
+    r[0] = 1.0 / v[0];
+    recip_step<L, 2, (L == 2 ? 2 : 1)>(v, r);
+    if constexpr (L == 4) recip_step<L, 4, 4>(v, r);
+  }
+}
+
 }  // namespace md
