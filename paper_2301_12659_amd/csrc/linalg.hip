@@ -251,11 +251,11 @@ __device__ __forceinline__ int red_width(int rows) {
 // (the status word then holds MD_EHIP and the caller's result is garbage).
 // The flag is polled with relaxed loads and a short sleep (an acquire load
 // would invalidate the caches on every poll, and a busy loop takes issue
-// slots from the waves sharing the CU); one acquire fence follows.  (Here a
-// release fence on the writer's side and an acquire fence on the reader's
-// are cheaper than agent-scope accesses to the board: only a few
-// workgroups take part, and the write-through stores would put a round trip
-// to memory on the critical path of every column.)
+// slots from the waves sharing the CU); one acquire fence follows, so that
+// the board is then read with plain loads.  The writer stores the board
+// with agent-scope stores and waits for them before raising the flag: a
+// release fence would write back the whole L2 of its chiplet at every
+// column, and beside the evaluation that L2 holds megabytes of its output.
 __device__ __forceinline__ bool wait_flag(const int *flag, int32_t *status) {
   long spins = 0;
   while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
@@ -360,20 +360,19 @@ __global__ void __launch_bounds__(256) qr_lds_kernel(int n, double *a, double *t
 #pragma unroll
         for (int l = 0; l < L; ++l) cq[l * n + i] = vi[l];
       }
-#pragma unroll
-      for (int l = 0; l < L; ++l) vboard[(size_t)c * L * n + (size_t)l * n + i] = vi[l];
+      st_agent<L>(vboard + (size_t)c * L * n, n, i, vi);
     }
     if (lane == 0) {
 #pragma unroll
       for (int l = 0; l < L; ++l) {
-        tboard[(size_t)c * L + l] = tc[l];
+        __hip_atomic_store(&tboard[(size_t)c * L + l], tc[l], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         tau[(size_t)l * n + c] = tc[l];
         sh_tau_own[l] = tc[l];
       }
     }
     wave_sync();
     if (lane == 0) {
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // board writes before the flag
+      wait_vm();  // the board stores are performed before the flag
       __hip_atomic_store(&flags[c], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   };
@@ -635,9 +634,9 @@ __device__ __forceinline__ double read_lane(double x, int i) {
 // Column c of M = R^{-1} Q^T for n <= 64, one wavefront per column with
 // row p in lane p.  The reciprocals 1/R_ii are formed here (lane i; the
 // singularity test of invdiag_kernel, reported by workgroup 0) and kept in
-// the lane's registers, the column R(., i-1) of the next step is loaded while
-// step i computes, so that no step waits for device memory, and z_i reaches
-// the other lanes by lane reads (no LDS round trip on the chain).
+// the lane's registers, the columns of R are loaded four steps before they
+// are used, so that no step waits for device memory, and z_i reaches the
+// other lanes by lane reads (no LDS round trip on the chain).
 template <int L>
 __global__ void __launch_bounds__(64, 1) m_from_qt_small_kernel(int n, const double *qr, const double *qt, double *M,
                                                              int32_t *status) {
@@ -656,16 +655,27 @@ __global__ void __launch_bounds__(64, 1) m_from_qt_small_kernel(int n, const dou
     else md::recip_newton<L>(rpp, dq);
     if (sing && c == 0) set_status(status, MD_ESINGULAR);
   }
-  double y[L], rn[L];
+  double y[L];
   md::zero<L>(y);
   if (on) ld<L>(qt, nn, (size_t)p * n + c, y);
-  md::zero<L>(rn);
-  if (lane < n - 1) ld<L>(qr, nn, (size_t)p * n + (n - 1), rn);  // R(p, n-1), p < n-1
+  // R(p, j) for p < j, four columns ahead of the step that uses them (R was
+  // just written by another kernel: its loads come from memory, not the L2)
+  auto ldcol = [&](int j, double (&r)[L]) {
+    md::zero<L>(r);
+    if (j >= 0 && lane < j) ld<L>(qr, nn, (size_t)p * n + j, r);
+  };
+  double r0[L], r1[L], r2[L], r3[L];
+  ldcol(n - 1, r0);
+  ldcol(n - 2, r1);
+  ldcol(n - 3, r2);
+  ldcol(n - 4, r3);
   for (int i = n - 1; i >= 0; --i) {
     double rc[L];
-    md::copy<L>(rn, rc);
-    md::zero<L>(rn);
-    if (i >= 1 && lane < i - 1) ld<L>(qr, nn, (size_t)p * n + (i - 1), rn);  // next column, rows above its diagonal
+    md::copy<L>(r0, rc);
+    md::copy<L>(r1, r0);
+    md::copy<L>(r2, r1);
+    md::copy<L>(r3, r2);
+    ldcol(i - 4, r3);
     double zl[L], z[L];
     MD<L>::mul(y, dq, zl);  // meaningful in lane i
 #pragma unroll
