@@ -525,13 +525,10 @@ static int newton_step_impl(const md_plan *p, int Ls, int lo, int hi, bool keep_
     if ((e = mdk::launch_stages(Ls, n, W, M, N, At, r, dxT, reinterpret_cast<int *>(at(ws, w.sync)), dev_status,
                                 st)) != hipSuccess)
       return hip_fail(e, "stages");
-    if ((e = mdk::launch_transpose_ld(Ls, dxT, n, dx + lo, D, W, n, nW, nD, st)) != hipSuccess)
-      return hip_fail(e, "dx");
   }
-  {
+  {  // dx to series-major, x += dx, norms: one launch
     Timed t(MD_CLASS_X_UPDATE, st);
-    e = mixed ? mdk::launch_update_mixed(L, Ls, n, D, lo, hi, b, dx, x, dev_norms, dev_status, st, tsz, scale)
-              : mdk::launch_update(L, n, D, lo, hi, b, dx, x, dev_norms, dev_status, st, tsz, scale);
+    e = mdk::launch_finish(L, Ls, n, D, lo, hi, dxT, dx, x, b, dev_norms, dev_status, st, tsz, scale);
     if (e != hipSuccess) return hip_fail(e, "update");
   }
   return MD_OK;

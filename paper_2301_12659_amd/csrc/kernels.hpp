@@ -70,9 +70,9 @@ hipError_t launch_stages(int L, int n, int D, const double *M, const double *NP,
 hipError_t launch_update(int L, int n, int D, int lo, int hi, const double *b, const double *dx, double *x,
                          double *norms, int32_t *status, hipStream_t st, const double *tsz = nullptr,
                          double *scale = nullptr);
-hipError_t launch_update_mixed(int L, int Ldx, int n, int D, int lo, int hi, const double *b, const double *dx,
-                               double *x, double *norms, int32_t *status, hipStream_t st,
-                               const double *tsz = nullptr, double *scale = nullptr);
+hipError_t launch_finish(int L, int Ldx, int n, int D, int lo, int hi, const double *dxT, double *dx, double *x,
+                         const double *b, double *norms, int32_t *status, hipStream_t st, const double *tsz = nullptr,
+                         double *rel = nullptr);
 // out[0 .. 3D]: norms[2][D], scale[D] and the status word (as a double),
 // written by one small kernel (out may be mapped host memory).
 hipError_t launch_report(int D, const double *norms, const double *scale, const int32_t *status, double *out,

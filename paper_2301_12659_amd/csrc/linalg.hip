@@ -1110,8 +1110,8 @@ __global__ void __launch_bounds__(256) dot_kernel(int64_t count, const double *a
 }
 
 // x := x + dx for the coefficients lo .. lo + W - 1 of every series, one
-// thread per (i, s); dx may carry fewer limbs (Ldx <= L), the update of a
-// mixed-precision step.
+// thread per (i, s), dx with Ldx <= L limbs (the complex step updates its
+// two planes with it; the real step uses finish_kernel below).
 template <int L, int Ldx = L>
 __global__ void update_kernel(int n, int D, int lo, int W, const double *dx, double *x) {
   const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1125,6 +1125,68 @@ __global__ void update_kernel(int n, int D, int lo, int W, const double *dx, dou
   md::widen<Ldx>(d, b);
   MD<L>::add(a, b, s);
   st<L>(x, nD, q, s);
+}
+
+// The end of a step on the window lo..hi-1 in one launch, one workgroup
+// per coefficient k: dx_k from the coefficient-major output of the staged
+// solve (dxT [Ldx][W][n]) into the series-major dx, x_k += dx_k at L limbs
+// (dx may carry fewer limbs), and the norms of norms_kernel below from the
+// same values (the transpose, update_kernel and norms_kernel fused).
+template <int L, int Ldx = L>
+__global__ void __launch_bounds__(256) finish_kernel(int n, int D, int lo, int hi, const double *dxT, double *dx,
+                                                     double *x, const double *b, double *norms, int32_t *status,
+                                                     const double *tsz, double *rel) {
+  __shared__ double sb[256], sx[256], ss[256];
+  __shared__ int sf[256];
+  const int k = blockIdx.x, t = threadIdx.x;
+  const bool has_b = k < hi, has_dx = k >= lo && k < hi;
+  const size_t nD = (size_t)n * D, nW = (size_t)n * (hi - lo);
+  double nb = 0.0, nx = 0.0, ns = 0.0;
+  int finite = 1;
+  for (int i = t; i < n; i += blockDim.x) {
+    const size_t q = (size_t)i * D + k;
+    double xi = 0.0;
+    if (has_dx) {
+      double d[Ldx], w[L], a[L], sum[L];
+      ld<Ldx>(dxT, nW, (size_t)(k - lo) * n + i, d);
+      st<Ldx>(dx, nD, q, d);
+      md::widen<Ldx>(d, w);
+      ld<L>(x, nD, q, a);
+      MD<L>::add(a, w, sum);
+      st<L>(x, nD, q, sum);
+      xi = d[0];
+    }
+    const double bi = has_b ? b[q] : 0.0;
+    finite &= (isfinite(bi) && isfinite(xi)) ? 1 : 0;
+    nb = fmax(nb, fabs(bi));
+    nx = fmax(nx, fabs(xi));
+    if (tsz && has_b) {  // |b_{i,k}| relative to the size of its own terms (0/0 = 0)
+      const double tz = tsz[q], ab = fabs(bi);
+      ns = fmax(ns, tz > 0.0 ? ab / tz : (ab > 0.0 ? INFINITY : 0.0));
+    }
+  }
+  sb[t] = nb;
+  sx[t] = nx;
+  ss[t] = ns;
+  sf[t] = finite;
+  __syncthreads();
+  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+    if (t < h) {
+      sb[t] = fmax(sb[t], sb[t + h]);
+      sx[t] = fmax(sx[t], sx[t + h]);
+      ss[t] = fmax(ss[t], ss[t + h]);
+      sf[t] &= sf[t + h];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    if (norms) {
+      norms[k] = sb[0];
+      norms[D + k] = sx[0];
+    }
+    if (tsz && rel) rel[k] = ss[0];
+    if (!sf[0]) set_status(status, MD_ENONFINITE);
+  }
 }
 
 // norms[k] = max_i |b_{i,k}| for k < hi, norms[D+k] = max_i |dx_{i,k}| for
@@ -1389,19 +1451,23 @@ hipError_t launch_update(int L, int n, int D, int lo, int hi, const double *b, c
   return hipGetLastError();
 }
 
-hipError_t launch_update_mixed(int L, int Ldx, int n, int D, int lo, int hi, const double *b, const double *dx,
-                               double *x, double *norms, int32_t *status, hipStream_t st, const double *tsz,
-                               double *scale) {
-  if (lo < 0 || hi > D || lo >= hi) return hipErrorInvalidValue;
-  const int W = hi - lo;
-  const size_t nW = (size_t)n * W;
-  const dim3 grid((nW + 255) / 256);
-  if (L == 4 && Ldx == 2) hipLaunchKernelGGL((update_kernel<4, 2>), grid, dim3(256), 0, st, n, D, lo, W, dx, x);
-  else if (L == 8 && Ldx == 2) hipLaunchKernelGGL((update_kernel<8, 2>), grid, dim3(256), 0, st, n, D, lo, W, dx, x);
-  else if (L == 8 && Ldx == 4) hipLaunchKernelGGL((update_kernel<8, 4>), grid, dim3(256), 0, st, n, D, lo, W, dx, x);
-  else return hipErrorInvalidValue;
-  hipLaunchKernelGGL(norms_kernel, dim3(D), dim3(256), 0, st, n, D, lo, hi, b, dx, norms, status, tsz,
-                     scale);
+hipError_t launch_finish(int L, int Ldx, int n, int D, int lo, int hi, const double *dxT, double *dx, double *x,
+                         const double *b, double *norms, int32_t *status, hipStream_t st, const double *tsz,
+                         double *rel) {
+  if (lo < 0 || hi > D || lo >= hi || n < 1) return hipErrorInvalidValue;
+  const dim3 grid(D), block(256);
+  if (Ldx == L) {
+    MD_DISPATCH(L, hipLaunchKernelGGL((finish_kernel<LL, LL>), grid, block, 0, st, n, D, lo, hi, dxT, dx, x, b, norms,
+                                      status, tsz, rel));
+  } else if (L == 4 && Ldx == 2) {
+    hipLaunchKernelGGL((finish_kernel<4, 2>), grid, block, 0, st, n, D, lo, hi, dxT, dx, x, b, norms, status, tsz, rel);
+  } else if (L == 8 && Ldx == 2) {
+    hipLaunchKernelGGL((finish_kernel<8, 2>), grid, block, 0, st, n, D, lo, hi, dxT, dx, x, b, norms, status, tsz, rel);
+  } else if (L == 8 && Ldx == 4) {
+    hipLaunchKernelGGL((finish_kernel<8, 4>), grid, block, 0, st, n, D, lo, hi, dxT, dx, x, b, norms, status, tsz, rel);
+  } else {
+    return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
