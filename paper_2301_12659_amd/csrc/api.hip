@@ -436,7 +436,9 @@ static int newton_step_impl(const md_plan *p, int Ls, int lo, int hi, bool keep_
   const int L = p->L, n = p->n, D = p->D, W = hi - lo;
   const bool mixed = Ls != L;
   hipError_t e;
-  if ((e = mdk::launch_status_init(dev_status, st)) != hipSuccess) return hip_fail(e, "status");
+  // the coefficient-0 pre-pass, when it runs, resets the status word itself
+  const bool pre0 = !keep_m && p->m > 0 && p->maxk <= mdk::evaldiff0_max_support(Ls);
+  if (!pre0 && (e = mdk::launch_status_init(dev_status, st)) != hipSuccess) return hip_fail(e, "status");
   double *b = at(ws, w.b), *A = at(ws, w.A), *qr = at(ws, w.qr), *tau = at(ws, w.tau), *qt = at(ws, w.qt);
   double *invd = at(ws, w.invd), *M = at(ws, w.M), *N = at(ws, w.N), *r = at(ws, w.r), *dx = at(ws, w.dx);
   double *tsz = scale ? at(ws, w.tsz) : nullptr;
@@ -448,8 +450,9 @@ static int newton_step_impl(const md_plan *p, int Ls, int lo, int hi, bool keep_
     {
       Timed t(MD_CLASS_QR, st);
       eval_args(p, cff, x, ws, 1, a);
-      e = (p->maxk <= mdk::evaldiff0_max_support(Ls)) ? mdk::launch_evaldiff0(Ls, a, st)
-                                                      : mdk::launch_evaldiff(Ls, a, p->maxexp, at(ws, w.pw), st);
+      if (pre0) a.reset_status = dev_status;
+      e = pre0 ? mdk::launch_evaldiff0(Ls, a, st) : mdk::launch_evaldiff(Ls, a, p->maxexp, at(ws, w.pw), st);
+      a.reset_status = nullptr;
       if (e != hipSuccess) return hip_fail(e, "A_0 pre-pass");
       if ((e = mdk::launch_assemble_A0(Ls, n, D, p->nnz, p->d_asm_ptr, p->d_asm_ent, a.der, qr, st)) != hipSuccess)
         return hip_fail(e, "A_0 assembly");

@@ -14,6 +14,7 @@ struct EvalArgs {
   size_t x_ls = 0, cff_ls = 0; // limb strides of x and cff when not n D and m (packed batches)
   double *vsize = nullptr;     // [m][D], nullable: max_j |f_j| over each monomial's forward chain (leading limbs)
   int beside_qr = 0;           // 1: runs beside the QR (one wavefront per monomial, more issue slots for the QR)
+  int32_t *reset_status = nullptr;  // coefficient-0 kernel: its first thread sets this status word to MD_OK
 };
 
 }  // namespace mdk

@@ -208,6 +208,9 @@ constexpr int EVAL0_MAXK = 8;
 template <int L>
 __global__ void __launch_bounds__(256) evaldiff0_kernel(EvalArgs a) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  // the step's status word, reset by its first launch (every launch that can
+  // report into it comes later in stream order; no evaluation kernel does)
+  if (t == 0 && a.reset_status) *a.reset_status = MD_OK;
   if (t >= a.m) return;
   const int mono = t;
   const int e0 = a.mon_ptr[mono], k = a.mon_ptr[mono + 1] - e0;
