@@ -830,16 +830,6 @@ __device__ __forceinline__ bool wait_geq(const int *ctr, int target, int32_t *st
 // polls of one do not contend with the updates of another.
 constexpr int SYNC_STRIDE = 64;
 
-// Bit pattern of a dx entry not yet solved (a signalling NaN: arithmetic
-// only produces quiet ones), written over dxT before the staged solve.
-constexpr long long DX_PENDING = 0x7FF4D5A000000000LL;
-
-__global__ void stages_prep_kernel(int *sync, int nsync, double *dxT, size_t ndx) {
-  const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q < (size_t)nsync) sync[q] = 0;
-  if (q < ndx) dxT[q] = __longlong_as_double(DX_PENDING);
-}
-
 // The whole staged solve in one launch, for n <= 64.  With P = M A_2 the
 // recurrence is reassociated once more,
 //     dx_k = M r'_k - N dx_{k-1} - P dx_{k-2},  r'_k = b_k - sum_{j>=3} A_j dx_{k-j},
@@ -848,12 +838,11 @@ __global__ void stages_prep_kernel(int *sync, int nsync, double *dxT, size_t ndx
 // row i = 4 s + w and keeps M(i,.), N(i,.), P(i,.) in registers (lane v holds
 // column v); stage k is one dot product of length 3n per row.  (One
 // workgroup cannot carry the stage: its n x 3n multiply-adds would keep one
-// CU busy for several microseconds.)  A solver wavefront waits for dx_{k-1}
-// by polling the entries themselves (dxT starts as a pattern no arithmetic
-// produces, lane v reads column v, the wavefront votes); after its rows of
-// dx_k are stored, solver s sets its flag to k + 1, and the last workgroup
-// (a forwarder) turns the flags into one count, which the updaters poll with
-// a longer sleep (they have two stages of slack).  Updater (g, b) owns the rows 16 b .. 16 b + 15
+// CU busy for several microseconds.)  After its rows of dx_k are in dxT,
+// solver s sets its flag to k + 1; a wavefront waits for all solvers with
+// one lane per flag and a vote.  The last workgroup (a forwarder) turns the
+// flags into one count, which the updaters poll with a longer sleep (they
+// have two stages of slack).  Updater (g, b) owns the rows 16 b .. 16 b + 15
 // (one team of 16 lanes per row) of the coefficients m = 3 + g + j Gm; in
 // round q, once dx_q is out, it applies r'_m -= A_{m-q} dx_q to its
 // m >= q + 3 and adds 1 to their round counters; stage k waits for the
@@ -949,41 +938,23 @@ __global__ void __launch_bounds__(256) stages_persistent_kernel(int n, int D, in
       MD<L>::fma_lazy(pre, m, a);
     }
     for (int k = 0; k < D; ++k) {
+      if (wv == 0) {
+        const bool ok = (k >= 1) ? wait_solvers(k) : true;
+        if (lane == 0) sh_ok = (ok && !sh_dead) ? 1 : 0;
+      }
+      __syncthreads();
+      if (!sh_ok) return;
       double acc[L], r[L];
       md::copy<L>(pre, acc);
-      if (k >= 1) {
-        // dx_{k-1}(v) polled where the solvers store it: the entries start as
-        // DX_PENDING, which no arithmetic produces, and every limb is one
-        // 64-bit store, so a lane is done when none of its limbs holds the
-        // pattern (one round trip to memory instead of a flag and then the
-        // data)
-        long spins = 0;
-        while (true) {
-          bool have = true;
-          if (col) {
-            ld_agent<L>(dxT, nD, (size_t)(k - 1) * n + v, x1);
-#pragma unroll
-            for (int l = 0; l < L; ++l) have = have && (__double_as_longlong(x1[l]) != DX_PENDING);
-          }
-          if (__all(have)) break;
-          __builtin_amdgcn_s_sleep(1);
-          if (++spins > (1L << 22)) {
-            if (lane == 0) {
-              set_status(status, MD_EHIP);
-              sh_dead = 1;
-            }
-            break;
-          }
-        }
-        if (col) MD<L>::fma_lazy(acc, nv, x1);
+      if (col && k >= 1) {
+        ld_agent<L>(dxT, nD, (size_t)(k - 1) * n + v, x1);
+        MD<L>::fma_lazy(acc, nv, x1);
       }
       team_sum_lazy<L>(acc, 64);
       MD<L>::renorm(acc, r);
       if (row && lane == 0) st_agent<L>(dxT, nD, (size_t)k * n + i, r);
       wait_vm();
       __syncthreads();
-      if (sh_dead) return;
-      // the flag serves the forwarder (and through it the updaters)
       if (tid == 64) __hip_atomic_store(solved(blockIdx.x), k + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if (k + 1 < D) {  // M r'_{k+1} + P dx_{k-1}
         if (k + 1 >= 3 && !wait_rounds(k + 1, Bm * (k - 1)) && lane == 0) sh_dead = 1;
@@ -1450,9 +1421,8 @@ hipError_t launch_stages(int L, int n, int D, const double *M, const double *NP,
     const int Gs = (n + 3) / 4, Bm = (n + 15) / 16;
     const int Gm = D > 3 ? std::min(D - 3, 60) : 0;  // coefficient groups of the updaters
     const int G = Gs + Gm * Bm + 1;                  // at most 16 + 240 + 1 workgroups of 256 threads
-    const size_t ndx = (size_t)L * D * n, nprep = std::max(ndx, (size_t)stages_sync_ints(D));
-    hipLaunchKernelGGL(stages_prep_kernel, dim3((unsigned)((nprep + 255) / 256)), dim3(256), 0, st, sync,
-                       stages_sync_ints(D), dxT, ndx);
+    hipLaunchKernelGGL(zero_i32_kernel, dim3((stages_sync_ints(D) + 255) / 256), dim3(256), 0, st, sync,
+                       stages_sync_ints(D));
     if (L == 2)
       hipLaunchKernelGGL(stages_persistent_kernel<2>, dim3(G), dim3(256), 0, st, n, D, Gs, Gm, M, NP, At, rT, dxT,
                          sync, status);
