@@ -93,9 +93,9 @@ hipError_t launch_assemble_A0(int L, int n, int D, int nnz, const int32_t *asm_p
                               const double *der, double *a0, hipStream_t st) {
   const size_t nn = (size_t)n * n;
   switch (L) {
-    case 2: hipLaunchKernelGGL(assemble_A0_kernel<2>, dim3((nn + 255) / 256), dim3(256), 0, st, n, D, nnz, asm_ptr, asm_ent, der, a0); break;
-    case 4: hipLaunchKernelGGL(assemble_A0_kernel<4>, dim3((nn + 255) / 256), dim3(256), 0, st, n, D, nnz, asm_ptr, asm_ent, der, a0); break;
-    case 8: hipLaunchKernelGGL(assemble_A0_kernel<8>, dim3((nn + 255) / 256), dim3(256), 0, st, n, D, nnz, asm_ptr, asm_ent, der, a0); break;
+    case 2: hipLaunchKernelGGL(assemble_A0_kernel<2>, dim3((nn + 63) / 64), dim3(64), 0, st, n, D, nnz, asm_ptr, asm_ent, der, a0); break;
+    case 4: hipLaunchKernelGGL(assemble_A0_kernel<4>, dim3((nn + 63) / 64), dim3(64), 0, st, n, D, nnz, asm_ptr, asm_ent, der, a0); break;
+    case 8: hipLaunchKernelGGL(assemble_A0_kernel<8>, dim3((nn + 63) / 64), dim3(64), 0, st, n, D, nnz, asm_ptr, asm_ent, der, a0); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

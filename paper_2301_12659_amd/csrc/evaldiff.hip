@@ -263,10 +263,12 @@ __global__ void __launch_bounds__(256) evaldiff0_kernel(EvalArgs a) {
 }
 
 hipError_t launch_evaldiff0(int L, const EvalArgs &a, hipStream_t st) {
-  const dim3 grid((a.m + 255) / 256);
+  // one wavefront per workgroup: the few thousand monomials spread over as
+  // many CUs as possible (each thread is a chain of dependent products)
+  const dim3 grid((a.m + 63) / 64);
   switch (L) {
-    case 2: hipLaunchKernelGGL(evaldiff0_kernel<2>, grid, dim3(256), 0, st, a); break;
-    case 4: hipLaunchKernelGGL(evaldiff0_kernel<4>, grid, dim3(256), 0, st, a); break;
+    case 2: hipLaunchKernelGGL(evaldiff0_kernel<2>, grid, dim3(64), 0, st, a); break;
+    case 4: hipLaunchKernelGGL(evaldiff0_kernel<4>, grid, dim3(64), 0, st, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
