@@ -516,7 +516,10 @@ static int newton_step_impl(const md_plan *p, int Ls, int lo, int hi, bool keep_
     if ((e = mdk::launch_transpose_ld(Ls, b + lo, D, r, n, n, W, nD, nW, st)) != hipSuccess)
       return hip_fail(e, "b^T");
   }
-  // 4. join, N = M A_1 (and P = M A_2), the staged solve of the window
+  // 4. join, N = M A_1 (and P = M A_2), the staged solve of the window (its
+  //    counters cleared before the join, while the factorization finishes)
+  int *sync = reinterpret_cast<int *>(at(ws, w.sync));
+  if ((e = mdk::launch_stages_sync(Ls, n, W, sync, st)) != hipSuccess) return hip_fail(e, "stage counters");
   if (!keep_m && (e = hipStreamWaitEvent(st, p->join, 0)) != hipSuccess) return hip_fail(e, "join wait");
   if (W > 1) {
     Timed t(MD_CLASS_GEMM, st);
@@ -525,8 +528,7 @@ static int newton_step_impl(const md_plan *p, int Ls, int lo, int hi, bool keep_
   }
   {
     Timed t(MD_CLASS_UPDATES, st);
-    if ((e = mdk::launch_stages(Ls, n, W, M, N, At, r, dxT, reinterpret_cast<int *>(at(ws, w.sync)), dev_status,
-                                st)) != hipSuccess)
+    if ((e = mdk::launch_stages(Ls, n, W, M, N, At, r, dxT, sync, dev_status, st, true)) != hipSuccess)
       return hip_fail(e, "stages");
   }
   {  // dx to series-major, x += dx, norms: one launch

@@ -61,8 +61,9 @@ hipError_t launch_gemm(int L, int n, const double *M, const double *B, size_t b_
 bool stages_persistent(int L, int n, int D);
 int stages_sync_ints(int D);
 int stages_products(int L, int n, int D);
+hipError_t launch_stages_sync(int L, int n, int D, int *sync, hipStream_t st);
 hipError_t launch_stages(int L, int n, int D, const double *M, const double *NP, const double *At, double *rT,
-                         double *dxT, int *sync, int32_t *status, hipStream_t st);
+                         double *dxT, int *sync, int32_t *status, hipStream_t st, bool sync_ready = false);
 // x_k += dx_k for lo <= k < hi; norms[2][D]: max |b_k| for k < hi and
 // max |dx_k| for lo <= k < hi, zero elsewhere; with tsz ([n][D] term sizes
 // from the assembly) rel[k] = max_i |b_{i,k}| / tsz[i][k] for k < hi, zero

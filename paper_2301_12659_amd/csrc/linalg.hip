@@ -669,20 +669,26 @@ __global__ void __launch_bounds__(64, 1) m_from_qt_small_kernel(int n, const dou
   ldcol(n - 2, r1);
   ldcol(n - 3, r2);
   ldcol(n - 4, r3);
-  for (int i = n - 1; i >= 0; --i) {
-    double rc[L];
-    md::copy<L>(r0, rc);
-    md::copy<L>(r1, r0);
-    md::copy<L>(r2, r1);
-    md::copy<L>(r3, r2);
-    ldcol(i - 4, r3);
+  // step i with column i of R in rc, which then receives column i - 4
+  auto step = [&](int i, double (&rc)[L]) {
     double zl[L], z[L];
     MD<L>::mul(y, dq, zl);  // meaningful in lane i
 #pragma unroll
     for (int l = 0; l < L; ++l) z[l] = read_lane(zl[l], i);
     if (lane == i) md::copy<L>(z, y);
     else if (lane < i) MD<L>::fms(y, rc, z);
+    ldcol(i - 4, rc);
+  };
+  int i = n - 1;
+  for (; i >= 3; i -= 4) {  // four steps a round: the four registers rotate by name, not by copies
+    step(i, r0);
+    step(i - 1, r1);
+    step(i - 2, r2);
+    step(i - 3, r3);
   }
+  if (i >= 0) step(i, r0);
+  if (i >= 1) step(i - 1, r1);
+  if (i >= 2) step(i - 2, r2);
   if (on) st<L>(M, nn, (size_t)p * n + c, y);
 }
 
@@ -1415,14 +1421,26 @@ int stages_sync_ints(int D) { return (D + 2 + 64) * SYNC_STRIDE; }
 
 int stages_products(int L, int n, int D) { return stages_persistent(L, n, D) ? std::min(2, D - 1) : std::min(1, D - 1); }
 
+// The counters of the persistent staged solve cleared ahead of it (a caller
+// may issue this before it waits for the factorization, off the critical
+// path, and then launch_stages with sync_ready).
+hipError_t launch_stages_sync(int L, int n, int D, int *sync, hipStream_t st) {
+  if (stages_persistent(L, n, D))
+    hipLaunchKernelGGL(zero_i32_kernel, dim3((stages_sync_ints(D) + 255) / 256), dim3(256), 0, st, sync,
+                       stages_sync_ints(D));
+  return hipGetLastError();
+}
+
 hipError_t launch_stages(int L, int n, int D, const double *M, const double *NP, const double *At, double *rT,
-                         double *dxT, int *sync, int32_t *status, hipStream_t st) {
+                         double *dxT, int *sync, int32_t *status, hipStream_t st, bool sync_ready) {
   if (stages_persistent(L, n, D)) {
     const int Gs = (n + 3) / 4, Bm = (n + 15) / 16;
     const int Gm = D > 3 ? std::min(D - 3, 60) : 0;  // coefficient groups of the updaters
     const int G = Gs + Gm * Bm + 1;                  // at most 16 + 240 + 1 workgroups of 256 threads
-    hipLaunchKernelGGL(zero_i32_kernel, dim3((stages_sync_ints(D) + 255) / 256), dim3(256), 0, st, sync,
-                       stages_sync_ints(D));
+    if (!sync_ready) {
+      const hipError_t e = launch_stages_sync(L, n, D, sync, st);
+      if (e != hipSuccess) return e;
+    }
     if (L == 2)
       hipLaunchKernelGGL(stages_persistent_kernel<2>, dim3(G), dim3(256), 0, st, n, D, Gs, Gm, M, NP, At, rT, dxT,
                          sync, status);
