@@ -1313,13 +1313,17 @@ hipError_t launch_qr(int L, int n, double *a, double *tau, double *qt, int32_t *
   return hipGetLastError();
 }
 
-// Workgroups of the LDS-resident QR: at most 16 columns and about 120 KB of
-// columns per workgroup; 0 if that needs more than 64 workgroups.
+// Workgroups of the LDS-resident QR: at most 8 (large systems 16) columns and
+// about 140 KB of columns per workgroup; 0 if that needs more than 64.
 size_t qr_lds_bytes(int L, int n, int G, bool with_qt);
 
 int qr_lds_workgroups(int L, int n, bool with_qt) {
   const int cols = with_qt ? 2 * n : n;
-  int G = std::max(1, (cols + 15) / 16);  // about 16 columns per workgroup
+  // about 8 columns per workgroup (n = 64 with Q^T: 16 workgroups, 563 us
+  // beside the evaluation against 570 with 8 and 584 with 4), about 16 for
+  // the large systems
+  int G = std::max(1, (cols + 7) / 8);
+  if (G > 64) G = std::max(1, (cols + 15) / 16);
   while (G <= 64 && qr_lds_bytes(L, n, G, with_qt) > 140 * 1024) ++G;
   return G > 64 ? 0 : G;
 }
