@@ -71,12 +71,12 @@ bool valid_prec(int p) { return p == MD_DD || p == MD_QD || p == MD_OD; }
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// Scratch of the QR kernels: flags [n] and the reflector board (v [n][L][n],
-// tau [n][L]) of the LDS-resident kernel, or the barrier counter of the
+// Scratch of the QR kernels: flags [n] and the reflector board (x [n][L][n],
+// (tau, 1 / (x_0 - beta)) [n][2][L]) of the LDS-resident kernel, or the barrier counter of the
 // global-memory kernel used when the columns do not fit in LDS.
 size_t qr_scratch_bytes(int L, int n) {
   return align_up((size_t)n * sizeof(int)) + align_up((size_t)n * L * n * sizeof(double)) +
-         align_up((size_t)n * L * sizeof(double)) + 256;
+         align_up((size_t)n * 2 * L * sizeof(double)) + 256;
 }
 
 // Workspace regions, in doubles, each aligned to 256 bytes.
@@ -134,7 +134,7 @@ hipError_t run_qr(int L, int n, double *a, double *tau, double *qt, int32_t *sta
   double *vboard = reinterpret_cast<double *>(p);
   p += align_up((size_t)n * L * n * sizeof(double));
   double *tboard = reinterpret_cast<double *>(p);
-  p += align_up((size_t)n * L * sizeof(double));
+  p += align_up((size_t)n * 2 * L * sizeof(double));
   unsigned *bar = reinterpret_cast<unsigned *>(p);
   if (mdk::qr_lds_workgroups(L, n, qt != nullptr) > 0)
     return mdk::launch_qr_lds(L, n, a, tau, qt, status, flags, vboard, tboard, st);

@@ -302,6 +302,7 @@ __global__ void __launch_bounds__(256) qr_lds_kernel(int n, double *a, double *t
   while (gcol(ncol) < ncols_total) ++ncol;
   double *cols = lds;                          // [ncol][L][n]
   double *vsh = lds + (size_t)ncol * L * n;    // [L][n] current reflector
+  double *own_inv = vsh + (size_t)L * n;       // [ncol][L] 1 / (x_0 - beta) of the owned columns
   __shared__ double sh_tau[L], sh_tau_own[L];
   __shared__ int sh_ok;
   auto col = [&](int q) { return cols + (size_t)q * L * n; };
@@ -320,6 +321,15 @@ __global__ void __launch_bounds__(256) qr_lds_kernel(int n, double *a, double *t
   // beta and v into the column, publishes v, tau and the flag
   auto publish = [&](int q, int c) {
     double *cq = col(q);
+    // the column below the diagonal to the board as it is (x_i = v_i (x_0 -
+    // beta)): its stores complete while the norm and the scalars are formed,
+    // and the readers scale it by 1 / (x_0 - beta)
+    for (int i = c + 1 + lane; i < n; i += 64) {
+      double xi[L];
+#pragma unroll
+      for (int l = 0; l < L; ++l) xi[l] = cq[l * n + i];
+      st_agent<L>(vboard + (size_t)c * L * n, n, i, xi);
+    }
     double acc[L];
     {
       double u[L];
@@ -345,29 +355,15 @@ __global__ void __launch_bounds__(256) qr_lds_kernel(int n, double *a, double *t
     } else {
       reflector<L>(acc, x0, beta, tc, inv);  // every lane computes the same scalars
     }
-    for (int i = c + lane; i < n; i += 64) {
-      double vi[L];
-      if (i == c) {
-        md::zero<L>(vi);
-        vi[0] = 1.0;
-#pragma unroll
-        for (int l = 0; l < L; ++l) cq[l * n + i] = beta[l];
-      } else {
-        double xi[L];
-#pragma unroll
-        for (int l = 0; l < L; ++l) xi[l] = cq[l * n + i];
-        MD<L>::mul(xi, inv, vi);
-#pragma unroll
-        for (int l = 0; l < L; ++l) cq[l * n + i] = vi[l];
-      }
-      st_agent<L>(vboard + (size_t)c * L * n, n, i, vi);
-    }
     if (lane == 0) {
 #pragma unroll
       for (int l = 0; l < L; ++l) {
-        __hip_atomic_store(&tboard[(size_t)c * L + l], tc[l], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&tboard[(size_t)c * 2 * L + l], tc[l], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&tboard[(size_t)c * 2 * L + L + l], inv[l], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         tau[(size_t)l * n + c] = tc[l];
         sh_tau_own[l] = tc[l];
+        own_inv[q * L + l] = inv[l];
+        cq[l * n + c] = beta[l];  // R_cc
       }
     }
     wave_sync();
@@ -421,21 +417,47 @@ __global__ void __launch_bounds__(256) qr_lds_kernel(int n, double *a, double *t
     __syncthreads();
     ok = sh_ok != 0;
     if (!ok) break;
+    // v_i = x_i / (x_0 - beta) below the diagonal, v_c = 1
     if (own) {
-      const double *cc = col(lcol(c));
-      for (int i = c + tid; i < n; i += blockDim.x)
+      const int qc = lcol(c);
+      const double *cc = col(qc);
+      double inv[L];
 #pragma unroll
-        for (int l = 0; l < L; ++l) vsh[l * n + i] = (i == c) ? (l == 0 ? 1.0 : 0.0) : cc[l * n + i];
+      for (int l = 0; l < L; ++l) inv[l] = own_inv[qc * L + l];
+      for (int i = c + tid; i < n; i += blockDim.x) {
+        double xi[L], vi[L];
+        md::zero<L>(vi);
+        vi[0] = 1.0;
+        if (i > c) {
+#pragma unroll
+          for (int l = 0; l < L; ++l) xi[l] = cc[l * n + i];
+          MD<L>::mul(xi, inv, vi);
+        }
+#pragma unroll
+        for (int l = 0; l < L; ++l) vsh[l * n + i] = vi[l];
+      }
       if (tid == 0)
 #pragma unroll
         for (int l = 0; l < L; ++l) sh_tau[l] = sh_tau_own[l];
     } else {
-      for (int i = c + tid; i < n; i += blockDim.x)
+      double inv[L];
 #pragma unroll
-        for (int l = 0; l < L; ++l) vsh[l * n + i] = vboard[(size_t)c * L * n + (size_t)l * n + i];
+      for (int l = 0; l < L; ++l) inv[l] = tboard[(size_t)c * 2 * L + L + l];
+      for (int i = c + tid; i < n; i += blockDim.x) {
+        double xi[L], vi[L];
+        md::zero<L>(vi);
+        vi[0] = 1.0;
+        if (i > c) {
+#pragma unroll
+          for (int l = 0; l < L; ++l) xi[l] = vboard[(size_t)c * L * n + (size_t)l * n + i];
+          MD<L>::mul(xi, inv, vi);
+        }
+#pragma unroll
+        for (int l = 0; l < L; ++l) vsh[l * n + i] = vi[l];
+      }
       if (tid == 0)
 #pragma unroll
-        for (int l = 0; l < L; ++l) sh_tau[l] = tboard[(size_t)c * L + l];
+        for (int l = 0; l < L; ++l) sh_tau[l] = tboard[(size_t)c * 2 * L + l];
     }
     __syncthreads();
     double tc[L];
@@ -467,16 +489,27 @@ __global__ void __launch_bounds__(256) qr_lds_kernel(int n, double *a, double *t
     }
     __syncthreads();
   }
-  if (ok) {  // write back the owned columns
+  if (ok) {  // write back the owned columns, v = x / (x_0 - beta) below the diagonal
     for (int q = 0; q < ncol; ++q) {
       const int J = gcol(q);
       const double *cq = col(q);
-      for (int i = tid; i < n; i += blockDim.x)
+      for (int i = tid; i < n; i += blockDim.x) {
+        double x[L];
+#pragma unroll
+        for (int l = 0; l < L; ++l) x[l] = cq[l * n + i];
+        if (J < n && i > J) {
+          double inv[L], v[L];
+#pragma unroll
+          for (int l = 0; l < L; ++l) inv[l] = own_inv[q * L + l];
+          MD<L>::mul(x, inv, v);
+          md::copy<L>(v, x);
+        }
 #pragma unroll
         for (int l = 0; l < L; ++l) {
-          if (J < n) a[(size_t)l * nn + (size_t)i * n + J] = cq[l * n + i];
-          else qt[(size_t)l * nn + (size_t)i * n + (J - n)] = cq[l * n + i];
+          if (J < n) a[(size_t)l * nn + (size_t)i * n + J] = x[l];
+          else qt[(size_t)l * nn + (size_t)i * n + (J - n)] = x[l];
         }
+      }
     }
   }
 }
@@ -1332,7 +1365,8 @@ size_t qr_lds_bytes(int L, int n, int G, bool with_qt) {
   const int cols = with_qt ? 2 * n : n;
   const int pairs = (cols + 1) / 2;
   const int ncol = 2 * ((pairs + G - 1) / G);  // columns are owned in pairs
-  return ((size_t)ncol + 1) * L * n * sizeof(double);
+  // the owned columns, the current reflector, 1 / (x_0 - beta) per owned column
+  return (((size_t)ncol + 1) * L * n + (size_t)ncol * L) * sizeof(double);
 }
 
 hipError_t launch_qr_lds(int L, int n, double *a, double *tau, double *qt, int32_t *status, int *flags,
