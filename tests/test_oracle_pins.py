@@ -753,3 +753,73 @@ def test_complex_column_system_closed_form(cols):
         x = oracle.complex_step(s, s.cff, s.cst, x)["x"]
     err = max(oracle.absdiff(x[0], s.xstar[0]).max(), oracle.absdiff(x[1], s.xstar[1]).max())
     assert err < 2.0 ** -200
+
+
+# --------------------------------------------------------------------------
+# 12. reference md arithmetic against exact rational arithmetic
+# --------------------------------------------------------------------------
+
+def _arith_inputs(L, cnt, seed):
+    """Seeded md operands with every limb drawn, plus exponent gaps and
+    leading-limb cancellation, so a swapped operand or op code shows."""
+    rng = np.random.default_rng(seed)
+    a = mdinputs.random_md(rng, L, (cnt,), -1.0, 1.0)
+    b = mdinputs.random_md(rng, L, (cnt,), -1.0, 1.0)
+    c = mdinputs.random_md(rng, L, (cnt,), -1.0, 1.0)
+    q = cnt // 3
+    b[:, :q] *= 2.0 ** rng.integers(-30, 30, size=q)
+    b[0, q:2 * q] = -a[0, q:2 * q]           # leading limbs cancel exactly
+    return a, b, c
+
+
+@pytest.mark.parametrize("L", [2, 4, 8])
+@pytest.mark.parametrize("op", ["add", "sub", "mul", "div", "sqrt", "fma"])
+def test_arith_against_exact_rationals(L, op):
+    """oracle.arith(op) is the correctly rounded result at its working
+    precision P: |out - exact| <= 2^(1-P) |exact| with the exact value from
+    Fraction arithmetic on the limbs (sqrt: the exact root of exact squares,
+    and out^2 = a within the same bound for arbitrary a).  fma is c + a*b.
+    The export into doubles stops at the subnormal range, so at 8 limbs
+    (P = 1696) an absolute floor of 2^-1070 is added to the bound."""
+    a, b, c = _arith_inputs(L, 60, 700 + L)
+    P = oracle.prec_bits(L)
+    if op == "sqrt":
+        # exact squares: y = m 2^-e with m an integer of 26 L bits, so y^2
+        # has at most 52 L significant bits and fits in L limbs exactly
+        rng = np.random.default_rng(710 + L)
+        bits = 26 * L
+        want = []
+        for _ in range(40):
+            m = int.from_bytes(rng.bytes(bits // 8 + 1), "little") % (1 << (bits - 1)) + (1 << (bits - 1))
+            want.append(Fraction(m, 1 << (bits - 1 + int(rng.integers(-8, 8)))))
+        a2 = to_md([w * w for w in want], L)
+        assert all(md_value(a2[:, q]) == want[q] ** 2 for q in range(len(want)))
+        got = exact(oracle.arith("sqrt", a2))
+        assert all(g == w for g, w in zip(got, want))
+        pos = a * np.sign(a[0])[None, :]
+        got = exact(oracle.arith("sqrt", pos))
+        for q in range(pos.shape[1]):
+            av = md_value(pos[:, q])
+            assert abs(got[q] ** 2 - av) <= Fraction(2) ** (2 - P) * av + Fraction(2) ** -1070
+        return
+    out = exact(oracle.arith(op, a, b, c))
+    for q in range(a.shape[1]):
+        x, y, z = md_value(a[:, q]), md_value(b[:, q]), md_value(c[:, q])
+        want = {"add": x + y, "sub": x - y, "mul": x * y, "div": x / y, "fma": z + x * y}[op]
+        bound = Fraction(2) ** (1 - P) * abs(want) + Fraction(2) ** -1070
+        assert abs(out[q] - want) <= bound, (op, L, q)
+
+
+def test_arith_op_codes_are_distinct():
+    """Every op code gives a different result on the same operands (a
+    mapping slip such as sub for add, or a*b + c read as a + b*c, shows)."""
+    a, b, c = _arith_inputs(4, 12, 9)
+    a = a * np.sign(a[0])[None, :]
+    res = {op: exact(oracle.arith(op, a, b, c)) for op in ("add", "sub", "mul", "div", "fma")}
+    ops = list(res)
+    for i in range(len(ops)):
+        for j in range(i + 1, len(ops)):
+            assert any(u != v for u, v in zip(res[ops[i]], res[ops[j]])), (ops[i], ops[j])
+    # fma operand order: c + a*b differs from a + b*c on generic data
+    alt = [md_value(a[:, q]) + md_value(b[:, q]) * md_value(c[:, q]) for q in range(a.shape[1])]
+    assert all(u != v for u, v in zip(res["fma"], alt))
