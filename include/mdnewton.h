@@ -110,6 +110,22 @@ int md_qr_workspace_size(int prec, int n, size_t *bytes);
 int md_qr(int prec, int n, double *a0, double *tau, void *ws, size_t ws_bytes, hipStream_t stream,
           int32_t *dev_status);
 
+/* md_qr for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * factorization, kernels and results as md_qr, with no workspace argument and
+ * no allocation.  Its scratch (the flags and the reflector board) is a static
+ * device array of MD_QR_NOALLOC_MAX_BYTES bytes; each GPU the library runs on
+ * holds its own copy until the process ends.  The call is refused with
+ * MD_ENOSPACE when md_qr_workspace_size(prec, n) exceeds that size (octo
+ * doubles up to n = 256, quad doubles up to n = 363, double doubles up to
+ * n = 514).  Every call on a GPU uses that GPU's one array, which keeps the
+ * last call's contents (the flags are cleared by a kernel at every call):
+ * calls that overlap in time on one GPU (several streams or host threads)
+ * race and give wrong results; order them on one stream or serialize them.
+ * Arguments, status and errors as md_qr. */
+#define MD_QR_NOALLOC_MAX_BYTES (4u * 1024u * 1024u + 64u * 1024u)
+int md_qr_noalloc(int prec, int n, double *a0, double *tau, hipStream_t stream, int32_t *dev_status);
+
 /* Solve the lower triangular block Toeplitz system of Section 2,
  *   A_0 dx_k = b_k - sum_{j=1..k} A_j dx_{k-j},  k = 0..d,
  * given the QR factors of A_0 from md_qr (qr [L][n][n], tau [L][n]) and the

@@ -39,6 +39,7 @@ _lib.md_workspace_size.argtypes = [_vp, _szp]
 _lib.md_eval_diff.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
 _lib.md_qr_workspace_size.argtypes = [_i32, _i32, _szp]
 _lib.md_qr.argtypes = [_i32, _i32, _vp, _vp, _vp, ctypes.c_size_t, _vp, _vp]
+_lib.md_qr_noalloc.argtypes = [_i32, _i32, _vp, _vp, _vp, _vp]
 _lib.md_solve_workspace_size.argtypes = [_i32, _i32, _i32, _szp]
 _lib.md_series_solve.argtypes = [_i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp, _vp]
 _lib.md_newton_step.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
@@ -284,6 +285,15 @@ def qr(prec, n, a0, tau, status, ws=None, stream=None):
     rc = _lib.md_qr(L, int(n), _ptr(a0, (L, n, n), "a0"), _ptr(tau, (L, n), "tau"), _ptr(ws, None, "ws"),
                     ws.numel() * 8, _stream(stream), _ptr(status, (1,), "status"))
     _check(rc, "md_qr")
+
+
+def qr_noalloc(prec, n, a0, tau, status, stream=None):
+    """md_qr without a workspace: the scratch is the library's static device
+    array (for callers that cannot allocate)."""
+    L = int(prec)
+    rc = _lib.md_qr_noalloc(L, int(n), _ptr(a0, (L, n, n), "a0"), _ptr(tau, (L, n), "tau"), _stream(stream),
+                            _ptr(status, (1,), "status"))
+    _check(rc, "md_qr_noalloc")
 
 
 def solve_workspace_bytes(prec, n, d):

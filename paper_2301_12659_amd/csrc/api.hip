@@ -141,6 +141,33 @@ hipError_t run_qr(int L, int n, double *a, double *tau, double *qt, int32_t *sta
   return mdk::launch_qr(L, n, a, tau, qt, status, bar, st);
 }
 
+// Scratch of md_qr_noalloc: the QR's flags and reflector board in a static
+// device array (each GPU holds its own copy, at its own address, until the
+// process ends).  Host code never passes the array's name to a kernel: it
+// stands for a host-side symbol there.  The device address is taken once per
+// device with hipGetSymbolAddress, with that device current, and kept.
+static __device__ __align__(256) unsigned char scratch[MD_QR_NOALLOC_MAX_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+int noalloc_scratch(void **out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return fail(MD_EINVAL, "device index beyond the static scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return hip_fail(e, "hipGetSymbolAddress of the static QR scratch");
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return MD_OK;
+}
+
 int series_solve_impl(int L, int n, int D, const double *qr, const double *tau, const double *A, double *rhs_dx,
                       void *ws, hipStream_t st, int32_t *status) {
   size_t off = 0;
@@ -393,6 +420,21 @@ int md_qr(int prec, int n, double *a0, double *tau, void *ws, size_t ws_bytes, h
   if (!a0 || !tau) return fail(MD_EINVAL, "NULL argument");
   if (!ws || ws_bytes < qr_scratch_bytes(prec, n)) return fail(MD_ENOSPACE, "workspace too small");
   hipError_t e = run_qr(prec, n, a0, tau, nullptr, dev_status, ws, st);
+  return e == hipSuccess ? MD_OK : hip_fail(e, "qr launch");
+}
+
+int md_qr_noalloc(int prec, int n, double *a0, double *tau, hipStream_t st, int32_t *dev_status) {
+  if (!valid_prec(prec) || n < 1 || n > MD_MAX_DIM) return fail(MD_EINVAL, "bad precision or dimension");
+  if (!a0 || !tau) return fail(MD_EINVAL, "NULL argument");
+  const size_t need = qr_scratch_bytes(prec, n);
+  if (need > (size_t)MD_QR_NOALLOC_MAX_BYTES)
+    return fail(MD_ENOSPACE, "md_qr_noalloc: the QR needs " + std::to_string(need) +
+                                 " bytes of scratch, more than the static " +
+                                 std::to_string((size_t)MD_QR_NOALLOC_MAX_BYTES) + " (use md_qr with a workspace)");
+  void *ptr = nullptr;
+  const int rc = noalloc_scratch(&ptr);
+  if (rc != MD_OK) return rc;
+  hipError_t e = run_qr(prec, n, a0, tau, nullptr, dev_status, ptr, st);
   return e == hipSuccess ? MD_OK : hip_fail(e, "qr launch");
 }
 
