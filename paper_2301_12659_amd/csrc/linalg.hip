@@ -1292,8 +1292,8 @@ __global__ void __launch_bounds__(256) arith_kernel(int op, int64_t count, const
   ld<L>(a, count, q, x);
   if (op != 4) ld<L>(b, count, q, y);
   switch (op) {
-    case 0: MD<L>::add(x, y, r); break;
-    case 1: MD<L>::sub(x, y, r); break;
+    case 0: MD<L>::add_acc(x, y, r); break;
+    case 1: MD<L>::sub_acc(x, y, r); break;
     case 2: MD<L>::mul(x, y, r); break;
     case 3: md::div<L>(x, y, r); break;
     case 4: md::sqrt<L>(x, r); break;

@@ -35,6 +35,14 @@ def _eps(L):
 
 # ---------------------------------------------------------------- arithmetic
 
+def _one_plus_pow2(L, j):
+    """1 + 2^-j as L-limb multiple doubles (exact for j < 53 L)."""
+    e = np.zeros((2, len(j)))
+    e[0] = 1.0
+    e[1] = np.ldexp(1.0, -np.asarray(j, dtype=np.int64))
+    return oracle.round_md(e, L)
+
+
 @pytest.mark.parametrize("L", PRECS)
 @pytest.mark.parametrize("op", ["add", "sub", "mul", "div", "sqrt", "fma"])
 def test_arith(mdn, L, op):
@@ -48,6 +56,10 @@ def test_arith(mdn, L, op):
     b[:, : cnt // 4] *= 2.0 ** rng.integers(-40, 40, size=cnt // 4)  # exponent gaps
     b[:, cnt // 4: cnt // 2] = -a[:, cnt // 4: cnt // 2]               # exact cancellation
     b[L - 1, cnt // 4: cnt // 2] *= 0.5
+    # b = -a (1 + 2^-j): the sum cancels down to limb j / 53
+    j = rng.integers(1, 53 * L, size=cnt // 4)
+    sl = slice(cnt // 2, cnt // 2 + cnt // 4)
+    b[:, sl] = -oracle.round_md(oracle.arith("mul", a[:, sl], _one_plus_pow2(L, j)), L)
     if op == "sqrt":
         a = a * np.sign(a[0])[None, :]  # |a| of a multiple double
     ta, tb, tc = dev(a), dev(b), dev(c)
@@ -57,7 +69,9 @@ def test_arith(mdn, L, op):
     ref = oracle.arith(op, a, b, c)
     err = oracle.absdiff(host(out), ref)
     if op in ("add", "sub"):
-        scale = np.abs(a[0]) + np.abs(b[0])
+        # add and sub are accurate relative to the result, also where the
+        # operands cancel (no result here is exactly zero)
+        scale = np.abs(ref[0])
     elif op == "fma":
         scale = np.abs(c[0]) + np.abs(a[0] * b[0])
     else:
