@@ -229,14 +229,17 @@ def _append_boost(poly_ptr, mon_ptr, var, exp, cff, L, s):
 def make_system(name: str, L: int, n: int, d: int, mons_per_poly, kmin: int, kmax: int,
                 exps, seed: int, cond_max: float | None, boost: bool, steps: int = 1,
                 damping: float = 1.0, max_tries: int = 64, boost_gamma: float = 0.125,
-                vectorized: bool = False) -> System:
+                vectorized: bool = False, cond_min: float | None = None) -> System:
     """Draw a system and its manufactured solution.
 
     Without ``boost`` the system is redrawn (from a derived seed) until the
     float64 estimate of cond_2(J(x*(0))) is at most ``cond_max``.  With
     ``boost`` one linear monomial s_i x_i is appended to every polynomial;
     s_i starts at 1/8 of the row's absolute sum of the estimated Jacobian and
-    is doubled until the condition bound holds.
+    is doubled until the condition bound holds.  With ``cond_min`` the boost
+    grows by factors of 2^(1/4) instead, s_i = gamma * rowsum_i, and a draw is
+    kept only if the first boost that meets ``cond_max`` leaves
+    cond_2(J) >= cond_min: a system near the condition bound.
     """
     D = d + 1
     for attempt in range(max_tries):
@@ -257,15 +260,20 @@ def make_system(name: str, L: int, n: int, d: int, mons_per_poly, kmin: int, kma
         if boost:
             rowsum = np.abs(J).sum(axis=1) + 1.0
             gamma = boost_gamma
-            for _ in range(40):
-                s = np.exp2(np.ceil(np.log2(gamma * rowsum))) * np.where(np.diag(J) < 0, -1.0, 1.0)
+            sign = np.where(np.diag(J) < 0, -1.0, 1.0)
+            for _ in range(40 if cond_min is None else 200):
+                if cond_min is None:
+                    s = np.exp2(np.ceil(np.log2(gamma * rowsum))) * sign
+                else:
+                    s = gamma * rowsum * sign
                 Jb = J + np.diag(s)
                 if cond_max is None or np.linalg.cond(Jb) <= cond_max:
                     break
-                gamma *= 2.0
+                gamma *= 2.0 if cond_min is None else 2.0 ** 0.25
             pp, mp, var, ex, cff, bidx = _append_boost(pp, mp, var, ex, cff, L, s)
             J = Jb
-        if cond_max is None or np.linalg.cond(J) <= cond_max:
+        c2 = np.linalg.cond(J)
+        if (cond_max is None or c2 <= cond_max) and (cond_min is None or c2 >= cond_min):
             return System(name, L, n, d, pp, mp, var, ex, np.ascontiguousarray(cff), xstar, seed,
                           steps, bidx)
     raise RuntimeError(f"no system with cond <= {cond_max} after {max_tries} draws")
@@ -305,6 +313,16 @@ def medium_qd(seed: int = 2) -> System:
                        damping=DAMPING, boost_gamma=BOOST_GAMMA)
 
 
+def medium_qd_near_bound(seed: int = 2, cond_range=(3e2, 1e3)) -> System:
+    """The medium quad-double system (n=64, d=63, 32 monomials of 2..6
+    variables, exponents {1,2}) with the smallest boost that brings
+    cond_2(A_0) at x*(0) under the configuration's bound 1e3, kept when that
+    leaves it at least 3e2: the conditioning the configuration allows, instead
+    of the well-conditioned default (cond ~ 4)."""
+    return make_system("medium_qd_near_bound", 4, 64, 63, 32, 2, 6, (1, 2), seed, cond_range[1], boost=True,
+                       steps=6, damping=DAMPING, boost_gamma=1e-3, cond_min=cond_range[0])
+
+
 def large_od(seed: int = 3) -> System:
     """n=128, d=127, od; 64 monomials x 4..8 variables, exponents {1,2,3}; 8 steps."""
     return make_system("large_od", 8, 128, 127, 64, 4, 8, (1, 2, 3), seed, 1e4, boost=True, steps=8,
@@ -338,6 +356,23 @@ def batch_paths(count: int = 2048, L: int = 4, seed: int = 7, n_range=(16, 96), 
         mons = int(rng.integers(mons_range[0], mons_range[1] + 1))
         out.append(make_system(f"path{j}", L, n, d, mons, k_range[0], k_range[1], exps, seed * 100003 + j, 1e3,
                                boost=True, steps=6, damping=DAMPING, boost_gamma=BOOST_GAMMA, vectorized=True))
+    return out
+
+
+def bucket_paths(L: int = 4, seed: int = 11, ns=(20, 48, 90), ds=(15, 31, 63)) -> list:
+    """One path per size class of the batched workload: every n of ``ns``
+    with every d of ``ds`` (by default one path in each of the nine (n, D)
+    classes n <= 32, <= 64, <= 96 and D <= 16, 32, 64), drawn like
+    batch_paths (8..32 monomials per polynomial of 2..5 variables, exponent
+    1, boost, damped manufactured solutions)."""
+    rng = np.random.default_rng([seed, 4711])
+    out = []
+    for n in ns:
+        for d in ds:
+            mons = int(rng.integers(8, 33))
+            out.append(make_system(f"bucket_n{n}_d{d}", L, n, d, mons, 2, 5, (1,), seed * 100003 + n * 131 + d,
+                                   1e3, boost=True, steps=6, damping=DAMPING, boost_gamma=BOOST_GAMMA,
+                                   vectorized=True))
     return out
 
 

@@ -26,6 +26,12 @@ STATUS_NAMES = {0: "ok", -2: "singular", -3: "nonfinite"}
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run paper_2301_12659_amd.build.build() (or __graft_entry__.build())")
 
+# torch first: it carries a HIP runtime of its own, and the library must bind
+# to that one (loaded first, it satisfies the library's dependency by its
+# soname).  Loaded the other way round, the process holds two HIP runtimes
+# and the second one sees no device.
+import torch  # noqa: E402,F401
+
 _lib = ctypes.CDLL(LIB_PATH)
 
 _vp = ctypes.c_void_p

@@ -8,7 +8,7 @@ import pytest
 
 import mdinputs
 import oracle
-from gpu_helpers import TOL, dev, host, series_err, step_err
+from gpu_helpers import TOL, coef_err, dev, host, series_err, step_err
 
 pytestmark = pytest.mark.gpu
 
@@ -162,3 +162,59 @@ def test_batch_rejects_bad_paths(mdn):
     big = mdinputs.tiny(4, 130, 1, mons=1, kmin=1, kmax=1, exps=(1,), seed=2, cond_max=None)
     with pytest.raises(mdn.MdError):
         mdn.Batch([big])
+
+
+@pytest.fixture(scope="module")
+def bucket_paths():
+    return mdinputs.bucket_paths(4)
+
+
+@pytest.mark.parametrize("tiles", [4, 16])
+@pytest.mark.parametrize("prec_solve", [4, 2])
+def test_batch_every_size_class(mdn, bucket_paths, tiles, prec_solve):
+    """One path in each (n, D) class of the batched workload (n 20, 48, 90 with
+    D 16, 32, 64): the batched step with reduction teams of ``tiles`` lanes
+    equals each path's solo step (md_newton_step, or md_newton_step_mixed for
+    the quad-double residual with a double-double solve) within the solve
+    precision's tolerance, normwise and per coefficient; the largest path
+    also against the oracle step (plain quad double)."""
+    import torch
+
+    paths = bucket_paths
+    b, csts, cff, cst, x, status, norms, ws = _setup(mdn, paths)
+    b.set_tiles([tiles] * 9)
+    b.step(cff, cst, x, status, norms, ws, prec_solve=prec_solve)
+    torch.cuda.synchronize()
+    assert host(status).tolist() == [0] * len(paths)
+    got = b.unpack_series(host(x))
+    tol = TOL[prec_solve]
+    for p, s in enumerate(paths):
+        solo = mdn.Newton(s, csts[p])
+        solo.step(prec_solve=prec_solve)
+        sx = host(solo.x)
+        assert step_err(got[p], sx, s.start()) <= tol, (p, s.n, s.d)
+        assert coef_err(got[p], sx, s.start()) <= tol, (p, s.n, s.d)
+    if prec_solve == 4:
+        p = max(range(len(paths)), key=lambda q: paths[q].n * paths[q].D)
+        s = paths[p]
+        ref = oracle.newton_step(s, s.cff, csts[p], s.start())["x"]
+        assert step_err(got[p], ref, s.start()) <= TOL[4]
+        assert coef_err(got[p], ref, s.start()) <= TOL[4]
+
+
+def test_batch_every_size_class_converges(mdn, bucket_paths):
+    """Steps of the whole batch reach every path's manufactured solution
+    (plain quad double, then the quad-double residual with a double-double
+    solve from the start again)."""
+    import torch
+
+    paths = bucket_paths
+    for prec_solve, steps in ((4, 7), (2, 10)):
+        b, csts, cff, cst, x, status, norms, ws = _setup(mdn, paths)
+        for _ in range(steps):
+            b.step(cff, cst, x, status, norms, ws, prec_solve=prec_solve)
+        torch.cuda.synchronize()
+        assert host(status).tolist() == [0] * len(paths)
+        got = b.unpack_series(host(x))
+        for p, s in enumerate(paths):
+            assert series_err(got[p], s.xstar) <= TOL[4], (prec_solve, p, s.n, s.d)
