@@ -56,6 +56,27 @@ def _recorded_traffic():
     return int(kv["fetch_bytes_per_launch"]) + int(kv["write_bytes_per_launch"])
 
 
+_SQ_FILE = os.path.join(ROOT, "profiles", "evaldiff_kernel_medium_qd_sq_counters.md")
+
+
+def _recorded_sq():
+    """FP64 VALU instruction counts per evaldiff launch from the recorded SQ
+    counters, or None when no record exists or the kernel's sources changed
+    since it was taken."""
+    try:
+        with open(_SQ_FILE) as fh:
+            kv = dict(line.strip().split(": ", 1) for line in fh if ": " in line and line.split(":")[0] in
+                      ("source_sha256", "add_f64", "mul_f64", "fma_f64", "trans_f64", "valu"))
+    except OSError:
+        return None
+    if kv.get("source_sha256") != evaldiff_source_sha256():
+        return None
+    try:
+        return {k: float(v) for k, v in kv.items() if k != "source_sha256"}
+    except ValueError:
+        return None
+
+
 def _err_vs(mdn, torch, x, ref):
     """Normwise relative error per series, max over series, of x against ref
     (both [L, n, D] device tensors), computed with the library's md subtraction."""
@@ -103,6 +124,17 @@ def _bench_batch(mdn, torch, np, mdinputs, npaths, steps):
                        "2..5 variables, exponent 1, manufactured solutions, seed 7",
            "paths": npaths, "total_unknown_series": int(sum(s.n for s in paths)),
            "tiles_per_bucket": tiles, "autotune_s": round(tune_s, 2)}
+    xs = dev(b.pack_series([s.xstar for s in paths]))
+    # per-path relative error against x*: the library's md subtraction, then
+    # max |diff| / max |x*| over each path's block (leading limbs)
+    bounds = [(int(o), int(o) + s.n * s.D) for o, s in zip(b.x_off, paths)]
+
+    def worst_err():
+        d = torch.empty_like(x)
+        mdn.arith(4, "sub", x.contiguous(), xs, d)
+        dd, xx = d[0].abs().cpu().numpy(), xs[0].abs().cpu().numpy()
+        return max(float(dd[a:c].max() / xx[a:c].max()) for a, c in bounds)
+
     for name, ls in (("plain_qd", 4), ("mixed_qd_dd", 2)):
         x.copy_(x0)
         for _ in range(2):  # eager, then captured
@@ -116,8 +148,118 @@ def _bench_batch(mdn, torch, np, mdinputs, npaths, steps):
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / steps
         bad = int((status != 0).sum().item())
+        # steps from x*(0) until every path is within the quad-double tolerance
+        x.copy_(x0)
+        k = 0
+        while k < 14:
+            b.step(cff, cst, x, status, norms, ws, prec_solve=ls)
+            k += 1
+            if worst_err() <= 1e-60:
+                break
         res[name] = {"ms_per_batched_step": round(ms, 3), "path_steps_per_s": round(npaths * 1000.0 / ms, 1),
-                     "paths_not_ok": bad}
+                     "paths_not_ok": bad, "steps_to_tol": k, "worst_path_err": worst_err(),
+                     "ms_to_tol": round(k * ms, 3)}
+    res["tol"] = 1e-60
+    return res
+
+
+def _manufactured(mdn, torch, np, s):
+    """A Newton driver on the system s with c_{i,0} = -P_i(x*) computed on the
+    GPU (the evaluation at x* with a zero constant), at x*(0)."""
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    drv = mdn.Newton(s, np.zeros((s.L, s.n, s.D)), s.xstar)
+    b = torch.empty((s.L, s.n, s.D), dtype=torch.float64, device="cuda")
+    A = torch.empty((s.L, s.n, s.n, s.D), dtype=torch.float64, device="cuda")
+    mdn.eval_diff(drv.plan, drv.cff, drv.cst, drv.x, b, A, drv.ws)
+    drv.cst.copy_(b)
+    drv.x.copy_(dev(s.start()))
+    del A
+    torch.cuda.synchronize()
+    return drv, dev(s.start()), dev(s.xstar)
+
+
+TOL = {2: 1e-28, 4: 1e-60, 8: 1e-120}
+
+
+def _bench_configs(mdn, torch, np, mdinputs, reps):
+    """The other configurations: their full runs from x*(0) (small dd: 4
+    steps, large od: 8, adjoint qd: 6) by md_newton_steps, steps/s over
+    `reps` runs after one untimed run, the error against the manufactured
+    solution; for the adjoint configuration also the backward pass of the
+    differentiable solve (loss = sum of squares of the top 8 coefficients,
+    gradient with respect to every monomial coefficient)."""
+    res = {}
+    for name, make, runs in (("small_dd", mdinputs.small_dd, reps), ("large_od", mdinputs.large_od, 1),
+                             ("adjoint_qd", mdinputs.adjoint_qd, reps)):
+        s = make()
+        drv, x0, xs = _manufactured(mdn, torch, np, s)
+        drv.steps(s.steps)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ms = 0.0
+        for _ in range(runs):
+            drv.x.copy_(x0)
+            e0.record()
+            drv.steps(s.steps)
+            e1.record()
+            torch.cuda.synchronize()
+            ms += e0.elapsed_time(e1)
+        r = {"n": s.n, "d": s.d, "precision": {2: "dd", 4: "qd", 8: "od"}[s.L], "steps_per_run": s.steps,
+             "ms_per_step": round(ms / (runs * s.steps), 4), "steps_per_s": round(runs * s.steps * 1000.0 / ms, 2),
+             "err_vs_manufactured": _err_vs(mdn, torch, drv.x, xs), "tol": TOL[s.L], "status": drv.status_code()}
+        if name == "adjoint_qd":
+            cff = drv.cff.clone().requires_grad_(True)
+            times = []
+            for q in range(reps + 1):
+                x = mdn.newton_solve(cff, drv.plan, drv.cst, x0, s.steps)
+                loss = mdn.top_coefficient_loss(x, s.D - 8)
+                torch.cuda.synchronize()
+                e0.record()
+                mdn.md_backward(loss)
+                e1.record()
+                torch.cuda.synchronize()
+                if q:
+                    times.append(e0.elapsed_time(e1))
+                cff.grad = None
+            r["backward_ms"] = round(min(times), 4)
+            r["backward"] = ("A(t) at the solution, QR of A_0, the transposed staged solve and the coefficient "
+                             "gradients (%d monomial coefficients)" % s.m)
+        res[name] = r
+        del drv
+        torch.cuda.empty_cache()
+    return res
+
+
+def _bench_mixed(mdn, torch, np, drv, x0, xstar, max_steps=12):
+    """Time to the quad-double tolerance on the medium system from x*(0):
+    plain quad-double steps against steps with a quad-double residual and a
+    double-double solve (md_newton_step_mixed), each as many steps as reach
+    1e-60 against the manufactured solution, timed back to back."""
+    res = {}
+    for name, ps in (("plain_qd", None), ("mixed_qd_dd", 2)):
+        drv.x.copy_(x0)
+        k = 0
+        while k < max_steps:
+            drv.step(prec_solve=ps)
+            k += 1
+            if _err_vs(mdn, torch, drv.x, xstar) <= 1e-60:
+                break
+        err = _err_vs(mdn, torch, drv.x, xstar)
+        times = []
+        for r in range(4):
+            drv.x.copy_(x0)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(k):
+                drv.step(prec_solve=ps)
+            e1.record()
+            torch.cuda.synchronize()
+            if r:
+                times.append(e0.elapsed_time(e1))
+        res[name] = {"steps_to_tol": k, "ms_to_tol": round(min(times), 4), "ms_per_step": round(min(times) / k, 4),
+                     "err_vs_manufactured": err}
+    res["tol"] = 1e-60
     return res
 
 
@@ -344,6 +486,8 @@ def main():
     ap.add_argument("--batch-paths", type=int, default=2048,
                     help="paths of the batched workload (0 skips it)")
     ap.add_argument("--batch-steps", type=int, default=4)
+    ap.add_argument("--config-reps", type=int, default=5,
+                    help="timed runs of the small dd, large od and adjoint configurations (0: skip)")
     ap.add_argument("--stagger-repeats", type=int, default=3,
                     help="timed runs of each staggered time-to-solution measurement (0: skip)")
     ap.add_argument("--replay", action="store_true",
@@ -398,15 +542,16 @@ def main():
 
     for _ in range(args.warmup):
         drv.step()
+    drv.steps(args.warmup)
     torch.cuda.synchronize()
 
-    # timed region 1: plain steps
+    # timed region 1: K steps by md_newton_steps (each step's factorization
+    # beside the previous step; the same iterates as K md_newton_step calls)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     e0.record()
-    for _ in range(args.steps):
-        drv.step()
+    drv.steps(args.steps)
     e1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -414,11 +559,18 @@ def main():
     status = drv.status_code()
     err_manufactured = _err_vs(mdn, torch, drv.x, xstar)
 
+    # the same number of single md_newton_step calls (QR on the critical path)
+    e0.record()
+    for _ in range(args.steps):
+        drv.step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms_single = e0.elapsed_time(e1) / args.steps
+
     # timed region 2: the same steps with per-kernel-class HIP events
     mdn.timing_enable(True)
     mdn.timing_read()
-    for _ in range(args.steps):
-        drv.step()
+    drv.steps(args.steps)
     torch.cuda.synchronize()
     classes = mdn.timing_read()
     mdn.timing_enable(False)
@@ -426,18 +578,43 @@ def main():
     w = work.step_work(sysm)
     breakdown = {}
     for cls, (ms, cnt) in classes.items():
-        per = ms / max(cnt, 1)
+        per_step = ms / args.steps
         fl = w[cls]["flops"] if cls in w else 0
-        breakdown[cls] = {"ms_per_step": round(ms / args.steps, 4), "launch_ms": round(per, 4),
-                          "tflops": round(fl / (per * 1e-3) / 1e12, 3) if per > 0 else None}
+        breakdown[cls] = {"ms_per_step": round(per_step, 4), "brackets_per_step": round(cnt / args.steps, 2),
+                          "tflops": round(fl / (per_step * 1e-3) / 1e12, 3) if per_step > 0 else None}
     # the dominant kernel is the evaluation/differentiation (class
     # "convolutions", one evaldiff launch per step on the caller's stream):
-    # it carries most of the arithmetic; the QR class runs on the second
-    # stream beside it and its time overlaps
+    # it carries most of the arithmetic and, with the factorization beside
+    # the previous step, it is on the critical path
     dom = "convolutions"
     dom_ms = classes[dom][0] / max(classes[dom][1], 1)
     achieved = w[dom]["flops"] / (dom_ms * 1e-3) / 1e12
     total_flops = sum(v["flops"] for v in w.values())
+    qr_b = work.qr_latency_bound(L, n)
+    st_b = work.stages_latency_bound(L, n, D)
+    qr_ms = (classes["qr"][0] + classes["qhb_bs"][0]) / args.steps
+    st_ms = classes["updates"][0] / args.steps
+    latency = {
+        "model": "dependent FP64 instructions on the chain x %.1f cycles at %.1f GHz + %.1f us per hand-over"
+                 % (work.CYCLES_PER_DEP_INSTR, work.CLOCK_HZ / 1e9, work.HANDOVER_S * 1e6),
+        "qr_and_m": {"bound_ms": round(qr_b["seconds"] * 1e3, 4), "chain_instr_per_column": qr_b["chain_instr_per_column"],
+                     "measured_ms": round(qr_ms, 4), "frac": round(qr_b["seconds"] * 1e3 / qr_ms, 3)},
+        "staged_solve": {"bound_ms": round(st_b["seconds"] * 1e3, 4), "chain_instr_per_stage": st_b["chain_instr_per_stage"],
+                         "measured_ms": round(st_ms, 4), "frac": round(st_b["seconds"] * 1e3 / st_ms, 3)},
+    }
+    sq = _recorded_sq()
+    conventions = {"useful_tflops": round(achieved, 3), "useful_frac": round(achieved / PEAK_FP64_TFLOPS, 4)}
+    if sq:
+        ex = 64.0 * (sq["add_f64"] + sq["mul_f64"] + sq.get("trans_f64", 0.0) + 2.0 * sq["fma_f64"])
+        lane_ops = 64.0 * (sq["add_f64"] + sq["mul_f64"] + sq.get("trans_f64", 0.0) + sq["fma_f64"])
+        t = dom_ms * 1e-3
+        conventions.update({
+            "executed_tflops": round(ex / t / 1e12, 3), "executed_frac": round(ex / t / 1e12 / PEAK_FP64_TFLOPS, 4),
+            "fp64_pipe_utilization": round(lane_ops / (64.0 * 256 * 2.4e9 * t), 4),
+            "counters": "profiles/evaldiff_kernel_medium_qd_sq_counters.md (same kernel sources)"})
+    else:
+        conventions.update({"executed_tflops": None, "fp64_pipe_utilization": None,
+                            "counters": "no SQ counters recorded for the current kernel sources"})
 
     out = {
         "metric": "Newton steps/s and FP64 GFLOPS (% FP64 vector peak) at n=64,d=63 qd; err vs oracle",
@@ -455,11 +632,17 @@ def main():
         "config": {"workload": "medium_qd: n=64, d=63 (D=64), quad double, 64 x (32 + 1 boost) monomials, "
                                "2..6 variables, exponents {1,2}, manufactured solution, seed 2",
                    "n": n, "d": sysm.d, "precision": "qd", "monomials": sysm.m, "support_entries": sysm.nnz},
+        "steps_entry_point": "md_newton_steps (each step's QR beside the previous step; iterates identical to "
+                             "md_newton_step calls)",
+        "single_step_ms": round(ms_single, 4),
+        "single_step_per_s": round(1000.0 / ms_single, 3),
         "gflops_step": round(total_flops / (ms_step * 1e-3) / 1e9, 2),
         "pct_fp64_peak_step": round(100 * total_flops / (ms_step * 1e-3) / (PEAK_FP64_TFLOPS * 1e12), 2),
         "roofline": {"bound": "alu", "kernel": "evaldiff_kernel<4> (" + dom + ")", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": _recorded_traffic(),
                      "flops_per_launch": w[dom]["flops"], "launch_ms": round(dom_ms, 4)},
+        "evaldiff_conventions": conventions,
+        "latency_roofline": latency,
         "kernel_classes": breakdown,
         "paper_convention_conv_gflops": round(work.paper_convention_flops(sysm) /
                                               (classes["convolutions"][0] / max(classes["convolutions"][1], 1) * 1e-3) / 1e9, 1),
@@ -489,6 +672,11 @@ def main():
     out["residual"] = res_t
 
     out["complex"] = _bench_complex(mdn, torch, np, mdinputs, sysm)
+
+    out["mixed"] = _bench_mixed(mdn, torch, np, drv, dev(sysm.start()), xstar)
+
+    if args.config_reps > 0:
+        out["configs"] = _bench_configs(mdn, torch, np, mdinputs, args.config_reps)
 
     if args.stagger_repeats > 0:
         out["staggered"] = _bench_staggered(mdn, torch, np, sysm, drv.cst, xstar, args.stagger_repeats)

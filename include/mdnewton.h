@@ -145,6 +145,25 @@ int md_series_solve(int prec, int n, int d, const double *qr, const double *tau,
 int md_newton_step(const md_plan *plan, const double *cff, const double *cst, double *x, int32_t *dev_status,
                    double *dev_norms, void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* count plain Newton steps, x := x + dx each time, with results identical bit
+ * for bit to count calls of md_newton_step.  The QR of A_0 is on the critical
+ * path of a single step; here it is taken off: A_0 of the next step depends
+ * only on coefficient 0 of the next iterate, x_0 + dx_0, and dx_0 = M b_0
+ * (the first stage of the staged solve, Section 2) is formed as soon as the
+ * current step has its factorization and its b.  The pre-pass, QR and
+ * back substitution of step s+1 then run on the plan's second stream beside
+ * the staged solve of step s and the evaluation of step s+1 (the QR is
+ * still computed for every step; Section 5.3 computes it once per path).
+ * This applies to plans whose staged solve runs in one persistent launch
+ * (double or quad double, n <= 64) with supports of at most 8 variables;
+ * other plans take count ordinary steps.  dev_status: MD_OK, or the failure
+ * of any of the steps (the steps overlap, so the status is not reset between
+ * them); dev_norms: those of the last step.  Workspace as md_newton_step;
+ * the last step leaves its factorization where md_newton_step does, for
+ * md_newton_step_window with keep_factorization.  MD_EINVAL for count < 0. */
+int md_newton_steps(const md_plan *plan, int count, const double *cff, const double *cst, double *x,
+                    int32_t *dev_status, double *dev_norms, void *ws, size_t ws_bytes, hipStream_t stream);
+
 /* One Newton step in mixed precision.  The introduction (Section 1) recalls
  * that the early coefficients must be computed more accurately than the late
  * ones, and Section 1.2 places multiple doubles in the trend of mixed
@@ -207,8 +226,10 @@ typedef struct md_stagger_report {
  * per monomial, the largest coefficient k of the products f_j along its
  * forward chain (leading limbs; tol = 0 drops only exactly zero residuals),
  * or whose relative residual max_i |b_{i,k}| / s_{i,k} did not halve since
- * the previous step (a Newton or chord step reduces it far more, so it has
- * reached the level of the rounding errors).  refactor_every_step = 0 factors
+ * the previous step while below 2^(-40 L) (a Newton or chord step reduces it
+ * far more, so it has reached the level of the rounding errors; the ceiling
+ * keeps a slowly contracting chord iteration from freezing a coefficient far
+ * above that level).  refactor_every_step = 0 factors
  * A_0 once, at the first step (Section 5.3), and makes every later step a
  * chord step; 1 factors at every step (Newton's method).  Stops when hi = D
  * and every coefficient meets the tolerance (converged = 1) or after

@@ -49,6 +49,7 @@ _lib.md_qr_noalloc.argtypes = [_i32, _i32, _vp, _vp, _vp, _vp]
 _lib.md_solve_workspace_size.argtypes = [_i32, _i32, _i32, _szp]
 _lib.md_series_solve.argtypes = [_i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp, _vp]
 _lib.md_newton_step.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
+_lib.md_newton_steps.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
 _lib.md_newton_step_mixed.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
 _lib.md_newton_step_window.argtypes = [_vp, _i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t,
                                        _vp]
@@ -324,6 +325,15 @@ def newton_step(plan: Plan, cff, cst, x, status, norms, ws, stream=None):
     _check(rc, "md_newton_step")
 
 
+def newton_steps(plan: Plan, count, cff, cst, x, status, norms, ws, stream=None):
+    """md_newton_steps: count plain steps, each factorization beside the previous step."""
+    L, n, D, m = plan.prec, plan.n, plan.D, plan.m
+    rc = _lib.md_newton_steps(plan._h, int(count), _ptr(cff, (L, m), "cff"), _ptr(cst, (L, n, D), "cst"),
+                              _ptr(x, (L, n, D), "x"), _ptr(status, (1,), "status"),
+                              _ptr(norms, (2, D), "norms"), _ptr(ws, None, "ws"), ws.numel() * 8, _stream(stream))
+    _check(rc, "md_newton_steps")
+
+
 def newton_step_mixed(plan: Plan, prec_solve, cff, cst, x, status, norms, ws, stream=None):
     L, n, D, m = plan.prec, plan.n, plan.D, plan.m
     rc = _lib.md_newton_step_mixed(plan._h, int(prec_solve), _ptr(cff, (L, m), "cff"), _ptr(cst, (L, n, D), "cst"),
@@ -502,6 +512,11 @@ class Newton:
             newton_step_mixed(self.plan, prec_solve, self.cff, self.cst, self.x, self.status, self.norms, self.ws,
                               stream)
 
+    def steps(self, count, stream=None):
+        """count plain steps (md_newton_steps): the same iterates as count calls
+        of step(), with each factorization computed beside the previous step."""
+        newton_steps(self.plan, count, self.cff, self.cst, self.x, self.status, self.norms, self.ws, stream)
+
     def step_window(self, lo, hi, keep_factorization=False, stream=None, prec_solve=None):
         """One step of the staggered method on the window lo..hi-1 (md_newton_step_window)."""
         ps = self.plan.prec if prec_solve is None else prec_solve
@@ -592,8 +607,7 @@ def _torch_fns():
             status = torch.zeros(1, dtype=torch.int32, device=cff.device)
             norms = torch.zeros((2, D), dtype=torch.float64, device=cff.device)
             x = x0.clone().contiguous()
-            for _ in range(int(steps)):
-                newton_step(plan, cff.contiguous(), cst, x, status, norms, ws)
+            newton_steps(plan, int(steps), cff.contiguous(), cst, x, status, norms, ws)
             ctx.plan = plan
             ctx.save_for_backward(cff, cst, x)
             return x

@@ -81,7 +81,12 @@ size_t qr_scratch_bytes(int L, int n) {
 
 // Workspace regions, in doubles, each aligned to 256 bytes.
 struct Layout {
-  size_t val, der, pw, unit, b, A, qr, tau, qt, bar, invd, M, N, At, r, dxT, dx, sync, vsz, tsz, scale, total;
+  size_t val, der, pw, unit, b, A, qr, tau, qt, bar, invd, M, N, At, r, dxT, dx, sync, vsz, tsz, scale;
+  // the second factorization of md_newton_steps (QR, tau, Q^T and M of the
+  // next step, computed while the current one finishes), coefficient 0 of
+  // the next iterate and the derivative products of its pre-pass
+  size_t qr2, tau2, qt2, M2, xn, der0;
+  size_t total;
 };
 
 Layout newton_layout(const md_plan *p) {
@@ -114,6 +119,12 @@ Layout newton_layout(const md_plan *p) {
   w.vsz = take((size_t)p->m * D);  // chain maxima of the monomials' forward products
   w.tsz = take(n * D);  // sizes of the terms of b_{i,k} and their maxima over i, for the staggered driver
   w.scale = take(D);
+  w.qr2 = take(L * n * n);
+  w.tau2 = take(L * n);
+  w.qt2 = take(L * n * n);
+  w.M2 = take(L * n * n);
+  w.xn = take(L * n);
+  w.der0 = take(L * p->nnz + 1);
   w.total = off;
   return w;
 }
@@ -588,6 +599,124 @@ int md_newton_step(const md_plan *p, const double *cff, const double *cst, doubl
   return newton_step_impl(p, p->L, 0, p->D, false, cff, cst, x, dev_status, dev_norms, nullptr, ws, st);
 }
 
+// Whether md_newton_steps can overlap the factorization of the next step
+// with the current one: plain steps whose staged solve is the persistent
+// kernel (its first stage is what next_x0_kernel reproduces) and whose A_0
+// comes from the coefficient-0 pre-pass.
+static bool steps_pipelined(const md_plan *p) {
+  return p->m > 0 && p->D > 1 && mdk::stages_persistent(p->L, p->n, p->D) &&
+         p->maxk <= mdk::evaldiff0_max_support(p->L);
+}
+
+// count plain Newton steps.  A_0 of step s+1 depends on coefficient 0 of its
+// iterate only, x_0 + dx_0, and dx_0 = M r_0 is known once step s has M and
+// b: next_x0_kernel forms it (bit for bit as the staged solve and the update
+// will) right after the join, and the pre-pass, QR and M of step s+1 run on
+// the second stream while step s finishes its staged solve and step s+1
+// evaluates.  Factorizations alternate between two sets of buffers, the last
+// step using the first set (the one md_newton_step and chord steps use).
+static int newton_steps_impl(const md_plan *p, int count, const double *cff, const double *cst, double *x,
+                             int32_t *dev_status, double *dev_norms, void *ws, hipStream_t st) {
+  if (!steps_pipelined(p)) {
+    for (int s = 0; s < count; ++s) {
+      const int rc = newton_step_impl(p, p->L, 0, p->D, false, cff, cst, x, dev_status, dev_norms, nullptr, ws, st);
+      if (rc != MD_OK) return rc;
+    }
+    return MD_OK;
+  }
+  Layout w = newton_layout(p);
+  const int L = p->L, n = p->n, D = p->D;
+  const size_t nn = (size_t)n * n;
+  hipError_t e;
+  if ((e = mdk::launch_status_init(dev_status, st)) != hipSuccess) return hip_fail(e, "status");
+  double *b = at(ws, w.b), *A = at(ws, w.A), *r = at(ws, w.r), *dx = at(ws, w.dx), *N = at(ws, w.N);
+  double *At = at(ws, w.At), *dxT = at(ws, w.dxT), *invd = at(ws, w.invd), *xn = at(ws, w.xn);
+  double *qrs[2] = {at(ws, w.qr), at(ws, w.qr2)}, *taus[2] = {at(ws, w.tau), at(ws, w.tau2)};
+  double *qts[2] = {at(ws, w.qt), at(ws, w.qt2)}, *Ms[2] = {at(ws, w.M), at(ws, w.M2)};
+  int *sync = reinterpret_cast<int *>(at(ws, w.sync));
+  // factorization of the iterate whose coefficient 0 is in xn ([L][n]) into
+  // buffer set k, on the second stream after the fork event; its pre-pass
+  // has derivative products of its own (der0), since the evaluation of the
+  // current step runs beside it
+  auto factor = [&](int k) -> int {
+    if ((e = hipEventRecord(p->fork, st)) != hipSuccess) return hip_fail(e, "fork");
+    if ((e = hipStreamWaitEvent(p->aux, p->fork, 0)) != hipSuccess) return hip_fail(e, "fork wait");
+    {
+      Timed t(MD_CLASS_QR, p->aux);
+      mdk::EvalArgs a;
+      eval_args(p, cff, xn, ws, 1, a);
+      a.D = 1;  // one coefficient per series: xn and der0 [L][nnz]
+      a.der = at(ws, w.der0);
+      if ((e = mdk::launch_evaldiff0(L, a, p->aux)) != hipSuccess) return hip_fail(e, "A_0 pre-pass");
+      if ((e = mdk::launch_assemble_A0(L, n, 1, p->nnz, p->d_asm_ptr, p->d_asm_ent, a.der, qrs[k], p->aux)) !=
+          hipSuccess)
+        return hip_fail(e, "A_0 assembly");
+      if ((e = run_qr(L, n, qrs[k], taus[k], qts[k], dev_status, at(ws, w.bar), p->aux)) != hipSuccess)
+        return hip_fail(e, "qr");
+    }
+    {
+      Timed t(MD_CLASS_QHB_BS, p->aux);
+      if ((e = mdk::launch_m_from_qt(L, n, qrs[k], qts[k], invd, Ms[k], dev_status, p->aux)) != hipSuccess)
+        return hip_fail(e, "M");
+    }
+    if ((e = hipEventRecord(p->join, p->aux)) != hipSuccess) return hip_fail(e, "join");
+    return MD_OK;
+  };
+  // coefficient 0 of the first iterate into xn
+  if ((e = mdk::launch_transpose_ld(L, x, D, xn, n, n, 1, (size_t)n * D, n, st)) != hipSuccess)
+    return hip_fail(e, "x_0");
+  int rc = factor((count - 1) % 2);
+  if (rc != MD_OK) return rc;
+  for (int s = 0; s < count; ++s) {
+    const int k = (count - 1 - s) % 2;
+    rc = eval_diff_impl(p, D, cff, cst, x, b, A, ws, st, nullptr, true);
+    if (rc != MD_OK) return rc;
+    {
+      Timed t(MD_CLASS_UPDATES, st);
+      if ((e = mdk::launch_transpose_ld(L, A, D, At, nn, nn, D, nn * D, nn * D, st)) != hipSuccess)
+        return hip_fail(e, "A^T");
+      if ((e = mdk::launch_transpose_ld(L, b, D, r, n, n, D, (size_t)n * D, (size_t)n * D, st)) != hipSuccess)
+        return hip_fail(e, "b^T");
+    }
+    if ((e = mdk::launch_stages_sync(L, n, D, sync, st)) != hipSuccess) return hip_fail(e, "stage counters");
+    if ((e = hipStreamWaitEvent(st, p->join, 0)) != hipSuccess) return hip_fail(e, "join wait");
+    if (s + 1 < count) {
+      // coefficient 0 of the next iterate, then its factorization beside
+      // the rest of this step and the next evaluation
+      {
+        Timed t(MD_CLASS_X_UPDATE, st);
+        if ((e = mdk::launch_next_x0(L, n, D, Ms[k], r, x, xn, st)) != hipSuccess) return hip_fail(e, "next x_0");
+      }
+      if ((rc = factor(1 - k)) != MD_OK) return rc;
+    }
+    {
+      Timed t(MD_CLASS_GEMM, st);
+      if ((e = mdk::launch_gemm(L, n, Ms[k], At + nn, nn * D, N, mdk::stages_products(L, n, D), st)) != hipSuccess)
+        return hip_fail(e, "gemm");
+    }
+    {
+      Timed t(MD_CLASS_UPDATES, st);
+      if ((e = mdk::launch_stages(L, n, D, Ms[k], N, At, r, dxT, sync, dev_status, st, true)) != hipSuccess)
+        return hip_fail(e, "stages");
+    }
+    {
+      Timed t(MD_CLASS_X_UPDATE, st);
+      if ((e = mdk::launch_finish(L, L, n, D, 0, D, dxT, dx, x, b, dev_norms, dev_status, st)) != hipSuccess)
+        return hip_fail(e, "update");
+    }
+  }
+  return MD_OK;
+}
+
+int md_newton_steps(const md_plan *p, int count, const double *cff, const double *cst, double *x, int32_t *dev_status,
+                    double *dev_norms, void *ws, size_t ws_bytes, hipStream_t st) {
+  if (!p || !cst || !x || (p->m > 0 && !cff)) return fail(MD_EINVAL, "NULL argument");
+  if (count < 0) return fail(MD_EINVAL, "negative step count");
+  if (!ws || ws_bytes < newton_layout(p).total) return fail(MD_ENOSPACE, "workspace too small");
+  if (count == 0) return MD_OK;
+  return newton_steps_impl(p, count, cff, cst, x, dev_status, dev_norms, ws, st);
+}
+
 int md_newton_step_mixed(const md_plan *p, int prec_solve, const double *cff, const double *cst, double *x,
                          int32_t *dev_status, double *dev_norms, void *ws, size_t ws_bytes, hipStream_t st) {
   if (!p || !cst || !x || (p->m > 0 && !cff)) return fail(MD_EINVAL, "NULL argument");
@@ -667,11 +796,18 @@ int md_newton_staggered(const md_plan *p, int prec_solve, int refactor_every_ste
     // leading coefficients that are done: residual within tol of its terms,
     // or a residual that did not halve since the last step (a Newton or chord
     // step reduces it far more: it is at the level of the rounding errors).
-    // Coefficients below lo are done and stay frozen, so lo never decreases.
+    // A chord step contracts an error e to about sigma e, sigma the distance
+    // of the kept factorization; with sigma above 1/2 a residual far above
+    // the rounding level would not halve either, so a stalled residual
+    // counts only once it is below 2^(-40 L), under the square root of the
+    // unit roundoff but far above the rounding level of these residuals
+    // (2^(-53 L) times the chain lengths).  Coefficients below lo are done
+    // and stay frozen, so lo never decreases.
+    const double stall_ceiling = std::ldexp(1.0, -40 * p->L);
     int k = lo;
     while (k < hi) {
       const double rk = h[2 * (size_t)D + k];
-      if (!(rk <= tol || rk > 0.5 * prev[k])) break;
+      if (!(rk <= tol || (rk > 0.5 * prev[k] && rk <= stall_ceiling))) break;
       ++k;
     }
     for (int q = 0; q < hi; ++q) prev[q] = h[2 * (size_t)D + q];

@@ -865,6 +865,40 @@ __device__ __forceinline__ bool wait_geq(const int *ctr, int target, int32_t *st
   return true;
 }
 
+// Coefficient 0 of the next iterate, x_0 + dx_0 with dx_0 = M r_0, by the
+// operations the persistent staged solve and finish_kernel apply to it: one
+// wavefront per row i, lane v accumulates M(i, v) r_0(v) into zeroed level
+// sums, one 64-lane butterfly of level sums, one renormalization (the first
+// stage of stages_persistent_kernel), then the addition of finish_kernel.
+// The result is therefore the x_0 that the next step reads, bit for bit,
+// available before the staged solve has run; xn [L][n].  The two kernels
+// must keep these operations in step.
+template <int L>
+__global__ void __launch_bounds__(256) next_x0_kernel(int n, int D, const double *M, const double *rT,
+                                                      const double *x, double *xn) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int i = blockIdx.x * 4 + wv;
+  const bool row = i < n, col = lane < n;
+  const int ii = row ? i : 0, v = col ? lane : 0;
+  const size_t nn = (size_t)n * n, nD = (size_t)n * D;
+  double acc[L], r[L];
+  md::zero<L>(acc);
+  if (col) {
+    double m[L], a[L];
+    ld<L>(M, nn, (size_t)ii * n + v, m);
+    ld<L>(rT, nD, (size_t)v, a);
+    MD<L>::fma_lazy(acc, m, a);
+  }
+  team_sum_lazy<L>(acc, 64);
+  MD<L>::renorm(acc, r);
+  if (row && lane == 0) {
+    double a[L], sum[L];
+    ld<L>(x, nD, (size_t)i * D, a);
+    MD<L>::add(a, r, sum);
+    st<L>(xn, n, i, sum);
+  }
+}
+
 // Counters of the persistent staged solve, one per 256 bytes so that the
 // polls of one do not contend with the updates of another.
 constexpr int SYNC_STRIDE = 64;
@@ -1493,6 +1527,17 @@ hipError_t launch_stages(int L, int n, int D, const double *M, const double *NP,
     const unsigned blocks = (unsigned)(crit_blocks + (bulk + 255) / 256);
     MD_DISPATCH(L, hipLaunchKernelGGL(stage_kernel<LL>, dim3(blocks), dim3(256), 0, st, n, D, k, M, NP, At, rT, dxT));
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_next_x0(int L, int n, int D, const double *M, const double *rT, const double *x, double *xn,
+                          hipStream_t st) {
+  if (!stages_persistent(L, n, D)) return hipErrorInvalidValue;
+  const dim3 grid((n + 3) / 4), block(256);
+  if (L == 2)
+    hipLaunchKernelGGL(next_x0_kernel<2>, grid, block, 0, st, n, D, M, rT, x, xn);
+  else
+    hipLaunchKernelGGL(next_x0_kernel<4>, grid, block, 0, st, n, D, M, rT, x, xn);
   return hipGetLastError();
 }
 

@@ -108,3 +108,76 @@ def convolution_flops(sys, order: int) -> dict:
     ours = (conv * order * (order + 1) // 2 * cost["fma_lazy"]["flops"] + conv * order * cost["renorm"]["flops"] +
             scal * order * cost["mul"]["flops"])
     return {"flops": int(ours), "paper_flops": int(conv * order * order * PAPER_MUL_COST[sys.L]), "products": conv}
+
+
+# ----------------------------------------------------------------- latency
+#
+# The QR of A_0 and the staged solve are dependent chains: each column of
+# the factorization needs the previous reflector, each stage the previous
+# dx.  Their bound is not the FP64 issue rate of the chip but the length of
+# the chain times the cycles one wavefront needs per dependent instruction
+# (measured with clock stamps in one wavefront: about 4.8 cycles per FP64
+# instruction of a multiple-double chain at 2.4 GHz), plus what a hand-over
+# between workgroups costs (measured: about 0.6 us for a flag).
+
+CYCLES_PER_DEP_INSTR = 4.8
+CLOCK_HZ = 2.4e9
+HANDOVER_S = 0.6e-6
+
+
+def _butterfly(c, width=64):
+    """A sum of level-sum accumulators over `width` lanes: log2(width)
+    add_lazy levels, then one renormalization."""
+    levels = int(np.log2(width))
+    return levels * c["add_lazy"]["instr"] + c["renorm"]["instr"]
+
+
+def newton_chain_instr(L: int, kind: str) -> int:
+    """FP64 instructions of the shortened 1/sqrt or reciprocal sequences of
+    the Householder reflector (md.hpp: rsqrt_short, recip_short; the full
+    sequences for octo doubles), counted from their multiple-double
+    operations."""
+    def c(P):
+        return md_costs(P)
+
+    if L >= 8:  # full sequence: steps at 2, 4, 8 limbs, then a one-limb-correction step at 8
+        steps = [(2, 1), (4, 2), (8, 8), (8, 1)]
+    elif L == 4:
+        steps = [(2, 1), (4, 4)]
+    else:
+        steps = [(2, 2)]
+    total = 2  # the double start: a square root or a division
+    for P, H in steps:
+        cp = c(P)
+        corr = 1 if H == 1 else c(H)["mul"]["instr"]
+        if kind == "rsqrt":  # y^2, a y^2, 1 - a y^2, correction, y + c
+            total += 2 * cp["mul"]["instr"] + cp["sub"]["instr"] + corr + cp["add"]["instr"]
+        else:                # v r, 1 - v r, correction, r + c
+            total += cp["mul"]["instr"] + cp["sub"]["instr"] + corr + cp["add"]["instr"]
+    return int(total)
+
+
+def qr_latency_bound(L: int, n: int, with_qt: bool = True) -> dict:
+    """Lower bound of the column-by-column Householder QR of A_0 (with Q^T
+    on the augmented columns): per column, the dot of the new reflector with
+    the next column (one lazy multiply-add per lane, a 64-lane butterfly),
+    that column's update (one multiply-add), its norm (the same dot
+    structure), the reflector scalars (1/sqrt and a reciprocal), x_0 - beta
+    and the scaling, and one hand-over to the other workgroups."""
+    c = md_costs(L)
+    dot = c["fma_lazy"]["instr"] + _butterfly(c)
+    per_col = (2 * dot + c["fma"]["instr"] + newton_chain_instr(L, "rsqrt") + newton_chain_instr(L, "recip") +
+               c["sub"]["instr"] + c["mul"]["instr"])
+    s = n * (per_col * CYCLES_PER_DEP_INSTR / CLOCK_HZ + HANDOVER_S)
+    return {"chain_instr_per_column": int(per_col), "columns": n, "seconds": s}
+
+
+def stages_latency_bound(L: int, n: int, D: int) -> dict:
+    """Lower bound of the persistent staged solve: per stage one lazy
+    multiply-add per lane (N dx_{k-1}, the other terms are accumulated off
+    the chain), a 64-lane butterfly, the renormalization, and one hand-over
+    of dx_k between the solver workgroups."""
+    c = md_costs(L)
+    per_stage = c["fma_lazy"]["instr"] + _butterfly(c)
+    s = D * (per_stage * CYCLES_PER_DEP_INSTR / CLOCK_HZ + HANDOVER_S)
+    return {"chain_instr_per_stage": int(per_stage), "stages": D, "seconds": s}

@@ -50,3 +50,50 @@ def step_err(gpu_out, ora_out, x_in):
     diff = oracle.absdiff(gpu_out, ora_out).max(axis=-1)
     scale = np.maximum(np.abs(x_in[0]).max(axis=-1), np.abs(ora_out[0]).max(axis=-1))
     return float(np.max(diff / scale))
+
+
+def coef_errs(gpu_out, ora_out, x_in=None):
+    """Error of every coefficient k separately: max_i |gpu - ora|_{i,k} divided
+    by max_i max(|x_in_{i,k}|, |ora_{i,k}|) (leading limbs), for series
+    gpu[L, n, D] and ora[K, n, D].  Damped series have coefficients of very
+    different sizes, so a normwise error says little about the late ones; this
+    one sees a wrong low limb of any coefficient.  Coefficients that are zero
+    on both sides must match exactly (their error is 0 or inf)."""
+    diff = oracle.absdiff(gpu_out, ora_out).max(axis=-2)  # [D]
+    mag = np.abs(ora_out[0]).max(axis=-2)
+    if x_in is not None:
+        mag = np.maximum(mag, np.abs(x_in[0]).max(axis=-2))
+    with np.errstate(divide="ignore", invalid="ignore"):
+        return np.where(mag > 0, diff / np.where(mag > 0, mag, 1.0), np.where(diff > 0, np.inf, 0.0))
+
+
+def coef_err(gpu_out, ora_out, x_in=None):
+    """Largest per-coefficient error (see coef_errs)."""
+    return float(np.max(coef_errs(gpu_out, ora_out, x_in)))
+
+
+# The per-coefficient bound of a step where rounding errors are amplified by
+# the problem itself (late coefficients of an unconverged iterate, or a
+# near-singular series problem): the error of the same step computed by the
+# oracle at the working precision (53 L bits, every operation correctly
+# rounded, LU instead of QR) against the oracle at 4 x 53 L bits, times
+# WORKING_FACTOR.  The library's multiple-double operations end a few units
+# of the last limb away from the correctly rounded result; measured ratios
+# of the two errors are at most 17 on the configurations of the tests.
+WORKING_FACTOR = 32.0
+
+
+def assert_step_per_coefficient(sys, cst, x_in, got, ref, tol):
+    """Every coefficient k of a step's output within max(tol, WORKING_FACTOR
+    e_k) relative to its size (coef_errs), e_k the per-coefficient error of
+    the oracle's step at the working precision."""
+    ce = coef_errs(got, ref, x_in)
+    if np.max(ce) <= tol:
+        return ce
+    low = oracle.newton_step(sys, sys.cff, cst, x_in, prec=53 * sys.L)["x"]
+    cl = coef_errs(low, ref, x_in)
+    bound = np.maximum(tol, WORKING_FACTOR * cl)
+    bad = np.nonzero(ce > bound)[0]
+    assert bad.size == 0, ("coefficients beyond the working-precision bound", bad.tolist(),
+                           ce[bad].tolist(), bound[bad].tolist())
+    return ce

@@ -9,7 +9,8 @@ import pytest
 
 import mdinputs
 import oracle
-from gpu_helpers import TOL, dev, host, matrix_series_err, scaled_err, series_err, step_err
+from gpu_helpers import (TOL, assert_step_per_coefficient, coef_err, dev, host, matrix_series_err, scaled_err,
+                         series_err, step_err)
 
 pytestmark = pytest.mark.gpu
 
@@ -39,6 +40,9 @@ def test_medium_qd_steps_vs_oracle(mdn, medium):
         if step in (1, 2, s.steps):
             ref = oracle.newton_step(s, s.cff, cst, x)["x"]
             assert step_err(got, ref, x) <= TOL[4], (step, step_err(got, ref, x))
+            assert_step_per_coefficient(s, cst, x, got, ref, TOL[4])
+            if step <= 2:  # from x*(0) and x_1 the bound is the tolerance itself
+                assert coef_err(got, ref, x) <= TOL[4], step
         x = got
     assert drv.status_code() == 0
     assert series_err(host(drv.x), s.xstar) <= TOL[4]
@@ -70,6 +74,11 @@ def large():
     return mdinputs.large_od()
 
 
+@pytest.fixture(scope="module")
+def large_cst(large):
+    return oracle.manufacture(large)
+
+
 def test_large_od_eval_sampled_rows(mdn, large):
     import torch
 
@@ -89,13 +98,75 @@ def test_large_od_eval_sampled_rows(mdn, large):
     assert matrix_series_err(gA[:, r:r + 1], oA) <= TOL[8]
 
 
-def test_large_od_converges_to_manufactured_solution(mdn, large):
+def test_large_od_first_step_vs_oracle(mdn, large, large_cst):
+    """The full-size octo-double system (n=128, d=127): the first step from
+    x*(0) against the oracle's step, normwise and coefficient by coefficient
+    (the power table, the evaluation with one worker per series coefficient
+    range at D = 128, m_from_qt_kernel and the per-stage solve)."""
+    s, cst = large, large_cst
+    drv = mdn.Newton(s, cst)
+    x = s.start()
+    drv.step()
+    got = host(drv.x)
+    assert drv.status_code() == 0
+    ref = oracle.newton_step(s, s.cff, cst, x)["x"]
+    assert step_err(got, ref, x) <= TOL[8]
+    assert coef_err(got, ref, x) <= TOL[8]
+
+
+def test_medium_qd_near_the_condition_bound(mdn):
+    """The medium quad-double system with the smallest boost that meets the
+    configuration's bound cond(A_0) <= 1e3 (cond ~ 9e2): the first two steps
+    within the quad-double tolerance coefficient by coefficient (the
+    shortened reflector scalars do not limit them), the next two within the
+    working-precision bound: the block Toeplitz solve of this system
+    amplifies rounding errors by about 60 per coefficient, for the oracle at
+    212 bits as for the GPU."""
+    s = mdinputs.medium_qd_near_bound()
+    cst = oracle.manufacture(s)
+    drv = mdn.Newton(s, cst)
+    x = s.start()
+    for step in range(1, 5):
+        drv.step()
+        got = host(drv.x)
+        assert drv.status_code() == 0
+        ref = oracle.newton_step(s, s.cff, cst, x)["x"]
+        ce = assert_step_per_coefficient(s, cst, x, got, ref, TOL[4])
+        if step <= 2:
+            assert np.max(ce) <= TOL[4], (step, float(np.max(ce)))
+        x = got
+
+
+def test_large_od_converges_to_manufactured_solution(mdn, large, large_cst):
     """8 steps from x*(0) with the right-hand side manufactured by the oracle
     reach x* (property of the method that holds at any size)."""
-    s = large
-    cst = oracle.manufacture(s)
+    s, cst = large, large_cst
     drv = mdn.Newton(s, cst)
     for _ in range(s.steps):
         drv.step()
     assert drv.status_code() == 0
     assert series_err(host(drv.x), s.xstar) <= TOL[8]
+
+
+@pytest.mark.parametrize("n,d", [(249, 1), (256, 3)])
+def test_global_memory_qr_in_the_newton_step(mdn, n, d):
+    """The LDS-resident QR keeps the 2n columns of [A_0 | I] in at most 64
+    workgroups of at most 140 KB of LDS (pairs of columns of n octo doubles,
+    the current reflector beside them): octo doubles from n = 249 on do not
+    fit, and the step factors A_0 with the global-memory QR (one workgroup per
+    16 trailing columns, a grid barrier per column), forms M with
+    m_from_qt_kernel (n > 64) and solves stage by stage (stage_kernel: octo
+    doubles).  One step from x*(0) against the oracle's step, normwise and
+    per coefficient."""
+    from gpu_helpers import coef_err
+
+    s = mdinputs.tiny(8, n, d, mons=2, kmin=1, kmax=2, exps=(1, 2), seed=n)
+    cst = oracle.manufacture(s)
+    drv = mdn.Newton(s, cst)
+    x = s.start()
+    drv.step()
+    got = host(drv.x)
+    assert drv.status_code() == 0
+    ref = oracle.newton_step(s, s.cff, cst, x)["x"]
+    assert step_err(got, ref, x) <= TOL[8]
+    assert coef_err(got, ref, x) <= TOL[8]

@@ -12,7 +12,8 @@ import pytest
 
 import mdinputs
 import oracle
-from gpu_helpers import TOL, dev, host, matrix_series_err, scaled_err, series_err, step_err
+from gpu_helpers import (TOL, assert_step_per_coefficient, dev, host, matrix_series_err, scaled_err, series_err,
+                         step_err)
 
 pytestmark = pytest.mark.gpu
 
@@ -236,6 +237,7 @@ def test_small_dd_config_converges(mdn):
         got = host(drv.x)
         ref = oracle.newton_step(sys, sys.cff, cst, x)["x"]
         assert step_err(got, ref, x) <= TOL[2], (step, step_err(got, ref, x))
+        assert_step_per_coefficient(sys, cst, x, got, ref, TOL[2])
         x = got
     xfix = sys.start()
     for _ in range(6):

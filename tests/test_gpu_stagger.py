@@ -127,3 +127,24 @@ def test_driver_medium_qd(mdn):
     rep2, _ = drv2.staggered(max_steps=40, refactor_every_step=True)
     assert rep2.converged == 1 and rep2.factorizations == rep2.steps
     assert series_err(host(drv2.x), s.xstar) <= TOL[4]
+
+
+def test_driver_slow_chord_contraction_does_not_freeze(mdn):
+    """A start a quarter off in every coefficient of x_0: the chord steps with
+    the factorization of that start contract slowly, and a residual that does
+    not halve from one step to the next is then far above the rounding level.
+    The driver must not take such a coefficient as done: it either reaches
+    the manufactured solution or reports no convergence (or a failed step)."""
+    s = mdinputs.tiny(4, 8, 15, mons=3, kmin=1, kmax=3, exps=(1, 2), seed=77)
+    cst = oracle.manufacture(s)
+    x0 = s.start()
+    x0[:, :, 0] *= 1.25
+    drv = mdn.Newton(s, cst, x0)
+    try:
+        rep, windows = drv.staggered(max_steps=40)
+    except mdn.MdError:
+        return  # a failed step (the chord iteration diverged) is reported, not a false convergence
+    if rep.converged:
+        assert series_err(host(drv.x), s.xstar) <= TOL[4], windows
+    else:
+        assert rep.steps == 40
