@@ -493,6 +493,8 @@ def main():
     ap.add_argument("--replay", action="store_true",
                     help="only run the paper's own workloads (n = 1024 column systems) and print their JSON line")
     ap.add_argument("--replay-steps", type=int, default=24)
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the timed medium quad-double steps and their kernel classes (for profilers)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -650,6 +652,10 @@ def main():
         "err_vs_manufactured": err_manufactured,
         "wall_s_timed": round(wall, 3),
     }
+
+    if args.headline_only:
+        print(json.dumps(out))
+        return
 
     # the linear residual of the last step's system (monitoring): every
     # equation, and one sampled equation
