@@ -29,7 +29,7 @@ PEAK_FP64_TFLOPS = 78.6  # MI355X FP64 vector, FMA = 2 flops
 # traffic recorded from hardware counters is reported only while they are
 # unchanged since the counters were taken
 _EVALDIFF_SOURCES = ("evaldiff.hip", "evaldiff_dev.hpp", "evalargs.hpp", "common.hpp", "md.hpp", "md_gen.inc")
-_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "evaldiff_kernel_medium_qd_hbm_traffic.md")
+_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "evaldiff_pair_kernel_medium_qd_hbm_traffic.md")
 
 
 def evaldiff_source_sha256():
@@ -56,7 +56,7 @@ def _recorded_traffic():
     return int(kv["fetch_bytes_per_launch"]) + int(kv["write_bytes_per_launch"])
 
 
-_SQ_FILE = os.path.join(ROOT, "profiles", "evaldiff_kernel_medium_qd_sq_counters.md")
+_SQ_FILE = os.path.join(ROOT, "profiles", "evaldiff_pair_kernel_medium_qd_sq_counters.md")
 
 
 def _recorded_sq():
@@ -613,7 +613,7 @@ def main():
         conventions.update({
             "executed_tflops": round(ex / t / 1e12, 3), "executed_frac": round(ex / t / 1e12 / PEAK_FP64_TFLOPS, 4),
             "fp64_pipe_utilization": round(lane_ops / (64.0 * 256 * 2.4e9 * t), 4),
-            "counters": "profiles/evaldiff_kernel_medium_qd_sq_counters.md (same kernel sources)"})
+            "counters": "profiles/evaldiff_pair_kernel_medium_qd_sq_counters.md (same kernel sources)"})
     else:
         conventions.update({"executed_tflops": None, "fp64_pipe_utilization": None,
                             "counters": "no SQ counters recorded for the current kernel sources"})
@@ -640,7 +640,7 @@ def main():
         "single_step_per_s": round(1000.0 / ms_single, 3),
         "gflops_step": round(total_flops / (ms_step * 1e-3) / 1e9, 2),
         "pct_fp64_peak_step": round(100 * total_flops / (ms_step * 1e-3) / (PEAK_FP64_TFLOPS * 1e12), 2),
-        "roofline": {"bound": "alu", "kernel": "evaldiff_kernel<4> (" + dom + ")", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
+        "roofline": {"bound": "alu", "kernel": "evaldiff_pair_kernel<4> (" + dom + ", two wavefronts per monomial)", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": _recorded_traffic(),
                      "flops_per_launch": w[dom]["flops"], "launch_ms": round(dom_ms, 4)},
         "evaldiff_conventions": conventions,
