@@ -178,7 +178,7 @@ def _manufactured(mdn, torch, np, s):
     return drv, dev(s.start()), dev(s.xstar)
 
 
-TOL = {2: 1e-28, 4: 1e-60, 8: 1e-120}
+TOL = {1: 1e-12, 2: 1e-28, 4: 1e-60, 8: 1e-120}
 
 
 def _bench_configs(mdn, torch, np, mdinputs, reps):
@@ -370,6 +370,10 @@ PAPER_T6 = {"V100": {1: 28.997, 2: 59.820, 3: 90.003, 5: 149.894, 8: 240.760, 12
                      27: 1412.459, 41: 1601.007, 62: 2472.086, 64: 2568.016}}
 PAPER_T7_V100 = {2: {"kernel": 22.6, "wall": 475.3}, 4: {"kernel": 146.4, "wall": 834.7},
                  8: {"kernel": 405.3, "wall": 1129.8}}
+# Table 8: kernel and wall-clock seconds of 16 steps at n = 512, order 64, on
+# the RTX 2080 Max-Q by precision (1: double).
+PAPER_T8_RTX2080 = {1: {"kernel": 1.4, "wall": 35.7}, 2: {"kernel": 16.6, "wall": 80.0},
+                    4: {"kernel": 122.4, "wall": 225.0}, 8: {"kernel": 380.1, "wall": 474.8}}
 
 
 def _replay(mdn, torch, np, mdinputs, steps):
@@ -377,48 +381,64 @@ def _replay(mdn, torch, np, mdinputs, steps):
     with triangular exponent matrices of ones, n = 1024, exponential
     solutions (Section 3), `steps` steps of the staggered method from x*(0)
     (order schedule 1, 2, 4, ..., 64, every coefficient in the window, A_0
-    factored once) with per-class kernel times, plus one residual of all
-    equations per step; the same by precision; the evaluation alone by
-    order; and the driver with its stopping test, to convergence."""
+    factored once) with per-class kernel times and the residual of all
+    equations after every step, the error against the exact solution and its
+    bound; the same by precision; the evaluation alone by order; the driver
+    with its stopping test, to convergence; and 16 steps at n = 512 in double
+    double, quad double and octo double, and in plain double (the "D" of
+    Tables 7 and 8; the shape of Tables 8 and 9)."""
     from paper_2301_12659_amd import work
 
-    def run(s):
+    def growth(s):
+        """n max_{i,k} |S_i|^k / k!: the systems' inherent loss of accuracy in
+        units of the working precision (S_i the partial sums of the alphas,
+        the exponents along the monomial chains)."""
+        S = np.cumsum(s.xstar[0, :, 1])
+        g, term = 1.0, np.ones_like(S)
+        for k in range(1, s.D):
+            term = term * np.abs(S) / k
+            g = max(g, float(term.max()))
+        return s.n * g
+
+    def run(s, steps):
         drv = mdn.Newton(s, s.cst, s.start())
+        pb, pA, pdx = mdn.step_arrays(drv.plan, drv.ws)
+        r = torch.empty((s.L, s.n, s.D), dtype=torch.float64, device="cuda")
+        nr = torch.empty(s.D, dtype=torch.float64, device="cuda")
+        r0, r1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         mdn.timing_enable(True)
         mdn.timing_read()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         # `steps` steps of the staggered schedule with every coefficient in
-        # the window (no early exit), A_0 factored at the first step only
-        win, hi = [], 1
+        # the window (no early exit), A_0 factored at the first step only,
+        # and after every step the residual of all equations (the paper's
+        # loop computes it at every step), timed with its own events
+        win, hi, res_ms = [], 1, 0.0
         for q in range(steps):
             drv.step_window(0, hi, keep_factorization=q > 0)
+            r0.record()
+            mdn.linear_residual(s.L, s.n, s.d, pA, pb, pdx, r, norm1=nr)
+            r1.record()
+            torch.cuda.synchronize()
+            res_ms += r0.elapsed_time(r1)
             win.append((0, hi))
             hi = mdn.stagger_next_order(hi, s.D)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         cls = mdn.timing_read()
         mdn.timing_enable(False)
-        rep = type("R", (), {"steps": steps, "factorizations": 1})()
-        # one residual of all equations at full order, as the paper's loop computes every step
-        pb, pA, pdx = mdn.step_arrays(drv.plan, drv.ws)
-        r = torch.empty((s.L, s.n, s.D), dtype=torch.float64, device="cuda")
-        nr = torch.empty(s.D, dtype=torch.float64, device="cuda")
-        mdn.linear_residual(s.L, s.n, s.d, pA, pb, pdx, r, norm1=nr)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        mdn.linear_residual(s.L, s.n, s.d, pA, pb, pdx, r, norm1=nr)
-        e1.record()
-        torch.cuda.synchronize()
-        res_s = e0.elapsed_time(e1) / 1000.0
         ms = {k: v[0] for k, v in cls.items()}
-        out = {"steps": rep.steps, "factorizations": rep.factorizations, "wall_s": round(wall, 3),
+        err = _err_vs(mdn, torch, drv.x, torch.as_tensor(s.xstar, device="cuda"))
+        bound = TOL[s.L] * growth(s)
+        out = {"steps": steps, "factorizations": 1, "wall_s": round(wall, 3),
                "kernel_s": {"convolution": round((ms["convolutions"] + ms["assembly"]) / 1e3, 4),
                             "householder_qr_and_prepass": round(ms["qr"] / 1e3, 4),
                             "qhb_and_back_substitution": round(ms["qhb_bs"] / 1e3, 4),
                             "updates": round((ms["gemm"] + ms["updates"] + ms["x_update"]) / 1e3, 4),
-                            "residuals": round(res_s * rep.steps, 4)},
-               "windows": [list(w) for w in win]}
+                            "residuals": round(res_ms / 1e3, 4)},
+               "windows": [list(w) for w in win],
+               "err_vs_exact": err, "growth_estimate": bound, "within_estimate": bool(err <= bound)}
         out["kernel_s"]["total_kernel"] = round(sum(out["kernel_s"].values()), 4)
         return drv, out
 
@@ -428,7 +448,7 @@ def _replay(mdn, torch, np, mdinputs, steps):
            "paper_table7_v100_s": PAPER_T7_V100}
     for cols, name in ((1, "one_column"), (2, "two_columns")):
         s = mdinputs.column_system(1024, 63, 8, cols, seed=1)
-        drv, out = run(s)
+        drv, out = run(s, steps)
         print(f"replay {name}: {out['wall_s']} s", file=sys.stderr, flush=True)
         if cols == 1:
             # Table 6: the evaluation alone at order k (window steps with the
@@ -464,15 +484,32 @@ def _replay(mdn, torch, np, mdinputs, steps):
         del drv
         torch.cuda.empty_cache()
     by_prec = {}
-    for L in (2, 4):
+    for L in (1, 2, 4):
         s = mdinputs.column_system(1024, 63, L, 1, seed=1)
-        drv, out = run(s)
+        drv, out = run(s, steps)
         print(f"replay one_column L={L}: {out['wall_s']} s", file=sys.stderr, flush=True)
-        by_prec[L] = {"wall_s": out["wall_s"], "total_kernel_s": out["kernel_s"]["total_kernel"]}
+        by_prec[L] = {"wall_s": out["wall_s"], "total_kernel_s": out["kernel_s"]["total_kernel"],
+                      "err_vs_exact": out["err_vs_exact"], "growth_estimate": out["growth_estimate"]}
         del drv
         torch.cuda.empty_cache()
-    by_prec[8] = {"wall_s": res["one_column"]["wall_s"], "total_kernel_s": res["one_column"]["kernel_s"]["total_kernel"]}
+    by_prec[8] = {"wall_s": res["one_column"]["wall_s"], "total_kernel_s": res["one_column"]["kernel_s"]["total_kernel"],
+                  "err_vs_exact": res["one_column"]["err_vs_exact"], "growth_estimate": res["one_column"]["growth_estimate"]}
     res["one_column_by_precision"] = by_prec
+    # Tables 8 and 9: n = 512, order 64, 16 steps, one column, by precision
+    n512 = {}
+    for L in (1, 2, 4, 8):
+        s = mdinputs.column_system(512, 63, L, 1, seed=2)
+        drv, out = run(s, 16)
+        ks = out["kernel_s"]
+        f = work.convolution_flops(s, s.D)
+        out["evaluation_gflops_per_full_order_step"] = round(f["flops"] / 1e9, 2)
+        n512[L] = out
+        print(f"replay n=512 L={L}: {out['wall_s']} s, err {out['err_vs_exact']:.2e} (estimate {out['growth_estimate']:.2e})",
+              file=sys.stderr, flush=True)
+        del drv
+        torch.cuda.empty_cache()
+    res["n512_one_column_16_steps"] = n512
+    res["paper_table8_rtx2080_16_steps_s"] = PAPER_T8_RTX2080
     return res
 
 

@@ -17,7 +17,7 @@
  * coefficient c_m per monomial and exponent vectors a_m >= 0.  Series are
  * truncated at degree d: D = d + 1 coefficients (the paper's "order D").
  *
- * Numbers.  A multiple double with L limbs (L = 2, 4 or 8) is an unevaluated
+ * Numbers.  A multiple double with L limbs (L = 2, 4 or 8; 1: a double) is an unevaluated
  * sum of L doubles (Section 1.2).  Every numeric array is stored limb-major
  * ("structure of arrays", Sections 1.2 and 6): limb l of element q of an array
  * of N elements is at ptr[l * N + q].  Element orders:
@@ -58,7 +58,10 @@ extern "C" {
 #define MD_EHIP (-4)       /* a HIP runtime call failed */
 #define MD_ENOSPACE (-5)   /* workspace too small */
 
-/* Precision = number of limbs L. */
+/* Precision = number of limbs L.  MD_D is plain double arithmetic (the
+ * paper's "D" in its comparisons across precisions, Section 7): every entry
+ * point but the batches and complex data accepts it. */
+#define MD_D 1
 #define MD_DD 2
 #define MD_QD 4
 #define MD_OD 8
@@ -73,7 +76,7 @@ typedef struct md_plan md_plan;
 
 /* Build a plan for a system of n polynomials in n variables with m monomials,
  * truncated at degree d (D = d + 1 <= MD_MAX_COEFFS), in precision prec
- * (MD_DD, MD_QD or MD_OD).  Index tables (host pointers, CSR):
+ * (MD_D, MD_DD, MD_QD or MD_OD).  Index tables (host pointers, CSR):
  *   poly_ptr[n+1] : monomials of polynomial i are poly_ptr[i] .. poly_ptr[i+1]-1
  *   mon_ptr[m+1]  : support entries of monomial j are mon_ptr[j] .. mon_ptr[j+1]-1
  *   var[nnz]      : variable of each entry, strictly increasing within a monomial

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libmdnewton.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "mdnewton.h")
 
 MD_OK, MD_EINVAL, MD_ESINGULAR, MD_ENONFINITE, MD_EHIP, MD_ENOSPACE = 0, -1, -2, -3, -4, -5
-MD_DD, MD_QD, MD_OD = 2, 4, 8
+MD_D, MD_DD, MD_QD, MD_OD = 1, 2, 4, 8
 OPS = {"add": 0, "sub": 1, "mul": 2, "div": 3, "sqrt": 4, "fma": 5, "dot": 6}
 STATUS_NAMES = {0: "ok", -2: "singular", -3: "nonfinite"}
 

@@ -67,7 +67,11 @@ int hip_fail(hipError_t e, const char *what) {
   return fail(MD_EHIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-bool valid_prec(int p) { return p == MD_DD || p == MD_QD || p == MD_OD; }
+bool valid_prec(int p) { return p == MD_D || p == MD_DD || p == MD_QD || p == MD_OD; }
+
+// A solve precision for a plan of L limbs: L itself, or fewer limbs among
+// dd and qd (the mixed-precision forms).
+bool valid_solve_prec(int ps, int L) { return ps == L || ((ps == MD_DD || ps == MD_QD) && ps < L); }
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -241,7 +245,7 @@ int md_plan_create(int prec, int n, int d, int m, const int32_t *poly_ptr, const
                    const int32_t *var, const int32_t *exp, md_plan **out) {
   if (!out) return fail(MD_EINVAL, "out is NULL");
   *out = nullptr;
-  if (!valid_prec(prec)) return fail(MD_EINVAL, "precision must be 2, 4 or 8 limbs");
+  if (!valid_prec(prec)) return fail(MD_EINVAL, "precision must be 1, 2, 4 or 8 limbs");
   if (n < 1 || n > MD_MAX_DIM) return fail(MD_EINVAL, "n out of range");
   if (d < 0 || d + 1 > MD_MAX_COEFFS) return fail(MD_EINVAL, "degree out of range");
   if (m < 0) return fail(MD_EINVAL, "m < 0");
@@ -723,8 +727,8 @@ int md_newton_steps(const md_plan *p, int count, const double *cff, const double
 int md_newton_step_mixed(const md_plan *p, int prec_solve, const double *cff, const double *cst, double *x,
                          int32_t *dev_status, double *dev_norms, void *ws, size_t ws_bytes, hipStream_t st) {
   if (!p || !cst || !x || (p->m > 0 && !cff)) return fail(MD_EINVAL, "NULL argument");
-  if (!valid_prec(prec_solve) || prec_solve > p->L)
-    return fail(MD_EINVAL, "solve precision must be dd, qd or od and at most the plan's");
+  if (!valid_solve_prec(prec_solve, p->L))
+    return fail(MD_EINVAL, "solve precision must be the plan's, or dd or qd below it");
   if (!ws || ws_bytes < newton_layout(p).total) return fail(MD_ENOSPACE, "workspace too small");
   return newton_step_impl(p, prec_solve, 0, p->D, false, cff, cst, x, dev_status, dev_norms, nullptr, ws, st);
 }
@@ -733,8 +737,8 @@ int md_newton_step_window(const md_plan *p, int prec_solve, int lo, int hi, int 
                           const double *cff, const double *cst, double *x, int32_t *dev_status, double *dev_norms,
                           void *ws, size_t ws_bytes, hipStream_t st) {
   if (!p || !cst || !x || (p->m > 0 && !cff)) return fail(MD_EINVAL, "NULL argument");
-  if (!valid_prec(prec_solve) || prec_solve > p->L)
-    return fail(MD_EINVAL, "solve precision must be dd, qd or od and at most the plan's");
+  if (!valid_solve_prec(prec_solve, p->L))
+    return fail(MD_EINVAL, "solve precision must be the plan's, or dd or qd below it");
   if (lo < 0 || hi > p->D || lo >= hi) return fail(MD_EINVAL, "window must satisfy 0 <= lo < hi <= D");
   if (!ws || ws_bytes < newton_layout(p).total) return fail(MD_ENOSPACE, "workspace too small");
   return newton_step_impl(p, prec_solve, lo, hi, keep_factorization != 0, cff, cst, x, dev_status, dev_norms,
@@ -749,8 +753,8 @@ int md_newton_staggered(const md_plan *p, int prec_solve, int refactor_every_ste
                         size_t ws_bytes, hipStream_t st) {
   if (!p || !cst || !x || !dev_status || !dev_norms || !report || (p->m > 0 && !cff))
     return fail(MD_EINVAL, "NULL argument");
-  if (!valid_prec(prec_solve) || prec_solve > p->L)
-    return fail(MD_EINVAL, "solve precision must be dd, qd or od and at most the plan's");
+  if (!valid_solve_prec(prec_solve, p->L))
+    return fail(MD_EINVAL, "solve precision must be the plan's, or dd or qd below it");
   if (max_steps < 1 || !(tol >= 0.0)) return fail(MD_EINVAL, "max_steps must be positive and tol non-negative");
   if (!ws || ws_bytes < newton_layout(p).total) return fail(MD_ENOSPACE, "workspace too small");
   const Layout w = newton_layout(p);
@@ -923,6 +927,7 @@ int md_eval_diff_complex(const md_plan *p, const double *cff, const double *cst,
                          double *A, void *ws, size_t ws_bytes, hipStream_t st) {
   if (!p || !cst || !x || !b || !A || (p->m > 0 && !cff)) return fail(MD_EINVAL, "NULL argument");
   if (p->maxexp > 2) return fail(MD_EINVAL, "complex data: exponents must be 1 or 2");
+  if (p->L == MD_D) return fail(MD_EINVAL, "complex data: double double, quad double or octo double");
   if (!ws || ws_bytes < complex_layout(p).total) return fail(MD_ENOSPACE, "workspace too small");
   return complex_eval_impl(p, cff, cst, x, b, A, ws, st);
 }
@@ -931,6 +936,7 @@ int md_newton_step_complex(const md_plan *p, const double *cff, const double *cs
                            double *dev_norms, void *ws, size_t ws_bytes, hipStream_t st) {
   if (!p || !cst || !x || (p->m > 0 && !cff)) return fail(MD_EINVAL, "NULL argument");
   if (p->maxexp > 2) return fail(MD_EINVAL, "complex data: exponents must be 1 or 2");
+  if (p->L == MD_D) return fail(MD_EINVAL, "complex data: double double, quad double or octo double");
   if (2 * p->n > MD_MAX_DIM) return fail(MD_EINVAL, "complex data: 2n must be at most MD_MAX_DIM");
   const CLayout w = complex_layout(p);
   if (!ws || ws_bytes < w.total) return fail(MD_ENOSPACE, "workspace too small");

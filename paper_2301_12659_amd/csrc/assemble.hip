@@ -93,6 +93,7 @@ hipError_t launch_assemble_A0(int L, int n, int D, int nnz, const int32_t *asm_p
                               const double *der, double *a0, hipStream_t st) {
   const size_t nn = (size_t)n * n;
   switch (L) {
+    case 1: hipLaunchKernelGGL(assemble_A0_kernel<1>, dim3((nn + 63) / 64), dim3(64), 0, st, n, D, nnz, asm_ptr, asm_ent, der, a0); break;
     case 2: hipLaunchKernelGGL(assemble_A0_kernel<2>, dim3((nn + 63) / 64), dim3(64), 0, st, n, D, nnz, asm_ptr, asm_ent, der, a0); break;
     case 4: hipLaunchKernelGGL(assemble_A0_kernel<4>, dim3((nn + 63) / 64), dim3(64), 0, st, n, D, nnz, asm_ptr, asm_ent, der, a0); break;
     case 8: hipLaunchKernelGGL(assemble_A0_kernel<8>, dim3((nn + 63) / 64), dim3(64), 0, st, n, D, nnz, asm_ptr, asm_ent, der, a0); break;
@@ -106,6 +107,7 @@ hipError_t launch_assemble_b(int L, int n, int D, int Dc, int m, const int32_t *
   if (Dc < 1 || Dc > D) return hipErrorInvalidValue;
   const unsigned blocks = (unsigned)(((size_t)n * Dc + 255) / 256);
   switch (L) {
+    case 1: hipLaunchKernelGGL(assemble_b_kernel<1>, dim3(blocks), dim3(256), 0, st, n, D, Dc, m, poly_ptr, cst, val, b, tsz, vsize); break;
     case 2: hipLaunchKernelGGL(assemble_b_kernel<2>, dim3(blocks), dim3(256), 0, st, n, D, Dc, m, poly_ptr, cst, val, b, tsz, vsize); break;
     case 4: hipLaunchKernelGGL(assemble_b_kernel<4>, dim3(blocks), dim3(256), 0, st, n, D, Dc, m, poly_ptr, cst, val, b, tsz, vsize); break;
     case 8: hipLaunchKernelGGL(assemble_b_kernel<8>, dim3(blocks), dim3(256), 0, st, n, D, Dc, m, poly_ptr, cst, val, b, tsz, vsize); break;
@@ -119,6 +121,7 @@ hipError_t launch_assemble_A(int L, int n, int D, int Dc, int nnz, const int32_t
   if (Dc < 1 || Dc > D) return hipErrorInvalidValue;
   const unsigned blocks = (unsigned)(((size_t)n * n * Dc + 255) / 256);
   switch (L) {
+    case 1: hipLaunchKernelGGL(assemble_A_kernel<1>, dim3(blocks), dim3(256), 0, st, n, D, Dc, nnz, asm_ptr, asm_ent, der, A); break;
     case 2: hipLaunchKernelGGL(assemble_A_kernel<2>, dim3(blocks), dim3(256), 0, st, n, D, Dc, nnz, asm_ptr, asm_ent, der, A); break;
     case 4: hipLaunchKernelGGL(assemble_A_kernel<4>, dim3(blocks), dim3(256), 0, st, n, D, Dc, nnz, asm_ptr, asm_ent, der, A); break;
     case 8: hipLaunchKernelGGL(assemble_A_kernel<8>, dim3(blocks), dim3(256), 0, st, n, D, Dc, nnz, asm_ptr, asm_ent, der, A); break;

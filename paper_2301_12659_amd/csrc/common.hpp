@@ -145,6 +145,7 @@ __device__ __forceinline__ void set_status(int32_t *status, int32_t code) {
 // Dispatch a launch on the limb count: the statement sees LL as a constant.
 #define MD_DISPATCH(L, ...)                                 \
   switch (L) {                                              \
+    case 1: { constexpr int LL = 1; __VA_ARGS__; } break; \
     case 2: { constexpr int LL = 2; __VA_ARGS__; } break; \
     case 4: { constexpr int LL = 4; __VA_ARGS__; } break; \
     case 8: { constexpr int LL = 8; __VA_ARGS__; } break; \

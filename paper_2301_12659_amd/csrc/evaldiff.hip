@@ -267,6 +267,7 @@ hipError_t launch_evaldiff0(int L, const EvalArgs &a, hipStream_t st) {
   // many CUs as possible (each thread is a chain of dependent products)
   const dim3 grid((a.m + 63) / 64);
   switch (L) {
+    case 1: hipLaunchKernelGGL(evaldiff0_kernel<1>, grid, dim3(64), 0, st, a); break;
     case 2: hipLaunchKernelGGL(evaldiff0_kernel<2>, grid, dim3(64), 0, st, a); break;
     case 4: hipLaunchKernelGGL(evaldiff0_kernel<4>, grid, dim3(64), 0, st, a); break;
     default: return hipErrorInvalidValue;
@@ -337,6 +338,7 @@ hipError_t launch_evaldiff_T(const EvalArgs &a, int maxexp, double *pw_mut, hipS
 
 hipError_t launch_evaldiff(int L, const EvalArgs &a, int maxexp, double *pw, hipStream_t st) {
   switch (L) {
+    case 1: return launch_evaldiff_T<1>(a, maxexp, pw, st);
     case 2: return launch_evaldiff_T<2>(a, maxexp, pw, st);
     case 4: return launch_evaldiff_T<4>(a, maxexp, pw, st);
     case 8: return launch_evaldiff_T<8>(a, maxexp, pw, st);

@@ -1490,7 +1490,7 @@ hipError_t launch_gemm(int L, int n, const double *M, const double *B, size_t b_
   return hipGetLastError();
 }
 
-bool stages_persistent(int L, int n, int D) { return L <= 4 && n <= 64 && D >= 1; }
+bool stages_persistent(int L, int n, int D) { return (L == 2 || L == 4) && n <= 64 && D >= 1; }
 
 int stages_sync_ints(int D) { return (D + 2 + 64) * SYNC_STRIDE; }
 

@@ -1,6 +1,7 @@
 // Multiple-double arithmetic: double double (L=2), quad double (L=4) and
 // octo double (L=8) numbers as unevaluated sums of L nonoverlapping doubles
-// (Section 1.2).  Every routine takes its operands as limbs held in
+// (Section 1.2); L=1 is plain double arithmetic (the paper's precision D in
+// its comparisons across precisions, Section 7).  Every routine takes its operands as limbs held in
 // registers, never as arrays in memory, like the paper's inlined
 // arithmetical kernels (Section 6); arrays in device memory are stored limb by
 // limb (structure of arrays) by the callers.
@@ -79,6 +80,10 @@ template <int L> MD_INLINE void mul_int(double (&a)[L], const int k) {
 // renormalization of the digits; the method of the quad-double library of
 // Hida, Li and Bailey, applied to any L.
 template <int L> MD_INLINE void div(const double (&a)[L], const double (&b)[L], double (&q)[L]) {
+  if constexpr (L == 1) {  // plain double: the IEEE quotient
+    q[0] = a[0] / b[0];
+    return;
+  }
   double r[L], t[L], qd[L + 1];
   copy<L>(a, r);
 #pragma unroll
@@ -104,7 +109,7 @@ template <int L> MD_INLINE void sqrt(const double (&a)[L], double (&y)[L]) {
     return;
   }
   y[0] = ::sqrt(a[0]);
-  constexpr int iters = (L == 2) ? 2 : (L == 4) ? 3 : 4;
+  constexpr int iters = (L == 1) ? 0 : (L == 2) ? 2 : (L == 4) ? 3 : 4;
 #pragma unroll
   for (int it = 0; it < iters; ++it) {
     double y2[L], d[L], two_y[L], c[L], yn[L];
@@ -193,6 +198,7 @@ template <int L>
 MD_INLINE void rsqrt_newton(const double (&a)[L], double (&y)[L]) {
   zero<L>(y);
   y[0] = 1.0 / ::sqrt(a[0]);
+  if constexpr (L == 1) return;  // plain double
   rsqrt_step<L, 2, 1>(a, y);
   if constexpr (L >= 4) rsqrt_step<L, 4, 2>(a, y);
   if constexpr (L >= 8) rsqrt_step<L, 8, 8>(a, y);
@@ -203,6 +209,7 @@ template <int L>
 MD_INLINE void recip_newton(const double (&v)[L], double (&r)[L]) {
   zero<L>(r);
   r[0] = 1.0 / v[0];
+  if constexpr (L == 1) return;  // plain double
   recip_step<L, 2, 1>(v, r);
   if constexpr (L >= 4) recip_step<L, 4, 2>(v, r);
   if constexpr (L >= 8) recip_step<L, 8, 8>(v, r);
@@ -218,7 +225,9 @@ MD_INLINE void recip_newton(const double (&v)[L], double (&r)[L]) {
 // keep the full sequence (a shortened one would stop near 2^(-412)).
 template <int L>
 MD_INLINE void rsqrt_short(const double (&a)[L], double (&y)[L]) {
-  if constexpr (L >= 8) {
+  if constexpr (L == 1) {
+    y[0] = 1.0 / ::sqrt(a[0]);
+  } else if constexpr (L >= 8) {
     rsqrt_newton<L>(a, y);
   } else {
     zero<L>(y);
@@ -230,7 +239,9 @@ MD_INLINE void rsqrt_short(const double (&a)[L], double (&y)[L]) {
 
 template <int L>
 MD_INLINE void recip_short(const double (&v)[L], double (&r)[L]) {
-  if constexpr (L >= 8) {
+  if constexpr (L == 1) {
+    r[0] = 1.0 / v[0];
+  } else if constexpr (L >= 8) {
     recip_newton<L>(v, r);
   } else {
     zero<L>(r);

@@ -85,8 +85,9 @@ def step_work(sys) -> dict:
 
 
 # The paper's convention (Table 2): md multiplications in zero-padded
-# convolutions (D^2 per product) times 23 / 336 / 1742 double flops.
-PAPER_MUL_COST = {2: 23, 4: 336, 8: 1742}
+# convolutions (D^2 per product) times 23 / 336 / 1742 double flops (one for
+# a double).
+PAPER_MUL_COST = {1: 1, 2: 23, 4: 336, 8: 1742}
 
 
 def paper_convention_flops(sys) -> int:

@@ -6,8 +6,10 @@ import numpy as np
 import oracle
 
 # Relative tolerances on well-conditioned inputs: double double, quad double,
-# octo double.
-TOL = {2: 1e-28, 4: 1e-60, 8: 1e-120}
+# octo double; plain double (one limb) takes about as many units of its last
+# place as the double-double tolerance does of its own (1e-28 is about 8 000
+# units of 2^-106, 1e-12 about 9 000 units of 2^-53).
+TOL = {1: 1e-12, 2: 1e-28, 4: 1e-60, 8: 1e-120}
 
 
 def dev(a):

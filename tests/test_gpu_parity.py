@@ -44,7 +44,7 @@ def _one_plus_pow2(L, j):
     return oracle.round_md(e, L)
 
 
-@pytest.mark.parametrize("L", PRECS)
+@pytest.mark.parametrize("L", [1] + PRECS)
 @pytest.mark.parametrize("op", ["add", "sub", "mul", "div", "sqrt", "fma"])
 def test_arith(mdn, L, op):
     import torch
@@ -85,6 +85,8 @@ def test_arith(mdn, L, op):
 
 EVAL_CASES = [
     # L, n, d, monomials/poly, kmin, kmax, exps
+    (1, 6, 12, 3, 1, 4, (1, 2, 3)),
+    (1, 5, 40, 3, 1, 4, (1, 2)),
     (2, 5, 0, 3, 1, 3, (1, 2)),
     (2, 6, 1, 3, 1, 3, (1, 2, 3)),
     (2, 7, 12, 4, 1, 4, (1, 2, 3)),
@@ -141,7 +143,7 @@ def test_eval_diff_constant_and_single_monomials(mdn):
 
 # ---------------------------------------------------------------- QR
 
-@pytest.mark.parametrize("L,n", [(2, 1), (2, 8), (4, 33), (4, 64), (8, 19)])
+@pytest.mark.parametrize("L,n", [(1, 24), (2, 1), (2, 8), (4, 33), (4, 64), (8, 19)])
 def test_qr(mdn, L, n):
     import torch
 
@@ -210,7 +212,7 @@ def test_series_solve(mdn, L, n, d):
 
 # ---------------------------------------------------------------- Newton step
 
-@pytest.mark.parametrize("L,n,d", [(2, 6, 7), (4, 8, 15), (4, 11, 26), (8, 5, 11)])
+@pytest.mark.parametrize("L,n,d", [(1, 7, 9), (1, 70, 20), (2, 6, 7), (4, 8, 15), (4, 11, 26), (8, 5, 11)])
 def test_newton_step_teacher_forced(mdn, L, n, d):
     sys = mdinputs.tiny(L, n, d, mons=3, kmin=1, kmax=4, exps=(1, 2, 3), seed=3 * n + d)
     cst = oracle.manufacture(sys)
