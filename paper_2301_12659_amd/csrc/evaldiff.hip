@@ -74,7 +74,7 @@ __device__ void eval_monomial_pair(const EvalArgs &a, int mono, double *buf0) {
       for (int q = 2; q <= k - 1; ++q) {
         load_series(X, a.x, xls, xoff(a.var[e0 + k - q]), L, Dc, lane, G);
         wave_sync();
-        conv<L>(B, X, Wb, Dc, lane, 1);
+        conv_any<L>(B, X, Wb, Dc, lane, 1);
         wave_sync();
         store_series(a.der, zD, der_off(k - q - 1), Wb, L, Dc, lane, G);
         double *t = B;
@@ -99,7 +99,7 @@ __device__ void eval_monomial_pair(const EvalArgs &a, int mono, double *buf0) {
       } else {
         load_series(V, src, sls, xoff(v), L, Dc, lane, G);
         wave_sync();
-        conv<L>(U, V, W, Dc, lane, 1);
+        conv_any<L>(U, V, W, Dc, lane, 1);
         wave_sync();
         double *t = U;
         U = W;
@@ -136,7 +136,7 @@ __device__ void eval_monomial_pair(const EvalArgs &a, int mono, double *buf0) {
       if (f0_scalar && j == 1)
         scal<L>(c, V, W, Dc, lane, G, 1);
       else
-        conv<L>(U, V, W, Dc, lane, 1);
+        conv_any<L>(U, V, W, Dc, lane, 1);
     } else if (derivs) {
       if (j < k) {
         if (k - j == 1)
@@ -147,7 +147,7 @@ __device__ void eval_monomial_pair(const EvalArgs &a, int mono, double *buf0) {
         if (f0_scalar && j == 1)
           scal<L>(c, Xq, Wq, Dc, lane, G, aj);
         else
-          conv<L>(U, Xq, Wq, Dc, lane, aj);
+          conv_any<L>(U, Xq, Wq, Dc, lane, aj);
         wave_sync();
         store_series(a.der, zD, der_off(ej), Wq, L, Dc, lane, G);
       } else {  // d/dx_{v_k} = a_k f_{k-1}
@@ -295,7 +295,7 @@ __global__ void __launch_bounds__(256, (L == 8) ? 1 : 2) power_kernel(int n, int
   load_series(U, x, nD, (size_t)v * D, L, Dc, lane, G);
   wave_sync();
   for (int p = 2; p <= maxp; ++p) {
-    conv<L>(U, X, W, Dc, lane, 1);
+    conv_any<L>(U, X, W, Dc, lane, 1);
     wave_sync();
     store_series(pw + (size_t)(p - 2) * L * nD, nD, (size_t)v * D, W, L, Dc, lane, G);
     double *t = U;

@@ -20,10 +20,12 @@ __host__ __device__ inline int worker_lanes(int D) { return split_factor(D) * pa
 // LDS series layout: [L][D + 1]; entry D of every limb is zero and is what
 // masked terms read.
 
-// Truncated product W = scale * (U * V) (all in LDS).
-template <int L>
+// Truncated product W = scale * (U * V) (all in LDS).  DP > 0: the buffers'
+// limb stride D + 1 known at compile time (the limb offsets of the LDS reads
+// become immediates); the operand pointers move by one entry per term.
+template <int L, int DP = 0>
 __device__ void conv(const double *U, const double *V, double *W, int D, int lane, int scale) {
-  const int Dp = D + 1, G2 = pair_lanes(D), S = split_factor(D);
+  const int Dp = DP > 0 ? DP : D + 1, G2 = pair_lanes(D), S = split_factor(D);
   const int h = lane / G2, p = lane - h * G2;
   const bool act = p < (D + 1) / 2;
   const int o1 = p, o2 = D - 1 - p;
@@ -31,20 +33,37 @@ __device__ void conv(const double *U, const double *V, double *W, int D, int lan
   const int t0 = h * H;
   double acc0[L];
   md::zero<L>(acc0);
-  for (int tt = 0; tt < H; ++tt) {
-    const int t = t0 + tt;
-    const bool ph1 = t <= o1;
-    int i = ph1 ? t : t - o1 - 1;
-    int j = (ph1 ? o1 : o2) - i;
-    if (!act || t > D) {  // reads the zero padding
+  // term t multiplies u_i v_j with i + j = o1 for t <= o1 and i + j = o2
+  // after (i = t - o1 - 1); masked terms read the zero padding (entry D)
+  int i, j;
+  {
+    const bool ph1 = t0 <= o1;
+    i = ph1 ? t0 : t0 - o1 - 1;
+    j = (ph1 ? o1 : o2) - i;
+    if (!act || t0 > D) {
       i = D;
       j = 0;
     }
+  }
+  for (int tt = 0; tt < H; ++tt) {
+    const int t = t0 + tt;
     double u[L], v[L];
 #pragma unroll
     for (int l = 0; l < L; ++l) {
       u[l] = U[l * Dp + i];
       v[l] = V[l * Dp + j];
+    }
+    // the next term's indices
+    if (t == o1) {
+      i = 0;
+      j = o2;
+    } else {
+      ++i;
+      --j;
+    }
+    if (!act || t + 1 > D) {
+      i = D;
+      j = 0;
     }
     MD<L>::fma_lazy(acc0, u, v);
     if (t == o1) {  // first output complete (always in the first half)
@@ -70,6 +89,19 @@ __device__ void conv(const double *U, const double *V, double *W, int D, int lan
     md::mul_int<L>(r, scale);
 #pragma unroll
     for (int l = 0; l < L; ++l) W[l * Dp + o2] = r[l];
+  }
+}
+
+// conv with the limb stride fixed at compile time for the orders of the
+// workloads (16, 32, 64, 128 coefficients), the runtime stride otherwise.
+template <int L>
+__device__ __forceinline__ void conv_any(const double *U, const double *V, double *W, int D, int lane, int scale) {
+  switch (D) {
+    case 16: conv<L, 17>(U, V, W, D, lane, scale); break;
+    case 32: conv<L, 33>(U, V, W, D, lane, scale); break;
+    case 64: conv<L, 65>(U, V, W, D, lane, scale); break;
+    case 128: conv<L, 129>(U, V, W, D, lane, scale); break;
+    default: conv<L>(U, V, W, D, lane, scale);
   }
 }
 
@@ -147,7 +179,7 @@ __device__ void eval_monomial(const EvalArgs &a, int mono, int lane, double *buf
     for (int q = 2; q <= k - 1; ++q) {
       load_series(X, a.x, xls, xoff(a.var[e0 + k - q]), L, Dc, lane, G);  // x_{v_{k-q+1}}
       wave_sync();
-      conv<L>(B, X, Wb, Dc, lane, 1);
+      conv_any<L>(B, X, Wb, Dc, lane, 1);
       wave_sync();
       // b_q is consumed by the cross product of forward step j = k - q (1-based),
       // i.e. entry k - q - 1 (0-based)
@@ -175,7 +207,7 @@ __device__ void eval_monomial(const EvalArgs &a, int mono, int lane, double *buf
     } else {
       load_series(V, src, sls, xoff(v), L, Dc, lane, G);
       wave_sync();
-      conv<L>(U, V, W, Dc, lane, 1);
+      conv_any<L>(U, V, W, Dc, lane, 1);
       wave_sync();
       double *t = U;
       U = W;
@@ -215,7 +247,7 @@ __device__ void eval_monomial(const EvalArgs &a, int mono, int lane, double *buf
       if (f0_scalar && j == 1)
         scal<L>(c, V, W, Dc, lane, G, aj);
       else
-        conv<L>(U, V, W, Dc, lane, aj);
+        conv_any<L>(U, V, W, Dc, lane, aj);
       wave_sync();
       store_series(a.der, zD, der_off(ej), W, L, Dc, lane, G);
     } else {  // d/dx_{v_k} = a_k f_{k-1}
@@ -246,7 +278,7 @@ __device__ void eval_monomial(const EvalArgs &a, int mono, int lane, double *buf
     if (f0_scalar && j == 1)
       scal<L>(c, V, W, Dc, lane, G, 1);
     else
-      conv<L>(U, V, W, Dc, lane, 1);
+      conv_any<L>(U, V, W, Dc, lane, 1);
     wave_sync();
     double *t = U;
     U = W;
