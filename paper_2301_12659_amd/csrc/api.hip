@@ -114,7 +114,7 @@ Layout newton_layout(const md_plan *p) {
   w.bar = take(qr_scratch_bytes(L, n) / sizeof(double) + 1);
   w.invd = take(L * n);
   w.M = take(L * n * n);
-  w.N = take(2 * L * n * n);  // N = M A_1 and P = M A_2
+  w.N = take(3 * L * n * n);  // N = M A_1, P = M A_2, Q = M A_3
   w.At = take(L * n * n * D);
   w.r = take(L * n * D);
   w.dxT = take(L * n * D);
@@ -135,7 +135,7 @@ Layout newton_layout(const md_plan *p) {
 
 size_t solve_bytes(int L, int n, int D) {
   return align_up((size_t)L * n * sizeof(double)) + align_up((size_t)L * n * n * sizeof(double)) +
-         align_up((size_t)2 * L * n * n * sizeof(double)) + align_up((size_t)L * n * n * D * sizeof(double)) +
+         align_up((size_t)3 * L * n * n * sizeof(double)) + align_up((size_t)L * n * n * D * sizeof(double)) +
          2 * align_up((size_t)L * n * D * sizeof(double)) + align_up((size_t)mdk::stages_sync_ints(D) * sizeof(int));
 }
 
@@ -192,7 +192,7 @@ int series_solve_impl(int L, int n, int D, const double *qr, const double *tau, 
     return p;
   };
   const size_t nn = (size_t)n * n, nD = (size_t)n * D;
-  double *invd = take((size_t)L * n), *M = take((size_t)L * nn), *N = take((size_t)2 * L * nn);
+  double *invd = take((size_t)L * n), *M = take((size_t)L * nn), *N = take((size_t)3 * L * nn);
   double *At = take((size_t)L * nn * D), *rT = take((size_t)L * nD), *dxT = take((size_t)L * nD);
   int *sync = reinterpret_cast<int *>(take(mdk::stages_sync_ints(D) / 2 + 1));
   hipError_t e;
@@ -573,7 +573,7 @@ static int newton_step_impl(const md_plan *p, int Ls, int lo, int hi, bool keep_
     if ((e = mdk::launch_transpose_ld(Ls, b + lo, D, r, n, n, W, nD, nW, st)) != hipSuccess)
       return hip_fail(e, "b^T");
   }
-  // 4. join, N = M A_1 (and P = M A_2), the staged solve of the window (its
+  // 4. join, N = M A_1 (and P = M A_2, Q = M A_3), the staged solve of the window (its
   //    counters cleared before the join, while the factorization finishes)
   int *sync = reinterpret_cast<int *>(at(ws, w.sync));
   if ((e = mdk::launch_stages_sync(Ls, n, W, sync, st)) != hipSuccess) return hip_fail(e, "stage counters");
@@ -975,7 +975,7 @@ int md_adjoint_workspace_size(int prec, int n, int d, size_t *bytes) {
   if (!bytes || !valid_prec(prec) || n < 1 || n > MD_MAX_DIM || d < 0 || d + 1 > MD_MAX_COEFFS)
     return fail(MD_EINVAL, "bad argument");
   const size_t L = prec, nn = (size_t)n * n, nD = (size_t)n * (d + 1);
-  *bytes = align_up(L * n * 8) + 2 * align_up(L * nn * 8) + align_up(2 * L * nn * 8) +
+  *bytes = align_up(L * n * 8) + 2 * align_up(L * nn * 8) + align_up(3 * L * nn * 8) +
            2 * align_up(L * nn * (d + 1) * 8) + 2 * align_up(L * nD * 8) +
            align_up((size_t)mdk::stages_sync_ints(d + 1) * sizeof(int));
   return MD_OK;
@@ -996,7 +996,7 @@ int md_adjoint_solve(int prec, int n, int d, const double *qr, const double *tau
     return p;
   };
   double *invd = take((size_t)L * n), *M = take((size_t)L * nn), *Mt = take((size_t)L * nn),
-         *Nt = take((size_t)2 * L * nn);
+         *Nt = take((size_t)3 * L * nn);
   double *At = take((size_t)L * nn * D), *AtT = take((size_t)L * nn * D), *rho = take((size_t)L * nD),
          *lamT = take((size_t)L * nD);
   int *sync = reinterpret_cast<int *>(take(mdk::stages_sync_ints(D) / 2 + 1));

@@ -14,7 +14,9 @@
 // which is A_0^{-1} (b_k - sum_{j=1..k} A_j dx_{k-j}) reassociated so that the
 // only work that waits for dx_{k-1} is one matrix-vector product per row; in
 // the same launch every later right-hand side r_m (m > k) receives its term
-// A_{m-k+1} dx_{k-1}.  Every stage is one launch over the whole GPU.
+// A_{m-k+1} dx_{k-1}.  Every stage is one launch over the whole GPU; for
+// n <= 64 in double and quad double one persistent launch runs all stages
+// with the recurrence reassociated further (stages_persistent_kernel).
 #include <algorithm>
 
 #include "common.hpp"
@@ -902,59 +904,64 @@ __global__ void __launch_bounds__(256) next_x0_kernel(int n, int D, const double
   }
 }
 
-// Counters of the persistent staged solve, one per 256 bytes so that the
-// polls of one do not contend with the updates of another.
+// Counters of the persistent staged solve: the updaters' counters one per
+// 256 bytes, the solvers' flags packed into the second block of 256 bytes.
 constexpr int SYNC_STRIDE = 64;
 
-// The whole staged solve in one launch, for n <= 64.  With P = M A_2 the
-// recurrence is reassociated once more,
-//     dx_k = M r'_k - N dx_{k-1} - P dx_{k-2},  r'_k = b_k - sum_{j>=3} A_j dx_{k-j},
-// so that a stage only needs right-hand-side terms at least two stages old.
-// Solver workgroups 0 .. Gs-1 (Gs = ceil(n/4)): wavefront w of solver s owns
-// row i = 4 s + w and keeps M(i,.), N(i,.), P(i,.) in registers (lane v holds
-// column v); stage k is one dot product of length 3n per row.  (One
-// workgroup cannot carry the stage: its n x 3n multiply-adds would keep one
-// CU busy for several microseconds.)  After its rows of dx_k are in dxT,
-// solver s sets its flag to k + 1; a wavefront waits for all solvers with
-// one lane per flag and a vote.  The last workgroup (a forwarder) turns the
-// flags into one count, which the updaters poll with a longer sleep (they
-// have two stages of slack).  Updater (g, b) owns the rows 16 b .. 16 b + 15
-// (one team of 16 lanes per row) of the coefficients m = 3 + g + j Gm; in
-// round q, once dx_q is out, it applies r'_m -= A_{m-q} dx_q to its
-// m >= q + 3 and adds 1 to their round counters; stage k waits for the
-// counter of m = k to reach Bm (k - 2).  Every (m, i) has one owner, so
-// rounds never update it concurrently.  Everything handed between
-// workgroups (dx, r', flags) goes through agent-scope loads and stores and a
-// wait for the stores before the flag, never through fences: a fence would
-// write back or invalidate a whole L2 at every hand-over, hundreds of them
-// per stage.  Counters sit 256 bytes apart.  All workgroups must be
-// resident together; waits are bounded and report MD_EHIP.
+// Products of M with the leading Jacobian coefficients that the persistent
+// staged solve takes as a whole: N = M A_1, P = M A_2, Q = M A_3.
+constexpr int STAGE_PRODUCTS = 3;
+
+// The whole staged solve in one launch, for n <= 64.  With P = M A_2 and
+// Q = M A_3 the recurrence is reassociated twice more,
+//     dx_k = M r''_k - N dx_{k-1} - P dx_{k-2} - Q dx_{k-3},
+//     r''_k = b_k - sum_{j>=4} A_j dx_{k-j},
+// so that a stage only needs right-hand-side terms at least three stages
+// old.  Solver workgroup s (s < Gs = ceil(n/2)) owns rows i = 2 s + w, w = 0, 1,
+// with two wavefronts per row (lane v holds column v):
+//   * the critical wavefront of row i keeps N(i,.) in registers; at stage k it
+//     waits for every solver's dx_{k-1}, adds N(i,.) dx_{k-1} to the level
+//     sums pre_k(i) left in LDS by its companion, reduces them over the 64
+//     lanes, renormalizes and stores dx_k(i);
+//   * the companion wavefront keeps M(i,.), P(i,.), Q(i,.) and forms, while
+//     stage k runs, pre_{k+1}(i) = M r''_{k+1} - Q dx_{k-2} - P dx_{k-1} in
+//     lane-wise level sums: r''_{k+1} once its updaters have published it,
+//     dx_{k-2} from its registers, dx_{k-1} from the LDS copy that the
+//     critical wavefront made at the start of stage k.
+// So a stage's critical path holds one multiply-add per lane, one butterfly
+// and the hand-overs.  One workgroup barrier per stage separates the two
+// wavefronts' uses of the LDS slots (pre_k in slot k mod 2).  After both rows
+// of dx_k are out, solver s sets its flag to k + 1; the flags share one
+// 128-byte line, and a wavefront waits for all solvers with one lane per flag
+// and a vote.  Updater (g, b) owns the rows 16 b .. 16 b + 15 (one team of 16
+// lanes per row) of coefficient m = 4 + g (and m + Gm when there are more than
+// 64 coefficients from 4 on): in round q, once dx_q is out, every lane adds
+// its four terms of A_{m-q}(i,.) dx_q to level sums kept in registers across
+// the rounds; after round m - 4 the team reduces them, renormalizes,
+// stores r''_m(i) = b_m(i) - sum and counts itself done for m, so r''_m is
+// written once, by its owner.  Everything handed between workgroups (dx,
+// r'', flags) goes through agent-scope loads and stores and a wait for the
+// stores before the flag, never through fences: a fence would write back or
+// invalidate a whole L2 at every hand-over, hundreds of them per stage.  All
+// workgroups must be resident together; waits are bounded and report
+// MD_EHIP, after which every wavefront of a workgroup leaves at the same
+// barrier.
 template <int L>
 __global__ void __launch_bounds__(256) stages_persistent_kernel(int n, int D, int Gs, int Gm, const double *M,
                                                                 const double *NP, const double *At, double *rT,
                                                                 double *dxT, int *sync, int32_t *status) {
-  __shared__ int sh_ok, sh_dead;  // sh_dead: a solver wavefront's wait timed out
-  __shared__ double xq[L * 64];  // dx_q of an updater round
+  __shared__ int sh_dead[2];               // a wait of stage k timed out (slot k mod 2)
+  __shared__ int sh_ok;                    // an updater round may start
+  __shared__ int sh_x1[2];                 // stage k whose dx_{k-1} is in x1s[w]
+  __shared__ double x1s[2][L * 64];        // dx_{k-1}, critical -> companion wavefront of row slot w
+  __shared__ double pres[2][2][L * 64];    // pre_k level sums of row slot w in slot k mod 2
+  __shared__ double xq[L * 64];            // dx_q of an updater round
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const size_t nn = (size_t)n * n, nD = (size_t)n * D, nnD = nn * D;
   const int Bm = (n + 15) / 16;
-  int *const forwarded = sync + SYNC_STRIDE;
   auto rounds = [&](int m) { return sync + (size_t)(2 + m) * SYNC_STRIDE; };
-  auto solved = [&](int s) { return sync + (size_t)(2 + D + s) * SYNC_STRIDE; };  // stages done by solver s
+  auto solved = [&](int s) { return sync + SYNC_STRIDE + s; };  // stages done by solver s (one 128-byte line)
   auto poll = [&](const int *p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); };
-  // bounded wait until *p >= target by one thread
-  auto wait_one = [&](const int *p, int target, int sleep16) {
-    long spins = 0;
-    while (poll(p) < target) {
-      if (sleep16) __builtin_amdgcn_s_sleep(16);
-      else __builtin_amdgcn_s_sleep(1);
-      if (++spins > (1L << 22)) {
-        set_status(status, MD_EHIP);
-        return false;
-      }
-    }
-    return true;
-  };
   // wavefront-wide wait until every solver has published stage k - 1: lane
   // s polls solver s's flag, the wavefront votes
   auto wait_solvers = [&](int k) {
@@ -971,94 +978,165 @@ __global__ void __launch_bounds__(256) stages_persistent_kernel(int n, int D, in
     return true;
   };
   if ((int)blockIdx.x < Gs) {
-    const int i = blockIdx.x * 4 + wv;
+    const int w = wv & 1;              // row slot
+    const bool crit = wv < 2;          // critical wavefront (else the companion)
+    const int i = blockIdx.x * 2 + w;
     const bool row = i < n, col = lane < n;
     const int ii = row ? i : 0, v = col ? lane : 0;
-    double m[L], nv[L], pv[L];
-    md::zero<L>(m);
-    md::zero<L>(nv);
-    md::zero<L>(pv);
-    if (col) {
-      ld<L>(M, nn, (size_t)ii * n + v, m);
-      if (D > 1) ld<L>(NP, nn, (size_t)ii * n + v, nv);
-      if (D > 2) ld<L>(NP + (size_t)L * nn, nn, (size_t)ii * n + v, pv);
-      md::neg<L>(nv, nv);
-      md::neg<L>(pv, pv);
+    if (tid < 2) {
+      sh_dead[tid] = 0;
+      sh_x1[tid] = 0;
     }
-    // wavefront-wide wait until the updaters have finished round target of
-    // coefficient mm (all lanes poll the same counter)
-    auto wait_rounds = [&](int mm, int target) {
-      long spins = 0;
-      while (true) {
-        const int f = poll(rounds(mm));
-        if (__all(f >= target)) break;
-        __builtin_amdgcn_s_sleep(1);
-        if (++spins > (1L << 22)) {
-          if (lane == 0) set_status(status, MD_EHIP);
-          return false;
-        }
+    double *const slot0 = &pres[w][0][0], *const slot1 = &pres[w][1][0];
+    if (crit) {
+      double nv[L];
+      md::zero<L>(nv);
+      if (row && col && D > 1) {
+        ld<L>(NP, nn, (size_t)ii * n + v, nv);
+        md::neg<L>(nv, nv);
       }
-      return true;
-    };
-    // Only N dx_{k-1} waits for the previous stage: M r'_k (final once the
-    // updaters have applied every dx_q, q <= k - 3) and P dx_{k-2} are
-    // accumulated into the lane's level sums while the solvers wait for each
-    // other, so a stage's critical path holds one multiply-add per lane.
-    if (tid == 0) sh_dead = 0;
-    double pre[L], x1[L];  // the terms of the coming stage known in advance; dx_{k-1}(v)
+      __syncthreads();  // pre_0 is in slot 0
+      for (int k = 0; k < D; ++k) {
+        double acc[L], r[L], x1[L];
+        const double *slot = (k & 1) ? slot1 : slot0;
+#pragma unroll
+        for (int l = 0; l < L; ++l) acc[l] = slot[l * 64 + lane];
+        if (k >= 1) {
+          const bool ok = row ? wait_solvers(k) : true;
+          if (!ok && lane == 0) sh_dead[k & 1] = 1;
+          md::zero<L>(x1);
+          if (ok && row && col) ld_agent<L>(dxT, nD, (size_t)(k - 1) * n + v, x1);
+#pragma unroll
+          for (int l = 0; l < L; ++l) x1s[w][l * 64 + lane] = x1[l];
+          __hip_atomic_store(&sh_x1[w], k, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+          MD<L>::fma_lazy(acc, nv, x1);
+        }
+        if (row) {
+          team_sum_lazy<L>(acc, 64);
+          MD<L>::renorm(acc, r);
+          if (lane == 0) st_agent<L>(dxT, nD, (size_t)k * n + i, r);
+        }
+        wait_vm();
+        __syncthreads();  // both rows of dx_k stored; pre_{k+1} is in its slot
+        if (sh_dead[k & 1]) return;
+        if (tid == 0) __hip_atomic_store(solved(blockIdx.x), k + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      return;
+    }
+    // companion wavefront
+    double m[L], pv[L], qv[L], x2[L], pre[L];
+    md::zero<L>(m);
+    md::zero<L>(pv);
+    md::zero<L>(qv);
+    md::zero<L>(x2);
     md::zero<L>(pre);
-    md::zero<L>(x1);
-    if (col) {
+    if (row && col) {
+      ld<L>(M, nn, (size_t)ii * n + v, m);
+      if (D > 2) ld<L>(NP + (size_t)L * nn, nn, (size_t)ii * n + v, pv);
+      if (D > 3) ld<L>(NP + (size_t)2 * L * nn, nn, (size_t)ii * n + v, qv);
+      md::neg<L>(pv, pv);
+      md::neg<L>(qv, qv);
       double a[L];
       ld_agent<L>(rT, nD, (size_t)v, a);
       MD<L>::fma_lazy(pre, m, a);
     }
+#pragma unroll
+    for (int l = 0; l < L; ++l) slot0[l * 64 + lane] = pre[l];
+    __syncthreads();  // pre_0 is in slot 0
     for (int k = 0; k < D; ++k) {
-      if (wv == 0) {
-        const bool ok = (k >= 1) ? wait_solvers(k) : true;
-        if (lane == 0) sh_ok = (ok && !sh_dead) ? 1 : 0;
-      }
-      __syncthreads();
-      if (!sh_ok) return;
-      double acc[L], r[L];
-      md::copy<L>(pre, acc);
-      if (col && k >= 1) {
-        ld_agent<L>(dxT, nD, (size_t)(k - 1) * n + v, x1);
-        MD<L>::fma_lazy(acc, nv, x1);
-      }
-      team_sum_lazy<L>(acc, 64);
-      MD<L>::renorm(acc, r);
-      if (row && lane == 0) st_agent<L>(dxT, nD, (size_t)k * n + i, r);
-      wait_vm();
-      __syncthreads();
-      if (tid == 64) __hip_atomic_store(solved(blockIdx.x), k + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (k + 1 < D) {  // M r'_{k+1} + P dx_{k-1}
-        if (k + 1 >= 3 && !wait_rounds(k + 1, Bm * (k - 1)) && lane == 0) sh_dead = 1;
+      if (k + 1 < D && row) {  // pre_{k+1} while stage k runs
+        bool ok = true;
+        if (k + 1 > STAGE_PRODUCTS) {  // r''_{k+1} published by its Bm updaters
+          long spins = 0;
+          while (true) {
+            const int f = poll(rounds(k + 1));
+            if (__all(f >= Bm)) break;
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins > (1L << 22)) {
+              if (lane == 0) set_status(status, MD_EHIP);
+              ok = false;
+              break;
+            }
+          }
+        }
         md::zero<L>(pre);
-        if (col) {
+        if (ok && col) {
           double a[L];
           ld_agent<L>(rT, nD, (size_t)(k + 1) * n + v, a);
           MD<L>::fma_lazy(pre, m, a);
-          if (k >= 1) MD<L>::fma_lazy(pre, pv, x1);
+          if (k >= 2) MD<L>::fma_lazy(pre, qv, x2);
         }
+        if (k >= 1) {  // dx_{k-1} from the critical wavefront of this row
+          long spins = 0;
+          while (__hip_atomic_load(&sh_x1[w], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < k) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins > (1L << 22)) {
+              if (lane == 0) set_status(status, MD_EHIP);
+              ok = false;
+              break;
+            }
+          }
+          double x1[L];
+#pragma unroll
+          for (int l = 0; l < L; ++l) x1[l] = x1s[w][l * 64 + lane];
+          if (ok && col) MD<L>::fma_lazy(pre, pv, x1);
+          md::copy<L>(x1, x2);
+        }
+        if (!ok && lane == 0) sh_dead[k & 1] = 1;
+        double *slot = ((k + 1) & 1) ? slot1 : slot0;
+#pragma unroll
+        for (int l = 0; l < L; ++l) slot[l * 64 + lane] = pre[l];
       }
+      __syncthreads();
+      if (sh_dead[k & 1]) return;
     }
     return;
   }
-  if ((int)blockIdx.x == gridDim.x - 1) {  // forwarder
-    if (wv == 0)
-      for (int k = 1; k + 2 < D; ++k) {
-        if (!wait_solvers(k)) break;
-        if (lane == 0) __hip_atomic_store(forwarded, k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
-    return;
-  }
+  // updater (g, b): rows 16 b .. 16 b + 15, coefficients m0 and m1 (if below D)
   const int u = blockIdx.x - Gs, g = u / Bm, b = u - g * Bm;
   const int team = tid / 16, tl = tid & 15;
   const int i = b * 16 + team;
-  const int m_last = 3 + g + ((D - 1 - (3 + g)) / Gm) * Gm;  // largest owned coefficient
-  for (int q = 0; q + 3 <= m_last; ++q) {
-    if (tid == 0) sh_ok = wait_one(forwarded, q + 1, 1) ? 1 : 0;
+  const bool live = i < n;
+  const int m0 = STAGE_PRODUCTS + 1 + g, m1 = m0 + Gm;
+  const int qlast = (m1 < D ? m1 : m0) - STAGE_PRODUCTS - 1;
+  double acc0[L], acc1[L];  // lane-wise level sums of sum_q A_{m-q}(i, v) dx_q(v)
+  md::zero<L>(acc0);
+  md::zero<L>(acc1);
+  // r''_m(i) = b_m(i) - (the team's sum of acc) once every round q <= m - 4 is in
+  auto publish = [&](int mm, const double (&acc)[L]) {
+    double t[L], r[L];
+    md::copy<L>(acc, t);
+    team_sum_lazy<L>(t, 16);
+    MD<L>::renorm(t, r);
+    if (live && tl == 0) {
+      double rv[L], s2[L];
+      ld_agent<L>(rT, nD, (size_t)mm * n + i, rv);
+      MD<L>::sub(rv, r, s2);
+      st_agent<L>(rT, nD, (size_t)mm * n + i, s2);
+    }
+    wait_vm();
+    __syncthreads();
+    if (tid == 0) __hip_atomic_fetch_add(rounds(mm), 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  };
+  // the row's four terms A_{m0-q}(i, tl + 16 j) of the coming round, loaded
+  // while the previous round waits (they do not depend on dx)
+  double an[4][L];
+  auto fetch0 = [&](int q) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int vv = tl + 16 * j;
+      if (live && vv < n && q + STAGE_PRODUCTS + 1 <= m0)
+        ld<L>(At + (size_t)(m0 - q) * nn, nnD, (size_t)i * n + vv, an[j]);
+      else
+        md::zero<L>(an[j]);
+    }
+  };
+  fetch0(0);
+  for (int q = 0; q <= qlast; ++q) {
+    if (wv == 0) {
+      const bool ok = wait_solvers(q + 1);  // dx_q is out
+      if (lane == 0) sh_ok = ok ? 1 : 0;
+    }
     __syncthreads();
     if (!sh_ok) return;
     for (int e = tid; e < L * n; e += blockDim.x) {
@@ -1067,37 +1145,32 @@ __global__ void __launch_bounds__(256) stages_persistent_kernel(int n, int D, in
                                           __HIP_MEMORY_SCOPE_AGENT);
     }
     __syncthreads();
-    int m0 = 3 + g;
-    while (m0 < q + 3) m0 += Gm;
-    for (int mm = m0; mm < D; mm += Gm) {
-      const double *Aj = At + (size_t)(mm - q) * nn;
-      double acc[L], r[L], rv[L];
-      md::zero<L>(acc);
-      // r'_m(i) was last written by this same lane (an earlier round) or by
-      // an earlier kernel
-      if (i < n && tl == 0) ld_agent<L>(rT, nD, (size_t)mm * n + i, rv);
-      if (i < n) {
-        for (int vv = tl; vv < n; vv += 16) {
-          double a[L], x[L];
-          ld<L>(Aj, nnD, (size_t)i * n + vv, a);
+    const bool use0 = q + STAGE_PRODUCTS + 1 <= m0, use1 = m1 < D && q + STAGE_PRODUCTS + 1 <= m1;
+    if (live && use0) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int vv = tl + 16 * j;
+        if (vv < n) {
+          double x[L];
 #pragma unroll
           for (int l = 0; l < L; ++l) x[l] = xq[l * 64 + vv];
-          MD<L>::fma_lazy(acc, a, x);
+          MD<L>::fma_lazy(acc0, an[j], x);
         }
       }
-      team_sum_lazy<L>(acc, 16);
-      MD<L>::renorm(acc, r);
-      if (i < n && tl == 0) {
-        double s2[L];
-        MD<L>::sub(rv, r, s2);
-        st_agent<L>(rT, nD, (size_t)mm * n + i, s2);
+    }
+    fetch0(q + 1);
+    if (live && use1) {
+      for (int vv = tl; vv < n; vv += 16) {
+        double a[L], x[L];
+#pragma unroll
+        for (int l = 0; l < L; ++l) x[l] = xq[l * 64 + vv];
+        ld<L>(At + (size_t)(m1 - q) * nn, nnD, (size_t)i * n + vv, a);
+        MD<L>::fma_lazy(acc1, a, x);
       }
     }
-    wait_vm();
-    __syncthreads();
-    if (tid == 0)
-      for (int mm = m0; mm < D; mm += Gm)
-        __hip_atomic_fetch_add(rounds(mm), 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (q + STAGE_PRODUCTS + 1 == m0) publish(m0, acc0);
+    if (m1 < D && q + STAGE_PRODUCTS + 1 == m1) publish(m1, acc1);
+    __syncthreads();  // xq is rewritten by the next round
   }
 }
 
@@ -1494,7 +1567,9 @@ bool stages_persistent(int L, int n, int D) { return (L == 2 || L == 4) && n <= 
 
 int stages_sync_ints(int D) { return (D + 2 + 64) * SYNC_STRIDE; }
 
-int stages_products(int L, int n, int D) { return stages_persistent(L, n, D) ? std::min(2, D - 1) : std::min(1, D - 1); }
+int stages_products(int L, int n, int D) {
+  return stages_persistent(L, n, D) ? std::min(STAGE_PRODUCTS, D - 1) : std::min(1, D - 1);
+}
 
 // The counters of the persistent staged solve cleared ahead of it (a caller
 // may issue this before it waits for the factorization, off the critical
@@ -1509,9 +1584,12 @@ hipError_t launch_stages_sync(int L, int n, int D, int *sync, hipStream_t st) {
 hipError_t launch_stages(int L, int n, int D, const double *M, const double *NP, const double *At, double *rT,
                          double *dxT, int *sync, int32_t *status, hipStream_t st, bool sync_ready) {
   if (stages_persistent(L, n, D)) {
-    const int Gs = (n + 3) / 4, Bm = (n + 15) / 16;
-    const int Gm = D > 3 ? std::min(D - 3, 60) : 0;  // coefficient groups of the updaters
-    const int G = Gs + Gm * Bm + 1;                  // at most 16 + 240 + 1 workgroups of 256 threads
+    const int Gs = (n + 1) / 2, Bm = (n + 15) / 16;
+    // coefficient groups of the updaters: coefficients STAGE_PRODUCTS + 1 .. D - 1,
+    // one per group up to 64 of them, else two
+    const int C = D > STAGE_PRODUCTS + 1 ? D - STAGE_PRODUCTS - 1 : 0;
+    const int Gm = C <= 64 ? C : (C + 1) / 2;
+    const int G = Gs + Gm * Bm;  // at most 32 + 256 workgroups of 256 threads
     if (!sync_ready) {
       const hipError_t e = launch_stages_sync(L, n, D, sync, st);
       if (e != hipSuccess) return e;
