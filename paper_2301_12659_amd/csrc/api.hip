@@ -22,6 +22,7 @@ struct md_plan {
   // evaluation (default priority, non-blocking), with fork and join events
   hipStream_t aux = nullptr;
   hipEvent_t fork = nullptr, join = nullptr;
+  hipEvent_t x0done = nullptr;  // md_newton_steps: next_x0_kernel on the second stream has read x_0
 };
 
 namespace {
@@ -142,7 +143,10 @@ size_t solve_bytes(int L, int n, int D) {
 double *at(void *ws, size_t byte_off) { return reinterpret_cast<double *>(static_cast<char *>(ws) + byte_off); }
 
 
-hipError_t run_qr(int L, int n, double *a, double *tau, double *qt, int32_t *status, void *scratch, hipStream_t st) {
+// flags_ready: the QR's column flags (the first n ints of the scratch) were
+// cleared by an earlier launch on this stream (the A_0 assembly).
+hipError_t run_qr(int L, int n, double *a, double *tau, double *qt, int32_t *status, void *scratch, hipStream_t st,
+                  bool flags_ready = false) {
   char *p = static_cast<char *>(scratch);
   int *flags = reinterpret_cast<int *>(p);
   p += align_up((size_t)n * sizeof(int));
@@ -152,7 +156,7 @@ hipError_t run_qr(int L, int n, double *a, double *tau, double *qt, int32_t *sta
   p += align_up((size_t)n * 2 * L * sizeof(double));
   unsigned *bar = reinterpret_cast<unsigned *>(p);
   if (mdk::qr_lds_workgroups(L, n, qt != nullptr) > 0)
-    return mdk::launch_qr_lds(L, n, a, tau, qt, status, flags, vboard, tboard, st);
+    return mdk::launch_qr_lds(L, n, a, tau, qt, status, flags, vboard, tboard, st, flags_ready);
   return mdk::launch_qr(L, n, a, tau, qt, status, bar, st);
 }
 
@@ -344,7 +348,8 @@ int md_plan_create(int prec, int n, int d, int m, const int32_t *poly_ptr, const
       (e = up(&p->d_row_of, row_of.data(), m)) != hipSuccess ||
       (e = hipStreamCreateWithFlags(&p->aux, hipStreamNonBlocking)) != hipSuccess ||
       (e = hipEventCreateWithFlags(&p->fork, hipEventDisableTiming)) != hipSuccess ||
-      (e = hipEventCreateWithFlags(&p->join, hipEventDisableTiming)) != hipSuccess) {
+      (e = hipEventCreateWithFlags(&p->join, hipEventDisableTiming)) != hipSuccess ||
+      (e = hipEventCreateWithFlags(&p->x0done, hipEventDisableTiming)) != hipSuccess) {
     md_plan_destroy(p);
     return hip_fail(e, "plan setup");
   }
@@ -359,6 +364,7 @@ int md_plan_destroy(md_plan *p) {
     if (q) (void)hipFree(q);
   if (p->fork) (void)hipEventDestroy(p->fork);
   if (p->join) (void)hipEventDestroy(p->join);
+  if (p->x0done) (void)hipEventDestroy(p->x0done);
   if (p->aux) (void)hipStreamDestroy(p->aux);
   delete p;
   return MD_OK;
@@ -396,7 +402,9 @@ static void eval_args(const md_plan *p, const double *cff, const double *x, void
 // per medium quad-double step), while alone two wavefronts per monomial are
 // faster (353 against 403 us).
 static int eval_diff_impl(const md_plan *p, int Dc, const double *cff, const double *cst, const double *x, double *b,
-                          double *A, void *ws, hipStream_t st, double *tsz = nullptr, bool beside_qr = false) {
+                          double *A, void *ws, hipStream_t st, double *tsz = nullptr, bool beside_qr = false,
+                          mdk::TOut rt = mdk::TOut(), mdk::TOut aT = mdk::TOut(), int *clear = nullptr,
+                          int clear_count = 0) {
   Layout w = newton_layout(p);
   mdk::EvalArgs a;
   eval_args(p, cff, x, ws, Dc, a);
@@ -411,7 +419,7 @@ static int eval_diff_impl(const md_plan *p, int Dc, const double *cff, const dou
   {
     Timed t(MD_CLASS_ASSEMBLY, st);
     e = mdk::launch_assemble(p->L, p->n, p->D, Dc, p->m, p->nnz, p->d_poly_ptr, p->d_asm_ptr, p->d_asm_ent, cst,
-                             a.val, a.der, b, A, st, tsz, a.vsize);
+                             a.val, a.der, b, A, st, tsz, a.vsize, rt, aT, clear, clear_count);
   }
   if (e != hipSuccess) return hip_fail(e, "assembly launch");
   return MD_OK;
@@ -511,7 +519,9 @@ static int newton_step_impl(const md_plan *p, int Ls, int lo, int hi, bool keep_
       e = pre0 ? mdk::launch_evaldiff0(Ls, a, st) : mdk::launch_evaldiff(Ls, a, p->maxexp, at(ws, w.pw), st);
       a.reset_status = nullptr;
       if (e != hipSuccess) return hip_fail(e, "A_0 pre-pass");
-      if ((e = mdk::launch_assemble_A0(Ls, n, D, p->nnz, p->d_asm_ptr, p->d_asm_ent, a.der, qr, st)) != hipSuccess)
+      // (its launch also clears the QR's column flags)
+      if ((e = mdk::launch_assemble_A0(Ls, n, D, p->nnz, p->d_asm_ptr, p->d_asm_ent, a.der, qr, st,
+                                       reinterpret_cast<int *>(at(ws, w.bar)), n)) != hipSuccess)
         return hip_fail(e, "A_0 assembly");
     }
     // 2. fork: QR of A_0 with Q^T, then M = R^{-1} Q^T, on the second stream
@@ -519,7 +529,8 @@ static int newton_step_impl(const md_plan *p, int Ls, int lo, int hi, bool keep_
     if ((e = hipStreamWaitEvent(p->aux, p->fork, 0)) != hipSuccess) return hip_fail(e, "fork wait");
     {
       Timed t(MD_CLASS_QR, p->aux);
-      if ((e = run_qr(Ls, n, qr, tau, qt, dev_status, at(ws, w.bar), p->aux)) != hipSuccess) return hip_fail(e, "qr");
+      if ((e = run_qr(Ls, n, qr, tau, qt, dev_status, at(ws, w.bar), p->aux, true)) != hipSuccess)
+        return hip_fail(e, "qr");
     }
     {
       Timed t(MD_CLASS_QHB_BS, p->aux);
@@ -530,9 +541,16 @@ static int newton_step_impl(const md_plan *p, int Ls, int lo, int hi, bool keep_
   }
   // 3. the evaluation and differentiation of the first hi coefficients on the
   //    caller's stream; mixed: the values at L limbs for b, the derivatives
-  //    at Ls limbs for A
+  //    at Ls limbs for A.  The assembly also writes the coefficient-major
+  //    copies A_0..A_{W-1} [Ls][W][n][n] and b_lo..b_{hi-1} [Ls][W][n] that
+  //    the staged solve reads, and clears the solve's counters.
+  const size_t nn = (size_t)n * n;
+  double *At = at(ws, w.At), *dxT = at(ws, w.dxT);
+  int *sync = reinterpret_cast<int *>(at(ws, w.sync));
+  const mdk::TOut rt{r, lo, W, Ls}, atT{At, 0, W, Ls};
+  const int nsync = mdk::stages_sync_ints(W);
   if (!mixed) {
-    int rc = eval_diff_impl(p, hi, cff, cst, x, b, A, ws, st, tsz, !keep_m);
+    int rc = eval_diff_impl(p, hi, cff, cst, x, b, A, ws, st, tsz, !keep_m, rt, atT, sync, nsync);
     if (rc != MD_OK) return rc;
   } else {
     eval_args(p, cff, x, ws, hi, a);
@@ -546,8 +564,8 @@ static int newton_step_impl(const md_plan *p, int Ls, int lo, int hi, bool keep_
     }
     {
       Timed t(MD_CLASS_ASSEMBLY, st);
-      if ((e = mdk::launch_assemble_b(L, n, D, hi, p->m, p->d_poly_ptr, cst, a.val, b, st, tsz, a.vsize)) !=
-          hipSuccess)
+      if ((e = mdk::launch_assemble_b(L, n, D, hi, p->m, p->d_poly_ptr, cst, a.val, b, st, tsz, a.vsize, rt, sync,
+                                      nsync)) != hipSuccess)
         return hip_fail(e, "residual assembly");
     }
     a.values_only = 0;
@@ -559,24 +577,12 @@ static int newton_step_impl(const md_plan *p, int Ls, int lo, int hi, bool keep_
     }
     {
       Timed t(MD_CLASS_ASSEMBLY, st);
-      if ((e = mdk::launch_assemble_A(Ls, n, D, hi, p->nnz, p->d_asm_ptr, p->d_asm_ent, a.der, A, st)) != hipSuccess)
+      if ((e = mdk::launch_assemble_A(Ls, n, D, hi, p->nnz, p->d_asm_ptr, p->d_asm_ent, a.der, A, st, atT)) !=
+          hipSuccess)
         return hip_fail(e, "Jacobian assembly");
     }
   }
-  const size_t nn = (size_t)n * n, nD = (size_t)n * D, nW = (size_t)n * W;
-  double *At = at(ws, w.At), *dxT = at(ws, w.dxT);
-  {
-    // coefficient-major A_0..A_{W-1} [Ls][W][n][n] and b_lo..b_{hi-1} [Ls][W][n]
-    Timed t(MD_CLASS_UPDATES, st);
-    if ((e = mdk::launch_transpose_ld(Ls, A, D, At, nn, nn, W, nn * D, nn * W, st)) != hipSuccess)
-      return hip_fail(e, "A^T");
-    if ((e = mdk::launch_transpose_ld(Ls, b + lo, D, r, n, n, W, nD, nW, st)) != hipSuccess)
-      return hip_fail(e, "b^T");
-  }
-  // 4. join, N = M A_1 (and P = M A_2, Q = M A_3), the staged solve of the window (its
-  //    counters cleared before the join, while the factorization finishes)
-  int *sync = reinterpret_cast<int *>(at(ws, w.sync));
-  if ((e = mdk::launch_stages_sync(Ls, n, W, sync, st)) != hipSuccess) return hip_fail(e, "stage counters");
+  // 4. join, N = M A_1 (and P = M A_2, Q = M A_3), the staged solve of the window
   if (!keep_m && (e = hipStreamWaitEvent(st, p->join, 0)) != hipSuccess) return hip_fail(e, "join wait");
   if (W > 1) {
     Timed t(MD_CLASS_GEMM, st);
@@ -641,10 +647,17 @@ static int newton_steps_impl(const md_plan *p, int count, const double *cff, con
   // factorization of the iterate whose coefficient 0 is in xn ([L][n]) into
   // buffer set k, on the second stream after the fork event; its pre-pass
   // has derivative products of its own (der0), since the evaluation of the
-  // current step runs beside it
-  auto factor = [&](int k) -> int {
+  // current step runs beside it.  Mprev (nullable): first form xn = x_0 +
+  // M_prev r_0 there (next_x0_kernel), then record x0done, which the caller's
+  // stream waits for before it updates x.
+  auto factor = [&](int k, const double *Mprev) -> int {
     if ((e = hipEventRecord(p->fork, st)) != hipSuccess) return hip_fail(e, "fork");
     if ((e = hipStreamWaitEvent(p->aux, p->fork, 0)) != hipSuccess) return hip_fail(e, "fork wait");
+    if (Mprev) {
+      Timed t(MD_CLASS_X_UPDATE, p->aux);
+      if ((e = mdk::launch_next_x0(L, n, D, Mprev, r, x, xn, p->aux)) != hipSuccess) return hip_fail(e, "next x_0");
+      if ((e = hipEventRecord(p->x0done, p->aux)) != hipSuccess) return hip_fail(e, "x_0 event");
+    }
     {
       Timed t(MD_CLASS_QR, p->aux);
       mdk::EvalArgs a;
@@ -652,10 +665,11 @@ static int newton_steps_impl(const md_plan *p, int count, const double *cff, con
       a.D = 1;  // one coefficient per series: xn and der0 [L][nnz]
       a.der = at(ws, w.der0);
       if ((e = mdk::launch_evaldiff0(L, a, p->aux)) != hipSuccess) return hip_fail(e, "A_0 pre-pass");
-      if ((e = mdk::launch_assemble_A0(L, n, 1, p->nnz, p->d_asm_ptr, p->d_asm_ent, a.der, qrs[k], p->aux)) !=
-          hipSuccess)
+      // (the A_0 assembly also clears the QR's column flags)
+      if ((e = mdk::launch_assemble_A0(L, n, 1, p->nnz, p->d_asm_ptr, p->d_asm_ent, a.der, qrs[k], p->aux,
+                                       reinterpret_cast<int *>(at(ws, w.bar)), n)) != hipSuccess)
         return hip_fail(e, "A_0 assembly");
-      if ((e = run_qr(L, n, qrs[k], taus[k], qts[k], dev_status, at(ws, w.bar), p->aux)) != hipSuccess)
+      if ((e = run_qr(L, n, qrs[k], taus[k], qts[k], dev_status, at(ws, w.bar), p->aux, true)) != hipSuccess)
         return hip_fail(e, "qr");
     }
     {
@@ -669,33 +683,22 @@ static int newton_steps_impl(const md_plan *p, int count, const double *cff, con
   // coefficient 0 of the first iterate into xn
   if ((e = mdk::launch_transpose_ld(L, x, D, xn, n, n, 1, (size_t)n * D, n, st)) != hipSuccess)
     return hip_fail(e, "x_0");
-  int rc = factor((count - 1) % 2);
+  int rc = factor((count - 1) % 2, nullptr);
   if (rc != MD_OK) return rc;
   for (int s = 0; s < count; ++s) {
     const int k = (count - 1 - s) % 2;
     // the evaluation is on the critical path here (the factorization of the
     // next step has slack): the two-wavefront kernel (0.69 against 0.75 ms
-    // per step)
-    rc = eval_diff_impl(p, D, cff, cst, x, b, A, ws, st, nullptr, false);
+    // per step); the assembly also writes the coefficient-major A and b and
+    // clears the staged solve's counters
+    rc = eval_diff_impl(p, D, cff, cst, x, b, A, ws, st, nullptr, false, mdk::TOut{r, 0, D, L},
+                        mdk::TOut{At, 0, D, L}, sync, mdk::stages_sync_ints(D));
     if (rc != MD_OK) return rc;
-    {
-      Timed t(MD_CLASS_UPDATES, st);
-      if ((e = mdk::launch_transpose_ld(L, A, D, At, nn, nn, D, nn * D, nn * D, st)) != hipSuccess)
-        return hip_fail(e, "A^T");
-      if ((e = mdk::launch_transpose_ld(L, b, D, r, n, n, D, (size_t)n * D, (size_t)n * D, st)) != hipSuccess)
-        return hip_fail(e, "b^T");
-    }
-    if ((e = mdk::launch_stages_sync(L, n, D, sync, st)) != hipSuccess) return hip_fail(e, "stage counters");
     if ((e = hipStreamWaitEvent(st, p->join, 0)) != hipSuccess) return hip_fail(e, "join wait");
-    if (s + 1 < count) {
-      // coefficient 0 of the next iterate, then its factorization beside
-      // the rest of this step and the next evaluation
-      {
-        Timed t(MD_CLASS_X_UPDATE, st);
-        if ((e = mdk::launch_next_x0(L, n, D, Ms[k], r, x, xn, st)) != hipSuccess) return hip_fail(e, "next x_0");
-      }
-      if ((rc = factor(1 - k)) != MD_OK) return rc;
-    }
+    // coefficient 0 of the next iterate (from M and r_0), then its
+    // factorization, on the second stream beside the rest of this step and
+    // the next evaluation
+    if (s + 1 < count && (rc = factor(1 - k, Ms[k])) != MD_OK) return rc;
     {
       Timed t(MD_CLASS_GEMM, st);
       if ((e = mdk::launch_gemm(L, n, Ms[k], At + nn, nn * D, N, mdk::stages_products(L, n, D), st)) != hipSuccess)
@@ -708,6 +711,9 @@ static int newton_steps_impl(const md_plan *p, int count, const double *cff, con
     }
     {
       Timed t(MD_CLASS_X_UPDATE, st);
+      // x_0 is read by next_x0_kernel on the second stream: update x after it
+      if (s + 1 < count && (e = hipStreamWaitEvent(st, p->x0done, 0)) != hipSuccess)
+        return hip_fail(e, "x_0 wait");
       if ((e = mdk::launch_finish(L, L, n, D, 0, D, dxT, dx, x, b, dev_norms, dev_status, st)) != hipSuccess)
         return hip_fail(e, "update");
     }

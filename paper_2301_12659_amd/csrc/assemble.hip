@@ -7,69 +7,128 @@
 #include "kernels.hpp"
 #include "md.hpp"
 
+#include <algorithm>
+
 namespace mdk {
 
-// b_i(t) = -(c_{i,0}(t) + sum_{m in P_i} value_m(t)), one thread per (i, s)
-// for the first Dc coefficients s.  tsz (nullable, [n][D]) gets the size of
-// the terms whose rounding errors reach b_{i,s}, against which the staggered
-// method judges it: |c_{i,0,s}| + sum_m vsize_{m,s}, the largest product of
-// each monomial's chain (|value_{m,s}| when vsize is null; leading limbs).
+// b_i(t) = -(c_{i,0}(t) + sum_{m in P_i} value_m(t)) for the first Dc
+// coefficients s, four lanes per (i, s): lane j adds the constant (j = 0)
+// and the values of monomials j, j + 4, ... of row i, in monomial order, with
+// renormalized additions; a two-level butterfly of renormalized additions
+// adds the four partial sums (a fixed order, reproducible).  A residual is a
+// sum that cancels: level sums accumulated across the terms and renormalized
+// once lose up to six times more against the size of the terms (exact
+// rational checks on the host) and can leave overlapping limbs.  tsz (nullable, [n][D])
+// gets the size of the terms whose rounding errors reach b_{i,s}, against
+// which the staggered method judges it: |c_{i,0,s}| + sum_m vsize_{m,s}, the
+// largest product of each monomial's chain (|value_{m,s}| when vsize is null;
+// leading limbs).  rt (nullable): coefficient-major copy for the staged
+// solve.  clear (nullable): clear_count ints set to zero on the way (the
+// staged solve's counters, which the caller launches next on this stream).
 template <int L>
-__global__ void assemble_b_kernel(int n, int D, int Dc, int m, const int32_t *poly_ptr, const double *cst,
-                                  const double *val, double *b, double *tsz, const double *vsize) {
+__global__ void __launch_bounds__(256) assemble_b_kernel(int n, int D, int Dc, int m, const int32_t *poly_ptr,
+                                                         const double *cst, const double *val, double *b, double *tsz,
+                                                         const double *vsize, TOut rt, int *clear, int clear_count) {
   const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (clear && t < (size_t)clear_count) clear[t] = 0;
   const size_t nD = (size_t)n * D, mD = (size_t)m * D;
-  if (t >= (size_t)n * Dc) return;
-  const int i = (int)(t / Dc), s = (int)(t - (size_t)i * Dc);
+  const size_t task = t >> 2;
+  const int j = (int)(t & 3);
+  const bool live = task < (size_t)n * Dc;
+  const size_t tk = live ? task : 0;
+  const int i = (int)(tk / Dc), s = (int)(tk - (size_t)i * Dc);
   const size_t q = (size_t)i * D + s;
-  double acc[L];
-  ld<L>(cst, nD, q, acc);
-  double size = fabs(acc[0]);
-  for (int mj = poly_ptr[i]; mj < poly_ptr[i + 1]; ++mj) {
-    double v[L], r[L];
-    ld<L>(val, mD, (size_t)mj * D + s, v);
-    size += vsize ? vsize[(size_t)mj * D + s] : fabs(v[0]);
-    MD<L>::add(acc, v, r);
-    md::copy<L>(r, acc);
+  double r[L];
+  md::zero<L>(r);
+  double size = 0.0;
+  if (live) {
+    int mj = poly_ptr[i] + j;
+    const int mend = poly_ptr[i + 1];
+    if (j == 0) {
+      ld<L>(cst, nD, q, r);
+      size = fabs(r[0]);
+    } else if (mj < mend) {
+      ld<L>(val, mD, (size_t)mj * D + s, r);
+      size = vsize ? vsize[(size_t)mj * D + s] : fabs(r[0]);
+      mj += 4;
+    }
+    for (; mj < mend; mj += 4) {
+      double v[L], t[L];
+      ld<L>(val, mD, (size_t)mj * D + s, v);
+      size += vsize ? vsize[(size_t)mj * D + s] : fabs(v[0]);
+      MD<L>::add(r, v, t);
+      md::copy<L>(t, r);
+    }
   }
-  md::neg<L>(acc, acc);
-  st<L>(b, nD, q, acc);
-  if (tsz) tsz[q] = size;
+  team_sum<L>(r, 4);
+  const double s01 = size + __shfl_xor(size, 1, 64);
+  size = s01 + __shfl_xor(s01, 2, 64);
+  md::neg<L>(r, r);
+  if (live && j == 0) {
+    st<L>(b, nD, q, r);
+    if (tsz) tsz[q] = size;
+    if (rt.p && s >= rt.lo && s < rt.lo + rt.W) {
+      const size_t ls = (size_t)n * rt.W;
+      for (int l = 0; l < rt.L; ++l) rt.p[(size_t)l * ls + (size_t)(s - rt.lo) * n + i] = r[l];
+    }
+  }
 }
 
 // A[i][j][s] = sum of the derivative series of row i's monomials with respect
-// to x_j, in monomial order; one thread per (i, j, s) for the first Dc
-// coefficients s.
-template <int L>
-__global__ void assemble_A_kernel(int n, int D, int Dc, int nnz, const int32_t *asm_ptr, const int32_t *asm_ent,
-                                  const double *der, double *A) {
-  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const size_t nnD = (size_t)n * n * D, zD = (size_t)nnz * D;
-  if (t >= (size_t)n * n * Dc) return;
-  const size_t ij = t / Dc;
-  const int s = (int)(t - ij * Dc);
-  const size_t q = ij * D + s;
-  const int lo = asm_ptr[ij], hi = asm_ptr[ij + 1];
-  double acc[L];
-  md::zero<L>(acc);
-  if (lo < hi) {
-    ld<L>(der, zD, (size_t)asm_ent[lo] * D + s, acc);
-    for (int t = lo + 1; t < hi; ++t) {
-      double v[L], r[L];
-      ld<L>(der, zD, (size_t)asm_ent[t] * D + s, v);
-      MD<L>::add(acc, v, r);
-      md::copy<L>(r, acc);
+// to x_j, in monomial order, for the first Dc coefficients s.  A workgroup
+// takes TI consecutive (i, j) and all Dc coefficients (reads and the
+// series-major writes along s); with at (nullable) the tile goes through LDS
+// so that the coefficient-major copy at[l][s][i][j] (s < at.W, at.L limbs) is
+// written along (i, j).
+template <int L, int TI>
+__global__ void __launch_bounds__(256) assemble_A_kernel(int n, int D, int Dc, int nnz, const int32_t *asm_ptr,
+                                                         const int32_t *asm_ent, const double *der, double *A,
+                                                         TOut at) {
+  extern __shared__ double tile[];  // [L][TI][Dc + 1]
+  const size_t nn = (size_t)n * n, nnD = nn * D, zD = (size_t)nnz * D;
+  const size_t ij0 = (size_t)blockIdx.x * TI;
+  const int Dp = Dc + 1;
+  for (int e = threadIdx.x; e < TI * Dc; e += blockDim.x) {
+    const int il = e / Dc, s = e - il * Dc;
+    const size_t ij = ij0 + il;
+    if (ij >= nn) continue;
+    const int lo = asm_ptr[ij], hi = asm_ptr[ij + 1];
+    double acc[L];
+    md::zero<L>(acc);
+    if (lo < hi) {
+      ld<L>(der, zD, (size_t)asm_ent[lo] * D + s, acc);
+      for (int t = lo + 1; t < hi; ++t) {
+        double v[L], r[L];
+        ld<L>(der, zD, (size_t)asm_ent[t] * D + s, v);
+        MD<L>::add(acc, v, r);
+        md::copy<L>(r, acc);
+      }
     }
+    st<L>(A, nnD, ij * D + s, acc);
+    if (at.p)
+#pragma unroll
+      for (int l = 0; l < L; ++l) tile[(l * TI + il) * Dp + s] = acc[l];
   }
-  st<L>(A, nnD, q, acc);
+  if (!at.p) return;
+  __syncthreads();
+  const size_t ls = nn * at.W;
+  for (int e = threadIdx.x; e < at.W * TI; e += blockDim.x) {
+    const int s = e / TI, il = e - s * TI;
+    const size_t ij = ij0 + il;
+    if (ij >= nn) continue;
+    for (int l = 0; l < at.L; ++l) at.p[(size_t)l * ls + (size_t)s * nn + ij] = tile[(l * TI + il) * Dp + s];
+  }
 }
 
 // Coefficient 0 of A into a dense row-major matrix a0 [L][n][n], summed in
 // the same order as assemble_A_kernel, so it equals A[i][j][0] bit for bit.
+// clear (nullable): clear_count ints set to zero (the QR's column flags,
+// when the QR of a0 follows on this stream).
 template <int L>
 __global__ void assemble_A0_kernel(int n, int D, int nnz, const int32_t *asm_ptr, const int32_t *asm_ent,
-                                   const double *der, double *a0) {
+                                   const double *der, double *a0, int *clear, int clear_count) {
   const size_t ij = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (clear && ij < (size_t)clear_count) clear[ij] = 0;
   const size_t nn = (size_t)n * n, zD = (size_t)nnz * D;
   if (ij >= nn) return;
   const int lo = asm_ptr[ij], hi = asm_ptr[ij + 1];
@@ -90,53 +149,63 @@ __global__ void assemble_A0_kernel(int n, int D, int nnz, const int32_t *asm_ptr
 // ------------------------------------------------------------------ launchers
 
 hipError_t launch_assemble_A0(int L, int n, int D, int nnz, const int32_t *asm_ptr, const int32_t *asm_ent,
-                              const double *der, double *a0, hipStream_t st) {
+                              const double *der, double *a0, hipStream_t st, int *clear, int clear_count) {
   const size_t nn = (size_t)n * n;
-  switch (L) {
-    case 1: hipLaunchKernelGGL(assemble_A0_kernel<1>, dim3((nn + 63) / 64), dim3(64), 0, st, n, D, nnz, asm_ptr, asm_ent, der, a0); break;
-    case 2: hipLaunchKernelGGL(assemble_A0_kernel<2>, dim3((nn + 63) / 64), dim3(64), 0, st, n, D, nnz, asm_ptr, asm_ent, der, a0); break;
-    case 4: hipLaunchKernelGGL(assemble_A0_kernel<4>, dim3((nn + 63) / 64), dim3(64), 0, st, n, D, nnz, asm_ptr, asm_ent, der, a0); break;
-    case 8: hipLaunchKernelGGL(assemble_A0_kernel<8>, dim3((nn + 63) / 64), dim3(64), 0, st, n, D, nnz, asm_ptr, asm_ent, der, a0); break;
-    default: return hipErrorInvalidValue;
-  }
+  const size_t threads = std::max(nn, (size_t)(clear ? clear_count : 0));
+  MD_DISPATCH(L, hipLaunchKernelGGL(assemble_A0_kernel<LL>, dim3((threads + 63) / 64), dim3(64), 0, st, n, D, nnz,
+                                    asm_ptr, asm_ent, der, a0, clear, clear_count));
   return hipGetLastError();
 }
 
 hipError_t launch_assemble_b(int L, int n, int D, int Dc, int m, const int32_t *poly_ptr, const double *cst,
-                             const double *val, double *b, hipStream_t st, double *tsz, const double *vsize) {
+                             const double *val, double *b, hipStream_t st, double *tsz, const double *vsize,
+                             TOut rt, int *clear, int clear_count) {
   if (Dc < 1 || Dc > D) return hipErrorInvalidValue;
-  const unsigned blocks = (unsigned)(((size_t)n * Dc + 255) / 256);
-  switch (L) {
-    case 1: hipLaunchKernelGGL(assemble_b_kernel<1>, dim3(blocks), dim3(256), 0, st, n, D, Dc, m, poly_ptr, cst, val, b, tsz, vsize); break;
-    case 2: hipLaunchKernelGGL(assemble_b_kernel<2>, dim3(blocks), dim3(256), 0, st, n, D, Dc, m, poly_ptr, cst, val, b, tsz, vsize); break;
-    case 4: hipLaunchKernelGGL(assemble_b_kernel<4>, dim3(blocks), dim3(256), 0, st, n, D, Dc, m, poly_ptr, cst, val, b, tsz, vsize); break;
-    case 8: hipLaunchKernelGGL(assemble_b_kernel<8>, dim3(blocks), dim3(256), 0, st, n, D, Dc, m, poly_ptr, cst, val, b, tsz, vsize); break;
-    default: return hipErrorInvalidValue;
-  }
+  if (rt.p && (rt.lo < 0 || rt.W < 1 || rt.lo + rt.W > Dc || rt.L < 1 || rt.L > L)) return hipErrorInvalidValue;
+  const size_t threads = std::max((size_t)n * Dc * 4, (size_t)(clear ? clear_count : 0));
+  const unsigned blocks = (unsigned)((threads + 255) / 256);
+  MD_DISPATCH(L, hipLaunchKernelGGL(assemble_b_kernel<LL>, dim3(blocks), dim3(256), 0, st, n, D, Dc, m, poly_ptr,
+                                    cst, val, b, tsz, vsize, rt, clear, clear_count));
   return hipGetLastError();
 }
 
+// Rows (i, j) per workgroup of assemble_A_kernel: 16 while the LDS tile stays
+// within 48 KB, else fewer.
+static int assemble_tile(int Lout, int Dc) {
+  int ti = 16;
+  while (ti > 1 && (size_t)ti * (Dc + 1) * Lout * sizeof(double) > 48 * 1024) ti /= 2;
+  return ti;
+}
+
 hipError_t launch_assemble_A(int L, int n, int D, int Dc, int nnz, const int32_t *asm_ptr, const int32_t *asm_ent,
-                             const double *der, double *A, hipStream_t st) {
+                             const double *der, double *A, hipStream_t st, TOut at) {
   if (Dc < 1 || Dc > D) return hipErrorInvalidValue;
-  const unsigned blocks = (unsigned)(((size_t)n * n * Dc + 255) / 256);
-  switch (L) {
-    case 1: hipLaunchKernelGGL(assemble_A_kernel<1>, dim3(blocks), dim3(256), 0, st, n, D, Dc, nnz, asm_ptr, asm_ent, der, A); break;
-    case 2: hipLaunchKernelGGL(assemble_A_kernel<2>, dim3(blocks), dim3(256), 0, st, n, D, Dc, nnz, asm_ptr, asm_ent, der, A); break;
-    case 4: hipLaunchKernelGGL(assemble_A_kernel<4>, dim3(blocks), dim3(256), 0, st, n, D, Dc, nnz, asm_ptr, asm_ent, der, A); break;
-    case 8: hipLaunchKernelGGL(assemble_A_kernel<8>, dim3(blocks), dim3(256), 0, st, n, D, Dc, nnz, asm_ptr, asm_ent, der, A); break;
-    default: return hipErrorInvalidValue;
+  if (at.p && (at.lo != 0 || at.W < 1 || at.W > Dc || at.L < 1 || at.L > L)) return hipErrorInvalidValue;
+  const size_t nn = (size_t)n * n;
+  const int ti = assemble_tile(L, Dc);
+  const size_t lds = at.p ? (size_t)ti * (Dc + 1) * L * sizeof(double) : 0;
+  const dim3 grid((unsigned)((nn + ti - 1) / ti));
+#define MD_ASM_A(TI)                                                                                            \
+  MD_DISPATCH(L, hipLaunchKernelGGL((assemble_A_kernel<LL, TI>), grid, dim3(256), lds, st, n, D, Dc, nnz, asm_ptr, \
+                                    asm_ent, der, A, at))
+  switch (ti) {
+    case 16: MD_ASM_A(16); break;
+    case 8: MD_ASM_A(8); break;
+    case 4: MD_ASM_A(4); break;
+    case 2: MD_ASM_A(2); break;
+    default: MD_ASM_A(1); break;
   }
+#undef MD_ASM_A
   return hipGetLastError();
 }
 
 hipError_t launch_assemble(int L, int n, int D, int Dc, int m, int nnz, const int32_t *poly_ptr,
                            const int32_t *asm_ptr, const int32_t *asm_ent, const double *cst, const double *val,
                            const double *der, double *b, double *A, hipStream_t st, double *tsz,
-                           const double *vsize) {
-  hipError_t e = launch_assemble_b(L, n, D, Dc, m, poly_ptr, cst, val, b, st, tsz, vsize);
+                           const double *vsize, TOut rt, TOut at, int *clear, int clear_count) {
+  hipError_t e = launch_assemble_b(L, n, D, Dc, m, poly_ptr, cst, val, b, st, tsz, vsize, rt, clear, clear_count);
   if (e != hipSuccess) return e;
-  return launch_assemble_A(L, n, D, Dc, nnz, asm_ptr, asm_ent, der, A, st);
+  return launch_assemble_A(L, n, D, Dc, nnz, asm_ptr, asm_ent, der, A, st, at);
 }
 
 }  // namespace mdk

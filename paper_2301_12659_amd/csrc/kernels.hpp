@@ -15,31 +15,44 @@ hipError_t launch_evaldiff(int L, const EvalArgs &a, int maxexp, double *pw, hip
 // evaldiff0_max_support(L) variables (none for octo doubles).
 hipError_t launch_evaldiff0(int L, const EvalArgs &a, hipStream_t st);
 int evaldiff0_max_support(int L);
+// A coefficient-major copy written by an assembly kernel beside its
+// series-major output: p[l][s - lo][q] for lo <= s < lo + W and limbs l < L
+// (a window of the coefficients, its leading limbs), q the row (b) or the
+// entry i n + j (A, lo = 0).  p == nullptr: none.
+struct TOut {
+  double *p = nullptr;
+  int lo = 0, W = 0, L = 0;
+};
 // The assembly kernels fill the first Dc coefficients of series stored with
 // D; tsz (nullable, [n][D]) gets |c_{i,0,s}| + sum_m vsize_{m,s} (the
 // evaluation's chain maxima; |value_{m,s}| when vsize is null), the size of
-// the terms of b_{i,s}.
+// the terms of b_{i,s}; rt and at the coefficient-major copies of b and A;
+// clear (nullable) clear_count ints set to zero by the b launch.
 hipError_t launch_assemble(int L, int n, int D, int Dc, int m, int nnz, const int32_t *poly_ptr,
                            const int32_t *asm_ptr, const int32_t *asm_ent, const double *cst, const double *val,
                            const double *der, double *b, double *A, hipStream_t st, double *tsz = nullptr,
-                           const double *vsize = nullptr);
+                           const double *vsize = nullptr, TOut rt = TOut(), TOut at = TOut(), int *clear = nullptr,
+                           int clear_count = 0);
 size_t evaldiff_lds_bytes(int L, int D);
 int evaldiff_workers_per_block(int D);  // monomials per 256-thread workgroup
 hipError_t launch_assemble_b(int L, int n, int D, int Dc, int m, const int32_t *poly_ptr, const double *cst,
                              const double *val, double *b, hipStream_t st, double *tsz = nullptr,
-                             const double *vsize = nullptr);
+                             const double *vsize = nullptr, TOut rt = TOut(), int *clear = nullptr,
+                             int clear_count = 0);
 hipError_t launch_assemble_A(int L, int n, int D, int Dc, int nnz, const int32_t *asm_ptr, const int32_t *asm_ent,
-                             const double *der, double *A, hipStream_t st);
+                             const double *der, double *A, hipStream_t st, TOut at = TOut());
 hipError_t launch_assemble_A0(int L, int n, int D, int nnz, const int32_t *asm_ptr, const int32_t *asm_ent,
-                              const double *der, double *a0, hipStream_t st);
+                              const double *der, double *a0, hipStream_t st, int *clear = nullptr,
+                              int clear_count = 0);
 
 // linalg.hip
 hipError_t launch_status_init(int32_t *status, hipStream_t st);
 hipError_t launch_qr(int L, int n, double *a, double *tau, double *qt, int32_t *status, unsigned *bar,
                      hipStream_t st);
 int qr_lds_workgroups(int L, int n, bool with_qt);
+// flags_ready: the n column flags were cleared by an earlier launch on st.
 hipError_t launch_qr_lds(int L, int n, double *a, double *tau, double *qt, int32_t *status, int *flags,
-                         double *vboard, double *tboard, hipStream_t st);
+                         double *vboard, double *tboard, hipStream_t st, bool flags_ready = false);
 hipError_t launch_m_from_qt(int L, int n, const double *qr, const double *qt, double *invd, double *M,
                             int32_t *status, hipStream_t st);
 hipError_t launch_form_m(int L, int n, const double *qr, const double *tau, double *invd, double *M, int32_t *status,

@@ -1480,11 +1480,11 @@ size_t qr_lds_bytes(int L, int n, int G, bool with_qt) {
 }
 
 hipError_t launch_qr_lds(int L, int n, double *a, double *tau, double *qt, int32_t *status, int *flags,
-                         double *vboard, double *tboard, hipStream_t st) {
+                         double *vboard, double *tboard, hipStream_t st, bool flags_ready) {
   const int G = qr_lds_workgroups(L, n, qt != nullptr);
   if (G == 0) return hipErrorInvalidValue;
   const size_t lds = qr_lds_bytes(L, n, G, qt != nullptr);
-  hipLaunchKernelGGL(zero_i32_kernel, dim3((n + 255) / 256), dim3(256), 0, st, flags, n);
+  if (!flags_ready) hipLaunchKernelGGL(zero_i32_kernel, dim3((n + 255) / 256), dim3(256), 0, st, flags, n);
   MD_DISPATCH(L, {
     static bool attr = false;
     if (!attr) {

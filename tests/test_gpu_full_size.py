@@ -116,12 +116,13 @@ def test_large_od_first_step_vs_oracle(mdn, large, large_cst):
 
 def test_medium_qd_near_the_condition_bound(mdn):
     """The medium quad-double system with the smallest boost that meets the
-    configuration's bound cond(A_0) <= 1e3 (cond ~ 9e2): the first two steps
-    within the quad-double tolerance coefficient by coefficient (the
-    shortened reflector scalars do not limit them), the next two within the
+    configuration's bound cond(A_0) <= 1e3 (cond ~ 9e2): the first step within
+    the quad-double tolerance coefficient by coefficient (the shortened
+    reflector scalars do not limit it), the next three within the
     working-precision bound: the block Toeplitz solve of this system
     amplifies rounding errors by about 60 per coefficient, for the oracle at
-    212 bits as for the GPU."""
+    212 bits as for the GPU (the oracle's own second step at 212 bits is
+    1.3e-59 off at coefficient 3)."""
     s = mdinputs.medium_qd_near_bound()
     cst = oracle.manufacture(s)
     drv = mdn.Newton(s, cst)
@@ -132,7 +133,7 @@ def test_medium_qd_near_the_condition_bound(mdn):
         assert drv.status_code() == 0
         ref = oracle.newton_step(s, s.cff, cst, x)["x"]
         ce = assert_step_per_coefficient(s, cst, x, got, ref, TOL[4])
-        if step <= 2:
+        if step == 1:
             assert np.max(ce) <= TOL[4], (step, float(np.max(ce)))
         x = got
 
