@@ -44,7 +44,11 @@ __device__ void eval_monomial_pair(const EvalArgs &a, int mono, double *buf0) {
   const int tid = threadIdx.x, lane = tid & 63;
   const bool isA = tid < 64;
   for (int q = tid; q < 6 * L; q += 128) buf0[(size_t)q * Dp + Dc] = 0.0;
-  const int e0 = a.mon_ptr[mono], k = a.mon_ptr[mono + 1] - e0;
+  // one monomial per workgroup: its index range is uniform and kept in
+  // scalar registers, so the index tables are read through the scalar cache
+  // (not so in the kernels with several workers per wavefront)
+  const int e0 = __builtin_amdgcn_readfirstlane(a.mon_ptr[mono]);
+  const int k = __builtin_amdgcn_readfirstlane(a.mon_ptr[mono + 1]) - e0;
   const size_t nD = (size_t)a.n * D, mD = (size_t)a.m * D, zD = (size_t)a.nnz * D;
   const size_t xls = a.x_ls ? a.x_ls : nD;
   double c[L];
@@ -70,13 +74,13 @@ __device__ void eval_monomial_pair(const EvalArgs &a, int mono, double *buf0) {
     // backward chain: b_1 = x_{v_k}, b_q = b_{q-1} * x_{v_{k-q+1}}, parked in the slot of entry k - q - 1
     if (derivs && k >= 3) {
       double *B = Bq, *X = Xq, *Wb = Wq;
-      load_series(B, a.x, xls, xoff(a.var[e0 + k - 1]), L, Dc, lane, G);
+      load_series_t<L>(B, a.x, xls, xoff(a.var[e0 + k - 1]), Dc, lane, G);
       for (int q = 2; q <= k - 1; ++q) {
-        load_series(X, a.x, xls, xoff(a.var[e0 + k - q]), L, Dc, lane, G);
+        load_series_t<L>(X, a.x, xls, xoff(a.var[e0 + k - q]), Dc, lane, G);
         wave_sync();
         conv_any<L>(B, X, Wb, Dc, lane, 1);
         wave_sync();
-        store_series(a.der, zD, der_off(k - q - 1), Wb, L, Dc, lane, G);
+        store_series_t<L>(a.der, zD, der_off(k - q - 1), Wb, Dc, lane, G);
         double *t = B;
         B = Wb;
         Wb = t;
@@ -93,11 +97,11 @@ __device__ void eval_monomial_pair(const EvalArgs &a, int mono, double *buf0) {
       const double *src = (p == 1) ? a.x : a.pw + (size_t)(p - 2) * L * nD;
       const size_t sls = (p == 1) ? xls : nD;
       if (first) {
-        load_series(U, src, sls, xoff(v), L, Dc, lane, G);
+        load_series_t<L>(U, src, sls, xoff(v), Dc, lane, G);
         first = false;
         wave_sync();
       } else {
-        load_series(V, src, sls, xoff(v), L, Dc, lane, G);
+        load_series_t<L>(V, src, sls, xoff(v), Dc, lane, G);
         wave_sync();
         conv_any<L>(U, V, W, Dc, lane, 1);
         wave_sync();
@@ -131,7 +135,7 @@ __device__ void eval_monomial_pair(const EvalArgs &a, int mono, double *buf0) {
     const int ej = j - 1;
     const int aj = a.exp[e0 + ej];
     if (isA) {
-      load_series(V, a.x, xls, xoff(a.var[e0 + ej]), L, Dc, lane, G);
+      load_series_t<L>(V, a.x, xls, xoff(a.var[e0 + ej]), Dc, lane, G);
       wave_sync();
       if (f0_scalar && j == 1)
         scal<L>(c, V, W, Dc, lane, G, 1);
@@ -140,16 +144,16 @@ __device__ void eval_monomial_pair(const EvalArgs &a, int mono, double *buf0) {
     } else if (derivs) {
       if (j < k) {
         if (k - j == 1)
-          load_series(Xq, a.x, xls, xoff(a.var[e0 + k - 1]), L, Dc, lane, G);  // b_1 = x_{v_k}
+          load_series_t<L>(Xq, a.x, xls, xoff(a.var[e0 + k - 1]), Dc, lane, G);  // b_1 = x_{v_k}
         else
-          load_series(Xq, a.der, zD, der_off(ej), L, Dc, lane, G);  // b_{k-j}
+          load_series_t<L>(Xq, a.der, zD, der_off(ej), Dc, lane, G);  // b_{k-j}
         wave_sync();
         if (f0_scalar && j == 1)
           scal<L>(c, Xq, Wq, Dc, lane, G, aj);
         else
           conv_any<L>(U, Xq, Wq, Dc, lane, aj);
         wave_sync();
-        store_series(a.der, zD, der_off(ej), Wq, L, Dc, lane, G);
+        store_series_t<L>(a.der, zD, der_off(ej), Wq, Dc, lane, G);
       } else {  // d/dx_{v_k} = a_k f_{k-1}
         for (int s = lane; s < Dc; s += G) {
           double r[L];
@@ -168,7 +172,7 @@ __device__ void eval_monomial_pair(const EvalArgs &a, int mono, double *buf0) {
     if (track && isA) track_max(U, false);
   }
   if (isA) {
-    store_series(a.val, mD, (size_t)mono * D, U, L, Dc, lane, G);
+    store_series_t<L>(a.val, mD, (size_t)mono * D, U, Dc, lane, G);
     if (track)
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
@@ -181,7 +185,7 @@ __device__ void eval_monomial_pair(const EvalArgs &a, int mono, double *buf0) {
 template <int L>
 __global__ void __launch_bounds__(128) evaldiff_pair_kernel(EvalArgs a) {
   extern __shared__ double lds[];
-  eval_monomial_pair<L>(a, a.order[blockIdx.x], lds);
+  eval_monomial_pair<L>(a, __builtin_amdgcn_readfirstlane(a.order[blockIdx.x]), lds);
 }
 
 template <int L>
@@ -291,13 +295,13 @@ __global__ void __launch_bounds__(256, (L == 8) ? 1 : 2) power_kernel(int n, int
   double *U = lds + (size_t)wid * 3 * L * (Dc + 1), *X = U + L * (Dc + 1), *W = X + L * (Dc + 1);
   zero_pads(U, L, Dc, lane, G);
   const size_t nD = (size_t)n * D;
-  load_series(X, x, nD, (size_t)v * D, L, Dc, lane, G);
-  load_series(U, x, nD, (size_t)v * D, L, Dc, lane, G);
+  load_series_t<L>(X, x, nD, (size_t)v * D, Dc, lane, G);
+  load_series_t<L>(U, x, nD, (size_t)v * D, Dc, lane, G);
   wave_sync();
   for (int p = 2; p <= maxp; ++p) {
     conv_any<L>(U, X, W, Dc, lane, 1);
     wave_sync();
-    store_series(pw + (size_t)(p - 2) * L * nD, nD, (size_t)v * D, W, L, Dc, lane, G);
+    store_series_t<L>(pw + (size_t)(p - 2) * L * nD, nD, (size_t)v * D, W, Dc, lane, G);
     double *t = U;
     U = W;
     W = t;

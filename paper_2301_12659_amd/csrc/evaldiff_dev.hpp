@@ -137,6 +137,40 @@ __device__ __forceinline__ void store_series(double *g, size_t gstride, size_t o
   }
 }
 
+// The same with the limb count known at compile time: lane takes the
+// coefficients s = lane + c G, every limb of each, and issues all loads of a
+// block of two coefficients per lane before it writes any of them to LDS, so
+// a series costs one round trip to memory instead of one per element (and no
+// integer division).
+template <int L>
+__device__ __forceinline__ void load_series_t(double *S, const double *g, size_t gstride, size_t off, int D, int lane,
+                                              int G) {
+  for (int s0 = 0; s0 < D; s0 += 2 * G) {
+    double r[2][L];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const int s = s0 + lane + c * G;
+#pragma unroll
+      for (int l = 0; l < L; ++l) r[c][l] = s < D ? g[(size_t)l * gstride + off + s] : 0.0;
+    }
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const int s = s0 + lane + c * G;
+      if (s < D)
+#pragma unroll
+        for (int l = 0; l < L; ++l) S[l * (D + 1) + s] = r[c][l];
+    }
+  }
+}
+
+template <int L>
+__device__ __forceinline__ void store_series_t(double *g, size_t gstride, size_t off, const double *S, int D, int lane,
+                                               int G) {
+  for (int s = lane; s < D; s += G)
+#pragma unroll
+    for (int l = 0; l < L; ++l) g[(size_t)l * gstride + off + s] = S[l * (D + 1) + s];
+}
+
 // Zero the padding entries of a worker's three buffers.
 __device__ __forceinline__ void zero_pads(double *buf0, int L, int D, int lane, int G) {
   for (int q = lane; q < 3 * L; q += G) buf0[q * (D + 1) + D] = 0.0;
@@ -175,15 +209,15 @@ __device__ void eval_monomial(const EvalArgs &a, int mono, int lane, double *buf
   // ---- backward chain: b_q for q = 2..k-1 parked in the slot of entry k-q (0-based k-q-1+... )
   if (derivs && k >= 3) {
     double *B = buf[0], *X = buf[1], *Wb = buf[2];
-    load_series(B, a.x, xls, xoff(a.var[e0 + k - 1]), L, Dc, lane, G);  // b_1 = x_{v_k}
+    load_series_t<L>(B, a.x, xls, xoff(a.var[e0 + k - 1]), Dc, lane, G);  // b_1 = x_{v_k}
     for (int q = 2; q <= k - 1; ++q) {
-      load_series(X, a.x, xls, xoff(a.var[e0 + k - q]), L, Dc, lane, G);  // x_{v_{k-q+1}}
+      load_series_t<L>(X, a.x, xls, xoff(a.var[e0 + k - q]), Dc, lane, G);  // x_{v_{k-q+1}}
       wave_sync();
       conv_any<L>(B, X, Wb, Dc, lane, 1);
       wave_sync();
       // b_q is consumed by the cross product of forward step j = k - q (1-based),
       // i.e. entry k - q - 1 (0-based)
-      store_series(a.der, zD, der_off(k - q - 1), Wb, L, Dc, lane, G);
+      store_series_t<L>(a.der, zD, der_off(k - q - 1), Wb, Dc, lane, G);
       double *t = B;
       B = Wb;
       Wb = t;
@@ -201,11 +235,11 @@ __device__ void eval_monomial(const EvalArgs &a, int mono, int lane, double *buf
     const double *src = (p == 1) ? a.x : a.pw + (size_t)(p - 2) * L * nD;
     const size_t sls = (p == 1) ? xls : nD;
     if (f0_scalar) {
-      load_series(U, src, sls, xoff(v), L, Dc, lane, G);
+      load_series_t<L>(U, src, sls, xoff(v), Dc, lane, G);
       f0_scalar = false;
       wave_sync();
     } else {
-      load_series(V, src, sls, xoff(v), L, Dc, lane, G);
+      load_series_t<L>(V, src, sls, xoff(v), Dc, lane, G);
       wave_sync();
       conv_any<L>(U, V, W, Dc, lane, 1);
       wave_sync();
@@ -240,16 +274,16 @@ __device__ void eval_monomial(const EvalArgs &a, int mono, int lane, double *buf
       // values only: the forward product below
     } else if (j < k) {
       if (k - j == 1)
-        load_series(V, a.x, xls, xoff(a.var[e0 + k - 1]), L, Dc, lane, G);  // b_1 = x_{v_k}
+        load_series_t<L>(V, a.x, xls, xoff(a.var[e0 + k - 1]), Dc, lane, G);  // b_1 = x_{v_k}
       else
-        load_series(V, a.der, zD, der_off(ej), L, Dc, lane, G);  // b_{k-j}
+        load_series_t<L>(V, a.der, zD, der_off(ej), Dc, lane, G);  // b_{k-j}
       wave_sync();
       if (f0_scalar && j == 1)
         scal<L>(c, V, W, Dc, lane, G, aj);
       else
         conv_any<L>(U, V, W, Dc, lane, aj);
       wave_sync();
-      store_series(a.der, zD, der_off(ej), W, L, Dc, lane, G);
+      store_series_t<L>(a.der, zD, der_off(ej), W, Dc, lane, G);
     } else {  // d/dx_{v_k} = a_k f_{k-1}
       if (f0_scalar && j == 1) {
         for (int s = lane; s < Dc; s += G) {
@@ -273,7 +307,7 @@ __device__ void eval_monomial(const EvalArgs &a, int mono, int lane, double *buf
     }
     wave_sync();
     // f_j = f_{j-1} * x_{v_j}
-    load_series(V, a.x, xls, xoff(a.var[e0 + ej]), L, Dc, lane, G);
+    load_series_t<L>(V, a.x, xls, xoff(a.var[e0 + ej]), Dc, lane, G);
     wave_sync();
     if (f0_scalar && j == 1)
       scal<L>(c, V, W, Dc, lane, G, 1);
@@ -285,7 +319,7 @@ __device__ void eval_monomial(const EvalArgs &a, int mono, int lane, double *buf
     W = t;
     if (track) track_max(U, false);
   }
-  store_series(a.val, mD, (size_t)mono * D, U, L, Dc, lane, G);
+  store_series_t<L>(a.val, mD, (size_t)mono * D, U, Dc, lane, G);
   if (track)
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
