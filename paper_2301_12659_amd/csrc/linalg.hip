@@ -258,9 +258,9 @@ __device__ __forceinline__ int red_width(int rows) {
 // with agent-scope stores and waits for them before raising the flag: a
 // release fence would write back the whole L2 of its chiplet at every
 // column, and beside the evaluation that L2 holds megabytes of its output.
-__device__ __forceinline__ bool wait_flag(const int *flag, int32_t *status) {
+__device__ __forceinline__ bool wait_flag(const int *flag, int32_t *status, int target = 1) {
   long spins = 0;
-  while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+  while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
     __builtin_amdgcn_s_sleep(1);
     if (++spins > (1L << 22)) {
       set_status(status, MD_EHIP);
@@ -272,13 +272,18 @@ __device__ __forceinline__ bool wait_flag(const int *flag, int32_t *status) {
 }
 
 // Householder QR of A_0 with Q^T, columns resident in LDS.  Column J of the
-// augmented matrix [A_0 | I] (J < 2n) belongs to workgroup J mod G and stays
-// in its LDS for the whole factorization.  Reflector c is published by the
-// owner of column c: v (rows c..n-1, v_c = 1) and tau on a board in device
-// memory, then flags[c] = 1.  The owner of column c+1 applies H_c to that
-// column first, computes reflector c+1 with one wavefront and publishes it
-// while its other wavefronts update the rest (look-ahead), so a column costs
-// one reflector computation and one flag hand-over on the critical path.
+// augmented matrix [A_0 | I] (J < 2n) belongs to workgroup (J / 2) mod G and
+// stays in its LDS for the whole factorization.  Reflector c is published by
+// the owner of column c in two parts: first the column x below the diagonal
+// as it is (flags[c] = 1), then, after its norm and the reflector scalars,
+// tau and 1/(x_0 - beta) (flags[c] = 2).  With v = x / (x_0 - beta) below the
+// diagonal and v_c = 1, H_c y = y - tau (v^T y) v needs of y only
+//     S = sum_{i>c} x_i y_i,  d = y_c + S / (x_0 - beta),
+// so every workgroup forms S for all its columns from the first part while
+// the owner still computes the scalars, and the second part only leaves one
+// multiply-add per row: y_c -= tau d, y_i -= (tau d / (x_0 - beta)) x_i.  The
+// owner of column c+1 updates that column first and publishes reflector c+1
+// from one wavefront while its other wavefronts update the rest (look-ahead).
 // Every column is written back at the end: R on and above the diagonal, v
 // below it for the A_0 part; Q^T for the identity part.
 template <int L>
@@ -303,9 +308,10 @@ __global__ void __launch_bounds__(256) qr_lds_kernel(int n, double *a, double *t
   int ncol = 0;
   while (gcol(ncol) < ncols_total) ++ncol;
   double *cols = lds;                          // [ncol][L][n]
-  double *vsh = lds + (size_t)ncol * L * n;    // [L][n] current reflector
+  double *vsh = lds + (size_t)ncol * L * n;    // [L][n] column c below the diagonal (another workgroup's)
   double *own_inv = vsh + (size_t)L * n;       // [ncol][L] 1 / (x_0 - beta) of the owned columns
-  __shared__ double sh_tau[L], sh_tau_own[L];
+  double *ssum = own_inv + (size_t)ncol * L;   // [ncol][L] S of every owned column for the current reflector
+  __shared__ double sh_tau[L], sh_inv[L], sh_tau_own[L];
   __shared__ int sh_ok;
   auto col = [&](int q) { return cols + (size_t)q * L * n; };
   // load the owned columns of [A_0 | I]
@@ -319,13 +325,12 @@ __global__ void __launch_bounds__(256) qr_lds_kernel(int n, double *a, double *t
   }
   __syncthreads();
 
-  // reflector of owned column q (global column c), by the wavefront w0; writes
-  // beta and v into the column, publishes v, tau and the flag
+  // reflector of owned column q (global column c), by one wavefront: the
+  // column below the diagonal to the board and flags[c] = 1, its norm, the
+  // scalars (beta into the column as R_cc), tau and 1 / (x_0 - beta) to the
+  // board and flags[c] = 2
   auto publish = [&](int q, int c) {
     double *cq = col(q);
-    // the column below the diagonal to the board as it is (x_i = v_i (x_0 -
-    // beta)): its stores complete while the norm and the scalars are formed,
-    // and the readers scale it by 1 / (x_0 - beta)
     for (int i = c + 1 + lane; i < n; i += 64) {
       double xi[L];
 #pragma unroll
@@ -344,6 +349,10 @@ __global__ void __launch_bounds__(256) qr_lds_kernel(int n, double *a, double *t
       }
       team_sum_lazy<L>(u, red_width(n - c));
       MD<L>::renorm(u, acc);
+    }
+    if (lane == 0) {
+      wait_vm();  // the board stores are performed before the flag
+      __hip_atomic_store(&flags[c], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     double x0[L], beta[L], tc[L], inv[L];
 #pragma unroll
@@ -370,42 +379,56 @@ __global__ void __launch_bounds__(256) qr_lds_kernel(int n, double *a, double *t
     }
     wave_sync();
     if (lane == 0) {
-      wait_vm();  // the board stores are performed before the flag
-      __hip_atomic_store(&flags[c], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      wait_vm();  // tau and 1 / (x_0 - beta) are performed before the flag
+      __hip_atomic_store(&flags[c], 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   };
 
-  // apply H_c (v in vsh, tau tc) to owned column q, rows c..n-1, with a team of T lanes
-  auto apply = [&](int q, int c, const double (&tc)[L], int tlane, int width) {
-    double *cq = col(q);
-    double dot[L];
-    {
-      double u[L];
-      md::zero<L>(u);
-      for (int i = c + tlane; i < n; i += width) {
-        double vi[L], x[L];
-#pragma unroll
-        for (int l = 0; l < L; ++l) {
-          vi[l] = vsh[l * n + i];
-          x[l] = cq[l * n + i];
-        }
-        MD<L>::fma_lazy(u, vi, x);
-      }
-      team_sum_lazy<L>(u, width == 64 ? red_width(n - c) : width);
-      MD<L>::renorm(u, dot);
-    }
-    double wj[L];
-    MD<L>::mul(dot, tc, wj);
-    for (int i = c + tlane; i < n; i += width) {
-      double vi[L], x[L];
+  // S = sum_{i>c} x_i y_i for owned column q (x in xs), team of `width` lanes
+  auto partial_dot = [&](int q, int c, const double *xs, int tlane, int width, double (&S)[L]) {
+    const double *cq = col(q);
+    double u[L];
+    md::zero<L>(u);
+    for (int i = c + 1 + tlane; i < n; i += width) {
+      double xi[L], y[L];
 #pragma unroll
       for (int l = 0; l < L; ++l) {
-        vi[l] = vsh[l * n + i];
-        x[l] = cq[l * n + i];
+        xi[l] = xs[l * n + i];
+        y[l] = cq[l * n + i];
       }
-      MD<L>::fms(x, vi, wj);
+      MD<L>::fma_lazy(u, xi, y);
+    }
+    team_sum_lazy<L>(u, width == 64 ? red_width(n - c - 1) : width);
+    MD<L>::renorm(u, S);
+  };
+
+  // H_c on owned column q given its S (tau tc, 1 / (x_0 - beta) inv)
+  auto finish_apply = [&](int q, int c, const double *xs, const double (&S)[L], const double (&tc)[L],
+                          const double (&inv)[L], int tlane, int width) {
+    double *cq = col(q);
+    double yc[L], t[L], d[L], wj[L], wi[L];
 #pragma unroll
-      for (int l = 0; l < L; ++l) cq[l * n + i] = x[l];
+    for (int l = 0; l < L; ++l) yc[l] = cq[l * n + c];
+    MD<L>::mul(S, inv, t);
+    MD<L>::add(yc, t, d);
+    MD<L>::mul(d, tc, wj);
+    MD<L>::mul(wj, inv, wi);
+    if (tlane == 0) {
+      double r[L];
+      MD<L>::sub(yc, wj, r);
+#pragma unroll
+      for (int l = 0; l < L; ++l) cq[l * n + c] = r[l];
+    }
+    for (int i = c + 1 + tlane; i < n; i += width) {
+      double xi[L], y[L];
+#pragma unroll
+      for (int l = 0; l < L; ++l) {
+        xi[l] = xs[l * n + i];
+        y[l] = cq[l * n + i];
+      }
+      MD<L>::fms(y, xi, wi);
+#pragma unroll
+      for (int l = 0; l < L; ++l) cq[l * n + i] = y[l];
     }
   };
 
@@ -413,80 +436,90 @@ __global__ void __launch_bounds__(256) qr_lds_kernel(int n, double *a, double *t
   bool ok = true;
   int q0 = 0;  // owned columns J <= c: a prefix of the local order
   for (int c = 0; c < n; ++c) {
-    // reflector c into vsh: from this workgroup's own column, or from the board
     const bool own = owner(c) == g;
-    if (tid == 0) sh_ok = own ? 1 : (wait_flag(&flags[c], status) ? 1 : 0);
-    __syncthreads();
-    ok = sh_ok != 0;
-    if (!ok) break;
-    // v_i = x_i / (x_0 - beta) below the diagonal, v_c = 1
-    if (own) {
-      const int qc = lcol(c);
-      const double *cc = col(qc);
-      double inv[L];
-#pragma unroll
-      for (int l = 0; l < L; ++l) inv[l] = own_inv[qc * L + l];
-      for (int i = c + tid; i < n; i += blockDim.x) {
-        double xi[L], vi[L];
-        md::zero<L>(vi);
-        vi[0] = 1.0;
-        if (i > c) {
-#pragma unroll
-          for (int l = 0; l < L; ++l) xi[l] = cc[l * n + i];
-          MD<L>::mul(xi, inv, vi);
-        }
-#pragma unroll
-        for (int l = 0; l < L; ++l) vsh[l * n + i] = vi[l];
+    // 1. the column below the diagonal: this workgroup's own, or from the board
+    if (!own) {
+      if (tid == 0) sh_ok = wait_flag(&flags[c], status, 1) ? 1 : 0;
+      __syncthreads();
+      if (!sh_ok) {
+        ok = false;
+        break;
       }
-      if (tid == 0)
+      for (int e = c + 1 + tid; e < n; e += blockDim.x)
 #pragma unroll
-        for (int l = 0; l < L; ++l) sh_tau[l] = sh_tau_own[l];
-    } else {
-      double inv[L];
-#pragma unroll
-      for (int l = 0; l < L; ++l) inv[l] = tboard[(size_t)c * 2 * L + L + l];
-      for (int i = c + tid; i < n; i += blockDim.x) {
-        double xi[L], vi[L];
-        md::zero<L>(vi);
-        vi[0] = 1.0;
-        if (i > c) {
-#pragma unroll
-          for (int l = 0; l < L; ++l) xi[l] = vboard[(size_t)c * L * n + (size_t)l * n + i];
-          MD<L>::mul(xi, inv, vi);
-        }
-#pragma unroll
-        for (int l = 0; l < L; ++l) vsh[l * n + i] = vi[l];
-      }
-      if (tid == 0)
-#pragma unroll
-        for (int l = 0; l < L; ++l) sh_tau[l] = tboard[(size_t)c * 2 * L + l];
+        for (int l = 0; l < L; ++l) vsh[l * n + e] = vboard[(size_t)c * L * n + (size_t)l * n + e];
     }
     __syncthreads();
-    double tc[L];
-#pragma unroll
-    for (int l = 0; l < L; ++l) tc[l] = sh_tau[l];
+    const double *xs = own ? col(lcol(c)) : vsh;
     while (q0 < ncol && gcol(q0) <= c) ++q0;
     const bool ahead = (c + 1 < n) && owner(c + 1) == g;
     const int qa = ahead ? lcol(c + 1) : -1;
-    if (ahead && w == 0) {  // look-ahead: update column c+1, publish reflector c+1
-      apply(qa, c, tc, lane, 64);
+    // 2. S of every live column: owned A columns J > c (a suffix q >= q0 of
+    // the owned ones) and every owned Q^T column; the look-ahead column by
+    // wavefront 0 with all its lanes, the others by teams 4.. (or 0..) of
+    // T lanes, team t0 taking the live columns t0, t0 + nt, ...
+    const int t0 = ahead ? team - 4 : team, nt = ahead ? (blockDim.x / T) - 4 : blockDim.x / T;
+    const int nlive = ncol - q0 - (ahead ? 1 : 0);
+    auto live_col = [&](int k) {
+      int q = q0 + k;
+      if (ahead && q >= qa) ++q;
+      return q;
+    };
+    double Sa[L];
+    if (ahead && w == 0) {
+      partial_dot(qa, c, xs, lane, 64, Sa);
+    } else {
+      for (int k = t0; k < nlive; k += nt) {
+        const int q = live_col(k);
+        double S[L];
+        partial_dot(q, c, xs, tl, T, S);
+        if (tl == 0)
+#pragma unroll
+          for (int l = 0; l < L; ++l) ssum[q * L + l] = S[l];
+      }
+    }
+    // 2. tau and 1 / (x_0 - beta)
+    if (tid == 0) {
+      if (own) {
+#pragma unroll
+        for (int l = 0; l < L; ++l) {
+          sh_tau[l] = sh_tau_own[l];
+          sh_inv[l] = own_inv[lcol(c) * L + l];
+        }
+        sh_ok = 1;
+      } else {
+        sh_ok = wait_flag(&flags[c], status, 2) ? 1 : 0;
+        if (sh_ok)
+#pragma unroll
+          for (int l = 0; l < L; ++l) {
+            sh_tau[l] = tboard[(size_t)c * 2 * L + l];
+            sh_inv[l] = tboard[(size_t)c * 2 * L + L + l];
+          }
+      }
+    }
+    __syncthreads();
+    if (!sh_ok) {
+      ok = false;
+      break;
+    }
+    double tc[L], inv[L];
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+      tc[l] = sh_tau[l];
+      inv[l] = sh_inv[l];
+    }
+    // 3. the updates; the look-ahead column first, then its reflector
+    if (ahead && w == 0) {
+      finish_apply(qa, c, xs, Sa, tc, inv, lane, 64);
       wave_sync();
       publish(qa, c + 1);
-    }
-    // the other owned columns: A columns j > c (except the look-ahead one) and all Q^T columns
-    // teams 0..3 form wavefront 0, busy with the look-ahead column
-    const int t0 = ahead ? team - 4 : team, nt = ahead ? (blockDim.x / T) - 4 : blockDim.x / T;
-    if (!(ahead && w == 0)) {
-      // live columns: owned A columns J > c (a suffix q >= q0 of the owned
-      // ones) and every owned Q^T column, without the look-ahead column qa.
-      // Team t0 takes the live columns t0, t0 + nt, ...: the teams of one
-      // wavefront step through their columns together (no serialization of
-      // the teams of a wavefront by divergent branches)
-      const int nlive = ncol - q0 - (ahead ? 1 : 0);
+    } else {
       for (int k = t0; k < nlive; k += nt) {
-        int q = q0 + k;
-        if (ahead && q >= qa) ++q;
-        apply(q, c, tc, tl, T);
+        const int q = live_col(k);
+        double S[L];
+#pragma unroll
+        for (int l = 0; l < L; ++l) S[l] = ssum[q * L + l];
+        finish_apply(q, c, xs, S, tc, inv, tl, T);
       }
     }
     __syncthreads();
@@ -1475,8 +1508,9 @@ size_t qr_lds_bytes(int L, int n, int G, bool with_qt) {
   const int cols = with_qt ? 2 * n : n;
   const int pairs = (cols + 1) / 2;
   const int ncol = 2 * ((pairs + G - 1) / G);  // columns are owned in pairs
-  // the owned columns, the current reflector, 1 / (x_0 - beta) per owned column
-  return (((size_t)ncol + 1) * L * n + (size_t)ncol * L) * sizeof(double);
+  // the owned columns, the current reflector's column, 1 / (x_0 - beta) and
+  // the partial dot product S per owned column
+  return (((size_t)ncol + 1) * L * n + 2 * (size_t)ncol * L) * sizeof(double);
 }
 
 hipError_t launch_qr_lds(int L, int n, double *a, double *tau, double *qt, int32_t *status, int *flags,
