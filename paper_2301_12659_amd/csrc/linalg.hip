@@ -271,8 +271,11 @@ __device__ __forceinline__ bool wait_flag(const int *flag, int32_t *status, int 
   return true;
 }
 
+// Consecutive columns of [A_0 | I] owned by one workgroup of the LDS QR.
+constexpr int QR_GROUP = 2;
+
 // Householder QR of A_0 with Q^T, columns resident in LDS.  Column J of the
-// augmented matrix [A_0 | I] (J < 2n) belongs to workgroup (J / 2) mod G and
+// augmented matrix [A_0 | I] (J < 2n) belongs to workgroup (J / QR_GROUP) mod G and
 // stays in its LDS for the whole factorization.  Reflector c is published by
 // the owner of column c in two parts: first the column x below the diagonal
 // as it is (flags[c] = 1), then, after its norm and the reflector scalars,
@@ -299,12 +302,14 @@ __global__ void __launch_bounds__(256) qr_lds_kernel(int n, double *a, double *t
   constexpr int T = 16;
   const int team = tid / T, tl = tid % T;
   const size_t nn = (size_t)n * n;
-  // columns are owned in pairs: J belongs to workgroup (J / 2) mod G, so that
-  // every second reflector is used by the workgroup that computed it, from
-  // its LDS, without a hand-over
-  auto owner = [&](int J) { return (J >> 1) % G; };
-  auto gcol = [&](int q) { return 2 * (g + (q >> 1) * G) + (q & 1); };  // local index -> J
-  auto lcol = [&](int J) { return 2 * ((J >> 1) / G) + (J & 1); };       // J -> local index
+  // columns are owned in groups of QR_GROUP: J belongs to workgroup
+  // (J / QR_GROUP) mod G, so that of QR_GROUP consecutive reflectors all but
+  // the first are used by the workgroup that computed them, from its LDS,
+  // without a hand-over
+  constexpr int OG = QR_GROUP;
+  auto owner = [&](int J) { return (J / OG) % G; };
+  auto gcol = [&](int q) { return OG * (g + (q / OG) * G) + (q % OG); };  // local index -> J
+  auto lcol = [&](int J) { return OG * ((J / OG) / G) + (J % OG); };       // J -> local index
   int ncol = 0;
   while (gcol(ncol) < ncols_total) ++ncol;
   double *cols = lds;                          // [ncol][L][n]
@@ -1506,8 +1511,8 @@ int qr_lds_workgroups(int L, int n, bool with_qt) {
 
 size_t qr_lds_bytes(int L, int n, int G, bool with_qt) {
   const int cols = with_qt ? 2 * n : n;
-  const int pairs = (cols + 1) / 2;
-  const int ncol = 2 * ((pairs + G - 1) / G);  // columns are owned in pairs
+  const int groups = (cols + QR_GROUP - 1) / QR_GROUP;
+  const int ncol = QR_GROUP * ((groups + G - 1) / G);  // columns are owned in groups
   // the owned columns, the current reflector's column, 1 / (x_0 - beta) and
   // the partial dot product S per owned column
   return (((size_t)ncol + 1) * L * n + 2 * (size_t)ncol * L) * sizeof(double);
