@@ -143,10 +143,25 @@ size_t solve_bytes(int L, int n, int D) {
 double *at(void *ws, size_t byte_off) { return reinterpret_cast<double *>(static_cast<char *>(ws) + byte_off); }
 
 
-// flags_ready: the QR's column flags (the first n ints of the scratch) were
-// cleared by an earlier launch on this stream (the A_0 assembly).
+// The hand-over memory of the LDS QR in its scratch, for a launch that
+// prepares it ahead of the QR (the A_0 assembly); none for the global QR.
+mdk::QrPrep qr_prep(int L, int n, void *scratch) {
+  mdk::QrPrep q;
+  if (mdk::qr_lds_workgroups(L, n, true) == 0) return q;
+  char *p = static_cast<char *>(scratch);
+  q.flags = reinterpret_cast<int *>(p);
+  p += align_up((size_t)n * sizeof(int));
+  p += align_up((size_t)n * L * n * sizeof(double));
+  q.tboard = reinterpret_cast<double *>(p);
+  q.n = n;
+  q.nt = 2 * L * n;
+  return q;
+}
+
+// prepared: the LDS QR's hand-over memory was prepared by an earlier launch
+// on this stream (qr_prep).
 hipError_t run_qr(int L, int n, double *a, double *tau, double *qt, int32_t *status, void *scratch, hipStream_t st,
-                  bool flags_ready = false) {
+                  bool prepared = false) {
   char *p = static_cast<char *>(scratch);
   int *flags = reinterpret_cast<int *>(p);
   p += align_up((size_t)n * sizeof(int));
@@ -156,7 +171,7 @@ hipError_t run_qr(int L, int n, double *a, double *tau, double *qt, int32_t *sta
   p += align_up((size_t)n * 2 * L * sizeof(double));
   unsigned *bar = reinterpret_cast<unsigned *>(p);
   if (mdk::qr_lds_workgroups(L, n, qt != nullptr) > 0)
-    return mdk::launch_qr_lds(L, n, a, tau, qt, status, flags, vboard, tboard, st, flags_ready);
+    return mdk::launch_qr_lds(L, n, a, tau, qt, status, flags, vboard, tboard, st, prepared);
   return mdk::launch_qr(L, n, a, tau, qt, status, bar, st);
 }
 
@@ -519,9 +534,9 @@ static int newton_step_impl(const md_plan *p, int Ls, int lo, int hi, bool keep_
       e = pre0 ? mdk::launch_evaldiff0(Ls, a, st) : mdk::launch_evaldiff(Ls, a, p->maxexp, at(ws, w.pw), st);
       a.reset_status = nullptr;
       if (e != hipSuccess) return hip_fail(e, "A_0 pre-pass");
-      // (its launch also clears the QR's column flags)
+      // (its launch also prepares the QR's hand-over memory)
       if ((e = mdk::launch_assemble_A0(Ls, n, D, p->nnz, p->d_asm_ptr, p->d_asm_ent, a.der, qr, st,
-                                       reinterpret_cast<int *>(at(ws, w.bar)), n)) != hipSuccess)
+                                       qr_prep(Ls, n, at(ws, w.bar)))) != hipSuccess)
         return hip_fail(e, "A_0 assembly");
     }
     // 2. fork: QR of A_0 with Q^T, then M = R^{-1} Q^T, on the second stream
@@ -665,9 +680,9 @@ static int newton_steps_impl(const md_plan *p, int count, const double *cff, con
       a.D = 1;  // one coefficient per series: xn and der0 [L][nnz]
       a.der = at(ws, w.der0);
       if ((e = mdk::launch_evaldiff0(L, a, p->aux)) != hipSuccess) return hip_fail(e, "A_0 pre-pass");
-      // (the A_0 assembly also clears the QR's column flags)
+      // (the A_0 assembly also prepares the QR's hand-over memory)
       if ((e = mdk::launch_assemble_A0(L, n, 1, p->nnz, p->d_asm_ptr, p->d_asm_ent, a.der, qrs[k], p->aux,
-                                       reinterpret_cast<int *>(at(ws, w.bar)), n)) != hipSuccess)
+                                       qr_prep(L, n, at(ws, w.bar)))) != hipSuccess)
         return hip_fail(e, "A_0 assembly");
       if ((e = run_qr(L, n, qrs[k], taus[k], qts[k], dev_status, at(ws, w.bar), p->aux, true)) != hipSuccess)
         return hip_fail(e, "qr");

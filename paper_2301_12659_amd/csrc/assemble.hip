@@ -122,13 +122,13 @@ __global__ void __launch_bounds__(256) assemble_A_kernel(int n, int D, int Dc, i
 
 // Coefficient 0 of A into a dense row-major matrix a0 [L][n][n], summed in
 // the same order as assemble_A_kernel, so it equals A[i][j][0] bit for bit.
-// clear (nullable): clear_count ints set to zero (the QR's column flags,
-// when the QR of a0 follows on this stream).
+// prep: the hand-over memory of the LDS QR of a0, which follows on this
+// stream (flags cleared, scalar slots emptied; none when its pointers are null).
 template <int L>
 __global__ void assemble_A0_kernel(int n, int D, int nnz, const int32_t *asm_ptr, const int32_t *asm_ent,
-                                   const double *der, double *a0, int *clear, int clear_count) {
+                                   const double *der, double *a0, QrPrep prep) {
   const size_t ij = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (clear && ij < (size_t)clear_count) clear[ij] = 0;
+  qr_prep_item(prep, ij);
   const size_t nn = (size_t)n * n, zD = (size_t)nnz * D;
   if (ij >= nn) return;
   const int lo = asm_ptr[ij], hi = asm_ptr[ij + 1];
@@ -149,11 +149,11 @@ __global__ void assemble_A0_kernel(int n, int D, int nnz, const int32_t *asm_ptr
 // ------------------------------------------------------------------ launchers
 
 hipError_t launch_assemble_A0(int L, int n, int D, int nnz, const int32_t *asm_ptr, const int32_t *asm_ent,
-                              const double *der, double *a0, hipStream_t st, int *clear, int clear_count) {
+                              const double *der, double *a0, hipStream_t st, QrPrep prep) {
   const size_t nn = (size_t)n * n;
-  const size_t threads = std::max(nn, (size_t)(clear ? clear_count : 0));
+  const size_t threads = std::max({nn, (size_t)prep.n, (size_t)prep.nt});
   MD_DISPATCH(L, hipLaunchKernelGGL(assemble_A0_kernel<LL>, dim3((threads + 63) / 64), dim3(64), 0, st, n, D, nnz,
-                                    asm_ptr, asm_ent, der, a0, clear, clear_count));
+                                    asm_ptr, asm_ent, der, a0, prep));
   return hipGetLastError();
 }
 

@@ -8,6 +8,21 @@
 
 namespace mdk {
 
+// Preparation of the LDS QR's hand-over memory, done by a launch ahead of
+// the QR on its stream: the column flags cleared and the slots of tau and
+// 1/(x_0 - beta) ([n][2 L] doubles) filled with QR_EMPTY, a NaN bit pattern
+// that no computed value has, which the readers poll for the owner's values.
+constexpr long long QR_EMPTY = 0x7ff4deadbeef5a5all;
+struct QrPrep {
+  int *flags = nullptr;      // [n]
+  double *tboard = nullptr;  // [n][2 L]
+  int n = 0, nt = 0;         // n, n 2 L
+};
+__device__ __forceinline__ void qr_prep_item(const QrPrep &q, size_t t) {
+  if (q.flags && t < (size_t)q.n) q.flags[t] = 0;
+  if (q.tboard && t < (size_t)q.nt) q.tboard[t] = __longlong_as_double(QR_EMPTY);
+}
+
 // evaldiff.hip
 hipError_t launch_evaldiff(int L, const EvalArgs &a, int maxexp, double *pw, hipStream_t st);
 // Coefficient 0 of the derivative products only (der[.][.][0]), one thread
@@ -42,17 +57,17 @@ hipError_t launch_assemble_b(int L, int n, int D, int Dc, int m, const int32_t *
 hipError_t launch_assemble_A(int L, int n, int D, int Dc, int nnz, const int32_t *asm_ptr, const int32_t *asm_ent,
                              const double *der, double *A, hipStream_t st, TOut at = TOut());
 hipError_t launch_assemble_A0(int L, int n, int D, int nnz, const int32_t *asm_ptr, const int32_t *asm_ent,
-                              const double *der, double *a0, hipStream_t st, int *clear = nullptr,
-                              int clear_count = 0);
+                              const double *der, double *a0, hipStream_t st, QrPrep prep);
 
 // linalg.hip
 hipError_t launch_status_init(int32_t *status, hipStream_t st);
 hipError_t launch_qr(int L, int n, double *a, double *tau, double *qt, int32_t *status, unsigned *bar,
                      hipStream_t st);
 int qr_lds_workgroups(int L, int n, bool with_qt);
-// flags_ready: the n column flags were cleared by an earlier launch on st.
+// prepared: the hand-over memory (flags, tboard) was prepared by an earlier
+// launch on st (QrPrep).
 hipError_t launch_qr_lds(int L, int n, double *a, double *tau, double *qt, int32_t *status, int *flags,
-                         double *vboard, double *tboard, hipStream_t st, bool flags_ready = false);
+                         double *vboard, double *tboard, hipStream_t st, bool prepared = false);
 hipError_t launch_m_from_qt(int L, int n, const double *qr, const double *qt, double *invd, double *M,
                             int32_t *status, hipStream_t st);
 hipError_t launch_form_m(int L, int n, const double *qr, const double *tau, double *invd, double *M, int32_t *status,

@@ -279,7 +279,9 @@ constexpr int QR_GROUP = 2;
 // stays in its LDS for the whole factorization.  Reflector c is published by
 // the owner of column c in two parts: first the column x below the diagonal
 // as it is (flags[c] = 1), then, after its norm and the reflector scalars,
-// tau and 1/(x_0 - beta) (flags[c] = 2).  With v = x / (x_0 - beta) below the
+// tau and 1/(x_0 - beta) into slots that an earlier launch on the stream
+// emptied (QrPrep), which the readers poll themselves: one round trip, and
+// no wait for the stores on the owner's chain.  With v = x / (x_0 - beta) below the
 // diagonal and v_c = 1, H_c y = y - tau (v^T y) v needs of y only
 //     S = sum_{i>c} x_i y_i,  d = y_c + S / (x_0 - beta),
 // so every workgroup forms S for all its columns from the first part while
@@ -332,8 +334,8 @@ __global__ void __launch_bounds__(256) qr_lds_kernel(int n, double *a, double *t
 
   // reflector of owned column q (global column c), by one wavefront: the
   // column below the diagonal to the board and flags[c] = 1, its norm, the
-  // scalars (beta into the column as R_cc), tau and 1 / (x_0 - beta) to the
-  // board and flags[c] = 2
+  // scalars (beta into the column as R_cc), tau and 1 / (x_0 - beta) into
+  // their slots
   auto publish = [&](int q, int c) {
     double *cq = col(q);
     for (int i = c + 1 + lane; i < n; i += 64) {
@@ -383,10 +385,6 @@ __global__ void __launch_bounds__(256) qr_lds_kernel(int n, double *a, double *t
       }
     }
     wave_sync();
-    if (lane == 0) {
-      wait_vm();  // tau and 1 / (x_0 - beta) are performed before the flag
-      __hip_atomic_store(&flags[c], 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
   };
 
   // S = sum_{i>c} x_i y_i for owned column q (x in xs), team of `width` lanes
@@ -493,13 +491,31 @@ __global__ void __launch_bounds__(256) qr_lds_kernel(int n, double *a, double *t
         }
         sh_ok = 1;
       } else {
-        sh_ok = wait_flag(&flags[c], status, 2) ? 1 : 0;
-        if (sh_ok)
+        // poll the 2 L slots (agent scope: the emptied value, or the owner's)
+        // until none holds QR_EMPTY; bounded, MD_EHIP on time-out
+        double ts[2 * L];
+        long spins = 0;
+        sh_ok = 1;
+        while (true) {
+          bool full = true;
 #pragma unroll
-          for (int l = 0; l < L; ++l) {
-            sh_tau[l] = tboard[(size_t)c * 2 * L + l];
-            sh_inv[l] = tboard[(size_t)c * 2 * L + L + l];
+          for (int l = 0; l < 2 * L; ++l) {
+            ts[l] = __hip_atomic_load(&tboard[(size_t)c * 2 * L + l], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            full = full && __double_as_longlong(ts[l]) != QR_EMPTY;
           }
+          if (full) break;
+          __builtin_amdgcn_s_sleep(1);
+          if (++spins > (1L << 22)) {
+            set_status(status, MD_EHIP);
+            sh_ok = 0;
+            break;
+          }
+        }
+#pragma unroll
+        for (int l = 0; l < L; ++l) {
+          sh_tau[l] = ts[l];
+          sh_inv[l] = ts[L + l];
+        }
       }
     }
     __syncthreads();
@@ -553,6 +569,8 @@ __global__ void __launch_bounds__(256) qr_lds_kernel(int n, double *a, double *t
     }
   }
 }
+
+__global__ void qr_prep_kernel(QrPrep q) { qr_prep_item(q, (size_t)blockIdx.x * blockDim.x + threadIdx.x); }
 
 __global__ void zero_i32_kernel(int *p, int count) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1519,11 +1537,18 @@ size_t qr_lds_bytes(int L, int n, int G, bool with_qt) {
 }
 
 hipError_t launch_qr_lds(int L, int n, double *a, double *tau, double *qt, int32_t *status, int *flags,
-                         double *vboard, double *tboard, hipStream_t st, bool flags_ready) {
+                         double *vboard, double *tboard, hipStream_t st, bool prepared) {
   const int G = qr_lds_workgroups(L, n, qt != nullptr);
   if (G == 0) return hipErrorInvalidValue;
   const size_t lds = qr_lds_bytes(L, n, G, qt != nullptr);
-  if (!flags_ready) hipLaunchKernelGGL(zero_i32_kernel, dim3((n + 255) / 256), dim3(256), 0, st, flags, n);
+  if (!prepared) {
+    QrPrep q;
+    q.flags = flags;
+    q.tboard = tboard;
+    q.n = n;
+    q.nt = 2 * L * n;
+    hipLaunchKernelGGL(qr_prep_kernel, dim3((q.nt + 255) / 256), dim3(256), 0, st, q);
+  }
   MD_DISPATCH(L, {
     static bool attr = false;
     if (!attr) {
