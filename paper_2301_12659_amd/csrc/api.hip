@@ -419,7 +419,7 @@ static void eval_args(const md_plan *p, const double *cff, const double *x, void
 static int eval_diff_impl(const md_plan *p, int Dc, const double *cff, const double *cst, const double *x, double *b,
                           double *A, void *ws, hipStream_t st, double *tsz = nullptr, bool beside_qr = false,
                           mdk::TOut rt = mdk::TOut(), mdk::TOut aT = mdk::TOut(), int *clear = nullptr,
-                          int clear_count = 0) {
+                          int clear_count = 0, double *empty = nullptr, size_t empty_count = 0) {
   Layout w = newton_layout(p);
   mdk::EvalArgs a;
   eval_args(p, cff, x, ws, Dc, a);
@@ -434,7 +434,7 @@ static int eval_diff_impl(const md_plan *p, int Dc, const double *cff, const dou
   {
     Timed t(MD_CLASS_ASSEMBLY, st);
     e = mdk::launch_assemble(p->L, p->n, p->D, Dc, p->m, p->nnz, p->d_poly_ptr, p->d_asm_ptr, p->d_asm_ent, cst,
-                             a.val, a.der, b, A, st, tsz, a.vsize, rt, aT, clear, clear_count);
+                             a.val, a.der, b, A, st, tsz, a.vsize, rt, aT, clear, clear_count, empty, empty_count);
   }
   if (e != hipSuccess) return hip_fail(e, "assembly launch");
   return MD_OK;
@@ -558,14 +558,16 @@ static int newton_step_impl(const md_plan *p, int Ls, int lo, int hi, bool keep_
   //    caller's stream; mixed: the values at L limbs for b, the derivatives
   //    at Ls limbs for A.  The assembly also writes the coefficient-major
   //    copies A_0..A_{W-1} [Ls][W][n][n] and b_lo..b_{hi-1} [Ls][W][n] that
-  //    the staged solve reads, and clears the solve's counters.
+  //    the staged solve reads, clears the solve's counters and empties its dx
+  //    slots.
   const size_t nn = (size_t)n * n;
   double *At = at(ws, w.At), *dxT = at(ws, w.dxT);
   int *sync = reinterpret_cast<int *>(at(ws, w.sync));
   const mdk::TOut rt{r, lo, W, Ls}, atT{At, 0, W, Ls};
   const int nsync = mdk::stages_sync_ints(W);
+  const size_t ndx = (size_t)Ls * n * W;
   if (!mixed) {
-    int rc = eval_diff_impl(p, hi, cff, cst, x, b, A, ws, st, tsz, !keep_m, rt, atT, sync, nsync);
+    int rc = eval_diff_impl(p, hi, cff, cst, x, b, A, ws, st, tsz, !keep_m, rt, atT, sync, nsync, dxT, ndx);
     if (rc != MD_OK) return rc;
   } else {
     eval_args(p, cff, x, ws, hi, a);
@@ -580,7 +582,7 @@ static int newton_step_impl(const md_plan *p, int Ls, int lo, int hi, bool keep_
     {
       Timed t(MD_CLASS_ASSEMBLY, st);
       if ((e = mdk::launch_assemble_b(L, n, D, hi, p->m, p->d_poly_ptr, cst, a.val, b, st, tsz, a.vsize, rt, sync,
-                                      nsync)) != hipSuccess)
+                                      nsync, dxT, ndx)) != hipSuccess)
         return hip_fail(e, "residual assembly");
     }
     a.values_only = 0;
@@ -704,10 +706,10 @@ static int newton_steps_impl(const md_plan *p, int count, const double *cff, con
     const int k = (count - 1 - s) % 2;
     // the evaluation is on the critical path here (the factorization of the
     // next step has slack): the two-wavefront kernel (0.69 against 0.75 ms
-    // per step); the assembly also writes the coefficient-major A and b and
-    // clears the staged solve's counters
+    // per step); the assembly also writes the coefficient-major A and b,
+    // clears the staged solve's counters and empties its dx slots
     rc = eval_diff_impl(p, D, cff, cst, x, b, A, ws, st, nullptr, false, mdk::TOut{r, 0, D, L},
-                        mdk::TOut{At, 0, D, L}, sync, mdk::stages_sync_ints(D));
+                        mdk::TOut{At, 0, D, L}, sync, mdk::stages_sync_ints(D), dxT, (size_t)L * n * D);
     if (rc != MD_OK) return rc;
     if ((e = hipStreamWaitEvent(st, p->join, 0)) != hipSuccess) return hip_fail(e, "join wait");
     // coefficient 0 of the next iterate (from M and r_0), then its

@@ -23,14 +23,18 @@ namespace mdk {
 // which the staggered method judges it: |c_{i,0,s}| + sum_m vsize_{m,s}, the
 // largest product of each monomial's chain (|value_{m,s}| when vsize is null;
 // leading limbs).  rt (nullable): coefficient-major copy for the staged
-// solve.  clear (nullable): clear_count ints set to zero on the way (the
-// staged solve's counters, which the caller launches next on this stream).
+// solve.  clear (nullable): clear_count ints set to zero on the way, and
+// empty (nullable): empty_count hand-over slots emptied (the staged solve's
+// counters and dx slots, for the solve the caller launches next on this
+// stream).
 template <int L>
 __global__ void __launch_bounds__(256) assemble_b_kernel(int n, int D, int Dc, int m, const int32_t *poly_ptr,
                                                          const double *cst, const double *val, double *b, double *tsz,
-                                                         const double *vsize, TOut rt, int *clear, int clear_count) {
+                                                         const double *vsize, TOut rt, int *clear, int clear_count,
+                                                         double *empty, size_t empty_count) {
   const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (clear && t < (size_t)clear_count) clear[t] = 0;
+  if (empty && t < empty_count) empty[t] = __longlong_as_double(SLOT_EMPTY);
   const size_t nD = (size_t)n * D, mD = (size_t)m * D;
   const size_t task = t >> 2;
   const int j = (int)(t & 3);
@@ -159,13 +163,13 @@ hipError_t launch_assemble_A0(int L, int n, int D, int nnz, const int32_t *asm_p
 
 hipError_t launch_assemble_b(int L, int n, int D, int Dc, int m, const int32_t *poly_ptr, const double *cst,
                              const double *val, double *b, hipStream_t st, double *tsz, const double *vsize,
-                             TOut rt, int *clear, int clear_count) {
+                             TOut rt, int *clear, int clear_count, double *empty, size_t empty_count) {
   if (Dc < 1 || Dc > D) return hipErrorInvalidValue;
   if (rt.p && (rt.lo < 0 || rt.W < 1 || rt.lo + rt.W > Dc || rt.L < 1 || rt.L > L)) return hipErrorInvalidValue;
-  const size_t threads = std::max((size_t)n * Dc * 4, (size_t)(clear ? clear_count : 0));
+  const size_t threads = std::max({(size_t)n * Dc * 4, (size_t)(clear ? clear_count : 0), empty ? empty_count : 0});
   const unsigned blocks = (unsigned)((threads + 255) / 256);
   MD_DISPATCH(L, hipLaunchKernelGGL(assemble_b_kernel<LL>, dim3(blocks), dim3(256), 0, st, n, D, Dc, m, poly_ptr,
-                                    cst, val, b, tsz, vsize, rt, clear, clear_count));
+                                    cst, val, b, tsz, vsize, rt, clear, clear_count, empty, empty_count));
   return hipGetLastError();
 }
 
@@ -202,8 +206,10 @@ hipError_t launch_assemble_A(int L, int n, int D, int Dc, int nnz, const int32_t
 hipError_t launch_assemble(int L, int n, int D, int Dc, int m, int nnz, const int32_t *poly_ptr,
                            const int32_t *asm_ptr, const int32_t *asm_ent, const double *cst, const double *val,
                            const double *der, double *b, double *A, hipStream_t st, double *tsz,
-                           const double *vsize, TOut rt, TOut at, int *clear, int clear_count) {
-  hipError_t e = launch_assemble_b(L, n, D, Dc, m, poly_ptr, cst, val, b, st, tsz, vsize, rt, clear, clear_count);
+                           const double *vsize, TOut rt, TOut at, int *clear, int clear_count, double *empty,
+                           size_t empty_count) {
+  hipError_t e = launch_assemble_b(L, n, D, Dc, m, poly_ptr, cst, val, b, st, tsz, vsize, rt, clear, clear_count, empty,
+                                   empty_count);
   if (e != hipSuccess) return e;
   return launch_assemble_A(L, n, D, Dc, nnz, asm_ptr, asm_ent, der, A, st, at);
 }

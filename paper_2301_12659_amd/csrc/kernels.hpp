@@ -8,11 +8,17 @@
 
 namespace mdk {
 
+// Hand-over slots between the workgroups of a running kernel that the
+// readers poll themselves: emptied by an earlier launch on the stream
+// (SLOT_EMPTY, a signalling-NaN bit pattern that no computed value has),
+// written once by their owner with agent-scope stores, read with
+// agent-scope loads until no limb holds SLOT_EMPTY.
+constexpr long long SLOT_EMPTY = 0x7ff4deadbeef5a5all;
+__device__ __forceinline__ bool slot_empty(double x) { return __double_as_longlong(x) == SLOT_EMPTY; }
+
 // Preparation of the LDS QR's hand-over memory, done by a launch ahead of
 // the QR on its stream: the column flags cleared and the slots of tau and
-// 1/(x_0 - beta) ([n][2 L] doubles) filled with QR_EMPTY, a NaN bit pattern
-// that no computed value has, which the readers poll for the owner's values.
-constexpr long long QR_EMPTY = 0x7ff4deadbeef5a5all;
+// 1/(x_0 - beta) ([n][2 L] doubles) emptied.
 struct QrPrep {
   int *flags = nullptr;      // [n]
   double *tboard = nullptr;  // [n][2 L]
@@ -20,7 +26,7 @@ struct QrPrep {
 };
 __device__ __forceinline__ void qr_prep_item(const QrPrep &q, size_t t) {
   if (q.flags && t < (size_t)q.n) q.flags[t] = 0;
-  if (q.tboard && t < (size_t)q.nt) q.tboard[t] = __longlong_as_double(QR_EMPTY);
+  if (q.tboard && t < (size_t)q.nt) q.tboard[t] = __longlong_as_double(SLOT_EMPTY);
 }
 
 // evaldiff.hip
@@ -42,18 +48,19 @@ struct TOut {
 // D; tsz (nullable, [n][D]) gets |c_{i,0,s}| + sum_m vsize_{m,s} (the
 // evaluation's chain maxima; |value_{m,s}| when vsize is null), the size of
 // the terms of b_{i,s}; rt and at the coefficient-major copies of b and A;
-// clear (nullable) clear_count ints set to zero by the b launch.
+// clear (nullable) clear_count ints set to zero and empty (nullable)
+// empty_count slots emptied (SLOT_EMPTY) by the b launch.
 hipError_t launch_assemble(int L, int n, int D, int Dc, int m, int nnz, const int32_t *poly_ptr,
                            const int32_t *asm_ptr, const int32_t *asm_ent, const double *cst, const double *val,
                            const double *der, double *b, double *A, hipStream_t st, double *tsz = nullptr,
                            const double *vsize = nullptr, TOut rt = TOut(), TOut at = TOut(), int *clear = nullptr,
-                           int clear_count = 0);
+                           int clear_count = 0, double *empty = nullptr, size_t empty_count = 0);
 size_t evaldiff_lds_bytes(int L, int D);
 int evaldiff_workers_per_block(int D);  // monomials per 256-thread workgroup
 hipError_t launch_assemble_b(int L, int n, int D, int Dc, int m, const int32_t *poly_ptr, const double *cst,
                              const double *val, double *b, hipStream_t st, double *tsz = nullptr,
                              const double *vsize = nullptr, TOut rt = TOut(), int *clear = nullptr,
-                             int clear_count = 0);
+                             int clear_count = 0, double *empty = nullptr, size_t empty_count = 0);
 hipError_t launch_assemble_A(int L, int n, int D, int Dc, int nnz, const int32_t *asm_ptr, const int32_t *asm_ent,
                              const double *der, double *A, hipStream_t st, TOut at = TOut());
 hipError_t launch_assemble_A0(int L, int n, int D, int nnz, const int32_t *asm_ptr, const int32_t *asm_ent,
@@ -89,7 +96,7 @@ hipError_t launch_gemm(int L, int n, const double *M, const double *B, size_t b_
 bool stages_persistent(int L, int n, int D);
 int stages_sync_ints(int D);
 int stages_products(int L, int n, int D);
-hipError_t launch_stages_sync(int L, int n, int D, int *sync, hipStream_t st);
+hipError_t launch_stages_sync(int L, int n, int D, int *sync, double *dxT, hipStream_t st);
 hipError_t launch_stages(int L, int n, int D, const double *M, const double *NP, const double *At, double *rT,
                          double *dxT, int *sync, int32_t *status, hipStream_t st, bool sync_ready = false);
 // xn [L][n] = x_0 + M r_0, coefficient 0 of the iterate after a step whose

@@ -492,7 +492,7 @@ __global__ void __launch_bounds__(256) qr_lds_kernel(int n, double *a, double *t
         sh_ok = 1;
       } else {
         // poll the 2 L slots (agent scope: the emptied value, or the owner's)
-        // until none holds QR_EMPTY; bounded, MD_EHIP on time-out
+        // until none holds SLOT_EMPTY; bounded, MD_EHIP on time-out
         double ts[2 * L];
         long spins = 0;
         sh_ok = 1;
@@ -501,7 +501,7 @@ __global__ void __launch_bounds__(256) qr_lds_kernel(int n, double *a, double *t
 #pragma unroll
           for (int l = 0; l < 2 * L; ++l) {
             ts[l] = __hip_atomic_load(&tboard[(size_t)c * 2 * L + l], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            full = full && __double_as_longlong(ts[l]) != QR_EMPTY;
+            full = full && __double_as_longlong(ts[l]) != SLOT_EMPTY;
           }
           if (full) break;
           __builtin_amdgcn_s_sleep(1);
@@ -571,6 +571,13 @@ __global__ void __launch_bounds__(256) qr_lds_kernel(int n, double *a, double *t
 }
 
 __global__ void qr_prep_kernel(QrPrep q) { qr_prep_item(q, (size_t)blockIdx.x * blockDim.x + threadIdx.x); }
+
+// The persistent staged solve's counters cleared and its dx slots emptied.
+__global__ void stages_prep_kernel(int *sync, int nsync, double *dxT, size_t ndx) {
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < (size_t)nsync) sync[t] = 0;
+  if (t < ndx) dxT[t] = __longlong_as_double(SLOT_EMPTY);
+}
 
 __global__ void zero_i32_kernel(int *p, int count) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
@@ -985,20 +992,23 @@ constexpr int STAGE_PRODUCTS = 3;
 //     dx_{k-2} from its registers, dx_{k-1} from the LDS copy that the
 //     critical wavefront made at the start of stage k.
 // So a stage's critical path holds one multiply-add per lane, one butterfly
-// and the hand-overs.  One workgroup barrier per stage separates the two
-// wavefronts' uses of the LDS slots (pre_k in slot k mod 2).  After both rows
-// of dx_k are out, solver s sets its flag to k + 1; the flags share one
-// 128-byte line, and a wavefront waits for all solvers with one lane per flag
-// and a vote.  Updater (g, b) owns the rows 16 b .. 16 b + 15 (one team of 16
+// and the hand-over.  One workgroup barrier per stage separates the two
+// wavefronts' uses of the LDS slots (pre_k in slot k mod 2).  dx itself is
+// the hand-over: its slots are emptied (SLOT_EMPTY) by the launch ahead of
+// this one on the stream, every dx_k(i) is written once with agent-scope
+// stores, and a reader polls the entries it needs with agent-scope loads
+// until no limb is empty (no flag, no wait for the stores, one round trip).
+// Updater (g, b) owns the rows 16 b .. 16 b + 15 (one team of 16
 // lanes per row) of coefficient m = 4 + g (and m + Gm when there are more than
 // 64 coefficients from 4 on): in round q, once dx_q is out, every lane adds
 // its four terms of A_{m-q}(i,.) dx_q to level sums kept in registers across
 // the rounds; after round m - 4 the team reduces them, renormalizes,
 // stores r''_m(i) = b_m(i) - sum and counts itself done for m, so r''_m is
 // written once, by its owner.  Everything handed between workgroups (dx,
-// r'', flags) goes through agent-scope loads and stores and a wait for the
-// stores before the flag, never through fences: a fence would write back or
-// invalidate a whole L2 at every hand-over, hundreds of them per stage.  All
+// r'', counters) goes through agent-scope loads and stores (r'' with a wait
+// for the stores before its counter), never through fences: a fence would
+// write back or invalidate a whole L2 at every hand-over, hundreds of them
+// per stage.  All
 // workgroups must be resident together; waits are bounded and report
 // MD_EHIP, after which every wavefront of a workgroup leaves at the same
 // barrier.
@@ -1016,22 +1026,26 @@ __global__ void __launch_bounds__(256) stages_persistent_kernel(int n, int D, in
   const size_t nn = (size_t)n * n, nD = (size_t)n * D, nnD = nn * D;
   const int Bm = (n + 15) / 16;
   auto rounds = [&](int m) { return sync + (size_t)(2 + m) * SYNC_STRIDE; };
-  auto solved = [&](int s) { return sync + SYNC_STRIDE + s; };  // stages done by solver s (one 128-byte line)
   auto poll = [&](const int *p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); };
-  // wavefront-wide wait until every solver has published stage k - 1: lane
-  // s polls solver s's flag, the wavefront votes
-  auto wait_solvers = [&](int k) {
+  // wavefront-wide poll of dx_k (lane v: dx_k(v), its L limbs) until no limb
+  // is empty; lanes v >= n get zeros.  Bounded: false and MD_EHIP on time-out.
+  auto poll_dx = [&](int k, double (&x)[L]) {
     long spins = 0;
     while (true) {
-      const int f = lane < Gs ? poll(solved(lane)) : k;
-      if (__all(f >= k)) break;
+      bool full = true;
+      md::zero<L>(x);
+      if (lane < n) {
+        ld_agent<L>(dxT, nD, (size_t)k * n + lane, x);
+#pragma unroll
+        for (int l = 0; l < L; ++l) full = full && !slot_empty(x[l]);
+      }
+      if (__all(full)) return true;
       __builtin_amdgcn_s_sleep(1);
       if (++spins > (1L << 22)) {
         if (lane == 0) set_status(status, MD_EHIP);
         return false;
       }
     }
-    return true;
   };
   if ((int)blockIdx.x < Gs) {
     const int w = wv & 1;              // row slot
@@ -1058,10 +1072,9 @@ __global__ void __launch_bounds__(256) stages_persistent_kernel(int n, int D, in
 #pragma unroll
         for (int l = 0; l < L; ++l) acc[l] = slot[l * 64 + lane];
         if (k >= 1) {
-          const bool ok = row ? wait_solvers(k) : true;
-          if (!ok && lane == 0) sh_dead[k & 1] = 1;
           md::zero<L>(x1);
-          if (ok && row && col) ld_agent<L>(dxT, nD, (size_t)(k - 1) * n + v, x1);
+          const bool ok = row ? poll_dx(k - 1, x1) : true;
+          if (!ok && lane == 0) sh_dead[k & 1] = 1;
 #pragma unroll
           for (int l = 0; l < L; ++l) x1s[w][l * 64 + lane] = x1[l];
           __hip_atomic_store(&sh_x1[w], k, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -1070,12 +1083,10 @@ __global__ void __launch_bounds__(256) stages_persistent_kernel(int n, int D, in
         if (row) {
           team_sum_lazy<L>(acc, 64);
           MD<L>::renorm(acc, r);
-          if (lane == 0) st_agent<L>(dxT, nD, (size_t)k * n + i, r);
+          if (lane == 0) st_agent<L>(dxT, nD, (size_t)k * n + i, r);  // the readers poll these slots
         }
-        wait_vm();
-        __syncthreads();  // both rows of dx_k stored; pre_{k+1} is in its slot
+        __syncthreads();  // pre_{k+1} is in its slot
         if (sh_dead[k & 1]) return;
-        if (tid == 0) __hip_atomic_store(solved(blockIdx.x), k + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
       return;
     }
@@ -1189,18 +1200,26 @@ __global__ void __launch_bounds__(256) stages_persistent_kernel(int n, int D, in
   };
   fetch0(0);
   for (int q = 0; q <= qlast; ++q) {
-    if (wv == 0) {
-      const bool ok = wait_solvers(q + 1);  // dx_q is out
-      if (lane == 0) sh_ok = ok ? 1 : 0;
-    }
-    __syncthreads();
-    if (!sh_ok) return;
+    // dx_q: every thread polls its entries until they are written (bounded)
+    int bad = 0;
     for (int e = tid; e < L * n; e += blockDim.x) {
       const int l = e / n, vv = e - l * n;
-      xq[l * 64 + vv] = __hip_atomic_load(dxT + (size_t)l * nD + (size_t)q * n + vv, __ATOMIC_RELAXED,
-                                          __HIP_MEMORY_SCOPE_AGENT);
+      const double *src = dxT + (size_t)l * nD + (size_t)q * n + vv;
+      double val;
+      long spins = 0;
+      while (true) {
+        val = __hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (!slot_empty(val)) break;
+        __builtin_amdgcn_s_sleep(2);
+        if (++spins > (1L << 22)) {
+          set_status(status, MD_EHIP);
+          bad = 1;
+          break;
+        }
+      }
+      xq[l * 64 + vv] = val;
     }
-    __syncthreads();
+    if (__syncthreads_or(bad)) return;
     const bool use0 = q + STAGE_PRODUCTS + 1 <= m0, use1 = m1 < D && q + STAGE_PRODUCTS + 1 <= m1;
     if (live && use0) {
 #pragma unroll
@@ -1638,10 +1657,12 @@ int stages_products(int L, int n, int D) {
 // The counters of the persistent staged solve cleared ahead of it (a caller
 // may issue this before it waits for the factorization, off the critical
 // path, and then launch_stages with sync_ready).
-hipError_t launch_stages_sync(int L, int n, int D, int *sync, hipStream_t st) {
-  if (stages_persistent(L, n, D))
-    hipLaunchKernelGGL(zero_i32_kernel, dim3((stages_sync_ints(D) + 255) / 256), dim3(256), 0, st, sync,
-                       stages_sync_ints(D));
+hipError_t launch_stages_sync(int L, int n, int D, int *sync, double *dxT, hipStream_t st) {
+  if (stages_persistent(L, n, D)) {
+    const size_t cnt = std::max((size_t)stages_sync_ints(D), (size_t)L * n * D);
+    hipLaunchKernelGGL(stages_prep_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, sync,
+                       stages_sync_ints(D), dxT, (size_t)L * n * D);
+  }
   return hipGetLastError();
 }
 
@@ -1655,7 +1676,7 @@ hipError_t launch_stages(int L, int n, int D, const double *M, const double *NP,
     const int Gm = C <= 64 ? C : (C + 1) / 2;
     const int G = Gs + Gm * Bm;  // at most 32 + 256 workgroups of 256 threads
     if (!sync_ready) {
-      const hipError_t e = launch_stages_sync(L, n, D, sync, st);
+      const hipError_t e = launch_stages_sync(L, n, D, sync, dxT, st);
       if (e != hipSuccess) return e;
     }
     if (L == 2)
