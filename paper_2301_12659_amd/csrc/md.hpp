@@ -216,11 +216,43 @@ MD_INLINE void recip_newton(const double (&v)[L], double (&r)[L]) {
   recip_step<L, L, 1>(v, r);
 }
 
+// The last doubling of quad doubles with the residual formed by one fused
+// multiply-subtract (1 - (a y) y, or 1 - v r) and renormalized a second
+// time, which moves significant bits into any zero limb that a deep
+// cancellation left inside it: its leading two limbs are then its leading
+// 106 bits, all that the correction, itself about 2^(-106) of the result,
+// needs; the correction is taken at two limbs.
+MD_INLINE void rsqrt_last4(const double (&a)[4], double (&y)[4]) {
+  double t[4], e[4] = {1.0, 0.0, 0.0, 0.0}, en[4], yn[4];
+  MD<4>::mul(a, y, t);
+  MD<4>::fms(e, t, y);
+  MD<4>::renorm(e, en);
+  const double yh[2] = {y[0], y[1]}, eh[2] = {en[0], en[1]};
+  double ch[2];
+  MD<2>::mul(yh, eh, ch);
+  const double c[4] = {0.5 * ch[0], 0.5 * ch[1], 0.0, 0.0};
+  MD<4>::add(y, c, yn);
+  copy<4>(yn, y);
+}
+
+MD_INLINE void recip_last4(const double (&v)[4], double (&r)[4]) {
+  double e[4] = {1.0, 0.0, 0.0, 0.0}, en[4], rn[4];
+  MD<4>::fms(e, v, r);
+  MD<4>::renorm(e, en);
+  const double rh[2] = {r[0], r[1]}, eh[2] = {en[0], en[1]};
+  double ch[2];
+  MD<2>::mul(rh, eh, ch);
+  const double c[4] = {ch[0], ch[1], 0.0, 0.0};
+  MD<4>::add(r, c, rn);
+  copy<4>(rn, r);
+}
+
 // The same doublings with every correction at full width and no repair
 // step, for double and quad doubles: the residual is never truncated, so a
 // zero limb inside it costs nothing, and the last doubling leaves a relative
 // error of about 2^(-53 L + 6) instead of a few units in the last limb, for
-// one full-precision step less.  Used where the result is on a chain of
+// one full-precision step less; for quad doubles the last doubling is
+// rsqrt_last4 / recip_last4.  Used where the result is on a chain of
 // dependent operations (the reflector of a Householder step).  Octo doubles
 // keep the full sequence (a shortened one would stop near 2^(-412)).
 template <int L>
@@ -233,7 +265,7 @@ MD_INLINE void rsqrt_short(const double (&a)[L], double (&y)[L]) {
     zero<L>(y);
     y[0] = 1.0 / ::sqrt(a[0]);
     rsqrt_step<L, 2, (L == 2 ? 2 : 1)>(a, y);
-    if constexpr (L == 4) rsqrt_step<L, 4, 4>(a, y);
+    if constexpr (L == 4) rsqrt_last4(a, y);
   }
 }
 
@@ -247,7 +279,7 @@ MD_INLINE void recip_short(const double (&v)[L], double (&r)[L]) {
     zero<L>(r);
     r[0] = 1.0 / v[0];
     recip_step<L, 2, (L == 2 ? 2 : 1)>(v, r);
-    if constexpr (L == 4) recip_step<L, 4, 4>(v, r);
+    if constexpr (L == 4) recip_last4(v, r);
   }
 }
 
