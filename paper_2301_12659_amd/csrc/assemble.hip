@@ -46,22 +46,38 @@ __global__ void __launch_bounds__(256) assemble_b_kernel(int n, int D, int Dc, i
   md::zero<L>(r);
   double size = 0.0;
   if (live) {
-    int mj = poly_ptr[i] + j;
     const int mend = poly_ptr[i + 1];
-    if (j == 0) {
+    bool have = j == 0;
+    if (have) {
       ld<L>(cst, nD, q, r);
       size = fabs(r[0]);
-    } else if (mj < mend) {
-      ld<L>(val, mD, (size_t)mj * D + s, r);
-      size = vsize ? vsize[(size_t)mj * D + s] : fabs(r[0]);
-      mj += 4;
     }
-    for (; mj < mend; mj += 4) {
-      double v[L], t[L];
-      ld<L>(val, mD, (size_t)mj * D + s, v);
-      size += vsize ? vsize[(size_t)mj * D + s] : fabs(v[0]);
-      MD<L>::add(r, v, t);
-      md::copy<L>(t, r);
+    // the lane's values in batches of four, each batch loaded before it is added
+    for (int mb = poly_ptr[i] + j; mb < mend; mb += 16) {
+      double v[4][L], sz[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int mj = mb + 4 * u;
+        if (mj < mend) {
+          ld<L>(val, mD, (size_t)mj * D + s, v[u]);
+          sz[u] = vsize ? vsize[(size_t)mj * D + s] : fabs(v[u][0]);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (mb + 4 * u < mend) {
+          if (have) {
+            double t[L];
+            MD<L>::add(r, v[u], t);
+            md::copy<L>(t, r);
+            size += sz[u];
+          } else {
+            md::copy<L>(v[u], r);
+            size = sz[u];
+            have = true;
+          }
+        }
+      }
     }
   }
   team_sum<L>(r, 4);
@@ -84,6 +100,10 @@ __global__ void __launch_bounds__(256) assemble_b_kernel(int n, int D, int Dc, i
 // series-major writes along s); with at (nullable) the tile goes through LDS
 // so that the coefficient-major copy at[l][s][i][j] (s < at.W, at.L limbs) is
 // written along (i, j).
+// Coefficients per thread of assemble_A_kernel: with the tiles of
+// assemble_tile at most 8, 8, 4, 2 for 1, 2, 4, 8 limbs (MD_MAX_COEFFS = 128).
+__host__ __device__ constexpr int asm_a_max_slices(int L) { return L >= 8 ? 2 : (L == 4 ? 4 : 8); }
+
 template <int L, int TI>
 __global__ void __launch_bounds__(256) assemble_A_kernel(int n, int D, int Dc, int nnz, const int32_t *asm_ptr,
                                                          const int32_t *asm_ent, const double *der, double *A,
@@ -92,26 +112,50 @@ __global__ void __launch_bounds__(256) assemble_A_kernel(int n, int D, int Dc, i
   const size_t nn = (size_t)n * n, nnD = nn * D, zD = (size_t)nnz * D;
   const size_t ij0 = (size_t)blockIdx.x * TI;
   const int Dp = Dc + 1;
-  for (int e = threadIdx.x; e < TI * Dc; e += blockDim.x) {
-    const int il = e / Dc, s = e - il * Dc;
-    const size_t ij = ij0 + il;
-    if (ij >= nn) continue;
+  // blockDim / TI threads per (i, j), each the coefficients s = sl + u per,
+  // u < NS (at most asm_a_max_slices(L)): the entry list is read once, and the
+  // NS values of an entry are loaded together before they are added
+  constexpr int MAXS = asm_a_max_slices(L);
+  const int per = blockDim.x / TI, il = threadIdx.x / per, sl = threadIdx.x - il * per;
+  const int NS = (Dc + per - 1) / per;
+  const size_t ij = ij0 + il;
+  if (ij < nn) {
     const int lo = asm_ptr[ij], hi = asm_ptr[ij + 1];
-    double acc[L];
-    md::zero<L>(acc);
-    if (lo < hi) {
-      ld<L>(der, zD, (size_t)asm_ent[lo] * D + s, acc);
-      for (int t = lo + 1; t < hi; ++t) {
-        double v[L], r[L];
-        ld<L>(der, zD, (size_t)asm_ent[t] * D + s, v);
-        MD<L>::add(acc, v, r);
-        md::copy<L>(r, acc);
+    double acc[MAXS][L];
+#pragma unroll
+    for (int u = 0; u < MAXS; ++u) md::zero<L>(acc[u]);
+    for (int t = lo; t < hi; ++t) {
+      const size_t eo = (size_t)asm_ent[t] * D;
+      double v[MAXS][L];
+#pragma unroll
+      for (int u = 0; u < MAXS; ++u) {
+        const int s = sl + u * per;
+        if (u < NS && s < Dc) ld<L>(der, zD, eo + s, v[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < MAXS; ++u) {
+        const int s = sl + u * per;
+        if (u < NS && s < Dc) {
+          if (t == lo) {
+            md::copy<L>(v[u], acc[u]);
+          } else {
+            double r[L];
+            MD<L>::add(acc[u], v[u], r);
+            md::copy<L>(r, acc[u]);
+          }
+        }
       }
     }
-    st<L>(A, nnD, ij * D + s, acc);
-    if (at.p)
 #pragma unroll
-      for (int l = 0; l < L; ++l) tile[(l * TI + il) * Dp + s] = acc[l];
+    for (int u = 0; u < MAXS; ++u) {
+      const int s = sl + u * per;
+      if (u < NS && s < Dc) {
+        st<L>(A, nnD, ij * D + s, acc[u]);
+        if (at.p)
+#pragma unroll
+          for (int l = 0; l < L; ++l) tile[(l * TI + il) * Dp + s] = acc[u][l];
+      }
+    }
   }
   if (!at.p) return;
   __syncthreads();
@@ -174,10 +218,13 @@ hipError_t launch_assemble_b(int L, int n, int D, int Dc, int m, const int32_t *
 }
 
 // Rows (i, j) per workgroup of assemble_A_kernel: 16 while the LDS tile stays
-// within 48 KB, else fewer.
-static int assemble_tile(int Lout, int Dc) {
+// within 48 KB and a thread has at most asm_a_max_slices(L) coefficients,
+// else fewer.
+static int assemble_tile(int L, int Dc) {
   int ti = 16;
-  while (ti > 1 && (size_t)ti * (Dc + 1) * Lout * sizeof(double) > 48 * 1024) ti /= 2;
+  while (ti > 1 && ((size_t)ti * (Dc + 1) * L * sizeof(double) > 48 * 1024 ||
+                    (Dc + 256 / ti - 1) / (256 / ti) > asm_a_max_slices(L)))
+    ti /= 2;
   return ti;
 }
 
@@ -187,6 +234,7 @@ hipError_t launch_assemble_A(int L, int n, int D, int Dc, int nnz, const int32_t
   if (at.p && (at.lo != 0 || at.W < 1 || at.W > Dc || at.L < 1 || at.L > L)) return hipErrorInvalidValue;
   const size_t nn = (size_t)n * n;
   const int ti = assemble_tile(L, Dc);
+  if ((Dc + 256 / ti - 1) / (256 / ti) > asm_a_max_slices(L)) return hipErrorInvalidValue;
   const size_t lds = at.p ? (size_t)ti * (Dc + 1) * L * sizeof(double) : 0;
   const dim3 grid((unsigned)((nn + ti - 1) / ti));
 #define MD_ASM_A(TI)                                                                                            \
