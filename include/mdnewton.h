@@ -107,7 +107,8 @@ int md_eval_diff(const md_plan *plan, const double *cff, const double *cst, cons
  * Q = H_0 H_1 ... H_{n-1}, H_c = I - tau_c v_c v_c^T, v_c = e_c + (entries below).
  * A zero column sets *dev_status = MD_ESINGULAR.  The factorization runs on
  * several workgroups that hand the reflectors over through the workspace
- * (md_qr_workspace_size bytes: flags and a reflector board); a hand-over
+ * (md_qr_workspace_size bytes: flags, a reflector board and the slots of the
+ * reflector scalars); a hand-over
  * time-out sets MD_EHIP. */
 int md_qr_workspace_size(int prec, int n, size_t *bytes);
 int md_qr(int prec, int n, double *a0, double *tau, void *ws, size_t ws_bytes, hipStream_t stream,
@@ -116,13 +117,15 @@ int md_qr(int prec, int n, double *a0, double *tau, void *ws, size_t ws_bytes, h
 /* md_qr for callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * factorization, kernels and results as md_qr, with no workspace argument and
- * no allocation.  Its scratch (the flags and the reflector board) is a static
+ * no allocation.  Its scratch (the flags, the reflector board and the slots of
+ * the reflector scalars) is a static
  * device array of MD_QR_NOALLOC_MAX_BYTES bytes; each GPU the library runs on
  * holds its own copy until the process ends.  The call is refused with
  * MD_ENOSPACE when md_qr_workspace_size(prec, n) exceeds that size (octo
  * doubles up to n = 256, quad doubles up to n = 363, double doubles up to
  * n = 514).  Every call on a GPU uses that GPU's one array, which keeps the
- * last call's contents (the flags are cleared by a kernel at every call):
+ * last call's contents (a kernel clears the flags and empties the scalar
+ * slots at every call):
  * calls that overlap in time on one GPU (several streams or host threads)
  * race and give wrong results; order them on one stream or serialize them.
  * Arguments, status and errors as md_qr. */

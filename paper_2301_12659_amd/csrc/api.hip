@@ -175,7 +175,7 @@ hipError_t run_qr(int L, int n, double *a, double *tau, double *qt, int32_t *sta
   return mdk::launch_qr(L, n, a, tau, qt, status, bar, st);
 }
 
-// Scratch of md_qr_noalloc: the QR's flags and reflector board in a static
+// Scratch of md_qr_noalloc: the QR's flags, reflector board and scalar slots in a static
 // device array (each GPU holds its own copy, at its own address, until the
 // process ends).  Host code never passes the array's name to a kernel: it
 // stands for a host-side symbol there.  The device address is taken once per

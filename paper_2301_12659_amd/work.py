@@ -141,13 +141,23 @@ def newton_chain_instr(L: int, kind: str) -> int:
     def c(P):
         return md_costs(P)
 
+    total = 2  # the double start: a square root or a division
+    if L == 4:
+        # one doubling at two limbs, then the last one with a fused residual
+        # at four limbs, two renormalizations and a two-limb correction
+        cp, c2, c4 = c(2), c(4), c(4)
+        if kind == "rsqrt":
+            total += 2 * cp["mul"]["instr"] + cp["sub"]["instr"] + 1 + cp["add"]["instr"]
+            total += (c4["mul"]["instr"] + c4["fms"]["instr"] + 2 * c4["renorm"]["instr"] + c2["mul"]["instr"] + 2 +
+                      c4["add"]["instr"])
+        else:
+            total += cp["mul"]["instr"] + cp["sub"]["instr"] + 1 + cp["add"]["instr"]
+            total += c4["fms"]["instr"] + 2 * c4["renorm"]["instr"] + c2["mul"]["instr"] + c4["add"]["instr"]
+        return int(total)
     if L >= 8:  # full sequence: steps at 2, 4, 8 limbs, then a one-limb-correction step at 8
         steps = [(2, 1), (4, 2), (8, 8), (8, 1)]
-    elif L == 4:
-        steps = [(2, 1), (4, 4)]
     else:
         steps = [(2, 2)]
-    total = 2  # the double start: a square root or a division
     for P, H in steps:
         cp = c(P)
         corr = 1 if H == 1 else c(H)["mul"]["instr"]
@@ -160,15 +170,18 @@ def newton_chain_instr(L: int, kind: str) -> int:
 
 def qr_latency_bound(L: int, n: int, with_qt: bool = True) -> dict:
     """Lower bound of the column-by-column Householder QR of A_0 (with Q^T
-    on the augmented columns): per column, the dot of the new reflector with
-    the next column (one lazy multiply-add per lane, a 64-lane butterfly),
-    that column's update (one multiply-add), its norm (the same dot
-    structure), the reflector scalars (1/sqrt and a reciprocal), x_0 - beta
-    and the scaling, and one hand-over to the other workgroups."""
+    on the augmented columns) as the LDS-resident kernel orders it.  The
+    dot S of reflector c with the next column is formed from the first part
+    of the hand-over while the owner of column c still computes the scalars,
+    so the chain of a column is: the finish of column c+1 with tau and
+    1/(x_0 - beta) (d = y_c + S/(x_0 - beta), tau d, tau d/(x_0 - beta), the
+    multiply-add of the rows), its norm (one lazy multiply-add per lane, a
+    64-lane butterfly), beta, the reflector scalars (1/sqrt and a
+    reciprocal), x_0 - beta, and one hand-over of the scalars."""
     c = md_costs(L)
     dot = c["fma_lazy"]["instr"] + _butterfly(c)
-    per_col = (2 * dot + c["fma"]["instr"] + newton_chain_instr(L, "rsqrt") + newton_chain_instr(L, "recip") +
-               c["sub"]["instr"] + c["mul"]["instr"])
+    per_col = (2 * c["fma"]["instr"] + 3 * c["mul"]["instr"] + dot + newton_chain_instr(L, "rsqrt") +
+               newton_chain_instr(L, "recip") + c["sub"]["instr"])
     s = n * (per_col * CYCLES_PER_DEP_INSTR / CLOCK_HZ + HANDOVER_S)
     return {"chain_instr_per_column": int(per_col), "columns": n, "seconds": s}
 
