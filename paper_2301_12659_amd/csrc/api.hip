@@ -22,7 +22,6 @@ struct md_plan {
   // evaluation (default priority, non-blocking), with fork and join events
   hipStream_t aux = nullptr;
   hipEvent_t fork = nullptr, join = nullptr;
-  hipEvent_t x0done = nullptr;  // md_newton_steps: next_x0_kernel on the second stream has read x_0
 };
 
 namespace {
@@ -363,8 +362,7 @@ int md_plan_create(int prec, int n, int d, int m, const int32_t *poly_ptr, const
       (e = up(&p->d_row_of, row_of.data(), m)) != hipSuccess ||
       (e = hipStreamCreateWithFlags(&p->aux, hipStreamNonBlocking)) != hipSuccess ||
       (e = hipEventCreateWithFlags(&p->fork, hipEventDisableTiming)) != hipSuccess ||
-      (e = hipEventCreateWithFlags(&p->join, hipEventDisableTiming)) != hipSuccess ||
-      (e = hipEventCreateWithFlags(&p->x0done, hipEventDisableTiming)) != hipSuccess) {
+      (e = hipEventCreateWithFlags(&p->join, hipEventDisableTiming)) != hipSuccess) {
     md_plan_destroy(p);
     return hip_fail(e, "plan setup");
   }
@@ -379,7 +377,6 @@ int md_plan_destroy(md_plan *p) {
     if (q) (void)hipFree(q);
   if (p->fork) (void)hipEventDestroy(p->fork);
   if (p->join) (void)hipEventDestroy(p->join);
-  if (p->x0done) (void)hipEventDestroy(p->x0done);
   if (p->aux) (void)hipStreamDestroy(p->aux);
   delete p;
   return MD_OK;
@@ -628,7 +625,7 @@ int md_newton_step(const md_plan *p, const double *cff, const double *cst, doubl
 
 // Whether md_newton_steps can overlap the factorization of the next step
 // with the current one: plain steps whose staged solve is the persistent
-// kernel (its first stage is what next_x0_kernel reproduces) and whose A_0
+// kernel (its first stage is what the next-x_0 blocks reproduce) and whose A_0
 // comes from the coefficient-0 pre-pass.
 static bool steps_pipelined(const md_plan *p) {
   return p->m > 0 && p->D > 1 && mdk::stages_persistent(p->L, p->n, p->D) &&
@@ -637,8 +634,9 @@ static bool steps_pipelined(const md_plan *p) {
 
 // count plain Newton steps.  A_0 of step s+1 depends on coefficient 0 of its
 // iterate only, x_0 + dx_0, and dx_0 = M r_0 is known once step s has M and
-// b: next_x0_kernel forms it (bit for bit as the staged solve and the update
-// will) right after the join, and the pre-pass, QR and M of step s+1 run on
+// b: the launch of the products N, P, Q forms it too (bit for bit as the
+// staged solve and the update will) right after the join, and the pre-pass,
+// QR and M of step s+1 run on
 // the second stream while step s finishes its staged solve and step s+1
 // evaluates.  Factorizations alternate between two sets of buffers, the last
 // step using the first set (the one md_newton_step and chord steps use).
@@ -664,17 +662,12 @@ static int newton_steps_impl(const md_plan *p, int count, const double *cff, con
   // factorization of the iterate whose coefficient 0 is in xn ([L][n]) into
   // buffer set k, on the second stream after the fork event; its pre-pass
   // has derivative products of its own (der0), since the evaluation of the
-  // current step runs beside it.  Mprev (nullable): first form xn = x_0 +
-  // M_prev r_0 there (next_x0_kernel), then record x0done, which the caller's
-  // stream waits for before it updates x.
-  auto factor = [&](int k, const double *Mprev) -> int {
+  // current step runs beside it.  xn was formed on the caller's stream
+  // before the fork (the first iterate's by a copy, the next ones' with the
+  // products N, P, Q in one launch).
+  auto factor = [&](int k) -> int {
     if ((e = hipEventRecord(p->fork, st)) != hipSuccess) return hip_fail(e, "fork");
     if ((e = hipStreamWaitEvent(p->aux, p->fork, 0)) != hipSuccess) return hip_fail(e, "fork wait");
-    if (Mprev) {
-      Timed t(MD_CLASS_X_UPDATE, p->aux);
-      if ((e = mdk::launch_next_x0(L, n, D, Mprev, r, x, xn, p->aux)) != hipSuccess) return hip_fail(e, "next x_0");
-      if ((e = hipEventRecord(p->x0done, p->aux)) != hipSuccess) return hip_fail(e, "x_0 event");
-    }
     {
       Timed t(MD_CLASS_QR, p->aux);
       mdk::EvalArgs a;
@@ -700,7 +693,7 @@ static int newton_steps_impl(const md_plan *p, int count, const double *cff, con
   // coefficient 0 of the first iterate into xn
   if ((e = mdk::launch_transpose_ld(L, x, D, xn, n, n, 1, (size_t)n * D, n, st)) != hipSuccess)
     return hip_fail(e, "x_0");
-  int rc = factor((count - 1) % 2, nullptr);
+  int rc = factor((count - 1) % 2);
   if (rc != MD_OK) return rc;
   for (int s = 0; s < count; ++s) {
     const int k = (count - 1 - s) % 2;
@@ -712,15 +705,18 @@ static int newton_steps_impl(const md_plan *p, int count, const double *cff, con
                         mdk::TOut{At, 0, D, L}, sync, mdk::stages_sync_ints(D), dxT, (size_t)L * n * D);
     if (rc != MD_OK) return rc;
     if ((e = hipStreamWaitEvent(st, p->join, 0)) != hipSuccess) return hip_fail(e, "join wait");
-    // coefficient 0 of the next iterate (from M and r_0), then its
-    // factorization, on the second stream beside the rest of this step and
-    // the next evaluation
-    if (s + 1 < count && (rc = factor(1 - k, Ms[k])) != MD_OK) return rc;
     {
+      // N, P, Q and, before the last step, coefficient 0 of the next iterate
+      // (from M and r_0; x is updated later in this stream)
       Timed t(MD_CLASS_GEMM, st);
-      if ((e = mdk::launch_gemm(L, n, Ms[k], At + nn, nn * D, N, mdk::stages_products(L, n, D), st)) != hipSuccess)
-        return hip_fail(e, "gemm");
+      e = (s + 1 < count)
+              ? mdk::launch_gemm_next_x0(L, n, D, Ms[k], At + nn, nn * D, N, mdk::stages_products(L, n, D), r, x, xn, st)
+              : mdk::launch_gemm(L, n, Ms[k], At + nn, nn * D, N, mdk::stages_products(L, n, D), st);
+      if (e != hipSuccess) return hip_fail(e, "gemm");
     }
+    // the next factorization on the second stream, beside the rest of this
+    // step and the next evaluation
+    if (s + 1 < count && (rc = factor(1 - k)) != MD_OK) return rc;
     {
       Timed t(MD_CLASS_UPDATES, st);
       if ((e = mdk::launch_stages(L, n, D, Ms[k], N, At, r, dxT, sync, dev_status, st, true)) != hipSuccess)
@@ -728,9 +724,6 @@ static int newton_steps_impl(const md_plan *p, int count, const double *cff, con
     }
     {
       Timed t(MD_CLASS_X_UPDATE, st);
-      // x_0 is read by next_x0_kernel on the second stream: update x after it
-      if (s + 1 < count && (e = hipStreamWaitEvent(st, p->x0done, 0)) != hipSuccess)
-        return hip_fail(e, "x_0 wait");
       if ((e = mdk::launch_finish(L, L, n, D, 0, D, dxT, dx, x, b, dev_norms, dev_status, st)) != hipSuccess)
         return hip_fail(e, "update");
     }

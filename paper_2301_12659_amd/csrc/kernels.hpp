@@ -99,11 +99,12 @@ int stages_products(int L, int n, int D);
 hipError_t launch_stages_sync(int L, int n, int D, int *sync, double *dxT, hipStream_t st);
 hipError_t launch_stages(int L, int n, int D, const double *M, const double *NP, const double *At, double *rT,
                          double *dxT, int *sync, int32_t *status, hipStream_t st, bool sync_ready = false);
-// xn [L][n] = x_0 + M r_0, coefficient 0 of the iterate after a step whose
-// staged solve is the persistent one, bit for bit as that solve and
-// launch_finish form it (rT: the step's coefficient-major right-hand side).
-hipError_t launch_next_x0(int L, int n, int D, const double *M, const double *rT, const double *x, double *xn,
-                          hipStream_t st);
+// launch_gemm (count products) and, in the same launch, xn [L][n] = x_0 +
+// M r_0: coefficient 0 of the iterate after a step whose staged solve is the
+// persistent one, bit for bit as that solve and launch_finish form it (rT:
+// the step's coefficient-major right-hand side).
+hipError_t launch_gemm_next_x0(int L, int n, int D, const double *M, const double *B, size_t b_ls, double *N,
+                               int count, const double *rT, const double *x, double *xn, hipStream_t st);
 // x_k += dx_k for lo <= k < hi; norms[2][D]: max |b_k| for k < hi and
 // max |dx_k| for lo <= k < hi, zero elsewhere; with tsz ([n][D] term sizes
 // from the assembly) rel[k] = max_i |b_{i,k}| / tsz[i][k] for k < hi, zero

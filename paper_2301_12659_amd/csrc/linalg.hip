@@ -829,14 +829,13 @@ __global__ void __launch_bounds__(256) transpose_kernel(const double *in, double
 }
 
 // N = M B for dense n x n matrices (B with limb stride b_ls); teams of 16
-// lanes per output entry, level-sum accumulation.
+// lanes per output entry, level-sum accumulation.  Product y: B + y n^2 (the
+// next series coefficient) into N + y L n^2.
 template <int L>
-__global__ void __launch_bounds__(256) gemm_kernel(int n, const double *M, const double *B, size_t b_ls, double *N) {
+__device__ __forceinline__ void gemm_block(int n, const double *M, const double *B, size_t b_ls, double *N, int y) {
   const int T = 16;
-  // blockIdx.y selects the product: B + y n^2 (the next series coefficient)
-  // into N + y L n^2
-  B += (size_t)blockIdx.y * n * n;
-  N += (size_t)blockIdx.y * L * n * n;
+  B += (size_t)y * n * n;
+  N += (size_t)y * L * n * n;
   const size_t task = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) / T;
   const int tl = threadIdx.x & (T - 1);
   const size_t nn = (size_t)n * n;
@@ -854,6 +853,11 @@ __global__ void __launch_bounds__(256) gemm_kernel(int n, const double *M, const
   team_sum_lazy<L>(acc, T);
   MD<L>::renorm(acc, r);
   if (live && tl == 0) st<L>(N, nn, (size_t)i * n + j, r);
+}
+
+template <int L>
+__global__ void __launch_bounds__(256) gemm_kernel(int n, const double *M, const double *B, size_t b_ls, double *N) {
+  gemm_block<L>(n, M, B, b_ls, N, blockIdx.y);
 }
 
 // One stage k of the block Toeplitz solve (see the file comment), on
@@ -939,11 +943,11 @@ __device__ __forceinline__ bool wait_geq(const int *ctr, int target, int32_t *st
 // sums, one 64-lane butterfly of level sums, one renormalization (the first
 // stage of stages_persistent_kernel), then the addition of finish_kernel.
 // The result is therefore the x_0 that the next step reads, bit for bit,
-// available before the staged solve has run; xn [L][n].  The two kernels
-// must keep these operations in step.
+// available before the staged solve has run; xn [L][n].  This and the two
+// kernels must keep these operations in step.
 template <int L>
-__global__ void __launch_bounds__(256) next_x0_kernel(int n, int D, const double *M, const double *rT,
-                                                      const double *x, double *xn) {
+__device__ __forceinline__ void next_x0_block(int n, int D, const double *M, const double *rT, const double *x,
+                                              double *xn) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int i = blockIdx.x * 4 + wv;
   const bool row = i < n, col = lane < n;
@@ -964,6 +968,20 @@ __global__ void __launch_bounds__(256) next_x0_kernel(int n, int D, const double
     ld<L>(x, nD, (size_t)i * D, a);
     MD<L>::add(a, r, sum);
     st<L>(xn, n, i, sum);
+  }
+}
+
+// The products of gemm_kernel (blockIdx.y < gridDim.y - 1) and, in the last
+// row of blocks, coefficient 0 of the next iterate (next_x0_block): one
+// launch where the caller's stream has both ready (M and r_0), so that the
+// update of x later in that stream comes after every read of x_0.
+template <int L>
+__global__ void __launch_bounds__(256) gemm_next_x0_kernel(int n, int D, const double *M, const double *B, size_t b_ls,
+                                                           double *N, const double *rT, const double *x, double *xn) {
+  if (blockIdx.y + 1 < gridDim.y) {
+    gemm_block<L>(n, M, B, b_ls, N, blockIdx.y);
+  } else if ((int)blockIdx.x * 4 < n) {
+    next_x0_block<L>(n, D, M, rT, x, xn);
   }
 }
 
@@ -1696,14 +1714,16 @@ hipError_t launch_stages(int L, int n, int D, const double *M, const double *NP,
   return hipGetLastError();
 }
 
-hipError_t launch_next_x0(int L, int n, int D, const double *M, const double *rT, const double *x, double *xn,
-                          hipStream_t st) {
-  if (!stages_persistent(L, n, D)) return hipErrorInvalidValue;
-  const dim3 grid((n + 3) / 4), block(256);
+hipError_t launch_gemm_next_x0(int L, int n, int D, const double *M, const double *B, size_t b_ls, double *N,
+                               int count, const double *rT, const double *x, double *xn, hipStream_t st) {
+  if (!stages_persistent(L, n, D) || count < 0) return hipErrorInvalidValue;
+  const size_t threads = (size_t)n * n * 16;
+  const unsigned bx = (unsigned)std::max<size_t>((threads + 255) / 256, (size_t)(n + 3) / 4);
+  const dim3 grid(bx, count + 1), block(256);
   if (L == 2)
-    hipLaunchKernelGGL(next_x0_kernel<2>, grid, block, 0, st, n, D, M, rT, x, xn);
+    hipLaunchKernelGGL(gemm_next_x0_kernel<2>, grid, block, 0, st, n, D, M, B, b_ls, N, rT, x, xn);
   else
-    hipLaunchKernelGGL(next_x0_kernel<4>, grid, block, 0, st, n, D, M, rT, x, xn);
+    hipLaunchKernelGGL(gemm_next_x0_kernel<4>, grid, block, 0, st, n, D, M, B, b_ls, N, rT, x, xn);
   return hipGetLastError();
 }
 
