@@ -28,11 +28,11 @@ namespace mdk {
 // counters and dx slots, for the solve the caller launches next on this
 // stream).
 template <int L>
-__global__ void __launch_bounds__(256) assemble_b_kernel(int n, int D, int Dc, int m, const int32_t *poly_ptr,
-                                                         const double *cst, const double *val, double *b, double *tsz,
-                                                         const double *vsize, TOut rt, int *clear, int clear_count,
-                                                         double *empty, size_t empty_count) {
-  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void assemble_b_block(unsigned bid, int n, int D, int Dc, int m, const int32_t *poly_ptr,
+                                                 const double *cst, const double *val, double *b, double *tsz,
+                                                 const double *vsize, TOut rt, int *clear, int clear_count,
+                                                 double *empty, size_t empty_count) {
+  const size_t t = (size_t)bid * blockDim.x + threadIdx.x;
   if (clear && t < (size_t)clear_count) clear[t] = 0;
   if (empty && t < empty_count) empty[t] = __longlong_as_double(SLOT_EMPTY);
   const size_t nD = (size_t)n * D, mD = (size_t)m * D;
@@ -94,6 +94,15 @@ __global__ void __launch_bounds__(256) assemble_b_kernel(int n, int D, int Dc, i
   }
 }
 
+template <int L>
+__global__ void __launch_bounds__(256) assemble_b_kernel(int n, int D, int Dc, int m, const int32_t *poly_ptr,
+                                                         const double *cst, const double *val, double *b, double *tsz,
+                                                         const double *vsize, TOut rt, int *clear, int clear_count,
+                                                         double *empty, size_t empty_count) {
+  assemble_b_block<L>(blockIdx.x, n, D, Dc, m, poly_ptr, cst, val, b, tsz, vsize, rt, clear, clear_count, empty,
+                      empty_count);
+}
+
 // A[i][j][s] = sum of the derivative series of row i's monomials with respect
 // to x_j, in monomial order, for the first Dc coefficients s.  A workgroup
 // takes TI consecutive (i, j) and all Dc coefficients (reads and the
@@ -105,12 +114,11 @@ __global__ void __launch_bounds__(256) assemble_b_kernel(int n, int D, int Dc, i
 __host__ __device__ constexpr int asm_a_max_slices(int L) { return L >= 8 ? 2 : (L == 4 ? 4 : 8); }
 
 template <int L, int TI>
-__global__ void __launch_bounds__(256) assemble_A_kernel(int n, int D, int Dc, int nnz, const int32_t *asm_ptr,
-                                                         const int32_t *asm_ent, const double *der, double *A,
-                                                         TOut at) {
-  extern __shared__ double tile[];  // [L][TI][Dc + 1]
+__device__ __forceinline__ void assemble_A_block(unsigned bid, int n, int D, int Dc, int nnz, const int32_t *asm_ptr,
+                                                 const int32_t *asm_ent, const double *der, double *A, TOut at,
+                                                 double *tile /* [L][TI][Dc + 1] */) {
   const size_t nn = (size_t)n * n, nnD = nn * D, zD = (size_t)nnz * D;
-  const size_t ij0 = (size_t)blockIdx.x * TI;
+  const size_t ij0 = (size_t)bid * TI;
   const int Dp = Dc + 1;
   // blockDim / TI threads per (i, j), each the coefficients s = sl + u per,
   // u < NS (at most asm_a_max_slices(L)): the entry list is read once, and the
@@ -166,6 +174,33 @@ __global__ void __launch_bounds__(256) assemble_A_kernel(int n, int D, int Dc, i
     if (ij >= nn) continue;
     for (int l = 0; l < at.L; ++l) at.p[(size_t)l * ls + (size_t)s * nn + ij] = tile[(l * TI + il) * Dp + s];
   }
+}
+
+template <int L, int TI>
+__global__ void __launch_bounds__(256) assemble_A_kernel(int n, int D, int Dc, int nnz, const int32_t *asm_ptr,
+                                                         const int32_t *asm_ent, const double *der, double *A,
+                                                         TOut at) {
+  extern __shared__ double tile[];
+  assemble_A_block<L, TI>(blockIdx.x, n, D, Dc, nnz, asm_ptr, asm_ent, der, A, at, tile);
+}
+
+// Both assemblies in one launch: workgroups 0 .. GA - 1 form A (as
+// assemble_A_kernel), the others b (as assemble_b_kernel); they read disjoint
+// inputs and write disjoint outputs.
+template <int L, int TI>
+__global__ void __launch_bounds__(256) assemble_bA_kernel(unsigned GA, int n, int D, int Dc, int m, int nnz,
+                                                          const int32_t *poly_ptr, const int32_t *asm_ptr,
+                                                          const int32_t *asm_ent, const double *cst,
+                                                          const double *val, const double *der, double *b,
+                                                          double *A, double *tsz, const double *vsize, TOut rt,
+                                                          TOut at, int *clear, int clear_count, double *empty,
+                                                          size_t empty_count) {
+  extern __shared__ double tile[];
+  if (blockIdx.x < GA)
+    assemble_A_block<L, TI>(blockIdx.x, n, D, Dc, nnz, asm_ptr, asm_ent, der, A, at, tile);
+  else
+    assemble_b_block<L>(blockIdx.x - GA, n, D, Dc, m, poly_ptr, cst, val, b, tsz, vsize, rt, clear, clear_count,
+                        empty, empty_count);
 }
 
 // Coefficient 0 of A into a dense row-major matrix a0 [L][n][n], summed in
@@ -256,10 +291,29 @@ hipError_t launch_assemble(int L, int n, int D, int Dc, int m, int nnz, const in
                            const double *der, double *b, double *A, hipStream_t st, double *tsz,
                            const double *vsize, TOut rt, TOut at, int *clear, int clear_count, double *empty,
                            size_t empty_count) {
-  hipError_t e = launch_assemble_b(L, n, D, Dc, m, poly_ptr, cst, val, b, st, tsz, vsize, rt, clear, clear_count, empty,
-                                   empty_count);
-  if (e != hipSuccess) return e;
-  return launch_assemble_A(L, n, D, Dc, nnz, asm_ptr, asm_ent, der, A, st, at);
+  if (Dc < 1 || Dc > D) return hipErrorInvalidValue;
+  if (rt.p && (rt.lo < 0 || rt.W < 1 || rt.lo + rt.W > Dc || rt.L < 1 || rt.L > L)) return hipErrorInvalidValue;
+  if (at.p && (at.lo != 0 || at.W < 1 || at.W > Dc || at.L < 1 || at.L > L)) return hipErrorInvalidValue;
+  const size_t nn = (size_t)n * n;
+  const int ti = assemble_tile(L, Dc);
+  if ((Dc + 256 / ti - 1) / (256 / ti) > asm_a_max_slices(L)) return hipErrorInvalidValue;
+  const size_t lds = at.p ? (size_t)ti * (Dc + 1) * L * sizeof(double) : 0;
+  const unsigned GA = (unsigned)((nn + ti - 1) / ti);
+  const size_t bthreads = std::max({(size_t)n * Dc * 4, (size_t)(clear ? clear_count : 0), empty ? empty_count : 0});
+  const dim3 grid(GA + (unsigned)((bthreads + 255) / 256));
+#define MD_ASM_BA(TI)                                                                                             \
+  MD_DISPATCH(L, hipLaunchKernelGGL((assemble_bA_kernel<LL, TI>), grid, dim3(256), lds, st, GA, n, D, Dc, m, nnz, \
+                                    poly_ptr, asm_ptr, asm_ent, cst, val, der, b, A, tsz, vsize, rt, at, clear,   \
+                                    clear_count, empty, empty_count))
+  switch (ti) {
+    case 16: MD_ASM_BA(16); break;
+    case 8: MD_ASM_BA(8); break;
+    case 4: MD_ASM_BA(4); break;
+    case 2: MD_ASM_BA(2); break;
+    default: MD_ASM_BA(1); break;
+  }
+#undef MD_ASM_BA
+  return hipGetLastError();
 }
 
 }  // namespace mdk
