@@ -210,6 +210,7 @@ __global__ void __launch_bounds__(256) assemble_bA_kernel(unsigned GA, int n, in
 template <int L>
 __global__ void assemble_A0_kernel(int n, int D, int nnz, const int32_t *asm_ptr, const int32_t *asm_ent,
                                    const double *der, double *a0, QrPrep prep) {
+  __builtin_amdgcn_s_setprio(3);  // on the factorization's chain, as the pre-pass
   const size_t ij = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   qr_prep_item(prep, ij);
   const size_t nn = (size_t)n * n, zD = (size_t)nnz * D;

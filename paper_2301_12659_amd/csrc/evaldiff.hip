@@ -211,6 +211,9 @@ constexpr int EVAL0_MAXK = 8;
 
 template <int L>
 __global__ void __launch_bounds__(256) evaldiff0_kernel(EvalArgs a) {
+  // it opens the factorization's chain, which runs beside the staged solve
+  // and the evaluation: the highest issue priority on a shared CU
+  __builtin_amdgcn_s_setprio(3);
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   // the step's status word, reset by its first launch (every launch that can
   // report into it comes later in stream order; no evaluation kernel does)
