@@ -31,8 +31,12 @@ __device__ void conv(const double *U, const double *V, double *W, int D, int lan
   const int o1 = p, o2 = D - 1 - p;
   const int H = (D + S) / S;  // terms per half: ceil((D + 1) / S)
   const int t0 = h * H;
-  double acc0[L];
+  // acc0 accumulates the current output; the first one's level sums are
+  // parked in acc1 when its last term is in (a different iteration in
+  // every lane) and renormalized after the loop, by all lanes together
+  double acc0[L], acc1[L];
   md::zero<L>(acc0);
+  md::zero<L>(acc1);
   // term t multiplies u_i v_j with i + j = o1 for t <= o1 and i + j = o2
   // after (i = t - o1 - 1); masked terms read the zero padding (entry D)
   int i, j;
@@ -67,15 +71,16 @@ __device__ void conv(const double *U, const double *V, double *W, int D, int lan
     }
     MD<L>::fma_lazy(acc0, u, v);
     if (t == o1) {  // first output complete (always in the first half)
-      if (act) {
-        double r[L];
-        MD<L>::renorm(acc0, r);
-        md::mul_int<L>(r, scale);
-#pragma unroll
-        for (int l = 0; l < L; ++l) W[l * Dp + o1] = r[l];
-      }
+      md::copy<L>(acc0, acc1);
       md::zero<L>(acc0);
     }
+  }
+  if (h == 0 && act) {
+    double r[L];
+    MD<L>::renorm(acc1, r);
+    md::mul_int<L>(r, scale);
+#pragma unroll
+    for (int l = 0; l < L; ++l) W[l * Dp + o1] = r[l];
   }
   if (S == 2) {  // add the second half's part of the second output, still as level sums
     double o[L];
