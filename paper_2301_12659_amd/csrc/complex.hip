@@ -50,8 +50,11 @@ __device__ void conv_c(const double *U, const double *V, double *W, int D, int l
   const int o1 = p, o2 = D - 1 - p;
   const int H = (D + S) / S;
   const int t0 = h * H;
-  double acc0[L];
+  // the first output's level sums are parked in acc1 when its last term is
+  // in and renormalized after the loop by all lanes together
+  double acc0[L], acc1[L];
   md::zero<L>(acc0);
+  md::zero<L>(acc1);
   for (int tt = 0; tt < H; ++tt) {
     const int t = t0 + tt;
     const bool ph1 = t <= o1;
@@ -75,15 +78,16 @@ __device__ void conv_c(const double *U, const double *V, double *W, int D, int l
     }
     MD<L>::fma_lazy(acc0, u, v);
     if (t == o1) {
-      if (act) {
-        double r[L];
-        MD<L>::renorm(acc0, r);
-        md::mul_int<L>(r, scale);
-#pragma unroll
-        for (int l = 0; l < L; ++l) Wp[l * Dp + o1] = r[l];
-      }
+      md::copy<L>(acc0, acc1);
       md::zero<L>(acc0);
     }
+  }
+  if (h == 0 && act) {
+    double r[L];
+    MD<L>::renorm(acc1, r);
+    md::mul_int<L>(r, scale);
+#pragma unroll
+    for (int l = 0; l < L; ++l) Wp[l * Dp + o1] = r[l];
   }
   if (S == 2) {  // lanes p and p + G2 of the same part hold the two halves
     double o[L];
