@@ -90,6 +90,7 @@ struct Layout {
   // next step, computed while the current one finishes), coefficient 0 of
   // the next iterate and the derivative products of its pre-pass
   size_t qr2, tau2, qt2, M2, xn, der0;
+  size_t xseq;  // count of xn's workgroups done (md_newton_steps)
   size_t total;
 };
 
@@ -129,6 +130,7 @@ Layout newton_layout(const md_plan *p) {
   w.M2 = take(L * n * n);
   w.xn = take(L * n);
   w.der0 = take(L * p->nnz + 1);
+  w.xseq = take(1);
   w.total = off;
   return w;
 }
@@ -653,7 +655,8 @@ static int newton_steps_impl(const md_plan *p, int count, const double *cff, con
   const int L = p->L, n = p->n, D = p->D;
   const size_t nn = (size_t)n * n;
   hipError_t e;
-  if ((e = mdk::launch_status_init(dev_status, st)) != hipSuccess) return hip_fail(e, "status");
+  int *xseq = reinterpret_cast<int *>(at(ws, w.xseq));
+  if ((e = mdk::launch_status_init(dev_status, st, xseq)) != hipSuccess) return hip_fail(e, "status");
   double *b = at(ws, w.b), *A = at(ws, w.A), *r = at(ws, w.r), *dx = at(ws, w.dx), *N = at(ws, w.N);
   double *At = at(ws, w.At), *dxT = at(ws, w.dxT), *invd = at(ws, w.invd), *xn = at(ws, w.xn);
   double *qrs[2] = {at(ws, w.qr), at(ws, w.qr2)}, *taus[2] = {at(ws, w.tau), at(ws, w.tau2)};
@@ -662,19 +665,29 @@ static int newton_steps_impl(const md_plan *p, int count, const double *cff, con
   // factorization of the iterate whose coefficient 0 is in xn ([L][n]) into
   // buffer set k, on the second stream after the fork event; its pre-pass
   // has derivative products of its own (der0), since the evaluation of the
-  // current step runs beside it.  xn was formed on the caller's stream
-  // before the fork (the first iterate's by a copy, the next ones' with the
-  // products N, P, Q in one launch).
-  auto factor = [&](int k) -> int {
-    if ((e = hipEventRecord(p->fork, st)) != hipSuccess) return hip_fail(e, "fork");
-    if ((e = hipStreamWaitEvent(p->aux, p->fork, 0)) != hipSuccess) return hip_fail(e, "fork wait");
+  // current step runs beside it.  The first iterate's xn is a copy made on
+  // the caller's stream before a fork event; the next ones' are formed by
+  // the launch of the products N, P, Q, whose xn workgroups count themselves
+  // done in xseq (xseq_target: the count to wait for, 0: the fork event), so
+  // that no event sits between that launch and the staged solve.
+  auto factor = [&](int k, int xseq_target) -> int {
+    if (xseq_target == 0) {
+      if ((e = hipEventRecord(p->fork, st)) != hipSuccess) return hip_fail(e, "fork");
+      if ((e = hipStreamWaitEvent(p->aux, p->fork, 0)) != hipSuccess) return hip_fail(e, "fork wait");
+    }
     {
-      Timed t(MD_CLASS_QR, p->aux);
       mdk::EvalArgs a;
       eval_args(p, cff, xn, ws, 1, a);
       a.D = 1;  // one coefficient per series: xn and der0 [L][nnz]
       a.der = at(ws, w.der0);
+      if (xseq_target > 0) {
+        a.wait_ctr = xseq;
+        a.wait_target = xseq_target;
+        a.wait_status = dev_status;
+      }
+      // the pre-pass is left out of the class timing: it may wait for xn
       if ((e = mdk::launch_evaldiff0(L, a, p->aux)) != hipSuccess) return hip_fail(e, "A_0 pre-pass");
+      Timed t(MD_CLASS_QR, p->aux);
       // (the A_0 assembly also prepares the QR's hand-over memory)
       if ((e = mdk::launch_assemble_A0(L, n, 1, p->nnz, p->d_asm_ptr, p->d_asm_ent, a.der, qrs[k], p->aux,
                                        qr_prep(L, n, at(ws, w.bar)))) != hipSuccess)
@@ -693,7 +706,7 @@ static int newton_steps_impl(const md_plan *p, int count, const double *cff, con
   // coefficient 0 of the first iterate into xn
   if ((e = mdk::launch_transpose_ld(L, x, D, xn, n, n, 1, (size_t)n * D, n, st)) != hipSuccess)
     return hip_fail(e, "x_0");
-  int rc = factor((count - 1) % 2);
+  int rc = factor((count - 1) % 2, 0);
   if (rc != MD_OK) return rc;
   for (int s = 0; s < count; ++s) {
     const int k = (count - 1 - s) % 2;
@@ -710,13 +723,14 @@ static int newton_steps_impl(const md_plan *p, int count, const double *cff, con
       // (from M and r_0; x is updated later in this stream)
       Timed t(MD_CLASS_GEMM, st);
       e = (s + 1 < count)
-              ? mdk::launch_gemm_next_x0(L, n, D, Ms[k], At + nn, nn * D, N, mdk::stages_products(L, n, D), r, x, xn, st)
+              ? mdk::launch_gemm_next_x0(L, n, D, Ms[k], At + nn, nn * D, N, mdk::stages_products(L, n, D), r, x, xn,
+                                         xseq, st)
               : mdk::launch_gemm(L, n, Ms[k], At + nn, nn * D, N, mdk::stages_products(L, n, D), st);
       if (e != hipSuccess) return hip_fail(e, "gemm");
     }
     // the next factorization on the second stream, beside the rest of this
     // step and the next evaluation
-    if (s + 1 < count && (rc = factor(1 - k)) != MD_OK) return rc;
+    if (s + 1 < count && (rc = factor(1 - k, ((n + 3) / 4) * (s + 1))) != MD_OK) return rc;
     {
       Timed t(MD_CLASS_UPDATES, st);
       if ((e = mdk::launch_stages(L, n, D, Ms[k], N, At, r, dxT, sync, dev_status, st, true)) != hipSuccess)

@@ -15,6 +15,13 @@ struct EvalArgs {
   double *vsize = nullptr;     // [m][D], nullable: max_j |f_j| over each monomial's forward chain (leading limbs)
   int beside_qr = 0;           // 1: runs beside the QR (one wavefront per monomial, more issue slots for the QR)
   int32_t *reset_status = nullptr;  // coefficient-0 kernel: its first thread sets this status word to MD_OK
+  // coefficient-0 kernel: x is written by a launch on another stream, which
+  // adds one to *wait_ctr per workgroup once its stores are performed; wait
+  // until it reaches wait_target (bounded: MD_EHIP into wait_status), then
+  // read x at the device's point of coherence
+  const int *wait_ctr = nullptr;
+  int wait_target = 0;
+  int32_t *wait_status = nullptr;
 };
 
 }  // namespace mdk

@@ -218,6 +218,23 @@ __global__ void __launch_bounds__(256) evaldiff0_kernel(EvalArgs a) {
   // the step's status word, reset by its first launch (every launch that can
   // report into it comes later in stream order; no evaluation kernel does)
   if (t == 0 && a.reset_status) *a.reset_status = MD_OK;
+  if (a.wait_ctr) {
+    __shared__ int ok;
+    if (threadIdx.x == 0) {
+      long spins = 0;
+      ok = 1;
+      while (__hip_atomic_load(a.wait_ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < a.wait_target) {
+        __builtin_amdgcn_s_sleep(2);
+        if (++spins > (1L << 22)) {
+          set_status(a.wait_status, MD_EHIP);
+          ok = 0;
+          break;
+        }
+      }
+    }
+    __syncthreads();
+    if (!ok) return;
+  }
   if (t >= a.m) return;
   const int mono = t;
   const int e0 = a.mon_ptr[mono], k = a.mon_ptr[mono + 1] - e0;
@@ -230,7 +247,8 @@ __global__ void __launch_bounds__(256) evaldiff0_kernel(EvalArgs a) {
     md::zero<L>(xs[j]);
     ex[j] = 1;
     if (j < k) {
-      ld<L>(a.x, nD, (size_t)a.var[e0 + j] * a.D, xs[j]);
+      if (a.wait_ctr) ld_agent<L>(a.x, nD, (size_t)a.var[e0 + j] * a.D, xs[j]);
+      else ld<L>(a.x, nD, (size_t)a.var[e0 + j] * a.D, xs[j]);
       ex[j] = a.exp[e0 + j];
     }
   }

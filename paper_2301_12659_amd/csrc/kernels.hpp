@@ -67,7 +67,7 @@ hipError_t launch_assemble_A0(int L, int n, int D, int nnz, const int32_t *asm_p
                               const double *der, double *a0, hipStream_t st, QrPrep prep);
 
 // linalg.hip
-hipError_t launch_status_init(int32_t *status, hipStream_t st);
+hipError_t launch_status_init(int32_t *status, hipStream_t st, int *counter = nullptr);  // and *counter = 0
 hipError_t launch_qr(int L, int n, double *a, double *tau, double *qt, int32_t *status, unsigned *bar,
                      hipStream_t st);
 int qr_lds_workgroups(int L, int n, bool with_qt);
@@ -104,7 +104,7 @@ hipError_t launch_stages(int L, int n, int D, const double *M, const double *NP,
 // persistent one, bit for bit as that solve and launch_finish form it (rT:
 // the step's coefficient-major right-hand side).
 hipError_t launch_gemm_next_x0(int L, int n, int D, const double *M, const double *B, size_t b_ls, double *N,
-                               int count, const double *rT, const double *x, double *xn, hipStream_t st);
+                               int count, const double *rT, const double *x, double *xn, int *done, hipStream_t st);
 // x_k += dx_k for lo <= k < hi; norms[2][D]: max |b_k| for k < hi and
 // max |dx_k| for lo <= k < hi, zero elsewhere; with tsz ([n][D] term sizes
 // from the assembly) rel[k] = max_i |b_{i,k}| / tsz[i][k] for k < hi, zero

@@ -26,8 +26,9 @@ namespace mdk {
 
 // ----------------------------------------------------------------- status
 
-__global__ void status_init_kernel(int32_t *status) {
+__global__ void status_init_kernel(int32_t *status, int *counter) {
   if (threadIdx.x == 0 && blockIdx.x == 0 && status) *status = MD_OK;
+  if (threadIdx.x == 0 && blockIdx.x == 0 && counter) *counter = 0;
 }
 
 // ----------------------------------------------------------------- QR
@@ -947,7 +948,7 @@ __device__ __forceinline__ bool wait_geq(const int *ctr, int target, int32_t *st
 // kernels must keep these operations in step.
 template <int L>
 __device__ __forceinline__ void next_x0_block(int n, int D, const double *M, const double *rT, const double *x,
-                                              double *xn) {
+                                              double *xn, int *done) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int i = blockIdx.x * 4 + wv;
   const bool row = i < n, col = lane < n;
@@ -967,21 +968,31 @@ __device__ __forceinline__ void next_x0_block(int n, int D, const double *M, con
     double a[L], sum[L];
     ld<L>(x, nD, (size_t)i * D, a);
     MD<L>::add(a, r, sum);
-    st<L>(xn, n, i, sum);
+    if (done) st_agent<L>(xn, n, i, sum);
+    else st<L>(xn, n, i, sum);
+  }
+  if (done) {  // a reader on another stream polls *done (one count per workgroup)
+    wait_vm();
+    __syncthreads();
+    if (tid == 0) __hip_atomic_fetch_add(done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
 // The products of gemm_kernel (blockIdx.y < gridDim.y - 1) and, in the last
 // row of blocks, coefficient 0 of the next iterate (next_x0_block): one
 // launch where the caller's stream has both ready (M and r_0), so that the
-// update of x later in that stream comes after every read of x_0.
+// update of x later in that stream comes after every read of x_0.  done
+// (nullable): each of the ceil(n / 4) workgroups of xn adds one to it once
+// its stores are performed, for the factorization that waits for xn on the
+// second stream.
 template <int L>
 __global__ void __launch_bounds__(256) gemm_next_x0_kernel(int n, int D, const double *M, const double *B, size_t b_ls,
-                                                           double *N, const double *rT, const double *x, double *xn) {
+                                                           double *N, const double *rT, const double *x, double *xn,
+                                                           int *done) {
   if (blockIdx.y + 1 < gridDim.y) {
     gemm_block<L>(n, M, B, b_ls, N, blockIdx.y);
   } else if ((int)blockIdx.x * 4 < n) {
-    next_x0_block<L>(n, D, M, rT, x, xn);
+    next_x0_block<L>(n, D, M, rT, x, xn, done);
   }
 }
 
@@ -1510,8 +1521,8 @@ __global__ void __launch_bounds__(256) arith_kernel(int op, int64_t count, const
 
 // ------------------------------------------------------------------ launchers
 
-hipError_t launch_status_init(int32_t *status, hipStream_t st) {
-  hipLaunchKernelGGL(status_init_kernel, dim3(1), dim3(64), 0, st, status);
+hipError_t launch_status_init(int32_t *status, hipStream_t st, int *counter) {
+  hipLaunchKernelGGL(status_init_kernel, dim3(1), dim3(64), 0, st, status, counter);
   return hipGetLastError();
 }
 
@@ -1715,15 +1726,15 @@ hipError_t launch_stages(int L, int n, int D, const double *M, const double *NP,
 }
 
 hipError_t launch_gemm_next_x0(int L, int n, int D, const double *M, const double *B, size_t b_ls, double *N,
-                               int count, const double *rT, const double *x, double *xn, hipStream_t st) {
+                               int count, const double *rT, const double *x, double *xn, int *done, hipStream_t st) {
   if (!stages_persistent(L, n, D) || count < 0) return hipErrorInvalidValue;
   const size_t threads = (size_t)n * n * 16;
   const unsigned bx = (unsigned)std::max<size_t>((threads + 255) / 256, (size_t)(n + 3) / 4);
   const dim3 grid(bx, count + 1), block(256);
   if (L == 2)
-    hipLaunchKernelGGL(gemm_next_x0_kernel<2>, grid, block, 0, st, n, D, M, B, b_ls, N, rT, x, xn);
+    hipLaunchKernelGGL(gemm_next_x0_kernel<2>, grid, block, 0, st, n, D, M, B, b_ls, N, rT, x, xn, done);
   else
-    hipLaunchKernelGGL(gemm_next_x0_kernel<4>, grid, block, 0, st, n, D, M, B, b_ls, N, rT, x, xn);
+    hipLaunchKernelGGL(gemm_next_x0_kernel<4>, grid, block, 0, st, n, D, M, B, b_ls, N, rT, x, xn, done);
   return hipGetLastError();
 }
 
