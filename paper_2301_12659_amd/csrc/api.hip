@@ -91,6 +91,7 @@ struct Layout {
   // the next iterate and the derivative products of its pre-pass
   size_t qr2, tau2, qt2, M2, xn, der0;
   size_t xseq;  // count of xn's workgroups done (md_newton_steps)
+  size_t rs;    // rows of R scaled by their diagonal (back substitution of M)
   size_t total;
 };
 
@@ -131,6 +132,7 @@ Layout newton_layout(const md_plan *p) {
   w.xn = take(L * n);
   w.der0 = take(L * p->nnz + 1);
   w.xseq = take(1);
+  w.rs = take(L * n * n);
   w.total = off;
   return w;
 }
@@ -548,7 +550,7 @@ static int newton_step_impl(const md_plan *p, int Ls, int lo, int hi, bool keep_
     }
     {
       Timed t(MD_CLASS_QHB_BS, p->aux);
-      if ((e = mdk::launch_m_from_qt(Ls, n, qr, qt, invd, M, dev_status, p->aux)) != hipSuccess)
+      if ((e = mdk::launch_m_from_qt(Ls, n, qr, qt, invd, M, dev_status, p->aux, at(ws, w.rs))) != hipSuccess)
         return hip_fail(e, "M");
     }
     if ((e = hipEventRecord(p->join, p->aux)) != hipSuccess) return hip_fail(e, "join");
@@ -697,7 +699,8 @@ static int newton_steps_impl(const md_plan *p, int count, const double *cff, con
     }
     {
       Timed t(MD_CLASS_QHB_BS, p->aux);
-      if ((e = mdk::launch_m_from_qt(L, n, qrs[k], qts[k], invd, Ms[k], dev_status, p->aux)) != hipSuccess)
+      if ((e = mdk::launch_m_from_qt(L, n, qrs[k], qts[k], invd, Ms[k], dev_status, p->aux, at(ws, w.rs))) !=
+          hipSuccess)
         return hip_fail(e, "M");
     }
     if ((e = hipEventRecord(p->join, p->aux)) != hipSuccess) return hip_fail(e, "join");

@@ -75,8 +75,10 @@ int qr_lds_workgroups(int L, int n, bool with_qt);
 // launch on st (QrPrep).
 hipError_t launch_qr_lds(int L, int n, double *a, double *tau, double *qt, int32_t *status, int *flags,
                          double *vboard, double *tboard, hipStream_t st, bool prepared = false);
+// rs (nullable): L n n doubles of scratch for the rows of R scaled by their
+// diagonal (n <= 64: a back substitution whose steps have no division)
 hipError_t launch_m_from_qt(int L, int n, const double *qr, const double *qt, double *invd, double *M,
-                            int32_t *status, hipStream_t st);
+                            int32_t *status, hipStream_t st, double *rs = nullptr);
 hipError_t launch_form_m(int L, int n, const double *qr, const double *tau, double *invd, double *M, int32_t *status,
                          hipStream_t st);
 hipError_t launch_extract(int L, int n, int D, int k, const double *A, double *out, hipStream_t st);

@@ -730,15 +730,49 @@ __device__ __forceinline__ double read_lane(double x, int i) {
   return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
-// Column c of M = R^{-1} Q^T for n <= 64, one wavefront per column with
-// row p in lane p.  The reciprocals 1/R_ii are formed here (lane i; the
-// singularity test of invdiag_kernel, reported by workgroup 0) and kept in
-// the lane's registers, the columns of R are loaded four steps before they
-// are used, so that no step waits for device memory, and z_i reaches the
-// other lanes by lane reads (no LDS round trip on the chain).
+// The rows of R scaled by their diagonal entries, for the back substitution
+// of M: dq[p] = 1 / R_pp and rs(p, j) = R_pj / R_pp for j > p ([L][n][n],
+// row-major), one wavefront per row p.  A diagonal entry below n 2^(-53 L)
+// times the largest one (leading limbs) means A_0 is singular to working
+// precision: MD_ESINGULAR, and the row's 1 / R_pp is zero.
 template <int L>
-__global__ void __launch_bounds__(64, 1) m_from_qt_small_kernel(int n, const double *qr, const double *qt, double *M,
-                                                             int32_t *status) {
+__global__ void __launch_bounds__(64) rscale_kernel(int n, const double *qr, double *rs, double *dq, int32_t *status) {
+  const int p = blockIdx.x, lane = threadIdx.x;
+  const size_t nn = (size_t)n * n;
+  double rmax = 0.0;
+  for (int j = lane; j < n; j += 64) {
+    double d[L];
+    ld<L>(qr, nn, (size_t)j * n + j, d);
+    rmax = fmax(rmax, fabs(d[0]));
+  }
+  for (int off = 32; off > 0; off >>= 1) rmax = fmax(rmax, __shfl_xor(rmax, off, 64));
+  double rpp[L], d[L];
+  ld<L>(qr, nn, (size_t)p * n + p, rpp);
+  const bool sing = !(fabs(rpp[0]) > ldexp((double)n, -53 * L) * rmax);
+  if (sing) md::zero<L>(d);
+  else md::recip_newton<L>(rpp, d);
+  if (lane == 0) {
+    st<L>(dq, n, p, d);
+    if (sing) set_status(status, MD_ESINGULAR);
+  }
+  for (int j = p + 1 + lane; j < n; j += 64) {
+    double r[L], q[L];
+    ld<L>(qr, nn, (size_t)p * n + j, r);
+    MD<L>::mul(r, d, q);
+    st<L>(rs, nn, (size_t)p * n + j, q);
+  }
+}
+
+// Column c of M = R^{-1} Q^T for n <= 64, one wavefront per column with
+// row p in lane p, on the scaled rows of rscale_kernel: with y~_p = y_p / R_pp
+// and R~_pi = R_pi / R_pp, back substitution takes z_i = y~_i and then
+// y~_p -= R~_pi z_i for p < i, so a step of the dependent chain is one lane
+// read and one multiply-add.  The columns of R~ are loaded four steps before
+// they are used (they were just written by another kernel: their loads come
+// from memory, not the L2).
+template <int L>
+__global__ void __launch_bounds__(64, 1) m_from_qt_small_kernel(int n, const double *rs, const double *dq,
+                                                             const double *qt, double *M) {
   // raised wave priority: the kernel runs beside the evaluation, whose
   // wavefronts fill the CUs (M beside it: 47 against 180 us)
   __builtin_amdgcn_s_setprio(3);
@@ -746,39 +780,30 @@ __global__ void __launch_bounds__(64, 1) m_from_qt_small_kernel(int n, const dou
   const size_t nn = (size_t)n * n;
   const bool on = lane < n;
   const int p = on ? lane : 0;
-  double rpp[L];
-  ld<L>(qr, nn, (size_t)p * n + p, rpp);
-  double rmax = on ? fabs(rpp[0]) : 0.0;
-  for (int off = 32; off > 0; off >>= 1) rmax = fmax(rmax, __shfl_xor(rmax, off, 64));
-  double dq[L];  // 1 / R_pp in lane p
-  {
-    const bool sing = on && !(fabs(rpp[0]) > ldexp((double)n, -53 * L) * rmax);
-    if (sing || !on) md::zero<L>(dq);
-    else md::recip_newton<L>(rpp, dq);
-    if (sing && c == 0) set_status(status, MD_ESINGULAR);
-  }
   double y[L];
   md::zero<L>(y);
-  if (on) ld<L>(qt, nn, (size_t)p * n + c, y);
-  // R(p, j) for p < j, four columns ahead of the step that uses them (R was
-  // just written by another kernel: its loads come from memory, not the L2)
+  if (on) {
+    double y0[L], d[L];
+    ld<L>(qt, nn, (size_t)p * n + c, y0);
+    ld<L>(dq, n, p, d);
+    MD<L>::mul(y0, d, y);
+  }
+  // R~(p, j) for p < j
   auto ldcol = [&](int j, double (&r)[L]) {
     md::zero<L>(r);
-    if (j >= 0 && lane < j) ld<L>(qr, nn, (size_t)p * n + j, r);
+    if (j >= 0 && lane < j) ld<L>(rs, nn, (size_t)p * n + j, r);
   };
   double r0[L], r1[L], r2[L], r3[L];
   ldcol(n - 1, r0);
   ldcol(n - 2, r1);
   ldcol(n - 3, r2);
   ldcol(n - 4, r3);
-  // step i with column i of R in rc, which then receives column i - 4
+  // step i with column i of R~ in rc, which then receives column i - 4
   auto step = [&](int i, double (&rc)[L]) {
-    double zl[L], z[L];
-    MD<L>::mul(y, dq, zl);  // meaningful in lane i
+    double z[L];
 #pragma unroll
-    for (int l = 0; l < L; ++l) z[l] = read_lane(zl[l], i);
-    if (lane == i) md::copy<L>(z, y);
-    else if (lane < i) MD<L>::fms(y, rc, z);
+    for (int l = 0; l < L; ++l) z[l] = read_lane(y[l], i);
+    if (lane < i) MD<L>::fms(y, rc, z);
     ldcol(i - 4, rc);
   };
   int i = n - 1;
@@ -1612,9 +1637,13 @@ hipError_t launch_qr_lds(int L, int n, double *a, double *tau, double *qt, int32
 }
 
 hipError_t launch_m_from_qt(int L, int n, const double *qr, const double *qt, double *invd, double *M,
-                            int32_t *status, hipStream_t st) {
-  if (n <= 64) {
-    MD_DISPATCH(L, hipLaunchKernelGGL(m_from_qt_small_kernel<LL>, dim3(n), dim3(64), 0, st, n, qr, qt, M, status));
+                            int32_t *status, hipStream_t st, double *rs) {
+  if (n <= 64 && rs) {
+    MD_DISPATCH(L, {
+      hipLaunchKernelGGL(rscale_kernel<LL>, dim3(n), dim3(64), 0, st, n, qr, rs, invd, status);
+      hipLaunchKernelGGL(m_from_qt_small_kernel<LL>, dim3(n), dim3(64), 0, st, n, (const double *)rs,
+                         (const double *)invd, qt, M);
+    });
     return hipGetLastError();
   }
   MD_DISPATCH(L, {
