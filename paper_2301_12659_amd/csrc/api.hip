@@ -91,6 +91,7 @@ struct Layout {
   // the next iterate and the derivative products of its pre-pass
   size_t qr2, tau2, qt2, M2, xn, der0;
   size_t xseq;  // count of xn's workgroups done (md_newton_steps)
+  size_t mseq;  // count of M's columns done (md_newton_steps)
   size_t rs;    // rows of R scaled by their diagonal (back substitution of M)
   size_t total;
 };
@@ -132,6 +133,7 @@ Layout newton_layout(const md_plan *p) {
   w.xn = take(L * n);
   w.der0 = take(L * p->nnz + 1);
   w.xseq = take(1);
+  w.mseq = take(1);
   w.rs = take(L * n * n);
   w.total = off;
   return w;
@@ -657,8 +659,10 @@ static int newton_steps_impl(const md_plan *p, int count, const double *cff, con
   const int L = p->L, n = p->n, D = p->D;
   const size_t nn = (size_t)n * n;
   hipError_t e;
-  int *xseq = reinterpret_cast<int *>(at(ws, w.xseq));
-  if ((e = mdk::launch_status_init(dev_status, st, xseq)) != hipSuccess) return hip_fail(e, "status");
+  int *xseq = reinterpret_cast<int *>(at(ws, w.xseq)), *mseq = reinterpret_cast<int *>(at(ws, w.mseq));
+  // M counted on the device only where the small back substitution forms it
+  const bool mcount = n <= 64;
+  if ((e = mdk::launch_status_init(dev_status, st, xseq, mseq)) != hipSuccess) return hip_fail(e, "status");
   double *b = at(ws, w.b), *A = at(ws, w.A), *r = at(ws, w.r), *dx = at(ws, w.dx), *N = at(ws, w.N);
   double *At = at(ws, w.At), *dxT = at(ws, w.dxT), *invd = at(ws, w.invd), *xn = at(ws, w.xn);
   double *qrs[2] = {at(ws, w.qr), at(ws, w.qr2)}, *taus[2] = {at(ws, w.tau), at(ws, w.tau2)};
@@ -699,8 +703,8 @@ static int newton_steps_impl(const md_plan *p, int count, const double *cff, con
     }
     {
       Timed t(MD_CLASS_QHB_BS, p->aux);
-      if ((e = mdk::launch_m_from_qt(L, n, qrs[k], qts[k], invd, Ms[k], dev_status, p->aux, at(ws, w.rs))) !=
-          hipSuccess)
+      if ((e = mdk::launch_m_from_qt(L, n, qrs[k], qts[k], invd, Ms[k], dev_status, p->aux, at(ws, w.rs),
+                                     mcount ? mseq : nullptr)) != hipSuccess)
         return hip_fail(e, "M");
     }
     if ((e = hipEventRecord(p->join, p->aux)) != hipSuccess) return hip_fail(e, "join");
@@ -720,7 +724,13 @@ static int newton_steps_impl(const md_plan *p, int count, const double *cff, con
     rc = eval_diff_impl(p, D, cff, cst, x, b, A, ws, st, nullptr, false, mdk::TOut{r, 0, D, L},
                         mdk::TOut{At, 0, D, L}, sync, mdk::stages_sync_ints(D), dxT, (size_t)L * n * D);
     if (rc != MD_OK) return rc;
-    if ((e = hipStreamWaitEvent(st, p->join, 0)) != hipSuccess) return hip_fail(e, "join wait");
+    // M of this step: a one-wavefront wait for its columns' count on the
+    // device (the factorizations so far: s + 1), else the join event
+    if (mcount) {
+      if ((e = mdk::launch_wait_count(mseq, n * (s + 1), dev_status, st)) != hipSuccess) return hip_fail(e, "M wait");
+    } else if ((e = hipStreamWaitEvent(st, p->join, 0)) != hipSuccess) {
+      return hip_fail(e, "join wait");
+    }
     {
       // N, P, Q and, before the last step, coefficient 0 of the next iterate
       // (from M and r_0; x is updated later in this stream)
@@ -745,6 +755,8 @@ static int newton_steps_impl(const md_plan *p, int count, const double *cff, con
         return hip_fail(e, "update");
     }
   }
+  // the caller's stream after every launch of the second stream
+  if (mcount && (e = hipStreamWaitEvent(st, p->join, 0)) != hipSuccess) return hip_fail(e, "join wait");
   return MD_OK;
 }
 

@@ -67,7 +67,10 @@ hipError_t launch_assemble_A0(int L, int n, int D, int nnz, const int32_t *asm_p
                               const double *der, double *a0, hipStream_t st, QrPrep prep);
 
 // linalg.hip
-hipError_t launch_status_init(int32_t *status, hipStream_t st, int *counter = nullptr);  // and *counter = 0
+// and *counter = *counter2 = 0
+hipError_t launch_status_init(int32_t *status, hipStream_t st, int *counter = nullptr, int *counter2 = nullptr);
+// one wavefront on st waits until *ctr >= target (bounded, MD_EHIP)
+hipError_t launch_wait_count(const int *ctr, int target, int32_t *status, hipStream_t st);
 hipError_t launch_qr(int L, int n, double *a, double *tau, double *qt, int32_t *status, unsigned *bar,
                      hipStream_t st);
 int qr_lds_workgroups(int L, int n, bool with_qt);
@@ -77,8 +80,10 @@ hipError_t launch_qr_lds(int L, int n, double *a, double *tau, double *qt, int32
                          double *vboard, double *tboard, hipStream_t st, bool prepared = false);
 // rs (nullable): L n n doubles of scratch for the rows of R scaled by their
 // diagonal (n <= 64: a back substitution whose steps have no division)
+// done (nullable, with rs): each column's workgroup adds one to it after
+// agent-scope stores and a wait for them
 hipError_t launch_m_from_qt(int L, int n, const double *qr, const double *qt, double *invd, double *M,
-                            int32_t *status, hipStream_t st, double *rs = nullptr);
+                            int32_t *status, hipStream_t st, double *rs = nullptr, int *done = nullptr);
 hipError_t launch_form_m(int L, int n, const double *qr, const double *tau, double *invd, double *M, int32_t *status,
                          hipStream_t st);
 hipError_t launch_extract(int L, int n, int D, int k, const double *A, double *out, hipStream_t st);

@@ -26,9 +26,25 @@ namespace mdk {
 
 // ----------------------------------------------------------------- status
 
-__global__ void status_init_kernel(int32_t *status, int *counter) {
+__global__ void status_init_kernel(int32_t *status, int *counter, int *counter2) {
   if (threadIdx.x == 0 && blockIdx.x == 0 && status) *status = MD_OK;
   if (threadIdx.x == 0 && blockIdx.x == 0 && counter) *counter = 0;
+  if (threadIdx.x == 0 && blockIdx.x == 0 && counter2) *counter2 = 0;
+}
+
+// One wavefront that waits until *ctr >= target (bounded: MD_EHIP), so that
+// the launches after it on its stream follow work on another stream that
+// counts itself done in *ctr after agent-scope stores and a wait for them.
+__global__ void __launch_bounds__(64) wait_count_kernel(const int *ctr, int target, int32_t *status) {
+  if (threadIdx.x != 0) return;
+  long spins = 0;
+  while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    __builtin_amdgcn_s_sleep(1);
+    if (++spins > (1L << 22)) {
+      set_status(status, MD_EHIP);
+      return;
+    }
+  }
 }
 
 // ----------------------------------------------------------------- QR
@@ -772,7 +788,7 @@ __global__ void __launch_bounds__(64) rscale_kernel(int n, const double *qr, dou
 // from memory, not the L2).
 template <int L>
 __global__ void __launch_bounds__(64, 1) m_from_qt_small_kernel(int n, const double *rs, const double *dq,
-                                                             const double *qt, double *M) {
+                                                             const double *qt, double *M, int *done) {
   // raised wave priority: the kernel runs beside the evaluation, whose
   // wavefronts fill the CUs (M beside it: 47 against 180 us)
   __builtin_amdgcn_s_setprio(3);
@@ -816,7 +832,14 @@ __global__ void __launch_bounds__(64, 1) m_from_qt_small_kernel(int n, const dou
   if (i >= 0) step(i, r0);
   if (i >= 1) step(i - 1, r1);
   if (i >= 2) step(i - 2, r2);
-  if (on) st<L>(M, nn, (size_t)p * n + c, y);
+  if (!done) {
+    if (on) st<L>(M, nn, (size_t)p * n + c, y);
+    return;
+  }
+  // a reader on another stream polls *done (one count per column)
+  if (on) st_agent<L>(M, nn, (size_t)p * n + c, y);
+  wait_vm();
+  if (lane == 0) __hip_atomic_fetch_add(done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Dense copy of the series coefficient k of A: out[i][j] = A[i][j][k].
@@ -1546,8 +1569,13 @@ __global__ void __launch_bounds__(256) arith_kernel(int op, int64_t count, const
 
 // ------------------------------------------------------------------ launchers
 
-hipError_t launch_status_init(int32_t *status, hipStream_t st, int *counter) {
-  hipLaunchKernelGGL(status_init_kernel, dim3(1), dim3(64), 0, st, status, counter);
+hipError_t launch_wait_count(const int *ctr, int target, int32_t *status, hipStream_t st) {
+  hipLaunchKernelGGL(wait_count_kernel, dim3(1), dim3(64), 0, st, ctr, target, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_status_init(int32_t *status, hipStream_t st, int *counter, int *counter2) {
+  hipLaunchKernelGGL(status_init_kernel, dim3(1), dim3(64), 0, st, status, counter, counter2);
   return hipGetLastError();
 }
 
@@ -1637,12 +1665,12 @@ hipError_t launch_qr_lds(int L, int n, double *a, double *tau, double *qt, int32
 }
 
 hipError_t launch_m_from_qt(int L, int n, const double *qr, const double *qt, double *invd, double *M,
-                            int32_t *status, hipStream_t st, double *rs) {
+                            int32_t *status, hipStream_t st, double *rs, int *done) {
   if (n <= 64 && rs) {
     MD_DISPATCH(L, {
       hipLaunchKernelGGL(rscale_kernel<LL>, dim3(n), dim3(64), 0, st, n, qr, rs, invd, status);
       hipLaunchKernelGGL(m_from_qt_small_kernel<LL>, dim3(n), dim3(64), 0, st, n, (const double *)rs,
-                         (const double *)invd, qt, M);
+                         (const double *)invd, qt, M, done);
     });
     return hipGetLastError();
   }
