@@ -675,8 +675,11 @@ static int newton_steps_impl(const md_plan *p, int count, const double *cff, con
   // the caller's stream before a fork event; the next ones' are formed by
   // the launch of the products N, P, Q, whose xn workgroups count themselves
   // done in xseq (xseq_target: the count to wait for, 0: the fork event), so
-  // that no event sits between that launch and the staged solve.
-  auto factor = [&](int k, int xseq_target) -> int {
+  // that no event sits between that launch and the staged solve.  The join
+  // event is recorded after the last factorization only (and after every
+  // one where the caller's stream waits for it instead of M's count): an
+  // event record on the second stream delays its next launch.
+  auto factor = [&](int k, int xseq_target, bool last) -> int {
     if (xseq_target == 0) {
       if ((e = hipEventRecord(p->fork, st)) != hipSuccess) return hip_fail(e, "fork");
       if ((e = hipStreamWaitEvent(p->aux, p->fork, 0)) != hipSuccess) return hip_fail(e, "fork wait");
@@ -707,13 +710,13 @@ static int newton_steps_impl(const md_plan *p, int count, const double *cff, con
                                      mcount ? mseq : nullptr)) != hipSuccess)
         return hip_fail(e, "M");
     }
-    if ((e = hipEventRecord(p->join, p->aux)) != hipSuccess) return hip_fail(e, "join");
+    if ((last || !mcount) && (e = hipEventRecord(p->join, p->aux)) != hipSuccess) return hip_fail(e, "join");
     return MD_OK;
   };
   // coefficient 0 of the first iterate into xn
   if ((e = mdk::launch_transpose_ld(L, x, D, xn, n, n, 1, (size_t)n * D, n, st)) != hipSuccess)
     return hip_fail(e, "x_0");
-  int rc = factor((count - 1) % 2, 0);
+  int rc = factor((count - 1) % 2, 0, count == 1);
   if (rc != MD_OK) return rc;
   for (int s = 0; s < count; ++s) {
     const int k = (count - 1 - s) % 2;
@@ -743,7 +746,7 @@ static int newton_steps_impl(const md_plan *p, int count, const double *cff, con
     }
     // the next factorization on the second stream, beside the rest of this
     // step and the next evaluation
-    if (s + 1 < count && (rc = factor(1 - k, ((n + 3) / 4) * (s + 1))) != MD_OK) return rc;
+    if (s + 1 < count && (rc = factor(1 - k, ((n + 3) / 4) * (s + 1), s + 2 == count)) != MD_OK) return rc;
     {
       Timed t(MD_CLASS_UPDATES, st);
       if ((e = mdk::launch_stages(L, n, D, Ms[k], N, At, r, dxT, sync, dev_status, st, true)) != hipSuccess)

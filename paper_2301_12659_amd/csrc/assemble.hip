@@ -113,6 +113,9 @@ __global__ void __launch_bounds__(256) assemble_b_kernel(int n, int D, int Dc, i
 // assemble_tile at most 8, 8, 4, 2 for 1, 2, 4, 8 limbs (MD_MAX_COEFFS = 128).
 __host__ __device__ constexpr int asm_a_max_slices(int L) { return L >= 8 ? 2 : (L == 4 ? 4 : 8); }
 
+// Entries of a Jacobian entry's list loaded together by the assemblies of A.
+constexpr int ASM_BATCH = 4;
+
 template <int L, int TI>
 __device__ __forceinline__ void assemble_A_block(unsigned bid, int n, int D, int Dc, int nnz, const int32_t *asm_ptr,
                                                  const int32_t *asm_ent, const double *der, double *A, TOut at,
@@ -132,27 +135,36 @@ __device__ __forceinline__ void assemble_A_block(unsigned bid, int n, int D, int
     double acc[MAXS][L];
 #pragma unroll
     for (int u = 0; u < MAXS; ++u) md::zero<L>(acc[u]);
-    for (int t = lo; t < hi; ++t) {
-      const size_t eo = (size_t)asm_ent[t] * D;
-      double v[MAXS][L];
+    // the list in batches of ASM_BATCH entries: a batch's indices, then all
+    // its values, are loaded before its values are added in list order (two
+    // memory round trips per batch instead of two per entry)
+    for (int t0 = lo; t0 < hi; t0 += ASM_BATCH) {
+      size_t eo[ASM_BATCH];
 #pragma unroll
-      for (int u = 0; u < MAXS; ++u) {
-        const int s = sl + u * per;
-        if (u < NS && s < Dc) ld<L>(der, zD, eo + s, v[u]);
-      }
+      for (int e = 0; e < ASM_BATCH; ++e) eo[e] = (t0 + e < hi) ? (size_t)asm_ent[t0 + e] * D : 0;
+      double v[ASM_BATCH][MAXS][L];
 #pragma unroll
-      for (int u = 0; u < MAXS; ++u) {
-        const int s = sl + u * per;
-        if (u < NS && s < Dc) {
-          if (t == lo) {
-            md::copy<L>(v[u], acc[u]);
-          } else {
-            double r[L];
-            MD<L>::add(acc[u], v[u], r);
-            md::copy<L>(r, acc[u]);
+      for (int e = 0; e < ASM_BATCH; ++e)
+#pragma unroll
+        for (int u = 0; u < MAXS; ++u) {
+          const int s = sl + u * per;
+          if (t0 + e < hi && u < NS && s < Dc) ld<L>(der, zD, eo[e] + s, v[e][u]);
+        }
+#pragma unroll
+      for (int e = 0; e < ASM_BATCH; ++e)
+#pragma unroll
+        for (int u = 0; u < MAXS; ++u) {
+          const int s = sl + u * per;
+          if (t0 + e < hi && u < NS && s < Dc) {
+            if (t0 + e == lo) {
+              md::copy<L>(v[e][u], acc[u]);
+            } else {
+              double r[L];
+              MD<L>::add(acc[u], v[e][u], r);
+              md::copy<L>(r, acc[u]);
+            }
           }
         }
-      }
     }
 #pragma unroll
     for (int u = 0; u < MAXS; ++u) {
@@ -218,13 +230,25 @@ __global__ void assemble_A0_kernel(int n, int D, int nnz, const int32_t *asm_ptr
   const int lo = asm_ptr[ij], hi = asm_ptr[ij + 1];
   double acc[L];
   md::zero<L>(acc);
-  if (lo < hi) {
-    ld<L>(der, zD, (size_t)asm_ent[lo] * D, acc);
-    for (int t = lo + 1; t < hi; ++t) {
-      double v[L], r[L];
-      ld<L>(der, zD, (size_t)asm_ent[t] * D, v);
-      MD<L>::add(acc, v, r);
-      md::copy<L>(r, acc);
+  // batches of ASM_BATCH entries, as in assemble_A_block
+  for (int t0 = lo; t0 < hi; t0 += ASM_BATCH) {
+    size_t eo[ASM_BATCH];
+#pragma unroll
+    for (int e = 0; e < ASM_BATCH; ++e) eo[e] = (t0 + e < hi) ? (size_t)asm_ent[t0 + e] * D : 0;
+    double v[ASM_BATCH][L];
+#pragma unroll
+    for (int e = 0; e < ASM_BATCH; ++e)
+      if (t0 + e < hi) ld<L>(der, zD, eo[e], v[e]);
+#pragma unroll
+    for (int e = 0; e < ASM_BATCH; ++e) {
+      if (t0 + e >= hi) continue;
+      if (t0 + e == lo) {
+        md::copy<L>(v[e], acc);
+      } else {
+        double r[L];
+        MD<L>::add(acc, v[e], r);
+        md::copy<L>(r, acc);
+      }
     }
   }
   st<L>(a0, nn, ij, acc);

@@ -218,6 +218,27 @@ __global__ void __launch_bounds__(256) evaldiff0_kernel(EvalArgs a) {
   // the step's status word, reset by its first launch (every launch that can
   // report into it comes later in stream order; no evaluation kernel does)
   if (t == 0 && a.reset_status) *a.reset_status = MD_OK;
+  // the monomial's support, exponents and coefficient do not depend on x:
+  // their loads are issued before any wait for x
+  const bool live = t < a.m;
+  const int mono = live ? t : 0;
+  int e0 = 0, k = 0;
+  int vv[EVAL0_MAXK], ex[EVAL0_MAXK];
+  double f[EVAL0_MAXK][L];  // f[j] = f_j for j < k (f_0 = c CF)
+  if (live) {
+    e0 = a.mon_ptr[mono];
+    k = a.mon_ptr[mono + 1] - e0;
+    ld<L>(a.cff, a.m, mono, f[0]);
+  }
+#pragma unroll
+  for (int j = 0; j < EVAL0_MAXK; ++j) {
+    vv[j] = 0;
+    ex[j] = 1;
+    if (j < k) {
+      vv[j] = a.var[e0 + j];
+      ex[j] = a.exp[e0 + j];
+    }
+  }
   if (a.wait_ctr) {
     __shared__ int ok;
     if (threadIdx.x == 0) {
@@ -235,25 +256,17 @@ __global__ void __launch_bounds__(256) evaldiff0_kernel(EvalArgs a) {
     __syncthreads();
     if (!ok) return;
   }
-  if (t >= a.m) return;
-  const int mono = t;
-  const int e0 = a.mon_ptr[mono], k = a.mon_ptr[mono + 1] - e0;
+  if (!live || k == 0) return;  // k == 0: no derivatives
   const size_t nD = (size_t)a.n * a.D, zD = (size_t)a.nnz * a.D;
-  if (k == 0) return;  // no derivatives
   double xs[EVAL0_MAXK][L];
-  int ex[EVAL0_MAXK];
 #pragma unroll
   for (int j = 0; j < EVAL0_MAXK; ++j) {
     md::zero<L>(xs[j]);
-    ex[j] = 1;
     if (j < k) {
-      if (a.wait_ctr) ld_agent<L>(a.x, nD, (size_t)a.var[e0 + j] * a.D, xs[j]);
-      else ld<L>(a.x, nD, (size_t)a.var[e0 + j] * a.D, xs[j]);
-      ex[j] = a.exp[e0 + j];
+      if (a.wait_ctr) ld_agent<L>(a.x, nD, (size_t)vv[j] * a.D, xs[j]);
+      else ld<L>(a.x, nD, (size_t)vv[j] * a.D, xs[j]);
     }
   }
-  double f[EVAL0_MAXK][L];  // f[j] = f_j for j < k (f_0 = c CF)
-  ld<L>(a.cff, a.m, mono, f[0]);
 #pragma unroll
   for (int j = 0; j < EVAL0_MAXK; ++j) {  // common factor: x^(a-1) for exponents >= 2
     if (j < k)

@@ -1026,19 +1026,19 @@ __device__ __forceinline__ void next_x0_block(int n, int D, const double *M, con
   }
 }
 
-// The products of gemm_kernel (blockIdx.y < gridDim.y - 1) and, in the last
-// row of blocks, coefficient 0 of the next iterate (next_x0_block): one
-// launch where the caller's stream has both ready (M and r_0), so that the
-// update of x later in that stream comes after every read of x_0.  done
-// (nullable): each of the ceil(n / 4) workgroups of xn adds one to it once
-// its stores are performed, for the factorization that waits for xn on the
-// second stream.
+// Coefficient 0 of the next iterate (next_x0_block) in the first row of
+// blocks and the products of gemm_kernel (product blockIdx.y - 1) in the
+// others: one launch where the caller's stream has both ready (M and r_0),
+// so that the update of x later in that stream comes after every read of
+// x_0.  The xn workgroups are dispatched first: the factorization on the
+// second stream waits for them.  done (nullable): each of the ceil(n / 4)
+// workgroups of xn adds one to it once its stores are performed.
 template <int L>
 __global__ void __launch_bounds__(256) gemm_next_x0_kernel(int n, int D, const double *M, const double *B, size_t b_ls,
                                                            double *N, const double *rT, const double *x, double *xn,
                                                            int *done) {
-  if (blockIdx.y + 1 < gridDim.y) {
-    gemm_block<L>(n, M, B, b_ls, N, blockIdx.y);
+  if (blockIdx.y > 0) {
+    gemm_block<L>(n, M, B, b_ls, N, blockIdx.y - 1);
   } else if ((int)blockIdx.x * 4 < n) {
     next_x0_block<L>(n, D, M, rT, x, xn, done);
   }
