@@ -422,7 +422,8 @@ static void eval_args(const md_plan *p, const double *cff, const double *x, void
 static int eval_diff_impl(const md_plan *p, int Dc, const double *cff, const double *cst, const double *x, double *b,
                           double *A, void *ws, hipStream_t st, double *tsz = nullptr, bool beside_qr = false,
                           mdk::TOut rt = mdk::TOut(), mdk::TOut aT = mdk::TOut(), int *clear = nullptr,
-                          int clear_count = 0, double *empty = nullptr, size_t empty_count = 0) {
+                          int clear_count = 0, double *empty = nullptr, size_t empty_count = 0,
+                          mdk::CountWait wait = mdk::CountWait()) {
   Layout w = newton_layout(p);
   mdk::EvalArgs a;
   eval_args(p, cff, x, ws, Dc, a);
@@ -437,7 +438,8 @@ static int eval_diff_impl(const md_plan *p, int Dc, const double *cff, const dou
   {
     Timed t(MD_CLASS_ASSEMBLY, st);
     e = mdk::launch_assemble(p->L, p->n, p->D, Dc, p->m, p->nnz, p->d_poly_ptr, p->d_asm_ptr, p->d_asm_ent, cst,
-                             a.val, a.der, b, A, st, tsz, a.vsize, rt, aT, clear, clear_count, empty, empty_count);
+                             a.val, a.der, b, A, st, tsz, a.vsize, rt, aT, clear, clear_count, empty, empty_count,
+                             wait);
   }
   if (e != hipSuccess) return hip_fail(e, "assembly launch");
   return MD_OK;
@@ -723,17 +725,14 @@ static int newton_steps_impl(const md_plan *p, int count, const double *cff, con
     // the evaluation is on the critical path here (the factorization of the
     // next step has slack): the two-wavefront kernel (0.69 against 0.75 ms
     // per step); the assembly also writes the coefficient-major A and b,
-    // clears the staged solve's counters and empties its dx slots
+    // clears the staged solve's counters and empties its dx slots, and ends
+    // only once M of this step is formed: a wait for its columns' count on
+    // the device (the factorizations so far: s + 1), else the join event
     rc = eval_diff_impl(p, D, cff, cst, x, b, A, ws, st, nullptr, false, mdk::TOut{r, 0, D, L},
-                        mdk::TOut{At, 0, D, L}, sync, mdk::stages_sync_ints(D), dxT, (size_t)L * n * D);
+                        mdk::TOut{At, 0, D, L}, sync, mdk::stages_sync_ints(D), dxT, (size_t)L * n * D,
+                        mcount ? mdk::CountWait{mseq, n * (s + 1), dev_status} : mdk::CountWait());
     if (rc != MD_OK) return rc;
-    // M of this step: a one-wavefront wait for its columns' count on the
-    // device (the factorizations so far: s + 1), else the join event
-    if (mcount) {
-      if ((e = mdk::launch_wait_count(mseq, n * (s + 1), dev_status, st)) != hipSuccess) return hip_fail(e, "M wait");
-    } else if ((e = hipStreamWaitEvent(st, p->join, 0)) != hipSuccess) {
-      return hip_fail(e, "join wait");
-    }
+    if (!mcount && (e = hipStreamWaitEvent(st, p->join, 0)) != hipSuccess) return hip_fail(e, "join wait");
     {
       // N, P, Q and, before the last step, coefficient 0 of the next iterate
       // (from M and r_0; x is updated later in this stream)

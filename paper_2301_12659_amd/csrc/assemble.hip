@@ -198,7 +198,10 @@ __global__ void __launch_bounds__(256) assemble_A_kernel(int n, int D, int Dc, i
 
 // Both assemblies in one launch: workgroups 0 .. GA - 1 form A (as
 // assemble_A_kernel), the others b (as assemble_b_kernel); they read disjoint
-// inputs and write disjoint outputs.
+// inputs and write disjoint outputs.  With wait.ctr, one thread of the first
+// workgroup waits for the count after its part, so the launch ends only
+// once the count is reached (a wait for another stream that costs no launch
+// of its own).
 template <int L, int TI>
 __global__ void __launch_bounds__(256) assemble_bA_kernel(unsigned GA, int n, int D, int Dc, int m, int nnz,
                                                           const int32_t *poly_ptr, const int32_t *asm_ptr,
@@ -206,13 +209,14 @@ __global__ void __launch_bounds__(256) assemble_bA_kernel(unsigned GA, int n, in
                                                           const double *val, const double *der, double *b,
                                                           double *A, double *tsz, const double *vsize, TOut rt,
                                                           TOut at, int *clear, int clear_count, double *empty,
-                                                          size_t empty_count) {
+                                                          size_t empty_count, CountWait wait) {
   extern __shared__ double tile[];
   if (blockIdx.x < GA)
     assemble_A_block<L, TI>(blockIdx.x, n, D, Dc, nnz, asm_ptr, asm_ent, der, A, at, tile);
   else
     assemble_b_block<L>(blockIdx.x - GA, n, D, Dc, m, poly_ptr, cst, val, b, tsz, vsize, rt, clear, clear_count,
                         empty, empty_count);
+  if (wait.ctr && blockIdx.x == 0 && threadIdx.x == 0) wait_count(wait.ctr, wait.target, wait.status);
 }
 
 // Coefficient 0 of A into a dense row-major matrix a0 [L][n][n], summed in
@@ -315,7 +319,7 @@ hipError_t launch_assemble(int L, int n, int D, int Dc, int m, int nnz, const in
                            const int32_t *asm_ptr, const int32_t *asm_ent, const double *cst, const double *val,
                            const double *der, double *b, double *A, hipStream_t st, double *tsz,
                            const double *vsize, TOut rt, TOut at, int *clear, int clear_count, double *empty,
-                           size_t empty_count) {
+                           size_t empty_count, CountWait wait) {
   if (Dc < 1 || Dc > D) return hipErrorInvalidValue;
   if (rt.p && (rt.lo < 0 || rt.W < 1 || rt.lo + rt.W > Dc || rt.L < 1 || rt.L > L)) return hipErrorInvalidValue;
   if (at.p && (at.lo != 0 || at.W < 1 || at.W > Dc || at.L < 1 || at.L > L)) return hipErrorInvalidValue;
@@ -329,7 +333,7 @@ hipError_t launch_assemble(int L, int n, int D, int Dc, int m, int nnz, const in
 #define MD_ASM_BA(TI)                                                                                             \
   MD_DISPATCH(L, hipLaunchKernelGGL((assemble_bA_kernel<LL, TI>), grid, dim3(256), lds, st, GA, n, D, Dc, m, nnz, \
                                     poly_ptr, asm_ptr, asm_ent, cst, val, der, b, A, tsz, vsize, rt, at, clear,   \
-                                    clear_count, empty, empty_count))
+                                    clear_count, empty, empty_count, wait))
   switch (ti) {
     case 16: MD_ASM_BA(16); break;
     case 8: MD_ASM_BA(8); break;

@@ -142,6 +142,21 @@ __device__ __forceinline__ void set_status(int32_t *status, int32_t code) {
   if (status) atomicCAS(status, 0, code);
 }
 
+// One thread waits until *ctr >= target, a count that workgroups of a
+// launch on another stream raise once their agent-scope stores are
+// performed.  Bounded: false (and MD_EHIP in status) when it runs out.
+__device__ __forceinline__ bool wait_count(const int *ctr, int target, int32_t *status) {
+  long spins = 0;
+  while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    __builtin_amdgcn_s_sleep(2);
+    if (++spins > (1L << 22)) {
+      set_status(status, MD_EHIP);
+      return false;
+    }
+  }
+  return true;
+}
+
 // Dispatch a launch on the limb count: the statement sees LL as a constant.
 #define MD_DISPATCH(L, ...)                                 \
   switch (L) {                                              \

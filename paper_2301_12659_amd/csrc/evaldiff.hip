@@ -241,18 +241,7 @@ __global__ void __launch_bounds__(256) evaldiff0_kernel(EvalArgs a) {
   }
   if (a.wait_ctr) {
     __shared__ int ok;
-    if (threadIdx.x == 0) {
-      long spins = 0;
-      ok = 1;
-      while (__hip_atomic_load(a.wait_ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < a.wait_target) {
-        __builtin_amdgcn_s_sleep(2);
-        if (++spins > (1L << 22)) {
-          set_status(a.wait_status, MD_EHIP);
-          ok = 0;
-          break;
-        }
-      }
-    }
+    if (threadIdx.x == 0) ok = wait_count(a.wait_ctr, a.wait_target, a.wait_status) ? 1 : 0;
     __syncthreads();
     if (!ok) return;
   }

@@ -44,17 +44,27 @@ struct TOut {
   double *p = nullptr;
   int lo = 0, W = 0, L = 0;
 };
+// A count to wait for (wait_count): the launch that takes it ends only once
+// *ctr >= target.  ctr == nullptr: none.
+struct CountWait {
+  const int *ctr = nullptr;
+  int target = 0;
+  int32_t *status = nullptr;
+};
 // The assembly kernels fill the first Dc coefficients of series stored with
 // D; tsz (nullable, [n][D]) gets |c_{i,0,s}| + sum_m vsize_{m,s} (the
 // evaluation's chain maxima; |value_{m,s}| when vsize is null), the size of
 // the terms of b_{i,s}; rt and at the coefficient-major copies of b and A;
 // clear (nullable) clear_count ints set to zero and empty (nullable)
-// empty_count slots emptied (SLOT_EMPTY) by the b launch.
+// empty_count slots emptied (SLOT_EMPTY) by the b launch; launch_assemble
+// also ends only after wait (so that the launches after it on st follow the
+// work on another stream that counts itself done).
 hipError_t launch_assemble(int L, int n, int D, int Dc, int m, int nnz, const int32_t *poly_ptr,
                            const int32_t *asm_ptr, const int32_t *asm_ent, const double *cst, const double *val,
                            const double *der, double *b, double *A, hipStream_t st, double *tsz = nullptr,
                            const double *vsize = nullptr, TOut rt = TOut(), TOut at = TOut(), int *clear = nullptr,
-                           int clear_count = 0, double *empty = nullptr, size_t empty_count = 0);
+                           int clear_count = 0, double *empty = nullptr, size_t empty_count = 0,
+                           CountWait wait = CountWait());
 size_t evaldiff_lds_bytes(int L, int D);
 int evaldiff_workers_per_block(int D);  // monomials per 256-thread workgroup
 hipError_t launch_assemble_b(int L, int n, int D, int Dc, int m, const int32_t *poly_ptr, const double *cst,
@@ -69,8 +79,6 @@ hipError_t launch_assemble_A0(int L, int n, int D, int nnz, const int32_t *asm_p
 // linalg.hip
 // and *counter = *counter2 = 0
 hipError_t launch_status_init(int32_t *status, hipStream_t st, int *counter = nullptr, int *counter2 = nullptr);
-// one wavefront on st waits until *ctr >= target (bounded, MD_EHIP)
-hipError_t launch_wait_count(const int *ctr, int target, int32_t *status, hipStream_t st);
 hipError_t launch_qr(int L, int n, double *a, double *tau, double *qt, int32_t *status, unsigned *bar,
                      hipStream_t st);
 int qr_lds_workgroups(int L, int n, bool with_qt);

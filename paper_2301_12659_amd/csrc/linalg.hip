@@ -32,21 +32,6 @@ __global__ void status_init_kernel(int32_t *status, int *counter, int *counter2)
   if (threadIdx.x == 0 && blockIdx.x == 0 && counter2) *counter2 = 0;
 }
 
-// One wavefront that waits until *ctr >= target (bounded: MD_EHIP), so that
-// the launches after it on its stream follow work on another stream that
-// counts itself done in *ctr after agent-scope stores and a wait for them.
-__global__ void __launch_bounds__(64) wait_count_kernel(const int *ctr, int target, int32_t *status) {
-  if (threadIdx.x != 0) return;
-  long spins = 0;
-  while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-    __builtin_amdgcn_s_sleep(1);
-    if (++spins > (1L << 22)) {
-      set_status(status, MD_EHIP);
-      return;
-    }
-  }
-}
-
 // ----------------------------------------------------------------- QR
 
 // Householder reflector of a column with squared norm nrm2 and leading entry
@@ -1568,11 +1553,6 @@ __global__ void __launch_bounds__(256) arith_kernel(int op, int64_t count, const
 }
 
 // ------------------------------------------------------------------ launchers
-
-hipError_t launch_wait_count(const int *ctr, int target, int32_t *status, hipStream_t st) {
-  hipLaunchKernelGGL(wait_count_kernel, dim3(1), dim3(64), 0, st, ctr, target, status);
-  return hipGetLastError();
-}
 
 hipError_t launch_status_init(int32_t *status, hipStream_t st, int *counter, int *counter2) {
   hipLaunchKernelGGL(status_init_kernel, dim3(1), dim3(64), 0, st, status, counter, counter2);
