@@ -164,9 +164,9 @@ int md_newton_step(const md_plan *plan, const double *cff, const double *cst, do
  * (double or quad double, n <= 64) with supports of at most 8 variables;
  * other plans take count ordinary steps.  The factorization of step s+1
  * waits on the device for the launch that forms its x_0 on the caller's
- * stream (a counter in the workspace, reset at the start of the call; the
- * wait is bounded and reports MD_EHIP), so two calls on one workspace must
- * not overlap.  dev_status: MD_OK, or the failure of any of the steps (the
+ * stream, and the caller's stream for M of each step (counters in the
+ * workspace, reset at the start of the call; the waits are bounded and
+ * report MD_EHIP), so two calls on one workspace must not overlap.  dev_status: MD_OK, or the failure of any of the steps (the
  * steps overlap, so the status is not reset between them); dev_norms: those
  * of the last step.  Workspace as md_newton_step;
  * the last step leaves its factorization where md_newton_step does, for
